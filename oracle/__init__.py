@@ -1,0 +1,233 @@
+"""Python access to the FP64 CPU oracle (``ssa_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
+benchmark's CPU-baseline leg may use this module; the product path never does.
+It imports nothing from the HIP package except the seeded input descriptions
+in ``paper_2602_19775_amd.workloads`` (which hold none of the method's
+arithmetic).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ssa_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-Wno-unused-parameter",
+                               SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Net(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32), ("n_params", C.c_int32),
+                ("reactant", C.c_void_p), ("rate_index", C.c_void_p), ("stoich", C.c_void_p)]
+
+
+class _Cfg(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("purpose", C.c_uint32), ("epoch", C.c_uint32),
+                ("n_steps", C.c_int64), ("t_end", C.c_double), ("obs_kind", C.c_int32),
+                ("n_bins", C.c_int32), ("t_obs", C.c_double), ("n_obs", C.c_int32),
+                ("obs_species", C.c_void_p), ("temperature", C.c_double),
+                ("tie_threshold", C.c_double), ("clock_tol", C.c_double)]
+
+
+class _Ov(C.Structure):
+    _fields_ = [("off", C.c_void_p), ("step", C.c_void_p), ("kind", C.c_void_p), ("val", C.c_void_p)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("min_margin", C.c_void_p), ("n_near", C.c_void_p), ("n_resync", C.c_void_p),
+                ("n_bad", C.c_void_p), ("bin_edge_dist", C.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_uniform.restype = C.c_double
+        L.orc_uniform.argtypes = [C.c_uint32]
+        L.orc_step_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                        C.c_uint32, C.c_int32, C.c_void_p]
+        common = [C.POINTER(_Net), C.POINTER(_Cfg), C.c_void_p, C.c_int64, C.c_void_p,
+                  C.c_void_p, C.POINTER(_Ov)]
+        L.orc_forward.argtypes = common + [C.c_void_p] * 4 + [C.POINTER(_Stats), C.c_int]
+        L.orc_forward.restype = C.c_int
+        L.orc_adjoint.argtypes = common + [C.c_void_p] * 6 + [C.POINTER(_Stats), C.c_int]
+        L.orc_adjoint.restype = C.c_int
+        L.orc_trace.argtypes = [C.POINTER(_Net), C.POINTER(_Cfg), C.c_void_p, C.c_uint32,
+                                C.c_void_p, C.c_int64] + [C.c_void_p] * 7
+        L.orc_trace.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+def philox4x32_10(counter: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    c = np.asarray(counter, np.uint32)
+    k = np.asarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def uniform(x: int) -> float:
+    return lib().orc_uniform(int(x) & 0xFFFFFFFF)
+
+
+def step_uniforms(seed: int, purpose: int, epoch: int, traj: int, step: int, n_words: int) -> np.ndarray:
+    u = np.zeros(n_words, np.float64)
+    lib().orc_step_uniforms(seed, purpose, epoch, traj, step, n_words, _p(u))
+    return u
+
+
+@dataclass
+class OracleResult:
+    x_final: np.ndarray        # [n_traj, N]
+    t_final: np.ndarray        # [n_traj]
+    steps_done: np.ndarray     # [n_traj]
+    obs: np.ndarray            # [n_traj, n_bins, n_obs] or [n_traj, n_obs]
+    min_margin: np.ndarray
+    n_near: np.ndarray
+    n_resync: np.ndarray
+    n_bad: np.ndarray
+    bin_edge_dist: np.ndarray
+    grad: Optional[np.ndarray] = None   # [n_traj, P]
+
+
+class _Keep:
+    """Keeps numpy buffers alive while ctypes structures point at them."""
+
+    def __init__(self):
+        self.items = []
+
+    def __call__(self, a):
+        self.items.append(a)
+        return a
+
+
+def _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species=None):
+    reactant = keep(np.ascontiguousarray(net.reactant, np.int32))
+    rate_index = keep(np.ascontiguousarray(net.rate_index, np.int32))
+    stoich = keep(np.ascontiguousarray(net.stoich, np.int32))
+    n = _Net(net.n_species, net.n_reactions, net.n_params, _p(reactant).value,
+             _p(rate_index).value, _p(stoich).value)
+    obs_sp = keep(np.ascontiguousarray(net.obs_species if obs_species is None else obs_species,
+                                       np.int32))
+    c = _Cfg(cfg.seed, cfg.purpose, cfg.epoch, min(int(cfg.n_steps), 2 ** 62),
+             float(cfg.t_end), cfg.obs_kind, cfg.n_bins, float(cfg.t_obs), len(obs_sp),
+             _p(obs_sp).value, float(cfg.temperature), tie_threshold, clock_tol)
+    return n, c
+
+
+def _overrides(n_traj, ties, keep):
+    """ties: iterable of (local traj index, step, kind, val)."""
+    if ties is None:
+        return None
+    t = np.asarray(list(ties), np.int64).reshape(-1, 4)
+    order = np.lexsort((t[:, 1], t[:, 0])) if len(t) else np.zeros(0, np.int64)
+    t = t[order]
+    off = keep(np.searchsorted(t[:, 0], np.arange(n_traj + 1)).astype(np.int64))
+    step = keep(np.ascontiguousarray(t[:, 1], np.int64))
+    kind = keep(np.ascontiguousarray(t[:, 2], np.int32))
+    val = keep(np.ascontiguousarray(t[:, 3], np.int32))
+    return _Ov(_p(off).value, _p(step).value, _p(kind).value, _p(val).value)
+
+
+def run(net, cfg, theta, x0: np.ndarray, traj_ids=None, ties=None, d_obs=None,
+        tie_threshold: float = 1e-6, clock_tol: float = 1e-5, n_threads: int = 0,
+        obs_species=None) -> OracleResult:
+    """Simulate (and, if d_obs is given, differentiate) a set of trajectories.
+
+    x0: [n_traj, N] or [N] (broadcast).  traj_ids: global trajectory ids (the
+    Philox counter), default 0..n_traj-1.  theta: ln k as float32 values."""
+    keep = _Keep()
+    N = net.n_species
+    x0 = np.asarray(x0, np.int32)
+    if traj_ids is None:
+        n_traj = x0.shape[0] if x0.ndim == 2 else 1
+        traj_ids = np.arange(n_traj, dtype=np.uint32)
+    traj_ids = keep(np.ascontiguousarray(traj_ids, np.uint32))
+    n_traj = len(traj_ids)
+    if x0.ndim == 1:
+        x0 = np.repeat(x0[None, :], n_traj, axis=0)
+    x0 = keep(np.ascontiguousarray(x0, np.int32))
+    assert x0.shape == (n_traj, N)
+    n, c = _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species)
+    th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
+    ov = _overrides(n_traj, ties, keep)
+    n_obs = c.n_obs
+    obs_shape = (n_traj, cfg.n_bins, n_obs) if cfg.obs_kind == 1 else (n_traj, n_obs)
+    res = OracleResult(np.zeros((n_traj, N), np.int32), np.zeros(n_traj), np.zeros(n_traj, np.int32),
+                       np.zeros(obs_shape), np.zeros(n_traj), np.zeros(n_traj, np.int32),
+                       np.zeros(n_traj, np.int32), np.zeros(n_traj, np.int32), np.zeros(n_traj))
+    st = _Stats(_p(res.min_margin).value, _p(res.n_near).value, _p(res.n_resync).value,
+                _p(res.n_bad).value, _p(res.bin_edge_dist).value)
+    L = lib()
+    ovp = C.byref(ov) if ov is not None else None
+    if d_obs is None:
+        rc = L.orc_forward(C.byref(n), C.byref(c), _p(th), n_traj, _p(traj_ids), _p(x0), ovp,
+                           _p(res.x_final), _p(res.t_final), _p(res.steps_done), _p(res.obs),
+                           C.byref(st), n_threads)
+    else:
+        d = keep(np.ascontiguousarray(np.broadcast_to(d_obs, obs_shape), np.float64))
+        res.grad = np.zeros((n_traj, net.n_params))
+        rc = L.orc_adjoint(C.byref(n), C.byref(c), _p(th), n_traj, _p(traj_ids), _p(x0), ovp,
+                           _p(d), _p(res.x_final), _p(res.t_final), _p(res.steps_done),
+                           _p(res.obs), _p(res.grad), C.byref(st), n_threads)
+    if rc != 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return res
+
+
+@dataclass
+class Trace:
+    X: np.ndarray       # [n+1, N]
+    t: np.ndarray       # [n+1]
+    tau: np.ndarray     # [n]
+    j: np.ndarray       # [n]
+    a: np.ndarray       # [n, M]
+    u: np.ndarray       # [n, M+1]
+    margin: np.ndarray  # [n]
+
+
+def trace(net, cfg, theta, x0, traj_id: int = 0, cap: int = 1000) -> Trace:
+    keep = _Keep()
+    n, c = _structs(net, cfg, keep, 1e-6, 1e-5)
+    N, M = net.n_species, net.n_reactions
+    th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
+    x = keep(np.ascontiguousarray(x0, np.int32))
+    X = np.zeros((cap + 1, N), np.int32)
+    t = np.zeros(cap + 1)
+    tau = np.zeros(cap)
+    j = np.zeros(cap, np.int32)
+    a = np.zeros((cap, M))
+    u = np.zeros((cap, M + 1))
+    mg = np.zeros(cap)
+    k = lib().orc_trace(C.byref(n), C.byref(c), _p(th), traj_id, _p(x), cap, _p(X), _p(t),
+                        _p(tau), _p(j), _p(a), _p(u), _p(mg))
+    if k < 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return Trace(X[:k + 1], t[:k + 1], tau[:k], j[:k], a[:k], u[:k], mg[:k])

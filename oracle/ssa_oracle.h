@@ -1,0 +1,113 @@
+/*
+ * FP64 CPU oracle of the batched exact Gillespie step and its Gumbel-Softmax
+ * straight-through adjoint.
+ *
+ * TEST INFRASTRUCTURE ONLY.  It is a plain, slow reference: one trajectory per
+ * OpenMP thread, loops over steps and reactions, FP64 everywhere.  Only the
+ * test suite, the package's smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no code, header or table with the HIP library.
+ */
+#ifndef SSA_ORACLE_H
+#define SSA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One reaction network (Sec. 2 of the paper): N species, M channels.
+ * reactant[2j], reactant[2j+1]: reactant species of channel j (-1 = none;
+ * equal pair = homodimerisation).  Parameters theta = ln k (Sec. 4.1);
+ * rate_index[j] picks the parameter of channel j.  stoich is the dense [M][N]
+ * table of change vectors v_j.
+ */
+typedef struct orc_net {
+    int32_t n_species;
+    int32_t n_reactions;
+    int32_t n_params;
+    const int32_t *reactant;    /* [M*2] */
+    const int32_t *rate_index;  /* [M] */
+    const int32_t *stoich;      /* [M*N] */
+} orc_net;
+
+enum { ORC_OBS_FINAL = 0, ORC_OBS_BINS = 1 };
+
+typedef struct orc_cfg {
+    uint64_t seed;
+    uint32_t purpose;
+    uint32_t epoch;
+    int64_t n_steps;        /* fire at most this many reactions */
+    double t_end;           /* fire only while t + tau <= t_end (INFINITY: no limit) */
+    int32_t obs_kind;       /* ORC_OBS_FINAL or ORC_OBS_BINS */
+    int32_t n_bins;
+    double t_obs;           /* bins split [0, t_obs] uniformly */
+    int32_t n_obs;
+    const int32_t *obs_species;  /* [n_obs] */
+    double temperature;     /* Gumbel-Softmax temperature T of Eq. (3) */
+    double tie_threshold;   /* relative margin that counts as a near-tie (1e-6) */
+    double clock_tol;       /* relative window |t + tau - t_end| <= clock_tol * t_end */
+} orc_cfg;
+
+/* Per-trajectory overrides taken from the GPU's near-tie log.  For trajectory
+ * q the entries ov_off[q] .. ov_off[q+1]-1 are sorted by step.
+ * kind 0: reaction near-tie, val = reaction the GPU fired.
+ * kind 1: clock near-tie at t_end, val = 1 if the GPU fired, 0 if it stopped. */
+typedef struct orc_overrides {
+    const int64_t *off;     /* [n_traj+1] */
+    const int64_t *step;
+    const int32_t *kind;
+    const int32_t *val;
+} orc_overrides;
+
+/* Per-trajectory diagnostics. */
+typedef struct orc_stats {
+    double *min_margin;     /* [n_traj] smallest relative margin seen (INFINITY if none) */
+    int32_t *n_near;        /* [n_traj] steps with margin <= tie_threshold */
+    int32_t *n_resync;      /* [n_traj] override steps where the GPU's choice was adopted */
+    int32_t *n_bad;         /* [n_traj] override disagreements that are not near-ties */
+    double *bin_edge_dist;  /* [n_traj] min |t_k - edge| over steps k>=1 and inner bin edges (bins only) */
+} orc_stats;
+
+/* Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Lattice uniform of a 32-bit word: (2*(x>>9)+1) * 2^-24, in (0, 1). */
+double orc_uniform(uint32_t x);
+
+/* The first n_words uniforms of step `step` of trajectory `traj`.
+ * Word w comes from block w/4 (lane w%4); block b uses counter
+ * (b, step, traj, purpose<<24 | epoch) and key (lo32(seed), hi32(seed)). */
+void orc_step_uniforms(uint64_t seed, uint32_t purpose, uint32_t epoch, uint32_t traj,
+                       uint32_t step, int32_t n_words, double *u);
+
+/* Forward simulation of n_traj trajectories (x0 and x_final are [n_traj][N]).
+ * obs: [n_traj][n_bins][n_obs] bin averages, or [n_traj][n_obs] final counts.
+ * theta: [P] (FP32 values promoted).  ov and stats may be NULL.
+ * Returns 0, or -1 on invalid arguments. */
+int orc_forward(const orc_net *net, const orc_cfg *cfg, const double *theta,
+                int64_t n_traj, const uint32_t *traj_ids, const int32_t *x0,
+                const orc_overrides *ov,
+                int32_t *x_final, double *t_final, int32_t *steps_done, double *obs,
+                const orc_stats *stats, int n_threads);
+
+/* Forward plus straight-through adjoint.  d_obs has the layout of obs;
+ * grad receives the per-trajectory gradient dL/dtheta, [n_traj][P]. */
+int orc_adjoint(const orc_net *net, const orc_cfg *cfg, const double *theta,
+                int64_t n_traj, const uint32_t *traj_ids, const int32_t *x0,
+                const orc_overrides *ov, const double *d_obs,
+                int32_t *x_final, double *t_final, int32_t *steps_done, double *obs,
+                double *grad, const orc_stats *stats, int n_threads);
+
+/* Step-by-step record of one trajectory (at most cap steps):
+ * X [(cap+1)][N], t [cap+1], tau [cap], j [cap], a [cap][M], u [cap][M+1],
+ * margin [cap].  Returns the number of fired steps. */
+int64_t orc_trace(const orc_net *net, const orc_cfg *cfg, const double *theta,
+                  uint32_t traj_id, const int32_t *x0, int64_t cap,
+                  int32_t *X, double *t, double *tau, int32_t *j, double *a,
+                  double *u, double *margin);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,297 @@
+"""Seeded synthetic workloads: reaction networks, initial states and run settings.
+
+This module only *describes* inputs.  It holds none of the method's arithmetic
+(no propensities, no random streams of the simulation, no gradients): both the
+HIP path and the CPU oracle read the same descriptions and each turns them into
+its own internal tables.  Host-side choices (random network topologies, rates,
+images) use numpy's PCG64 generator seeded explicitly; the simulation's own
+random numbers are drawn by each side from its own Philox4x32-10 stream.
+
+Networks follow the problem statement of Sec. 2 of the paper: N species with
+integer copy numbers, M reaction channels with mass-action propensities
+(order 0, 1, 2, or homodimerisation, Sec. 2) and integer change vectors v_j.
+Rate constants are parameterised as theta = ln k (Sec. 4.1).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# Observation kinds.
+OBS_FINAL = 0   # final copy numbers of the observed species
+OBS_BINS = 1    # exact time average of the piecewise-constant path over uniform bins (Sec. 4.4)
+
+# Random-stream purposes (high byte of the fourth Philox counter word).
+PURPOSE_SIMULATE = 0
+PURPOSE_TARGET = 1
+PURPOSE_PILOT = 2
+
+
+@dataclass
+class Network:
+    """One reaction network.
+
+    reactant[j] = (s1, s2): reactant species of channel j, -1 for none.
+      (-1, -1) -> order 0, a = k
+      (s, -1)  -> order 1, a = k X_s
+      (s, s')  -> order 2, a = k X_s X_s'       (s != s')
+      (s, s)   -> homodimer, a = k X_s (X_s - 1) / 2
+    rate_index[j]: which entry of theta (= ln k) channel j uses (allows tied rates).
+    stoich[j, :]: the change vector v_j.
+    """
+    name: str
+    species: List[str]
+    reactant: np.ndarray        # [M, 2] int32
+    rate_index: np.ndarray      # [M] int32
+    stoich: np.ndarray          # [M, N] int32
+    n_params: int
+    theta0: np.ndarray          # [P] float32, ln k
+    x0: np.ndarray              # [N] int32
+    obs_species: np.ndarray     # [n_obs] int32
+    param_names: Optional[List[str]] = None
+
+    @property
+    def n_species(self) -> int:
+        return len(self.species)
+
+    @property
+    def n_reactions(self) -> int:
+        return int(self.reactant.shape[0])
+
+    def validate(self) -> None:
+        M, N = self.n_reactions, self.n_species
+        assert self.reactant.shape == (M, 2) and self.stoich.shape == (M, N)
+        assert self.rate_index.shape == (M,)
+        assert np.all((self.reactant >= -1) & (self.reactant < N))
+        # a lone second reactant is not a valid encoding
+        assert not np.any((self.reactant[:, 0] < 0) & (self.reactant[:, 1] >= 0))
+        assert np.all((self.rate_index >= 0) & (self.rate_index < self.n_params))
+        assert np.all(np.abs(self.stoich) <= 2)
+        assert self.theta0.shape == (self.n_params,)
+        assert self.x0.shape == (N,) and np.all(self.x0 >= 0)
+        assert np.all((self.obs_species >= 0) & (self.obs_species < N))
+
+
+def _net(name, species, reactions, n_params, theta0, x0, obs, param_names=None) -> Network:
+    """reactions: list of (reactant tuple, rate slot, {species: delta})."""
+    idx = {s: i for i, s in enumerate(species)}
+    M, N = len(reactions), len(species)
+    reactant = -np.ones((M, 2), np.int32)
+    rate_index = np.zeros(M, np.int32)
+    stoich = np.zeros((M, N), np.int32)
+    for j, (rs, slot, delta) in enumerate(reactions):
+        for q, s in enumerate(rs):
+            reactant[j, q] = idx[s]
+        rate_index[j] = slot
+        for s, d in delta.items():
+            stoich[j, idx[s]] += d
+    net = Network(name, list(species), reactant, rate_index, stoich, n_params,
+                  np.asarray(theta0, np.float32), np.asarray(x0, np.int32),
+                  np.asarray([idx[s] for s in obs], np.int32), param_names)
+    net.validate()
+    return net
+
+
+# --------------------------------------------------------------------------
+# Networks named in the paper or used as textbook pins
+# --------------------------------------------------------------------------
+
+def dimerization_2a(kf: float = 1.0e-3, kb: float = 0.1, a0: int = 100) -> Network:
+    """Reversible homodimerisation 2A <-> A2 with mass-action kinetics (Sec. 2:
+    homodimer propensity k X (X-1)/2).  A + 2*A2 is conserved."""
+    return _net("dimerization_2A", ["A", "A2"],
+                [(("A", "A"), 0, {"A": -2, "A2": +1}),
+                 (("A2",), 1, {"A": +2, "A2": -1})],
+                2, np.log([kf, kb]), [a0, 0], ["A"], ["ln_kf", "ln_kb"])
+
+
+def dimerization_abc(k1: float = 0.01, k2: float = 0.32, x0=(100, 90, 0)) -> Network:
+    """A + B <-> C of Sec. 4.1 (Eq. 8): a1 = k1 X_A X_B, a2 = k2 X_C."""
+    return _net("dimerization_ABC", ["A", "B", "C"],
+                [(("A", "B"), 0, {"A": -1, "B": -1, "C": +1}),
+                 (("C",), 1, {"A": +1, "B": +1, "C": -1})],
+                2, np.log([k1, k2]), list(x0), ["A", "B", "C"], ["ln_k1", "ln_k2"])
+
+
+def ion_channel_coi(k_open=0.75, k_close=0.103, k_inact=1.159, n_channels: int = 2) -> Network:
+    """Closed/open/inactivated channel scheme of Sec. 4.4: C->O, O->C, O->I, with I
+    absorbing.  All channels start closed."""
+    return _net("ion_channel_COI", ["C", "O", "I"],
+                [(("C",), 0, {"C": -1, "O": +1}),
+                 (("O",), 1, {"O": -1, "C": +1}),
+                 (("O",), 2, {"O": -1, "I": +1})],
+                3, np.log([k_open, k_close, k_inact]), [n_channels, 0, 0], ["O"],
+                ["ln_k_open", "ln_k_close", "ln_k_inact"])
+
+
+def decay(k: float = 0.2, a0: int = 50) -> Network:
+    """A -> 0.  Closed form: A(t) ~ Binomial(A0, exp(-k t))."""
+    return _net("decay", ["A"], [(("A",), 0, {"A": -1})], 1, np.log([k]), [a0], ["A"])
+
+
+def birth_death(k_birth: float = 20.0, k_death: float = 0.5, a0: int = 0) -> Network:
+    """0 -> A, A -> 0.  Stationary law Poisson(k_birth / k_death)."""
+    return _net("birth_death", ["A"],
+                [((), 0, {"A": +1}), (("A",), 1, {"A": -1})],
+                2, np.log([k_birth, k_death]), [a0], ["A"])
+
+
+def isomerization(k_ab: float = 0.3, k_ba: float = 0.7, n: int = 40) -> Network:
+    """A <-> B with A + B = n.  Stationary law A ~ Binomial(n, k_ba / (k_ab + k_ba))."""
+    return _net("isomerization", ["A", "B"],
+                [(("A",), 0, {"A": -1, "B": +1}), (("B",), 1, {"A": +1, "B": -1})],
+                2, np.log([k_ab, k_ba]), [n, 0], ["A"])
+
+
+OSC_SPECIES = ["D_A", "D_A'", "D_R", "D_R'", "M_A", "M_R", "A", "R", "C"]
+OSC_PARAMS = ["gamma_A", "theta_A", "gamma_R", "theta_R", "alpha_A", "alpha'_A",
+              "alpha_R", "alpha'_R", "beta_A", "beta_R", "delta_MA", "delta_MR",
+              "delta_A", "delta_R", "gamma_C"]
+
+
+def oscillator(rate_seed: int = 0, log10_range=(-2.0, 3.0), rates=None) -> Network:
+    """Activator-repressor oscillator of Sec. 4.2: 9 species, 16 mass-action channels
+    (promoter binding/unbinding, transcription from both promoter states,
+    translation, mRNA and protein degradation, A+R->C, C->R).  The complex C
+    releases R at the activator's degradation rate, so 16 channels use 15 rates.
+    The paper's nominal rates are in a supplement that is not available, so the
+    rates are drawn log-uniformly (seeded) unless given."""
+    if rates is None:
+        g = np.random.default_rng(np.random.SeedSequence([rate_seed, 3]))
+        rates = 10.0 ** g.uniform(log10_range[0], log10_range[1], size=15)
+    rates = np.asarray(rates, np.float64)
+    P = {n: i for i, n in enumerate(OSC_PARAMS)}
+    R = [
+        (("D_A", "A"), P["gamma_A"], {"D_A": -1, "A": -1, "D_A'": +1}),
+        (("D_A'",), P["theta_A"], {"D_A'": -1, "D_A": +1, "A": +1}),
+        (("D_R", "A"), P["gamma_R"], {"D_R": -1, "A": -1, "D_R'": +1}),
+        (("D_R'",), P["theta_R"], {"D_R'": -1, "D_R": +1, "A": +1}),
+        (("D_A",), P["alpha_A"], {"M_A": +1}),
+        (("D_A'",), P["alpha'_A"], {"M_A": +1}),
+        (("D_R",), P["alpha_R"], {"M_R": +1}),
+        (("D_R'",), P["alpha'_R"], {"M_R": +1}),
+        (("M_A",), P["beta_A"], {"A": +1}),
+        (("M_R",), P["beta_R"], {"R": +1}),
+        (("M_A",), P["delta_MA"], {"M_A": -1}),
+        (("M_R",), P["delta_MR"], {"M_R": -1}),
+        (("A",), P["delta_A"], {"A": -1}),
+        (("R",), P["delta_R"], {"R": -1}),
+        (("A", "R"), P["gamma_C"], {"A": -1, "R": -1, "C": +1}),
+        (("C",), P["delta_A"], {"C": -1, "R": +1}),
+    ]
+    x0 = [1, 0, 1, 0, 0, 0, 0, 0, 0]
+    return _net("oscillator", OSC_SPECIES, R, 15, np.log(rates), x0, ["R"], list(OSC_PARAMS))
+
+
+def random_network(g: np.random.Generator, name: str = "random",
+                   n_range=(4, 64), m_range=(8, 256), log10_k=(-3.0, 2.0),
+                   x0_mean: float = 50.0) -> Network:
+    """One random mass-action network: orders 0-2 (order-2 channels are
+    homodimers or heterodimers with equal odds), reactants consumed, 0-2
+    product molecules on uniform species, change vectors in {-2..2}, never zero.
+    One rate per channel, log-uniform; Poisson initial counts."""
+    N = int(g.integers(n_range[0], n_range[1] + 1))
+    M = int(g.integers(m_range[0], m_range[1] + 1))
+    reactant = -np.ones((M, 2), np.int32)
+    stoich = np.zeros((M, N), np.int32)
+    for j in range(M):
+        while True:
+            order = int(g.integers(0, 3))
+            r = -np.ones(2, np.int32)
+            v = np.zeros(N, np.int32)
+            if order >= 1:
+                r[0] = g.integers(0, N)
+            if order == 2:
+                r[1] = r[0] if g.random() < 0.5 else g.integers(0, N)
+            for s in r:
+                if s >= 0:
+                    v[s] -= 1
+            for _ in range(int(g.integers(0, 3))):
+                v[g.integers(0, N)] += 1
+            if np.any(v != 0) and np.all(np.abs(v) <= 2):
+                break
+        reactant[j] = r
+        stoich[j] = v
+    theta0 = np.log(10.0 ** g.uniform(log10_k[0], log10_k[1], size=M))
+    x0 = g.poisson(x0_mean, size=N).astype(np.int32)
+    obs = np.arange(min(N, 4), dtype=np.int32)
+    net = Network(name, [f"S{i}" for i in range(N)], reactant,
+                  np.arange(M, dtype=np.int32), stoich, M,
+                  theta0.astype(np.float32), x0, obs)
+    net.validate()
+    return net
+
+
+def random_network_batch(n_networks: int, seed: int = 0, **kw) -> List[Network]:
+    g = np.random.default_rng(np.random.SeedSequence([seed, 3]))
+    return [random_network(g, name=f"random_{i}", **kw) for i in range(n_networks)]
+
+
+# --------------------------------------------------------------------------
+# Run settings
+# --------------------------------------------------------------------------
+
+@dataclass
+class RunConfig:
+    seed: int = 0
+    purpose: int = PURPOSE_SIMULATE
+    epoch: int = 0
+    n_steps: int = 2 ** 31 - 1        # fired reactions per trajectory (upper bound)
+    t_end: float = float("inf")       # fire only while t + tau <= t_end
+    obs_kind: int = OBS_FINAL
+    n_bins: int = 0
+    t_obs: float = 0.0
+    temperature: float = 0.5
+    ckpt_every: int = 256
+
+    def replace(self, **kw) -> "RunConfig":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return RunConfig(**d)
+
+
+@dataclass
+class Workload:
+    """A network, its trajectory count and run settings, named by what it is."""
+    name: str
+    net: Network
+    n_traj: int
+    cfg: RunConfig
+    theta: np.ndarray = None          # ln k used for the run (float32)
+    extra: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        if self.theta is None:
+            self.theta = self.net.theta0.copy()
+
+    def x0_soa(self) -> np.ndarray:
+        """[N, B] int32, every trajectory starts from net.x0."""
+        return np.repeat(self.net.x0[:, None], self.n_traj, axis=1).astype(np.int32)
+
+
+def dimer_forward_1k() -> Workload:
+    """2A<->A2, kf=1e-3, kb=0.1, A(0)=100, 1,024 trajectories to t_end=50, final state."""
+    net = dimerization_2a(1.0e-3, 0.1, 100)
+    return Workload("dimer_2A_1024traj_tend50", net, 1024,
+                    RunConfig(seed=0, t_end=50.0, obs_kind=OBS_FINAL, n_steps=2 ** 31 - 1))
+
+
+DIMER_TARGET_RATES = (2.0e-3, 0.05)
+
+
+def dimer_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 10000) -> Workload:
+    """2A<->A2 at kf=1e-3, kb=0.1 with gradients: 65,536 trajectories x 10,000 steps,
+    20 exact bin averages of A on [0, 2500], temperature 0.5, checkpoints every 256."""
+    net = dimerization_2a(1.0e-3, 0.1, 100)
+    cfg = RunConfig(seed=0, n_steps=n_steps, obs_kind=OBS_BINS, n_bins=20, t_obs=2500.0,
+                    temperature=0.5, ckpt_every=256)
+    return Workload(f"dimer_2A_{n_traj}traj_{n_steps}steps_20bins", net, n_traj, cfg)
+
+
+def oscillator_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 200000, t_obs: float = None) -> Workload:
+    net = oscillator(rate_seed=0)
+    cfg = RunConfig(seed=0, n_steps=n_steps, obs_kind=OBS_BINS, n_bins=256,
+                    t_obs=t_obs if t_obs is not None else 0.0, temperature=0.5, ckpt_every=1024)
+    return Workload(f"oscillator_{n_traj}traj_{n_steps}steps_256bins", net, n_traj, cfg)

@@ -1,0 +1,242 @@
+"""Pins of the oracle's straight-through adjoint.
+
+The backward result is the gradient of the frozen surrogate F(theta): the
+forward's hard choices j_k and noise stay fixed, the state update is
+X_{k+1} = X_k + v_{j_k} + sum_j v_j (y~_j(X_k, theta) - y~_j|ref) (Eqs. 5-7),
+the clock is t_{k+1} = t_k + E_0/a0(X_k; theta) (Sec. 3.1), and the loss is
+linear in the observation with weights d_obs.  Three independent checks:
+
+1. central finite differences of F written out in numpy (FP64);
+2. torch float64 autograd of the literal stop-gradient graph of Eq. (5), built
+   step by step from the same uniforms (what the paper's TensorFlow code does);
+3. for very large T the soft path vanishes and the gradient is the pathwise
+   derivative of the hard loss with common random numbers (tiny delta), which
+   the oracle's forward alone can produce.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_19775_amd import workloads as W
+
+
+def _h(net, X):
+    """Mass-action combinatorial factors for a real-valued state (Sec. 2)."""
+    h = np.ones(net.n_reactions)
+    for j, (s1, s2) in enumerate(net.reactant):
+        if s1 < 0:
+            continue
+        if s2 < 0:
+            h[j] = X[s1]
+        elif s1 == s2:
+            h[j] = X[s1] * (X[s1] - 1) / 2
+        else:
+            h[j] = X[s1] * X[s2]
+    return h
+
+
+def _overlaps(t0, t1, t_obs, nb):
+    e = np.linspace(0.0, t_obs, nb + 1)
+    t1 = min(t1, t_obs)
+    return np.clip(np.minimum(t1, e[1:]) - np.maximum(t0, e[:-1]), 0.0, None)
+
+
+def _softmax_masked(z, active):
+    z = np.where(active, z, -np.inf)
+    z = z - z[active].max()
+    y = np.where(active, np.exp(z), 0.0)
+    return y / y.sum()
+
+
+def surrogate_F(net, cfg, theta, theta_ref, tr, d_obs):
+    T = cfg.temperature
+    n = len(tr.j)
+    E = -np.log(tr.u)
+    k_ref = np.exp(theta_ref.astype(np.float64)[net.rate_index])
+    k = np.exp(theta[net.rate_index])
+    V = net.stoich.astype(np.float64)
+    y_ref, act = [], []
+    for s in range(n):
+        a = k_ref * _h(net, tr.X[s].astype(np.float64))
+        active = a > 0
+        y_ref.append(_softmax_masked((np.log(np.where(active, a, 1.0)) - np.log(E[s, 1:])) / T, active))
+        act.append(active)
+    X = tr.X[0].astype(np.float64)
+    t = 0.0
+    bins = cfg.obs_kind == W.OBS_BINS
+    obs = np.zeros((cfg.n_bins, len(net.obs_species))) if bins else None
+    for s in range(n):
+        a = k * _h(net, X)
+        tau = E[s, 0] / a.sum()
+        y = _softmax_masked((np.log(np.where(act[s], a, 1.0)) - np.log(E[s, 1:])) / T, act[s])
+        if bins:
+            obs += np.outer(_overlaps(t, t + tau, cfg.t_obs, cfg.n_bins), X[net.obs_species])
+        X = X + V[tr.j[s]] + (y - y_ref[s]) @ V
+        t += tau
+    if bins:
+        obs += np.outer(_overlaps(t, cfg.t_obs, cfg.t_obs, cfg.n_bins), X[net.obs_species])
+        obs *= cfg.n_bins / cfg.t_obs
+    else:
+        obs = X[net.obs_species]
+    return float(np.sum(d_obs * obs))
+
+
+def literal_st_grad(net, cfg, theta0, tr, d_obs):
+    """torch float64 autograd through y_ST = stopgrad(y - y~) + y~ (Eq. 5)."""
+    T = cfg.temperature
+    dt = torch.float64
+    theta = torch.tensor(theta0.astype(np.float64), dtype=dt, requires_grad=True)
+    ri = torch.tensor(net.rate_index, dtype=torch.long)
+    k = torch.exp(theta[ri])
+    V = torch.tensor(net.stoich, dtype=dt)
+    u = torch.tensor(tr.u, dtype=dt)
+    X = torch.tensor(tr.X[0], dtype=dt)
+    t = torch.zeros((), dtype=dt)
+    bins = cfg.obs_kind == W.OBS_BINS
+    osp = torch.tensor(net.obs_species, dtype=torch.long)
+    edges = torch.linspace(0.0, cfg.t_obs, cfg.n_bins + 1, dtype=dt) if bins else None
+    obs = torch.zeros((cfg.n_bins, len(net.obs_species)), dtype=dt) if bins else None
+
+    def h_of(X):
+        hs = []
+        for s1, s2 in net.reactant:
+            if s1 < 0:
+                hs.append(torch.ones((), dtype=dt))
+            elif s2 < 0:
+                hs.append(X[s1])
+            elif s1 == s2:
+                hs.append(X[s1] * (X[s1] - 1) / 2)
+            else:
+                hs.append(X[s1] * X[s2])
+        return torch.stack(hs)
+
+    def ov(t0, t1):
+        t1 = torch.clamp(t1, max=cfg.t_obs)
+        return torch.clamp(torch.minimum(t1, edges[1:]) - torch.maximum(t0, edges[:-1]), min=0.0)
+
+    for s in range(len(tr.j)):
+        a = k * h_of(X)
+        active = a.detach() > 0
+        G = -torch.log(-torch.log(u[s, 1:]))                    # Gumbel noise (Sec. 3.2)
+        logit = torch.where(active, torch.log(torch.where(active, a, torch.ones_like(a))) + G,
+                            torch.full_like(a, -math.inf))
+        y_soft = torch.softmax(logit / T, dim=0)                 # Eq. (3)
+        j = int(torch.argmax(logit.detach()))                    # Gumbel-max (Sec. 3.2)
+        assert j == int(tr.j[s])
+        y_hard = torch.nn.functional.one_hot(torch.tensor(j), len(a)).to(dt)
+        y_st = (y_hard - y_soft).detach() + y_soft               # Eq. (5)
+        tau = -torch.log(u[s, 0]) / a.sum()                      # Sec. 3.1
+        if bins:
+            obs = obs + torch.outer(ov(t, t + tau), X[osp])
+        Xn = X + y_st @ V                                        # Eqs. (6)-(7)
+        X = Xn + (Xn.detach().round() - Xn.detach())             # value stays integer
+        t = t + tau
+    if bins:
+        obs = obs + torch.outer(ov(t, torch.tensor(cfg.t_obs, dtype=dt)), X[osp])
+        obs = obs * (cfg.n_bins / cfg.t_obs)
+    else:
+        obs = X[osp]
+    L = torch.sum(torch.tensor(d_obs, dtype=dt) * obs)
+    L.backward()
+    return theta.grad.numpy()
+
+
+def _case(name):
+    g = np.random.default_rng(7)
+    if name == "dimer_bins":
+        net = W.dimerization_2a()
+        cfg = W.RunConfig(n_steps=60, obs_kind=W.OBS_BINS, n_bins=5, t_obs=12.0, temperature=0.5)
+    elif name == "dimer_bins_coldT":
+        net = W.dimerization_2a()
+        cfg = W.RunConfig(n_steps=60, obs_kind=W.OBS_BINS, n_bins=5, t_obs=12.0, temperature=0.05)
+    elif name == "abc_final":
+        net = W.dimerization_abc()
+        cfg = W.RunConfig(n_steps=80, obs_kind=W.OBS_FINAL, temperature=0.7)
+    elif name == "oscillator_bins":
+        net = W.oscillator(0)
+        cfg = W.RunConfig(n_steps=150, obs_kind=W.OBS_BINS, n_bins=7, t_obs=0.0, temperature=0.5)
+    elif name == "random_bins":
+        net = W.random_network_batch(3, seed=11, n_range=(4, 8), m_range=(8, 16))[2]
+        cfg = W.RunConfig(n_steps=120, obs_kind=W.OBS_BINS, n_bins=6, t_obs=0.0, temperature=0.5)
+    elif name == "channel_absorbing":
+        net = W.ion_channel_coi()
+        cfg = W.RunConfig(n_steps=50, obs_kind=W.OBS_BINS, n_bins=8, t_obs=4.0, temperature=0.3)
+    else:
+        raise KeyError(name)
+    return net, cfg, g
+
+
+CASES = ["dimer_bins", "dimer_bins_coldT", "abc_final", "oscillator_bins", "random_bins",
+         "channel_absorbing"]
+
+
+def _prepare(orc, name, traj_id=1):
+    net, cfg, g = _case(name)
+    theta0 = net.theta0.copy()
+    if cfg.obs_kind == W.OBS_BINS and cfg.t_obs == 0.0:
+        tr0 = orc.trace(net, cfg.replace(obs_kind=W.OBS_FINAL), theta0, net.x0, traj_id=traj_id,
+                        cap=cfg.n_steps)
+        cfg = cfg.replace(t_obs=float(tr0.t[-1]) * 0.8)
+    tr = orc.trace(net, cfg, theta0, net.x0, traj_id=traj_id, cap=cfg.n_steps)
+    shape = (cfg.n_bins, len(net.obs_species)) if cfg.obs_kind == W.OBS_BINS else (len(net.obs_species),)
+    d_obs = g.normal(size=shape)
+    r = orc.run(net, cfg, theta0, net.x0[None, :], traj_ids=[traj_id], d_obs=d_obs[None])
+    assert r.steps_done[0] == len(tr.j)
+    return net, cfg, theta0, tr, d_obs, r.grad[0]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_adjoint_matches_surrogate_fd(orc, name):
+    net, cfg, theta0, tr, d_obs, grad = _prepare(orc, name)
+    th = theta0.astype(np.float64)
+    fd = np.zeros_like(th)
+    def central(p, d):
+        e = np.zeros_like(th); e[p] = d
+        return (surrogate_F(net, cfg, th + e, theta0, tr, d_obs)
+                - surrogate_F(net, cfg, th - e, theta0, tr, d_obs)) / (2 * d)
+
+    for p in range(len(th)):
+        # Richardson extrapolation of two central differences (error O(d^4))
+        fd[p] = (4 * central(p, 1e-6) - central(p, 2e-6)) / 3
+    # F at the reference point is the hard loss the oracle observes
+    scale = np.abs(fd).max()
+    assert scale > 0
+    assert np.allclose(grad, fd, rtol=1e-6, atol=1e-7 * scale), (grad, fd)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_adjoint_matches_literal_stopgrad_graph(orc, name):
+    net, cfg, theta0, tr, d_obs, grad = _prepare(orc, name)
+    ref = literal_st_grad(net, cfg, theta0, tr, d_obs)
+    scale = np.abs(ref).max()
+    assert np.allclose(grad, ref, rtol=1e-10, atol=1e-12 * scale), (grad, ref)
+
+
+def test_large_temperature_gives_pathwise_crn_derivative(orc):
+    """T -> infinity switches the soft path off; what remains is the exact
+    derivative of the hard loss under common random numbers (choices frozen),
+    which central differences of the oracle's forward reproduce.  The hard loss
+    has kinks where an event time crosses a bin edge, so trajectories with an
+    event time within 1e-3 of an edge are left out."""
+    net = W.dimerization_2a()
+    cfg = W.RunConfig(n_steps=200, obs_kind=W.OBS_BINS, n_bins=6, t_obs=40.0, temperature=1e12)
+    n = 32
+    g = np.random.default_rng(3)
+    d_obs = g.normal(size=(n, cfg.n_bins, 1))
+    theta0 = net.theta0.astype(np.float64)
+    r = orc.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n), d_obs=d_obs)
+    keep = r.bin_edge_dist > 1e-3
+    assert keep.sum() >= n // 2
+    for p in range(2):
+        # theta is consumed as FP32 values: step by a few FP32 spacings
+        d = 16 * float(np.spacing(np.float32(theta0[p])))
+        e = np.zeros(2); e[p] = d
+        tp, tm = np.float32(theta0 + e), np.float32(theta0 - e)
+        rp = orc.run(net, cfg, tp, net.x0, traj_ids=np.arange(n))
+        rm = orc.run(net, cfg, tm, net.x0, traj_ids=np.arange(n))
+        assert np.array_equal(rp.x_final, rm.x_final) and np.array_equal(rp.steps_done, rm.steps_done)
+        fd = ((rp.obs - rm.obs) * d_obs).sum((1, 2)) / (float(tp[p]) - float(tm[p]))
+        ref = r.grad[:, p]
+        assert np.allclose(fd[keep], ref[keep], rtol=1e-5, atol=1e-6 * np.abs(ref).max())
