@@ -1,0 +1,226 @@
+/*
+ * ssa.h — C ABI of libssa: the massively batched exact Gillespie step and its
+ * Gumbel-Softmax straight-through backward on AMD Instinct MI355X (gfx950).
+ *
+ * What the library computes (paper: "Exact Discrete Stochastic Simulation
+ * with Deep-Learning-Scale Gradient Optimization", Vilar & Saiz):
+ *   Forward (Sec. 2, Sec. 3.2, Eq. 6): for every trajectory, repeat
+ *     a_j = k_j h_j(X) (mass action, Sec. 2), a0 = sum_j a_j,
+ *     tau = -ln(u_0)/a0, j* = argmax_j [ln a_j + G_j] with G_j = -ln(-ln u_{1+j}),
+ *     X += v_{j*}, t += tau,
+ *   and record an observation of the path (exact bin time averages, Sec. 4.4,
+ *   or the final counts).
+ *   Backward (Sec. 3.1, Sec. 3.3-3.4, Eqs. 3-7, Fig. 1): gradient of a loss
+ *   L(obs) with respect to theta = ln k (Sec. 4.1) through the
+ *   straight-through surrogate: the forward's noise is regenerated from the
+ *   counter-based random stream, soft samples y~ = softmax((ln a + G)/T) carry
+ *   the selection gradient and the reparameterised waiting time carries the
+ *   clock gradient.
+ *
+ * Random stream: Philox4x32-10 (Salmon et al., SC'11).  Word w of step k of
+ * trajectory id i is lane w%4 of the block with counter
+ * (w/4, k, i, purpose<<24 | epoch) and key (lo32(seed), hi32(seed)); it maps
+ * to u = (2*(x>>9)+1)*2^-24.  Word 0 drives tau, word 1+j channel j.
+ *
+ * Memory: unless stated otherwise, array arguments of ssa_forward,
+ * ssa_backward and ssa_step_batch are DEVICE pointers owned by the caller.
+ * Those calls never allocate, free or synchronise: all work is enqueued on
+ * `stream`, so they can be captured into a HIP graph.  Host-side argument
+ * errors return before anything is enqueued.  The C ABI uses no C++ types and
+ * throws nothing.
+ *
+ * Batches of networks: a network handle may hold several networks with
+ * different species, channel and trajectory counts.  Network n owns
+ * N_n species, M_n channels, P_n parameters, B_n trajectories and n_obs_n
+ * observed species.  Arrays are packed network after network:
+ *   theta / d_params   float  [sum P_n]            (slice at param_offset[n])
+ *   x0 / x_final       int32  [sum N_n*B_n]        (block [N_n][B_n], species-major)
+ *   t_final            double [sum B_n]
+ *   steps_done         int32  [sum B_n]
+ *   obs / d_obs        double [sum W_n*B_n]        (block [W_n][B_n];
+ *                       W_n = n_bins*n_obs_n as [bin][obs] for bins, n_obs_n for final counts)
+ *   d_params_per_traj  float  [sum P_n*B_n]        (block [P_n][B_n])
+ * ssa_net_layout() returns every offset.
+ */
+#ifndef SSA_H
+#define SSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ssa_status {
+    SSA_OK = 0,
+    SSA_EINVAL = -1,       /* bad argument (NULL, out of range, inconsistent sizes) */
+    SSA_ESHAPE = -2,       /* network or batch shape the library cannot run */
+    SSA_EWORKSPACE = -3,   /* a buffer is smaller than the size the library asked for */
+    SSA_EOVERFLOW = -4,    /* device: a copy number left the int32 range */
+    SSA_ENONFINITE = -5,   /* device: a non-finite or negative propensity or clock */
+    SSA_EHIP = -6,         /* a HIP runtime call failed */
+    SSA_ENOTSUP = -7       /* valid request this build does not implement */
+} ssa_status;
+
+/* Observation kinds. */
+enum { SSA_OBS_FINAL = 0, SSA_OBS_BINS = 1 };
+
+/* How ssa_backward obtains the fired channel of each step.
+ *   SSA_BWD_TAPE:      ssa_forward stores the fired channel index of every
+ *                      step in a compact tape (1, 2, 4 or 8 bits a step);
+ *                      the backward sweeps each checkpoint segment in reverse
+ *                      and regenerates noise, propensities and waiting times
+ *                      from the Philox counters.
+ *   SSA_BWD_RECOMPUTE: nothing per step is stored; the backward re-runs each
+ *                      segment forward from its checkpoint to recover the
+ *                      choices, then sweeps it in reverse.
+ *   SSA_BWD_AUTO:      the library picks. */
+enum { SSA_BWD_AUTO = 0, SSA_BWD_TAPE = 1, SSA_BWD_RECOMPUTE = 2 };
+
+/* Host description of one or more networks (all pointers are HOST memory and
+ * are copied by ssa_net_create).  Channel tables are packed network after
+ * network; species indices are local to their network.
+ *   reactant[2j], reactant[2j+1]: reactant species of channel j, -1 for none.
+ *     (-1,-1): order 0, a = k;  (s,-1): a = k X_s;  (s,s'), s != s': a = k X_s X_s';
+ *     (s,s): homodimerisation, a = k X_s (X_s - 1)/2   (Sec. 2).
+ *   rate_index[j]: local parameter slot of channel j (tied rates allowed).
+ *   stoich: dense change vectors, network n contributes M_n*N_n entries in
+ *     [channel][species] order; every entry must be in [-8, 7].
+ *   obs_species: local species observed, n_obs_n entries per network.
+ *   t_obs: window of the bin observation of each network (may be NULL if no
+ *     run uses bins). */
+typedef struct ssa_network_desc {
+    int32_t n_networks;
+    const int32_t *n_species;      /* [n_networks] */
+    const int32_t *n_reactions;    /* [n_networks] */
+    const int32_t *n_params;       /* [n_networks] */
+    const int32_t *n_traj;         /* [n_networks] */
+    const int32_t *n_obs;          /* [n_networks] */
+    const int32_t *reactant;       /* [sum M_n * 2] */
+    const int32_t *rate_index;     /* [sum M_n] */
+    const int8_t *stoich;          /* [sum M_n * N_n] */
+    const int32_t *obs_species;    /* [sum n_obs_n] */
+    const double *t_obs;           /* [n_networks] bin observations split [0, t_obs[n]] */
+} ssa_network_desc;
+
+typedef struct ssa_net ssa_net;    /* opaque handle: device-resident tables */
+
+/* Offsets of network n inside the packed arrays (see the header comment). */
+typedef struct ssa_net_layout_t {
+    int64_t traj_offset;
+    int64_t state_offset;
+    int64_t param_offset;
+    int64_t obs_offset;            /* for the observation kind and n_bins of the query */
+    int64_t ppt_offset;            /* d_params_per_traj */
+} ssa_net_layout_t;
+
+/* Run settings shared by forward, backward and step calls.
+ * Set every field; ssa_config_default() fills sensible values. */
+typedef struct ssa_config {
+    uint64_t seed;
+    uint32_t purpose;              /* stream domain: 0 simulate, 1 target, 2 pilot, ... */
+    uint32_t epoch;                /* low 24 bits enter the counter */
+    const uint32_t *d_epoch;       /* optional DEVICE scalar overriding epoch (graph replays) */
+    const uint32_t *traj_ids;      /* optional DEVICE [sum B_n] global trajectory ids; NULL: 0..B-1 */
+    int32_t n_steps;               /* fire at most this many channels per trajectory */
+    double t_end;                  /* fire only while t + tau <= t_end; +INFINITY: no limit */
+    int32_t obs_kind;              /* SSA_OBS_FINAL or SSA_OBS_BINS */
+    int32_t n_bins;                /* bins per observed species (bins only) */
+    float temperature;             /* Gumbel-Softmax temperature T of Eq. (3), > 0 */
+    int32_t ckpt_every;            /* K: steps between state checkpoints (>= 1) */
+    int32_t bwd_mode;              /* SSA_BWD_* */
+    int32_t tie_capacity;          /* entries the near-tie log can hold */
+} ssa_config;
+
+/* One logged step where the selection (kind 0) or the t_end stop decision
+ * (kind 1) was within the library's FP32 error of the alternative:
+ * kind 0: relative gap of the two smallest E_j/a_j <= 2e-6;
+ * kind 1: |t + tau - t_end| <= 1e-5 t_end, chosen = 1 if the step fired. */
+typedef struct ssa_tie {
+    uint32_t traj;                 /* packed trajectory index (not the global id) */
+    uint32_t step;
+    int32_t chosen;
+    int32_t second;
+    float margin;
+    int32_t kind;
+} ssa_tie;
+
+void ssa_config_default(ssa_config *cfg);
+
+/* Copies the description to the device and plans execution (allocates device
+ * memory; call outside graph capture).  Returns SSA_ESHAPE for networks this
+ * build cannot run. */
+ssa_status ssa_net_create(const ssa_network_desc *desc, ssa_net **out);
+void ssa_net_destroy(ssa_net *net);
+
+/* Totals of a handle. */
+ssa_status ssa_net_sizes(const ssa_net *net, int64_t *n_traj_total, int64_t *state_total,
+                         int64_t *param_total, int64_t *n_networks);
+ssa_status ssa_net_layout(const ssa_net *net, int32_t obs_kind, int32_t n_bins, int32_t network,
+                          ssa_net_layout_t *out);
+
+/* Device bytes the caller must provide:
+ *   ckpt_bytes:  checkpoints and choice tape written by ssa_forward, read by
+ *                ssa_backward (0 when cfg->n_steps is unbounded);
+ *   work_bytes:  scratch for ssa_forward and ssa_backward. */
+ssa_status ssa_buffer_sizes(const ssa_net *net, const ssa_config *cfg, size_t *ckpt_bytes,
+                            size_t *work_bytes);
+
+/* Forward simulation of every trajectory.
+ *   theta [sum P_n] (ln k, float), x0 (int32 state layout);
+ *   out: x_final, t_final, steps_done, obs (may be NULL if n_obs = 0);
+ *   ckpt: may be NULL (then no backward is possible);
+ *   ties/n_ties: near-tie log (may be NULL); *n_ties counts every near-tie,
+ *   entries beyond tie_capacity are dropped;
+ *   work: work_bytes of scratch (the library clears what it needs).
+ * Device-side faults (overflow, non-finite propensities) set sticky flags
+ * that ssa_device_status() reports. */
+ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *theta,
+                       const int32_t *x0, int32_t *x_final, double *t_final,
+                       int32_t *steps_done, double *obs, void *ckpt, size_t ckpt_bytes,
+                       ssa_tie *ties, uint32_t *n_ties, void *work, size_t work_bytes,
+                       hipStream_t stream);
+
+/* Straight-through backward.  Inputs are the forward's inputs and outputs
+ * (same cfg, theta, x0) and d_obs = dL/dobs (double, obs layout).
+ *   d_params [sum P_n] float: overwritten with dL/dtheta (deterministic:
+ *     per-trajectory FP64 partials reduced in a fixed order);
+ *   d_params_per_traj: optional [sum P_n*B_n] per-trajectory gradients. */
+ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *theta,
+                        const int32_t *x0, const int32_t *x_final, const double *t_final,
+                        const int32_t *steps_done, const void *ckpt, size_t ckpt_bytes,
+                        const double *d_obs, float *d_params, float *d_params_per_traj,
+                        void *work, size_t work_bytes, hipStream_t stream);
+
+/* One direct-method step (step index `step`) for every trajectory, for
+ * step-wise inspection.  x (state layout) and t [sum B_n] are updated in
+ * place for trajectories that fire.  chosen [sum B_n]: fired channel, -1 if
+ * a0 = 0, -2 if the step would pass t_end.  tau [sum B_n] float.
+ * a: optional [sum M_n*B_n] propensities (block [M_n][B_n]). */
+ssa_status ssa_step_batch(const ssa_net *net, const ssa_config *cfg, const float *theta,
+                          int32_t *x, double *t, uint32_t step, int32_t *chosen, float *tau,
+                          float *a, hipStream_t stream);
+
+/* Sticky device flags raised since the handle was created (bit 0: overflow,
+ * bit 1: non-finite propensity or clock).  Synchronises `stream`. */
+ssa_status ssa_device_status(const ssa_net *net, hipStream_t stream, uint32_t *flags);
+
+const char *ssa_status_string(ssa_status s);
+/* Detail of the last failing call on this thread ("" if none). */
+const char *ssa_last_error(void);
+
+/* Device primitives exposed for verification.
+ * ssa_selftest_philox: n blocks; ctr_key [n][6] = (c0,c1,c2,c3,k0,k1), out [n][4].
+ * ssa_selftest_neglog: out[i] = the library's FP32 -ln(u) for lattice point
+ *   m = first + i, u = (2m+1) 2^-24, for count points (m < 2^23). */
+ssa_status ssa_selftest_philox(const uint32_t *ctr_key, uint32_t *out, int64_t n,
+                               hipStream_t stream);
+ssa_status ssa_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSA_H */

@@ -1,0 +1,553 @@
+// C ABI of libssa (declared in include/ssa.h): argument checks, device
+// tables, buffer layout and kernel launches.  Nothing here allocates,
+// frees or synchronises inside ssa_forward / ssa_backward / ssa_step_batch.
+#include "ssa.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ssa_lane.hpp"
+#include "ssa_misc.hpp"
+#include "ssa_plan.hpp"
+
+using namespace ssa;
+
+static_assert(sizeof(TieRec) == sizeof(ssa_tie), "tie record layout");
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ssa_status fail(ssa_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+ssa_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(SSA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    if (src.empty()) return hipSuccess;
+    hipError_t e = hipMalloc((void **)dst, sizeof(T) * src.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+size_t align_up(size_t x, size_t a)
+{
+    return (x + a - 1) / a * a;
+}
+
+}  // namespace
+
+struct ssa_net {
+    int n_networks = 0;
+    std::vector<NetDev> nets_h;
+    NetDev *nets_d = nullptr;
+    ReactDesc *rd_d = nullptr;
+    uint32_t *rows_d = nullptr;
+    int32_t *csr_d = nullptr;
+    int32_t *obs_sp_d = nullptr;
+    int32_t *pmap_off_d = nullptr;
+    int32_t *pmap_ch_d = nullptr;
+    int32_t *param_net_d = nullptr;
+    LaneItem *items_d[kLaneClassCount] = {};
+    int n_items[kLaneClassCount] = {};
+    uint32_t *flags_d = nullptr;
+    int64_t traj_total = 0, state_total = 0, param_total = 0, obsb_total = 0, part_total = 0,
+            ppt_total = 0;
+    int max_M = 0;
+    int device = 0;
+};
+
+namespace {
+
+// Layout of the caller's checkpoint buffer for a configuration.
+struct CkptLayout {
+    int32_t n_ckpt = 0;
+    int32_t tape_bits = 0;
+    int32_t tape_words = 0;
+    size_t off_t = 0, off_x = 0, off_tape = 0, bytes = 0;
+};
+
+int bits_for(int M)
+{
+    if (M <= 2) return 1;
+    if (M <= 4) return 2;
+    if (M <= 16) return 4;
+    return 8;
+}
+
+int resolve_bwd_mode(const ssa_config *cfg)
+{
+    return cfg->bwd_mode == SSA_BWD_AUTO ? SSA_BWD_TAPE : cfg->bwd_mode;
+}
+
+constexpr int kMaxRecomputeSegment = 64;
+
+bool bounded_steps(const ssa_config *cfg)
+{
+    return cfg->n_steps < INT32_MAX;
+}
+
+CkptLayout ckpt_layout(const ssa_net *net, const ssa_config *cfg)
+{
+    CkptLayout L;
+    if (!bounded_steps(cfg) || cfg->ckpt_every < 1) return L;
+    L.n_ckpt = (cfg->n_steps + cfg->ckpt_every - 1) / cfg->ckpt_every;
+    if (resolve_bwd_mode(cfg) == SSA_BWD_TAPE) {
+        L.tape_bits = bits_for(net->max_M);
+        const int spw = 32 / L.tape_bits;
+        L.tape_words = (cfg->n_steps + spw - 1) / spw + 1;
+    }
+    size_t off = 0;
+    L.off_t = off;
+    off = align_up(off + sizeof(double) * (size_t)L.n_ckpt * net->traj_total, 256);
+    L.off_x = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)L.n_ckpt * net->state_total, 256);
+    L.off_tape = off;
+    off = align_up(off + sizeof(uint32_t) * (size_t)L.tape_words * net->traj_total, 256);
+    L.bytes = off;
+    return L;
+}
+
+// Work buffer: [tie counter | flags scratch] then FP64 per-channel partials.
+constexpr size_t kWorkHeader = 256;
+
+size_t work_bytes_for(const ssa_net *net)
+{
+    return kWorkHeader + align_up(sizeof(double) * (size_t)net->part_total, 256);
+}
+
+ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
+{
+    if (!net) return fail(SSA_EINVAL, "network handle is NULL");
+    if (!cfg) return fail(SSA_EINVAL, "config is NULL");
+    if (cfg->n_steps < 0) return fail(SSA_EINVAL, "n_steps must be >= 0");
+    if (!(cfg->t_end > 0.0)) return fail(SSA_EINVAL, "t_end must be > 0 (use INFINITY for no limit)");
+    if (cfg->obs_kind != SSA_OBS_FINAL && cfg->obs_kind != SSA_OBS_BINS)
+        return fail(SSA_EINVAL, "obs_kind must be SSA_OBS_FINAL or SSA_OBS_BINS");
+    if (cfg->obs_kind == SSA_OBS_BINS) {
+        if (cfg->n_bins < 1) return fail(SSA_EINVAL, "bin observation needs n_bins >= 1");
+        for (const NetDev &nd : net->nets_h)
+            if (nd.n_obs > 0 && !(nd.t_obs > 0.0) )
+                return fail(SSA_EINVAL, "bin observation needs t_obs > 0 for every observed network");
+    }
+    if (!(cfg->temperature > 0.f) || !std::isfinite(cfg->temperature))
+        return fail(SSA_EINVAL, "temperature must be finite and > 0");
+    if (cfg->ckpt_every < 1) return fail(SSA_EINVAL, "ckpt_every must be >= 1");
+    const int mode = resolve_bwd_mode(cfg);
+    if (mode != SSA_BWD_TAPE && mode != SSA_BWD_RECOMPUTE) return fail(SSA_EINVAL, "unknown bwd_mode");
+    if (mode == SSA_BWD_RECOMPUTE && cfg->ckpt_every > kMaxRecomputeSegment)
+        return fail(SSA_EINVAL, "recompute mode needs ckpt_every <= 64");
+    if (cfg->tie_capacity < 0) return fail(SSA_EINVAL, "tie_capacity must be >= 0");
+    return SSA_OK;
+}
+
+RunParams base_params(const ssa_net *net, const ssa_config *cfg)
+{
+    RunParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.nets = net->nets_d;
+    p.rd = net->rd_d;
+    p.rows = net->rows_d;
+    p.csr = net->csr_d;
+    p.obs_sp = net->obs_sp_d;
+    p.flags = net->flags_d;
+    p.seed_lo = (uint32_t)cfg->seed;
+    p.seed_hi = (uint32_t)(cfg->seed >> 32);
+    p.purpose = cfg->purpose & 0xFFu;
+    p.epoch = cfg->epoch;
+    p.d_epoch = cfg->d_epoch;
+    p.traj_ids = cfg->traj_ids;
+    p.n_steps = cfg->n_steps;
+    p.t_end = cfg->t_end;
+    p.obs_kind = cfg->obs_kind;
+    p.n_bins = cfg->obs_kind == SSA_OBS_BINS ? cfg->n_bins : 0;
+    p.K = cfg->ckpt_every;
+    p.state_total = net->state_total;
+    p.traj_total = net->traj_total;
+    p.temperature = cfg->temperature;
+    p.recompute = resolve_bwd_mode(cfg) == SSA_BWD_RECOMPUTE ? 1 : 0;
+    return p;
+}
+
+ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hipStream_t stream)
+{
+    for (int c = 0; c < kLaneClassCount; ++c) {
+        if (!net->n_items[c]) continue;
+        p.items = net->items_d[c];
+        p.n_items = net->n_items[c];
+        hipError_t e = lane_launch(c, p, backward, stream);
+        if (e != hipSuccess) return hip_fail(e, backward ? "backward launch" : "forward launch");
+    }
+    return SSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ssa_config_default(ssa_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n_steps = INT32_MAX;
+    cfg->t_end = INFINITY;
+    cfg->obs_kind = SSA_OBS_FINAL;
+    cfg->n_bins = 0;
+    cfg->temperature = 0.5f;
+    cfg->ckpt_every = 256;
+    cfg->bwd_mode = SSA_BWD_AUTO;
+    cfg->tie_capacity = 0;
+}
+
+const char *ssa_status_string(ssa_status s)
+{
+    switch (s) {
+    case SSA_OK: return "ok";
+    case SSA_EINVAL: return "invalid argument";
+    case SSA_ESHAPE: return "unsupported network or batch shape";
+    case SSA_EWORKSPACE: return "buffer too small";
+    case SSA_EOVERFLOW: return "copy number overflow";
+    case SSA_ENONFINITE: return "non-finite propensity or clock";
+    case SSA_EHIP: return "HIP runtime error";
+    case SSA_ENOTSUP: return "not supported";
+    }
+    return "unknown status";
+}
+
+const char *ssa_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
+{
+    g_last_error.clear();
+    if (!d || !out) return fail(SSA_EINVAL, "NULL argument");
+    *out = nullptr;
+    const int nn = d->n_networks;
+    if (nn < 1) return fail(SSA_EINVAL, "n_networks must be >= 1");
+    if (!d->n_species || !d->n_reactions || !d->n_params || !d->n_traj || !d->n_obs || !d->reactant ||
+        !d->rate_index || !d->stoich)
+        return fail(SSA_EINVAL, "missing table in network description");
+
+    ssa_net *net = new ssa_net();
+    net->n_networks = nn;
+    std::vector<ReactDesc> rd;
+    std::vector<uint32_t> rows;
+    std::vector<int32_t> csr, obs_sp, pmap_off, pmap_ch, param_net;
+    std::vector<LaneItem> items[kLaneClassCount];
+    int64_t roff = 0, soff = 0, ooff = 0;
+    auto bail = [&](ssa_status s, const std::string &m) {
+        ssa_net_destroy(net);
+        return fail(s, m);
+    };
+    for (int n = 0; n < nn; ++n) {
+        const int N = d->n_species[n], M = d->n_reactions[n], P = d->n_params[n], B = d->n_traj[n];
+        const int nob = d->n_obs[n];
+        if (N < 1 || M < 1 || P < 1 || B < 0 || nob < 0)
+            return bail(SSA_EINVAL, "network " + std::to_string(n) + ": sizes must be positive");
+        if (nob > 4) return bail(SSA_ESHAPE, "at most 4 observed species per network");
+        if (nob > 0 && !d->obs_species) return bail(SSA_EINVAL, "obs_species is NULL");
+        const int cls = lane_class_for(N, M);
+        if (cls < 0)
+            return bail(SSA_ESHAPE, "network " + std::to_string(n) + " (N=" + std::to_string(N) +
+                                        ", M=" + std::to_string(M) + ") exceeds the lane-mode bounds");
+        NetDev nd;
+        std::memset(&nd, 0, sizeof(nd));
+        nd.N = N; nd.M = M; nd.P = P; nd.n_obs = nob; nd.B = B;
+        const int nmax = lane_class_nmax(cls);
+        nd.wpr = (nmax + 7) / 8;
+        nd.react_off = (int32_t)rd.size();
+        nd.rows_off = (int32_t)rows.size();
+        nd.obs_sp_off = (int32_t)obs_sp.size();
+        nd.mode = cls;
+        nd.traj_off = net->traj_total;
+        nd.state_off = net->state_total;
+        nd.param_off = net->param_total;
+        nd.obsb_off = net->obsb_total;
+        nd.part_off = net->part_total;
+        nd.ppt_off = net->ppt_total;
+        nd.t_obs = d->t_obs ? d->t_obs[n] : 0.0;
+        for (int j = 0; j < M; ++j) {
+            const int s1 = d->reactant[2 * (roff + j)], s2 = d->reactant[2 * (roff + j) + 1];
+            const int ri = d->rate_index[roff + j];
+            if (s1 < -1 || s1 >= N || s2 < -1 || s2 >= N || (s1 < 0 && s2 >= 0))
+                return bail(SSA_EINVAL, "network " + std::to_string(n) + ": bad reactant of channel " +
+                                            std::to_string(j));
+            if (ri < 0 || ri >= P)
+                return bail(SSA_EINVAL, "network " + std::to_string(n) + ": rate_index out of range");
+            ReactDesc r;
+            std::memset(&r, 0, sizeof(r));
+            r.s1 = (uint8_t)(s1 < 0 ? kNoSpecies : s1);
+            r.s2 = (uint8_t)(s2 < 0 ? kNoSpecies : s2);
+            r.homodimer = (uint8_t)(s1 >= 0 && s1 == s2);
+            r.rate = ri;
+            r.mult = r.homodimer ? 0.5f : 1.0f;
+            const int beg = (int)csr.size();
+            std::vector<uint32_t> packed(nd.wpr, 0u);
+            for (int s = 0; s < N; ++s) {
+                const int v = d->stoich[soff + (int64_t)j * N + s];
+                if (v < -8 || v > 7)
+                    return bail(SSA_EINVAL, "network " + std::to_string(n) + ": change vector entry out of [-8,7]");
+                if (v != 0) {
+                    csr.push_back((int32_t)((uint32_t)s | ((uint32_t)(v & 0xFFFF) << 16)));
+                    packed[s / 8] |= (uint32_t)(v & 0xF) << (4 * (s % 8));
+                }
+            }
+            const int cnt = (int)csr.size() - beg;
+            if (cnt > 255) return bail(SSA_ESHAPE, "change vector too long");
+            r.csr = beg | (cnt << 24);
+            rd.push_back(r);
+            rows.insert(rows.end(), packed.begin(), packed.end());
+        }
+        for (int o = 0; o < nob; ++o) {
+            const int s = d->obs_species[ooff + o];
+            if (s < 0 || s >= N) return bail(SSA_EINVAL, "observed species out of range");
+            obs_sp.push_back(s);
+        }
+        // parameter -> channels map for the gradient reduction
+        for (int p = 0; p < P; ++p) {
+            pmap_off.push_back((int32_t)pmap_ch.size());
+            for (int j = 0; j < M; ++j)
+                if (d->rate_index[roff + j] == p) pmap_ch.push_back(j);
+            param_net.push_back(n);
+        }
+        for (int first = 0; first < B; first += 64) {
+            LaneItem it;
+            it.net = n; it.first = first; it.count = std::min(64, B - first); it.pad = M;
+            items[cls].push_back(it);
+        }
+        net->traj_total += B;
+        net->state_total += (int64_t)N * B;
+        net->param_total += P;
+        net->obsb_total += (int64_t)nob * B;
+        net->part_total += (int64_t)M * B;
+        net->ppt_total += (int64_t)P * B;
+        net->max_M = std::max(net->max_M, M);
+        net->nets_h.push_back(nd);
+        roff += M;
+        soff += (int64_t)M * N;
+        ooff += nob;
+    }
+    pmap_off.push_back((int32_t)pmap_ch.size());
+    if (net->traj_total > 0xFFFFFFFFll) return bail(SSA_ESHAPE, "too many trajectories");
+    // more channels first: longer work items start early
+    for (auto &v : items)
+        std::stable_sort(v.begin(), v.end(), [](const LaneItem &a, const LaneItem &b) { return a.pad > b.pad; });
+
+    hipError_t e = hipGetDevice(&net->device);
+    if (e == hipSuccess) e = upload(&net->nets_d, net->nets_h);
+    if (e == hipSuccess) e = upload(&net->rd_d, rd);
+    if (e == hipSuccess) e = upload(&net->rows_d, rows);
+    if (e == hipSuccess) e = upload(&net->csr_d, csr.empty() ? std::vector<int32_t>{0} : csr);
+    if (e == hipSuccess) e = upload(&net->obs_sp_d, obs_sp.empty() ? std::vector<int32_t>{0} : obs_sp);
+    if (e == hipSuccess) e = upload(&net->pmap_off_d, pmap_off);
+    if (e == hipSuccess) e = upload(&net->pmap_ch_d, pmap_ch.empty() ? std::vector<int32_t>{0} : pmap_ch);
+    if (e == hipSuccess) e = upload(&net->param_net_d, param_net);
+    for (int c = 0; c < kLaneClassCount && e == hipSuccess; ++c) {
+        net->n_items[c] = (int)items[c].size();
+        e = upload(&net->items_d[c], items[c]);
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&net->flags_d, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(net->flags_d, 0, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        ssa_status s = hip_fail(e, "ssa_net_create");
+        std::string m = g_last_error;
+        ssa_net_destroy(net);
+        return fail(s, m);
+    }
+    *out = net;
+    return SSA_OK;
+}
+
+void ssa_net_destroy(ssa_net *net)
+{
+    if (!net) return;
+    (void)hipFree(net->nets_d);
+    (void)hipFree(net->rd_d);
+    (void)hipFree(net->rows_d);
+    (void)hipFree(net->csr_d);
+    (void)hipFree(net->obs_sp_d);
+    (void)hipFree(net->pmap_off_d);
+    (void)hipFree(net->pmap_ch_d);
+    (void)hipFree(net->param_net_d);
+    for (auto p : net->items_d) (void)hipFree(p);
+    (void)hipFree(net->flags_d);
+    delete net;
+}
+
+ssa_status ssa_net_sizes(const ssa_net *net, int64_t *n_traj_total, int64_t *state_total,
+                         int64_t *param_total, int64_t *n_networks)
+{
+    if (!net) return fail(SSA_EINVAL, "network handle is NULL");
+    if (n_traj_total) *n_traj_total = net->traj_total;
+    if (state_total) *state_total = net->state_total;
+    if (param_total) *param_total = net->param_total;
+    if (n_networks) *n_networks = net->n_networks;
+    return SSA_OK;
+}
+
+ssa_status ssa_net_layout(const ssa_net *net, int32_t obs_kind, int32_t n_bins, int32_t network,
+                          ssa_net_layout_t *out)
+{
+    if (!net || !out) return fail(SSA_EINVAL, "NULL argument");
+    if (network < 0 || network >= net->n_networks) return fail(SSA_EINVAL, "network index out of range");
+    const NetDev &nd = net->nets_h[network];
+    out->traj_offset = nd.traj_off;
+    out->state_offset = nd.state_off;
+    out->param_offset = nd.param_off;
+    out->obs_offset = nd.obsb_off * (obs_kind == SSA_OBS_BINS ? n_bins : 1);
+    out->ppt_offset = nd.ppt_off;
+    return SSA_OK;
+}
+
+ssa_status ssa_buffer_sizes(const ssa_net *net, const ssa_config *cfg, size_t *ckpt_bytes,
+                            size_t *work_bytes)
+{
+    ssa_status s = check_config(net, cfg);
+    if (s != SSA_OK) return s;
+    if (ckpt_bytes) *ckpt_bytes = ckpt_layout(net, cfg).bytes;
+    if (work_bytes) *work_bytes = work_bytes_for(net);
+    return SSA_OK;
+}
+
+ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *theta, const int32_t *x0,
+                       int32_t *x_final, double *t_final, int32_t *steps_done, double *obs, void *ckpt,
+                       size_t ckpt_bytes, ssa_tie *ties, uint32_t *n_ties, void *work, size_t work_bytes,
+                       hipStream_t stream)
+{
+    g_last_error.clear();
+    ssa_status s = check_config(net, cfg);
+    if (s != SSA_OK) return s;
+    if (!theta || !x0 || !x_final || !t_final || !steps_done)
+        return fail(SSA_EINVAL, "theta, x0, x_final, t_final and steps_done are required");
+    if (net->obsb_total > 0 && !obs) return fail(SSA_EINVAL, "obs is NULL but species are observed");
+    if (!work || work_bytes < work_bytes_for(net)) return fail(SSA_EWORKSPACE, "work buffer too small");
+    if ((ties == nullptr) != (n_ties == nullptr)) return fail(SSA_EINVAL, "ties and n_ties go together");
+    const CkptLayout L = ckpt_layout(net, cfg);
+    if (ckpt && ckpt_bytes < L.bytes) return fail(SSA_EWORKSPACE, "checkpoint buffer too small");
+    if (ckpt && L.bytes == 0) return fail(SSA_EINVAL, "checkpoints need a bounded n_steps");
+
+    RunParams p = base_params(net, cfg);
+    p.theta = theta;
+    p.x0 = x0;
+    p.x_final = x_final;
+    p.t_final = t_final;
+    p.steps_done = steps_done;
+    p.obs = obs;
+    if (ckpt) {
+        char *base = (char *)ckpt;
+        p.ck_t = (double *)(base + L.off_t);
+        p.ck_x = (int32_t *)(base + L.off_x);
+        p.tape = L.tape_words ? (uint32_t *)(base + L.off_tape) : nullptr;
+        p.n_ckpt = L.n_ckpt;
+        p.tape_bits = L.tape_words ? L.tape_bits : 0;
+        p.tape_words = L.tape_words;
+    }
+    p.ties = reinterpret_cast<TieRec *>(ties);
+    p.n_ties = n_ties;
+    p.tie_cap = (uint32_t)cfg->tie_capacity;
+    if (n_ties) {
+        hipError_t e = launch_fill_u32(n_ties, 1, 0u, stream);
+        if (e != hipSuccess) return hip_fail(e, "clearing the tie counter");
+    }
+    return launch_all_classes(net, p, false, stream);
+}
+
+ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *theta, const int32_t *x0,
+                        const int32_t *x_final, const double *t_final, const int32_t *steps_done,
+                        const void *ckpt, size_t ckpt_bytes, const double *d_obs, float *d_params,
+                        float *d_params_per_traj, void *work, size_t work_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    ssa_status s = check_config(net, cfg);
+    if (s != SSA_OK) return s;
+    if (!theta || !x0 || !x_final || !t_final || !steps_done || !d_params)
+        return fail(SSA_EINVAL, "theta, x0, x_final, t_final, steps_done and d_params are required");
+    if (net->obsb_total > 0 && !d_obs) return fail(SSA_EINVAL, "d_obs is NULL but species are observed");
+    const CkptLayout L = ckpt_layout(net, cfg);
+    if (L.bytes == 0) return fail(SSA_EINVAL, "the backward needs a bounded n_steps");
+    if (!ckpt || ckpt_bytes < L.bytes) return fail(SSA_EWORKSPACE, "checkpoint buffer too small");
+    if (!work || work_bytes < work_bytes_for(net)) return fail(SSA_EWORKSPACE, "work buffer too small");
+
+    RunParams p = base_params(net, cfg);
+    p.theta = theta;
+    p.x0 = x0;
+    p.x_final = const_cast<int32_t *>(x_final);
+    p.t_final = const_cast<double *>(t_final);
+    p.steps_done = const_cast<int32_t *>(steps_done);
+    p.d_obs = d_obs;
+    const char *base = (const char *)ckpt;
+    p.ck_t = (double *)(base + L.off_t);
+    p.ck_x = (int32_t *)(base + L.off_x);
+    p.tape = L.tape_words ? (uint32_t *)(base + L.off_tape) : nullptr;
+    p.n_ckpt = L.n_ckpt;
+    p.tape_bits = L.tape_words ? L.tape_bits : 0;
+    p.tape_words = L.tape_words;
+    p.partials = (double *)((char *)work + kWorkHeader);
+    s = launch_all_classes(net, p, true, stream);
+    if (s != SSA_OK) return s;
+    hipError_t e = launch_reduce_params(net->nets_d, net->n_networks, net->pmap_off_d, net->pmap_ch_d,
+                                        net->param_net_d, net->param_total, p.partials, d_params,
+                                        d_params_per_traj, stream);
+    if (e != hipSuccess) return hip_fail(e, "gradient reduction");
+    return SSA_OK;
+}
+
+ssa_status ssa_step_batch(const ssa_net *net, const ssa_config *cfg, const float *theta, int32_t *x,
+                          double *t, uint32_t step, int32_t *chosen, float *tau, float *a, hipStream_t stream)
+{
+    g_last_error.clear();
+    ssa_status s = check_config(net, cfg);
+    if (s != SSA_OK) return s;
+    if (!theta || !x || !t || !chosen || !tau) return fail(SSA_EINVAL, "theta, x, t, chosen, tau are required");
+    RunParams p = base_params(net, cfg);
+    p.theta = theta;
+    hipError_t e = launch_step_batch(p, net->n_networks, step, x, t, chosen, tau, a, stream);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return SSA_OK;
+}
+
+ssa_status ssa_device_status(const ssa_net *net, hipStream_t stream, uint32_t *flags)
+{
+    if (!net || !flags) return fail(SSA_EINVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(flags, net->flags_d, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "reading device flags");
+    if (*flags & kFlagOverflow) return fail(SSA_EOVERFLOW, "copy number overflow on the device");
+    if (*flags & kFlagNonFinite) return fail(SSA_ENONFINITE, "non-finite propensity or clock on the device");
+    return SSA_OK;
+}
+
+ssa_status ssa_selftest_philox(const uint32_t *ctr_key, uint32_t *out, int64_t n, hipStream_t stream)
+{
+    if (n < 0 || (n > 0 && (!ctr_key || !out))) return fail(SSA_EINVAL, "bad arguments");
+    hipError_t e = launch_selftest_philox(ctr_key, out, n, stream);
+    return e == hipSuccess ? SSA_OK : hip_fail(e, "philox self-test");
+}
+
+ssa_status ssa_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream)
+{
+    if (count < 0 || (count > 0 && !out) || (int64_t)first + count > (1ll << 23))
+        return fail(SSA_EINVAL, "lattice range is [0, 2^23)");
+    hipError_t e = launch_selftest_neglog(first, count, out, stream);
+    return e == hipSuccess ? SSA_OK : hip_fail(e, "-ln self-test");
+}
+
+}  // extern "C"

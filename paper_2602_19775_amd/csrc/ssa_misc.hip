@@ -1,0 +1,192 @@
+// Small kernels around the simulation: the single-step kernel used for
+// step-wise inspection, the deterministic FP64 gradient reduction, counter
+// clearing and the self-test entry points of the device primitives.
+#include "ssa_device.hpp"
+#include "ssa_misc.hpp"
+
+#include <math.h>
+
+namespace ssa {
+
+namespace {
+
+__device__ int find_network(const NetDev *nets, int n_networks, int64_t g)
+{
+    int lo = 0, hi = n_networks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (nets[mid].traj_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One direct-method step for every trajectory (one thread each).  Same
+// arithmetic as the simulation kernels: a_j = (k_j mult X[s1]) (X[s2] - h),
+// tau = E_0 rcp(a0), j = argmin E_j rcp(a_j).
+__global__ void step_batch_kernel(RunParams p, int n_networks, uint32_t step, int32_t *x, double *t,
+                                  int32_t *chosen, float *tau_out, float *a_out)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= p.traj_total) return;
+    const int n = find_network(p.nets, n_networks, g);
+    const NetDev nd = p.nets[n];
+    const int64_t B = nd.B;
+    const int64_t i = g - nd.traj_off;
+    const ReactDesc *rd = p.rd + nd.react_off;
+    const uint32_t tid = p.traj_ids ? p.traj_ids[g] : (uint32_t)g;
+    const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
+    const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
+    int32_t *xs = x + nd.state_off + i;
+
+    auto xval = [&](int s) -> int { return s == kNoSpecies ? 1 : xs[(int64_t)s * B]; };
+    float a0 = 0.f;
+    for (int j = 0; j < nd.M; ++j) {
+        const ReactDesc r = rd[j];
+        const float c = expf(p.theta[nd.param_off + r.rate]) * r.mult;
+        const float aj = (c * (float)xval(r.s1)) * (float)(xval(r.s2) - (int)r.homodimer);
+        if (a_out) a_out[nd.part_off + (int64_t)j * B + i] = aj;
+        a0 += aj;
+    }
+    if (!(a0 > 0.f)) {
+        chosen[g] = -1;
+        tau_out[g] = 0.f;
+        return;
+    }
+    Philox::Out blk = Philox::block(0u, step, tid, pe, p.seed_lo, p.seed_hi);
+    const float tau = neglog_u(blk.x) * fast_rcp(a0);
+    tau_out[g] = tau;
+    const double tn = t[g] + (double)tau;
+    if (p.t_end < INFINITY && !(tn <= p.t_end)) {
+        chosen[g] = -2;
+        return;
+    }
+    float r1 = INFINITY;
+    int j1 = 0;
+    for (int j = 0; j < nd.M; ++j) {
+        const int w = 1 + j;
+        if ((w & 3) == 0) blk = Philox::block((uint32_t)(w >> 2), step, tid, pe, p.seed_lo, p.seed_hi);
+        const uint32_t word = (w & 3) == 0 ? blk.x : (w & 3) == 1 ? blk.y : (w & 3) == 2 ? blk.z : blk.w;
+        const ReactDesc r = rd[j];
+        const float c = expf(p.theta[nd.param_off + r.rate]) * r.mult;
+        const float aj = (c * (float)xval(r.s1)) * (float)(xval(r.s2) - (int)r.homodimer);
+        const float rj = aj > 0.f ? neglog_u(word) * fast_rcp(aj) : INFINITY;
+        j1 = rj < r1 ? j : j1;
+        r1 = fminf(r1, rj);
+    }
+    chosen[g] = j1;
+    const int beg = rd[j1].csr & 0xFFFFFF, cnt = (int)((uint32_t)rd[j1].csr >> 24);
+    for (int e = 0; e < cnt; ++e) {
+        const int32_t ent = p.csr[beg + e];
+        xs[(int64_t)csr_species(ent) * B] += csr_delta(ent);
+    }
+    t[g] = tn;
+}
+
+// d_params[p] = sum over channels j with rate(j) = p and over trajectories i
+// of partials[j][i], summed in a fixed order (thread-strided FP64 sums, then
+// a fixed LDS tree), so repeated runs give identical bits.
+constexpr int kRedThreads = 256;
+
+__global__ __launch_bounds__(kRedThreads) void reduce_params_kernel(
+    const NetDev *nets, int n_networks, const int32_t *pmap_off, const int32_t *pmap_ch,
+    const int32_t *param_net, const double *partials, float *d_params, float *d_ppt)
+{
+    __shared__ double s[kRedThreads];
+    const int pg = blockIdx.x;                   // global parameter index
+    const int n = param_net[pg];
+    const NetDev nd = nets[n];
+    const int pl = (int)(pg - nd.param_off);
+    const int64_t B = nd.B;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < B; i += kRedThreads) {
+        double v = 0.0;
+        for (int e = pmap_off[pg]; e < pmap_off[pg + 1]; ++e)
+            v += partials[nd.part_off + (int64_t)pmap_ch[e] * B + i];
+        if (d_ppt) d_ppt[nd.ppt_off + (int64_t)pl * B + i] = (float)v;
+        acc += v;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d_params[pg] = (float)s[0];
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void selftest_philox_kernel(const uint32_t *ck, uint32_t *out, int64_t n)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t *c = ck + 6 * q;
+    const Philox::Out o = Philox::block(c[0], c[1], c[2], c[3], c[4], c[5]);
+    out[4 * q] = o.x;
+    out[4 * q + 1] = o.y;
+    out[4 * q + 2] = o.z;
+    out[4 * q + 3] = o.w;
+}
+
+__global__ void selftest_neglog_kernel(uint32_t first, int64_t count, float *out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const uint32_t m = first + (uint32_t)q;
+    out[q] = neglog_u(m << 9);
+}
+
+unsigned grid_for(int64_t n, int threads)
+{
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+}  // namespace
+
+hipError_t launch_step_batch(const RunParams &p, int n_networks, uint32_t step, int32_t *x, double *t,
+                             int32_t *chosen, float *tau, float *a, hipStream_t stream)
+{
+    if (p.traj_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(step_batch_kernel, dim3(grid_for(p.traj_total, 256)), dim3(256), 0, stream, p,
+                       n_networks, step, x, t, chosen, tau, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_params(const NetDev *nets, int n_networks, const int32_t *pmap_off,
+                                const int32_t *pmap_ch, const int32_t *param_net, int64_t param_total,
+                                const double *partials, float *d_params, float *d_ppt, hipStream_t stream)
+{
+    if (param_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_params_kernel, dim3((unsigned)param_total), dim3(kRedThreads), 0, stream,
+                       nets, n_networks, pmap_off, pmap_ch, param_net, partials, d_params, d_ppt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_selftest_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(selftest_philox_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, ck, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(selftest_neglog_kernel, dim3(grid_for(count, 256)), dim3(256), 0, stream, first,
+                       count, out);
+    return hipGetLastError();
+}
+
+}  // namespace ssa

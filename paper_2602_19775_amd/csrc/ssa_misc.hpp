@@ -1,0 +1,19 @@
+// Launchers of the auxiliary kernels (ssa_misc.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ssa_plan.hpp"
+
+namespace ssa {
+
+hipError_t launch_step_batch(const RunParams &p, int n_networks, uint32_t step, int32_t *x, double *t,
+                             int32_t *chosen, float *tau, float *a, hipStream_t stream);
+hipError_t launch_reduce_params(const NetDev *nets, int n_networks, const int32_t *pmap_off,
+                                const int32_t *pmap_ch, const int32_t *param_net, int64_t param_total,
+                                const double *partials, float *d_params, float *d_ppt, hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
+hipError_t launch_selftest_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t stream);
+hipError_t launch_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream);
+
+}  // namespace ssa

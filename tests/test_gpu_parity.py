@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (taken from the method's requirements):
+- copy numbers, step counts and fired channels: bit-exact, except at steps the
+  GPU logged as near-ties where the oracle's own FP64 relative margin is
+  <= 1e-6 (the oracle then adopts the GPU's choice and must agree after);
+- clock, waiting times, propensities, bin averages: relative 1e-5;
+- gradients: relative 1e-5 of the largest component per trajectory group
+  (|g - g*| <= 1e-5 max(|g*|, 1e-2 ||g*||_inf)), plus ||g - g*|| / ||g*|| <= 1e-5.
+  Per-trajectory checks leave out trajectories with an event time within 1e-3
+  of a bin edge: there the bin assignment of a derivative term may legitimately
+  differ between an FP32 and an FP64 clock.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_19775_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_19775_amd import ssa as m
+    m.lib()
+    return m
+
+
+def _x0(nets, n_traj):
+    parts = [np.repeat(n.x0[:, None], b, axis=1).reshape(-1) for n, b in zip(nets, n_traj)]
+    return torch.tensor(np.concatenate(parts), dtype=torch.int32, device="cuda")
+
+
+def _ties_for_oracle(recs, traj_offset=0, traj_index=None):
+    """GPU tie records -> oracle overrides (local traj index, step, kind, val)."""
+    out = []
+    for t in recs:
+        q = int(t["traj"]) - traj_offset
+        if traj_index is not None:
+            if q not in traj_index:
+                continue
+            q = traj_index[q]
+        out.append((q, int(t["step"]), int(t["kind"]), int(t["chosen"])))
+    return out
+
+
+def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=None, per_traj=True):
+    """GPU forward (+backward) over B trajectories and the oracle on `sample`
+    trajectory ids (default: all)."""
+    theta = net.theta0 if theta is None else theta
+    h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
+    th = torch.tensor(theta, dtype=torch.float32, device="cuda")
+    x0 = _x0([net], [B])
+    fwd = ssa.forward(h, cfg, th, x0, keep_ckpt=d_obs is not None, tie_capacity=1 << 16,
+                      bwd_mode=bwd_mode)
+    bins = cfg.obs_kind == W.OBS_BINS
+    nob = len(net.obs_species)
+    gpu = {}
+    if d_obs is not None:
+        dd = torch.tensor(np.ascontiguousarray(d_obs).reshape(-1), device="cuda")
+        dp, ppt = ssa.backward(h, cfg, th, x0, fwd, dd, per_traj=True)
+        gpu["d_params"] = dp.cpu().numpy()
+        gpu["ppt"] = ppt.cpu().numpy().reshape(net.n_params, B).T
+    torch.cuda.synchronize()
+    assert ssa.device_status(h) == 0
+    ties = fwd.tie_records()
+    N = net.n_species
+    gpu["x_final"] = fwd.x_final.cpu().numpy().reshape(N, B).T
+    gpu["t_final"] = fwd.t_final.cpu().numpy()
+    gpu["steps_done"] = fwd.steps_done.cpu().numpy()
+    obs = fwd.obs.cpu().numpy()
+    gpu["obs"] = (obs[: cfg.n_bins * nob * B].reshape(cfg.n_bins, nob, B).transpose(2, 0, 1) if bins
+                  else obs[: nob * B].reshape(nob, B).T)
+    gpu["ties"] = ties
+    ids = np.arange(B) if sample is None else np.asarray(sample)
+    index = {int(q): k for k, q in enumerate(ids)}
+    ov = _ties_for_oracle(ties, 0, index)
+    oracle_dobs = None
+    if d_obs is not None:
+        oracle_dobs = (np.transpose(d_obs, (2, 0, 1))[ids] if bins else np.asarray(d_obs).T[ids])
+    r = oracle.run(net, cfg, theta, net.x0, traj_ids=ids, ties=ov, d_obs=oracle_dobs)
+    return gpu, r, ids, h
+
+
+def assert_forward_parity(gpu, r, ids):
+    assert r.n_bad.sum() == 0, "a GPU/oracle disagreement outside a logged near-tie"
+    assert np.array_equal(gpu["steps_done"][ids], r.steps_done)
+    assert np.array_equal(gpu["x_final"][ids], r.x_final)
+    assert np.allclose(gpu["t_final"][ids], r.t_final, rtol=1e-5, atol=0)
+    o = gpu["obs"][ids]
+    assert np.allclose(o, r.obs, rtol=1e-5, atol=1e-9 * max(1.0, np.abs(r.obs).max()))
+
+
+def assert_grad_parity(gpu_g, ref, keep=None, rtol=1e-5):
+    if keep is not None:
+        gpu_g, ref = gpu_g[keep], ref[keep]
+    scale = np.abs(ref).max()
+    tol = rtol * np.maximum(np.abs(ref), 1e-2 * scale)
+    bad = np.abs(gpu_g - ref) > tol
+    assert not bad.any(), (np.argwhere(bad)[:5], gpu_g[bad][:5], ref[bad][:5])
+    assert np.linalg.norm(gpu_g - ref) <= rtol * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------------------
+def test_philox_matches_oracle(ssa):
+    g = np.random.default_rng(5)
+    ck = g.integers(0, 2 ** 32, size=(4096, 6), dtype=np.uint64).astype(np.uint32)
+    ck[:4] = [[0, 0, 0, 0, 0, 0], [2 ** 32 - 1] * 6, [1, 2, 3, 4, 5, 6], [7, 0, 9, 1 << 24, 3, 0]]
+    got = ssa.selftest_philox(ck)
+    ref = np.array([oracle.philox4x32_10(c[:4], c[4:]) for c in ck], np.uint32)
+    assert np.array_equal(got, ref)
+
+
+def test_neglog_exhaustive_lattice(ssa):
+    """The GPU's FP32 -ln(u) over all 2^23 lattice points vs FP64: relative
+    error within 2 units in the last place of the FP32 result."""
+    n = 1 << 23
+    e = ssa.selftest_neglog(0, n).cpu().numpy().astype(np.float64)
+    m = np.arange(n, dtype=np.float64)
+    ref = -np.log((2 * m + 1) * 2.0 ** -24)
+    ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
+    err = np.abs(e - ref) / ulp
+    assert np.all(np.isfinite(e)) and np.all(e > 0)
+    assert err.max() <= 2.0, (err.max(), int(err.argmax()))
+
+
+def test_dimer_forward_t_end_1024(ssa):
+    """2A<->A2, kf=1e-3, kb=0.1, A(0)=100, 1,024 trajectories to t_end=50: every
+    trajectory, full length."""
+    wl = W.dimer_forward_1k()
+    gpu, r, ids, _ = run_pair(ssa, wl.net, wl.cfg, wl.n_traj)
+    assert_forward_parity(gpu, r, ids)
+    assert np.all(gpu["x_final"][:, 0] + 2 * gpu["x_final"][:, 1] == 100)
+    assert np.all(gpu["t_final"] <= 50.0)
+
+
+def test_step_batch_matches_oracle_trace(ssa):
+    net = W.oscillator(0)
+    B, steps = 100, 40
+    cfg = W.RunConfig(seed=3, n_steps=steps)
+    h = ssa.Net([net], [B])
+    th = torch.tensor(net.theta0, device="cuda")
+    x = _x0([net], [B])
+    t = torch.zeros(B, dtype=torch.float64, device="cuda")
+    traces = [oracle.trace(net, cfg, net.theta0, net.x0, traj_id=i, cap=steps) for i in range(B)]
+    for k in range(steps):
+        chosen, tau, a = ssa.step_batch(h, cfg, th, x, t, k, want_a=True)
+        ch = chosen.cpu().numpy()
+        ta = tau.cpu().numpy()
+        aa = a.cpu().numpy().reshape(net.n_reactions, B).T
+        for i in range(B):
+            tr = traces[i]
+            if k < len(tr.j):
+                if tr.margin[k] > 1e-6:
+                    assert ch[i] == tr.j[k], (k, i)
+                assert abs(ta[i] - tr.tau[k]) <= 1e-5 * tr.tau[k]
+                assert np.allclose(aa[i], tr.a[k], rtol=1e-5, atol=0)
+    xf = x.cpu().numpy().reshape(net.n_species, B).T
+    for i in range(B):
+        assert np.array_equal(xf[i], traces[i].X[-1])
+
+
+@pytest.mark.parametrize("B", [1, 63, 64, 200])
+def test_ragged_batches_and_edge_sizes(ssa, B):
+    net = W.dimerization_abc()
+    cfg = W.RunConfig(seed=11, n_steps=300, obs_kind=W.OBS_BINS, n_bins=3, t_obs=2.0)
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B)
+    assert_forward_parity(gpu, r, ids)
+
+
+def test_zero_steps_and_absorbing(ssa):
+    net = W.ion_channel_coi()
+    cfg = W.RunConfig(seed=2, n_steps=0, obs_kind=W.OBS_BINS, n_bins=4, t_obs=3.0)
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, 70)
+    assert_forward_parity(gpu, r, ids)
+    assert np.all(gpu["steps_done"] == 0)
+    cfg = cfg.replace(n_steps=500)
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, 130)
+    assert_forward_parity(gpu, r, ids)
+    assert np.all(gpu["x_final"][:, 2] == 2) and np.all(gpu["steps_done"] < 500)
+
+
+@pytest.mark.parametrize("mode", ["tape", "recompute"])
+def test_dimer_gradients_small(ssa, mode):
+    net = W.dimerization_2a()
+    B = 300
+    cfg = W.RunConfig(seed=1, n_steps=1500, obs_kind=W.OBS_BINS, n_bins=20, t_obs=300.0,
+                      temperature=0.5, ckpt_every=64)
+    g = np.random.default_rng(2)
+    d_obs = g.normal(size=(cfg.n_bins, 1, B))
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode=mode)
+    assert_forward_parity(gpu, r, ids)
+    keep = r.bin_edge_dist > 1e-3
+    assert keep.mean() > 0.9
+    assert_grad_parity(gpu["ppt"], r.grad, keep)
+    tot = r.grad.sum(0)
+    assert np.allclose(gpu["d_params"], tot, rtol=1e-5, atol=1e-5 * np.abs(tot).max())
+
+
+def test_oscillator_gradients_small(ssa):
+    net = W.oscillator(0)
+    B = 128
+    cfg = W.RunConfig(seed=4, n_steps=3000, obs_kind=W.OBS_FINAL, temperature=0.5, ckpt_every=256)
+    pilot = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(16))
+    t_obs = float(np.percentile(pilot.t_final, 1)) * 0.9
+    cfg = cfg.replace(obs_kind=W.OBS_BINS, n_bins=16, t_obs=t_obs)
+    g = np.random.default_rng(3)
+    d_obs = g.normal(size=(cfg.n_bins, 1, B))
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs)
+    assert_forward_parity(gpu, r, ids)
+    keep = r.bin_edge_dist > 1e-3 * t_obs / 100
+    assert_grad_parity(gpu["ppt"], r.grad, keep, rtol=1e-5)
+
+
+def test_random_networks_batch_forward(ssa):
+    nets = W.random_network_batch(6, seed=5, n_range=(4, 16), m_range=(8, 32))
+    B = [64, 37, 128, 1, 90, 65]
+    cfg = W.RunConfig(seed=9, n_steps=400, obs_kind=W.OBS_FINAL)
+    h = ssa.Net(nets, B)
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    x0 = _x0(nets, B)
+    fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 12)
+    torch.cuda.synchronize()
+    ties = fwd.tie_records()
+    xf = fwd.x_final.cpu().numpy()
+    sd = fwd.steps_done.cpu().numpy()
+    for n, (net, b) in enumerate(zip(nets, B)):
+        L = h.layout(n)
+        ov = _ties_for_oracle([t for t in ties if L.traj_offset <= t["traj"] < L.traj_offset + b],
+                              L.traj_offset)
+        r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=L.traj_offset + np.arange(b), ties=ov)
+        assert r.n_bad.sum() == 0
+        got = xf[L.state_offset: L.state_offset + net.n_species * b].reshape(net.n_species, b).T
+        assert np.array_equal(got, r.x_final), n
+        assert np.array_equal(sd[L.traj_offset: L.traj_offset + b], r.steps_done)
+
+
+def test_forward_backward_deterministic(ssa):
+    net = W.dimerization_2a()
+    B = 512
+    cfg = W.RunConfig(seed=7, n_steps=800, obs_kind=W.OBS_BINS, n_bins=5, t_obs=150.0, ckpt_every=128)
+    h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = _x0([net], [B])
+    d = torch.randn(cfg.n_bins * B, dtype=torch.float64, device="cuda")
+    outs = []
+    for _ in range(2):
+        f = ssa.forward(h, cfg, th, x0)
+        dp = ssa.backward(h, cfg, th, x0, f, d)
+        outs.append((f.obs.clone(), f.x_final.clone(), dp.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
