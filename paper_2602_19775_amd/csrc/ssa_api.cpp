@@ -7,11 +7,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include "ssa_jit.hpp"
 #include "ssa_lane.hpp"
 #include "ssa_misc.hpp"
 #include "ssa_plan.hpp"
@@ -63,8 +66,15 @@ struct ssa_net {
     int32_t *pmap_off_d = nullptr;
     int32_t *pmap_ch_d = nullptr;
     int32_t *param_net_d = nullptr;
-    LaneItem *items_d[kLaneClassCount] = {};
-    int n_items[kLaneClassCount] = {};
+    // one launch per group: a generic lane class, or a topology-specialised kernel pair
+    struct Group {
+        bool spec = false;
+        int lane_class = -1;
+        SpecKernels kernels;
+        LaneItem *items_d = nullptr;
+        int n_items = 0;
+    };
+    std::vector<Group> groups;
     uint32_t *flags_d = nullptr;
     int64_t traj_total = 0, state_total = 0, param_total = 0, obsb_total = 0, part_total = 0,
             ppt_total = 0;
@@ -186,14 +196,28 @@ RunParams base_params(const ssa_net *net, const ssa_config *cfg)
 
 ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hipStream_t stream)
 {
-    for (int c = 0; c < kLaneClassCount; ++c) {
-        if (!net->n_items[c]) continue;
-        p.items = net->items_d[c];
-        p.n_items = net->n_items[c];
-        hipError_t e = lane_launch(c, p, backward, stream);
+    for (const auto &gr : net->groups) {
+        if (!gr.n_items) continue;
+        p.items = gr.items_d;
+        p.n_items = gr.n_items;
+        hipError_t e = gr.spec ? spec_launch(gr.kernels, p, backward, stream)
+                               : lane_launch(gr.lane_class, p, backward, stream);
         if (e != hipSuccess) return hip_fail(e, backward ? "backward launch" : "forward launch");
     }
     return SSA_OK;
+}
+
+// Topology-specialised kernels are used unless SSA_SPECIALIZE=0, for networks
+// small enough to keep their state in registers, and only while a batch has
+// few distinct topologies (each costs one runtime compilation).
+constexpr int kSpecMaxSpecies = 64;
+constexpr int kSpecMaxChannels = 64;
+constexpr int kSpecMaxTopologies = 16;
+
+bool specialisation_enabled()
+{
+    const char *e = std::getenv("SSA_SPECIALIZE");
+    return !(e && e[0] == '0');
 }
 
 }  // namespace
@@ -251,6 +275,9 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     std::vector<uint32_t> rows;
     std::vector<int32_t> csr, obs_sp, pmap_off, pmap_ch, param_net;
     std::vector<LaneItem> items[kLaneClassCount];
+    std::map<std::string, std::vector<LaneItem>> spec_items;
+    std::map<std::string, SpecKernels> spec_kernels;
+    const bool try_spec = specialisation_enabled();
     int64_t roff = 0, soff = 0, ooff = 0;
     auto bail = [&](ssa_status s, const std::string &m) {
         ssa_net_destroy(net);
@@ -263,19 +290,45 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
             return bail(SSA_EINVAL, "network " + std::to_string(n) + ": sizes must be positive");
         if (nob > 4) return bail(SSA_ESHAPE, "at most 4 observed species per network");
         if (nob > 0 && !d->obs_species) return bail(SSA_EINVAL, "obs_species is NULL");
-        const int cls = lane_class_for(N, M);
-        if (cls < 0)
+        const int cls_generic = lane_class_for(N, M);
+        std::string src;
+        bool use_spec = false;
+        if (try_spec && N <= kSpecMaxSpecies && M <= kSpecMaxChannels) {
+            bool ok_tables = true;
+            for (int q = 0; q < M * N; ++q) {
+                const int v = d->stoich[soff + q];
+                if (v < -8 || v > 7) ok_tables = false;
+            }
+            if (ok_tables) {
+                src = spec_source(N, M, d->reactant + 2 * roff, d->rate_index + roff, d->stoich + soff, nob,
+                                  d->obs_species ? d->obs_species + ooff : nullptr);
+                if (spec_kernels.count(src)) {
+                    use_spec = true;
+                } else if ((int)spec_kernels.size() < kSpecMaxTopologies) {
+                    SpecKernels k;
+                    std::string log;
+                    if (spec_compile(src, &k, &log)) {
+                        spec_kernels[src] = k;
+                        use_spec = true;
+                    } else if (cls_generic < 0) {
+                        return bail(SSA_EHIP, "network " + std::to_string(n) + ": " + log);
+                    }
+                }
+            }
+        }
+        const int cls = use_spec ? kLane_N16_M32 : cls_generic;
+        if (!use_spec && cls < 0)
             return bail(SSA_ESHAPE, "network " + std::to_string(n) + " (N=" + std::to_string(N) +
                                         ", M=" + std::to_string(M) + ") exceeds the lane-mode bounds");
         NetDev nd;
         std::memset(&nd, 0, sizeof(nd));
         nd.N = N; nd.M = M; nd.P = P; nd.n_obs = nob; nd.B = B;
-        const int nmax = lane_class_nmax(cls);
+        const int nmax = use_spec ? N : lane_class_nmax(cls);
         nd.wpr = (nmax + 7) / 8;
         nd.react_off = (int32_t)rd.size();
         nd.rows_off = (int32_t)rows.size();
         nd.obs_sp_off = (int32_t)obs_sp.size();
-        nd.mode = cls;
+        nd.mode = use_spec ? -1 : cls;
         nd.traj_off = net->traj_total;
         nd.state_off = net->state_total;
         nd.param_off = net->param_total;
@@ -330,7 +383,8 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         for (int first = 0; first < B; first += 64) {
             LaneItem it;
             it.net = n; it.first = first; it.count = std::min(64, B - first); it.pad = M;
-            items[cls].push_back(it);
+            if (use_spec) spec_items[src].push_back(it);
+            else items[cls].push_back(it);
         }
         net->traj_total += B;
         net->state_total += (int64_t)N * B;
@@ -347,6 +401,9 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     pmap_off.push_back((int32_t)pmap_ch.size());
     if (net->traj_total > 0xFFFFFFFFll) return bail(SSA_ESHAPE, "too many trajectories");
     // more channels first: longer work items start early
+    for (auto &kv : spec_items)
+        std::stable_sort(kv.second.begin(), kv.second.end(),
+                         [](const LaneItem &a, const LaneItem &b) { return a.pad > b.pad; });
     for (auto &v : items)
         std::stable_sort(v.begin(), v.end(), [](const LaneItem &a, const LaneItem &b) { return a.pad > b.pad; });
 
@@ -359,9 +416,22 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     if (e == hipSuccess) e = upload(&net->pmap_off_d, pmap_off);
     if (e == hipSuccess) e = upload(&net->pmap_ch_d, pmap_ch.empty() ? std::vector<int32_t>{0} : pmap_ch);
     if (e == hipSuccess) e = upload(&net->param_net_d, param_net);
+    for (auto &kv : spec_items) {
+        if (e != hipSuccess) break;
+        ssa_net::Group gr;
+        gr.spec = true;
+        gr.kernels = spec_kernels[kv.first];
+        gr.n_items = (int)kv.second.size();
+        e = upload(&gr.items_d, kv.second);
+        net->groups.push_back(gr);
+    }
     for (int c = 0; c < kLaneClassCount && e == hipSuccess; ++c) {
-        net->n_items[c] = (int)items[c].size();
-        e = upload(&net->items_d[c], items[c]);
+        if (items[c].empty()) continue;
+        ssa_net::Group gr;
+        gr.lane_class = c;
+        gr.n_items = (int)items[c].size();
+        e = upload(&gr.items_d, items[c]);
+        net->groups.push_back(gr);
     }
     if (e == hipSuccess) e = hipMalloc((void **)&net->flags_d, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(net->flags_d, 0, sizeof(uint32_t));
@@ -387,7 +457,7 @@ void ssa_net_destroy(ssa_net *net)
     (void)hipFree(net->pmap_off_d);
     (void)hipFree(net->pmap_ch_d);
     (void)hipFree(net->param_net_d);
-    for (auto p : net->items_d) (void)hipFree(p);
+    for (auto &gr : net->groups) (void)hipFree(gr.items_d);
     (void)hipFree(net->flags_d);
     delete net;
 }

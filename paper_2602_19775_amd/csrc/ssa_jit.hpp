@@ -1,0 +1,27 @@
+// Plan-time compiled lane kernels specialised to one network topology.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "ssa_plan.hpp"
+
+namespace ssa {
+
+constexpr int spec_waves_per_block = 4;   // matches spec::kWaves
+
+struct SpecKernels {
+    hipModule_t module = nullptr;
+    hipFunction_t fwd = nullptr;
+    hipFunction_t bwd = nullptr;
+};
+
+// Source of the specialised kernel pair for one network (host tables).
+std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *rate_index,
+                        const int8_t *stoich, int n_obs, const int32_t *obs_species);
+// Compiles (or fetches from the in-process cache) the module for `src`.
+bool spec_compile(const std::string &src, SpecKernels *out, std::string *log);
+hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, hipStream_t stream);
+
+}  // namespace ssa

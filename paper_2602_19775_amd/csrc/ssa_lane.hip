@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void fwd_lane_kernel(RunParams p)
     constexpr int NB = (MMAX + 4) / 4;
     __shared__ uint32_t s_rows[kWaves][MMAX * WPR];
 
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wid = uniform_i((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int item_idx = blockIdx.x * kWaves + wid;
     const bool have = item_idx < p.n_items;
     const LaneItem it = p.items[have ? item_idx : 0];
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void bwd_lane_kernel(RunParams p)
     __shared__ uint32_t s_rows[kWaves][MMAX * WPR];
     __shared__ uint8_t s_tape[kWaves][KMAX_REC][64];
 
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wid = uniform_i((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int item_idx = blockIdx.x * kWaves + wid;
     const bool have = item_idx < p.n_items;
     const LaneItem it = p.items[have ? item_idx : 0];

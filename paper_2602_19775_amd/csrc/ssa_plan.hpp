@@ -2,7 +2,17 @@
 // kernels.  Everything here is plain data with a fixed layout.
 #pragma once
 
+#ifdef __HIPCC_RTC__
+// runtime compilation: the fixed-width integer types come with the builtin headers
+using __hip_internal::int8_t;
+using __hip_internal::uint8_t;
+using __hip_internal::int32_t;
+using __hip_internal::uint32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint64_t;
+#else
 #include <stdint.h>
+#endif
 
 namespace ssa {
 

@@ -1,0 +1,556 @@
+// Lane-mode kernels specialised to one network topology.  The network comes
+// in as a type NET with compile-time tables:
+//   N, M, NOBS                       species, channels, observed species
+//   S1[M], S2[M], HOMO[M], MULT[M]   a_j = k_j MULT[j] X[S1[j]] (X[S2[j]] - HOMO[j]);
+//                                    index N is a register that always holds 1
+//   RATE[M]                          parameter slot of channel j
+//   V[M][N]                          change vectors
+//   OBS[NOBS]                        observed species
+// so every species index is a constant and the state, its adjoint and the
+// per-channel values live in plain registers.  The library compiles one such
+// kernel pair per topology at plan time (hipRTC); rates, states and all run
+// settings stay runtime inputs.
+//
+// Forward (Sec. 2, Sec. 3.2): a_j, a0, tau = E_0/a0, j* = argmin_j E_j/a_j
+// (= argmax_j ln a_j + G_j with G_j = -ln E_j), X += v_j*, t += tau (FP64),
+// exact bin integrals of the observed species (Sec. 4.4), checkpoints every
+// K steps and the compact choice tape.
+// Backward (Sec. 3.1, Eqs. 3-7, Fig. 1): reverse sweep with the noise,
+// propensities and waiting times regenerated from the Philox counters.
+#pragma once
+
+#include "ssa_device.hpp"
+#include "ssa_plan.hpp"
+
+namespace ssa {
+namespace spec {
+
+constexpr int kWaves = 4;
+constexpr int kBlock = 64 * kWaves;
+constexpr int kFold = 32;   // FP32 adjoint increments are folded into FP64 this often
+
+__device__ __forceinline__ double bin_edge(double t_obs, int b, int n_bins)
+{
+    return t_obs * (double)b / (double)n_bins;
+}
+
+__device__ __forceinline__ void log_tie(const RunParams &p, uint32_t g, int k, int chosen, int second,
+                                     float margin, int kind)
+{
+    if (!p.ties) return;
+    const uint32_t idx = atomicAdd(p.n_ties, 1u);
+    if (idx < p.tie_cap) {
+        TieRec r;
+        r.traj = g; r.step = (uint32_t)k; r.chosen = chosen; r.second = second;
+        r.margin = margin; r.kind = kind;
+        p.ties[idx] = r;
+    }
+}
+
+template <class NET>
+struct Blocks {
+    static constexpr int NB = (NET::M + 1 + 3) / 4;
+    static constexpr int W = 4 * NB;
+};
+
+// Philox words of step k (word 0: tau, word 1+j: channel j).
+template <class NET>
+__device__ __forceinline__ void words(uint32_t k, uint32_t tid, uint32_t pe, uint32_t k0, uint32_t k1,
+                                      uint32_t (&wd)[Blocks<NET>::W])
+{
+#pragma unroll
+    for (int b = 0; b < Blocks<NET>::NB; ++b) {
+        const Philox::Out o = Philox::block((uint32_t)b, k, tid, pe, k0, k1);
+        wd[4 * b] = o.x;
+        wd[4 * b + 1] = o.y;
+        wd[4 * b + 2] = o.z;
+        wd[4 * b + 3] = o.w;
+    }
+}
+
+// a_j and (optionally) A1 = c_j X[S1], A2 = c_j (X[S2] - HOMO): da_j/dX[S2], da_j/dX[S1].
+template <class NET, bool DERIV>
+__device__ __forceinline__ float propensities(const float (&c)[NET::M], const int (&X)[NET::N + 1],
+                                              float (&a)[NET::M], float (&A1)[NET::M], float (&A2)[NET::M])
+{
+    float a0 = 0.f;
+#pragma unroll
+    for (int j = 0; j < NET::M; ++j) {
+        const float x1 = (float)X[NET::S1[j]];
+        const float x2 = (float)(X[NET::S2[j]] - NET::HOMO[j]);
+        const float u1 = c[j] * x1;
+        // a homodimer at X = 0 gives 0 * (-1) = -0; |.| keeps it +0 so that
+        // its reciprocal is +inf and the channel never wins the race
+        a[j] = fabsf(u1 * x2);
+        if (DERIV) {
+            A1[j] = u1;
+            A2[j] = c[j] * x2;
+        }
+        a0 += a[j];
+    }
+    return a0;
+}
+
+// X += sign * v_j for a per-lane channel j.
+template <class NET>
+__device__ __forceinline__ void apply(int (&X)[NET::N + 1], int j, int sign)
+{
+#pragma unroll
+    for (int s = 0; s < NET::N; ++s) {
+        int d = 0;
+#pragma unroll
+        for (int q = 0; q < NET::M; ++q)
+            if (NET::V[q][s] != 0) d = (j == q) ? NET::V[q][s] : d;
+        X[s] += sign * d;
+    }
+}
+
+template <class NET>
+__device__ __forceinline__ void rates(const RunParams &p, const NetDev &nd, float (&c)[NET::M])
+{
+#pragma unroll
+    for (int j = 0; j < NET::M; ++j) c[j] = expf(p.theta[nd.param_off + NET::RATE[j]]) * NET::MULT[j];
+}
+
+constexpr int obs_cap(int n) { return n > 0 ? n : 1; }
+
+// --------------------------------------------------------------------------
+template <class NET>
+__device__ void forward(const RunParams &p)
+{
+    constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
+    const int wid = uniform_i((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int item_idx = blockIdx.x * kWaves + wid;
+    if (item_idx >= p.n_items) return;
+    const LaneItem it = p.items[item_idx];
+    const NetDev nd = p.nets[it.net];
+
+    float c[M];
+    rates<NET>(p, nd, c);
+
+    const bool valid = lane < it.count;
+    const int64_t B = nd.B;
+    const int64_t i = it.first + (valid ? lane : 0);
+    const int64_t g = nd.traj_off + i;
+    const uint32_t tid = p.traj_ids ? p.traj_ids[g] : (uint32_t)g;
+    const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
+    const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
+
+    int X[N + 1];
+#pragma unroll
+    for (int s = 0; s < N; ++s) X[s] = p.x0[nd.state_off + s * B + i];
+    X[N] = 1;
+
+    const bool bins = p.obs_kind == 1 && NOBS > 0;
+    const int n_bins = p.n_bins;
+    const double t_obs = nd.t_obs;
+    int bin = bins ? 0 : n_bins;
+    double bin_hi = bins ? bin_edge(t_obs, 1, n_bins) : INFINITY;
+    double acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+    double *obs_lane = p.obs + nd.obsb_off * (p.obs_kind == 1 ? n_bins : 1) + i;
+    const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
+
+    const int spw = p.tape_bits ? 32 / p.tape_bits : 0;
+    const int tshift = spw ? __builtin_ctz(spw) : 0;
+    uint32_t tword = 0u;
+    const bool has_t_end = p.t_end < INFINITY;
+
+    double t = 0.0;
+    bool active = valid;
+    int n_done = 0;
+    uint32_t flags = 0u;
+    int ck_left = 0;
+    int64_t ck_idx = 0;
+
+    for (int k = 0; k < p.n_steps; ++k) {
+        if (ballot(active) == 0ull) break;
+        if (!active) continue;
+        if (p.ck_x) {
+            if (ck_left == 0) {
+#pragma unroll
+                for (int s = 0; s < N; ++s) p.ck_x[ck_idx * p.state_total + nd.state_off + s * B + i] = X[s];
+                p.ck_t[ck_idx * p.traj_total + g] = t;
+                ck_idx += 1;
+                ck_left = p.K;
+            }
+            ck_left -= 1;
+        }
+        float a[M], A1[M], A2[M];
+        const float a0 = propensities<NET, false>(c, X, a, A1, A2);
+        if (!(a0 > 0.f)) {
+            if (!(a0 == 0.f)) flags |= kFlagNonFinite;
+            active = false;
+            continue;
+        }
+        uint32_t wd[Blocks<NET>::W];
+        words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, wd);
+        const float tau = neglog_u(wd[0]) * fast_rcp(a0);
+        const double tn = t + (double)tau;
+        if (has_t_end) {
+            const bool fire = tn <= p.t_end;
+            if (fabs(tn - p.t_end) <= kClockTieLog * p.t_end)
+                log_tie(p, (uint32_t)g, k, fire ? 1 : 0, 0, (float)((tn - p.t_end) / p.t_end), 1);
+            if (!fire) {
+                active = false;
+                continue;
+            }
+        }
+        // exponential race: smallest and second smallest E_j / a_j
+        float r[M];
+        float r1 = INFINITY, r2 = INFINITY;
+        int j1 = 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            r[j] = neglog_u(wd[1 + j]) * fast_rcp(a[j]);    // a_j = 0 gives +inf: never fires
+            const bool lt = r[j] < r1;
+            r2 = lt ? r1 : fminf(r2, r[j]);
+            j1 = lt ? j : j1;
+            r1 = fminf(r1, r[j]);
+        }
+        if (r2 <= r1 * (1.f + kTieLog)) {
+            int j2 = -1;
+            float best = INFINITY;
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (j != j1 && r[j] < best) { best = r[j]; j2 = j; }
+            log_tie(p, (uint32_t)g, k, j1, j2, (r2 - r1) / r1, 0);
+        }
+        if (bin < n_bins) {
+            if (tn <= bin_hi) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) acc[o] += (double)X[NET::OBS[o]] * (double)tau;
+            } else {
+                double t0 = t;
+                while (bin < n_bins) {
+                    const double hi = bin_hi;
+                    if (tn <= hi) {
+#pragma unroll
+                        for (int o = 0; o < NO; ++o) acc[o] += (double)X[NET::OBS[o]] * (tn - t0);
+                        break;
+                    }
+#pragma unroll
+                    for (int o = 0; o < NO; ++o) {
+                        acc[o] += (double)X[NET::OBS[o]] * fmax(hi - t0, 0.0);
+                        if (o < NOBS) obs_lane[((int64_t)bin * NOBS + o) * B] = acc[o] * inv_dt;
+                        acc[o] = 0.0;
+                    }
+                    t0 = fmax(t0, hi);
+                    bin += 1;
+                    bin_hi = bin < n_bins ? bin_edge(t_obs, bin + 1, n_bins) : INFINITY;
+                }
+            }
+        }
+        if (spw) {
+            const int pos = k & (spw - 1);
+            tword |= (uint32_t)j1 << (p.tape_bits * pos);
+            if (pos == spw - 1) {
+                p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
+                tword = 0u;
+            }
+        }
+        apply<NET>(X, j1, +1);
+        t = tn;
+        n_done = k + 1;
+    }
+    if (!valid) return;
+    if (spw && (n_done & (spw - 1)) != 0) p.tape[(int64_t)(n_done >> tshift) * p.traj_total + g] = tword;
+    if (bin < n_bins) {
+        // hold the last state up to t_obs
+        double t0 = t;
+        while (bin < n_bins) {
+            const double hi = bin_hi;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                acc[o] += (double)X[NET::OBS[o]] * fmax(fmin(hi, t_obs) - t0, 0.0);
+                if (o < NOBS) obs_lane[((int64_t)bin * NOBS + o) * B] = acc[o] * inv_dt;
+                acc[o] = 0.0;
+            }
+            t0 = fmax(t0, hi);
+            bin += 1;
+            bin_hi = bin < n_bins ? bin_edge(t_obs, bin + 1, n_bins) : INFINITY;
+        }
+    }
+    if (p.obs_kind == 0) {
+#pragma unroll
+        for (int o = 0; o < NOBS; ++o) obs_lane[(int64_t)o * B] = (double)X[NET::OBS[o]];
+    }
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        p.x_final[nd.state_off + s * B + i] = X[s];
+        if (X[s] < 0) flags |= kFlagOverflow;
+    }
+    p.t_final[g] = t;
+    p.steps_done[g] = n_done;
+    if (flags) atomicOr(p.flags, flags);
+}
+
+// --------------------------------------------------------------------------
+template <class NET>
+__device__ void backward(const RunParams &p)
+{
+    constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
+    constexpr int KREC = 64;     // recompute mode: steps of a segment kept in LDS
+    __shared__ uint8_t s_tape[kWaves][KREC][64];
+
+    const int wid = uniform_i((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int item_idx = blockIdx.x * kWaves + wid;
+    if (item_idx >= p.n_items) return;
+    const LaneItem it = p.items[item_idx];
+    const NetDev nd = p.nets[it.net];
+
+    float c[M];
+    rates<NET>(p, nd, c);
+
+    const bool valid = lane < it.count;
+    const int64_t B = nd.B;
+    const int64_t i = it.first + (valid ? lane : 0);
+    const int64_t g = nd.traj_off + i;
+    const uint32_t tid = p.traj_ids ? p.traj_ids[g] : (uint32_t)g;
+    const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
+    const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
+    const float invT = 1.0f / p.temperature;
+    const bool invT_is_2 = invT == 2.0f, invT_is_1 = invT == 1.0f;
+
+    const int n = valid ? p.steps_done[g] : 0;
+    int kmax = n;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
+    kmax = uniform_i(kmax);
+
+    int X[N + 1];
+#pragma unroll
+    for (int s = 0; s < N; ++s) X[s] = valid ? p.x_final[nd.state_off + s * B + i] : 0;
+    X[N] = 1;
+    double t = valid ? p.t_final[g] : 0.0;
+
+    const bool bins = p.obs_kind == 1 && NOBS > 0;
+    const int n_bins = p.n_bins;
+    const double t_obs = nd.t_obs;
+    const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
+    const double *dobs_lane = p.d_obs + nd.obsb_off * (p.obs_kind == 1 ? n_bins : 1) + i;
+
+    // adjoint of the state: FP64 accumulator, FP32 increments folded every kFold steps
+    double lam[N];
+    float lam32[N], dlam[N];
+#pragma unroll
+    for (int s = 0; s < N; ++s) { lam[s] = 0.0; dlam[s] = 0.f; }
+    double lam_t = 0.0;
+    double dth[M];
+    float dth32[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) { dth[j] = 0.0; dth32[j] = 0.f; }
+
+    // reverse-time bin tracker
+    int rbin = n_bins;
+    double rlo = t_obs;
+    double dob[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) dob[o] = 0.0;
+    if (valid) {
+        if (bins) {
+            double hi = t_obs;
+            while (rbin > 0 && t < rlo) {
+                rbin -= 1;
+                rlo = bin_edge(t_obs, rbin, n_bins);
+#pragma unroll
+                for (int o = 0; o < NO; ++o)
+                    dob[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] : 0.0;
+                const double seg = hi - fmax(t, rlo);
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dob[o] * seg * inv_dt;
+                hi = rlo;
+            }
+        } else if (p.obs_kind == 0) {
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[(int64_t)o * B];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < N; ++s) lam32[s] = (float)lam[s];
+
+    const int spw = p.tape_bits ? 32 / p.tape_bits : 1;
+    const int tshift = __builtin_ctz(spw);
+    const uint32_t tmask = p.tape_bits ? ((1u << p.tape_bits) - 1u) : 0u;
+    const int n_seg = (kmax + p.K - 1) / p.K;
+    uint32_t flags = 0u;
+    int fold_left = kFold;
+
+    for (int cseg = n_seg - 1; cseg >= 0; --cseg) {
+        const int k_lo = cseg * p.K;
+        const int k_hi = min(k_lo + p.K, kmax);
+        if (p.recompute) {
+            int Xr[N + 1];
+            if (k_lo < n) {
+#pragma unroll
+                for (int s = 0; s < N; ++s)
+                    Xr[s] = p.ck_x[(int64_t)cseg * p.state_total + nd.state_off + s * B + i];
+            } else {
+#pragma unroll
+                for (int s = 0; s < N; ++s) Xr[s] = X[s];
+            }
+            Xr[N] = 1;
+            for (int k = k_lo; k < k_hi; ++k) {
+                if (k >= n) continue;
+                float a[M], A1[M], A2[M];
+                propensities<NET, false>(c, Xr, a, A1, A2);
+                uint32_t wd[Blocks<NET>::W];
+                words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, wd);
+                float r1 = INFINITY;
+                int j1 = 0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    const float rj = neglog_u(wd[1 + j]) * fast_rcp(a[j]);
+                    j1 = rj < r1 ? j : j1;
+                    r1 = fminf(r1, rj);
+                }
+                s_tape[wid][k - k_lo][lane] = (uint8_t)j1;
+                apply<NET>(Xr, j1, +1);
+            }
+        }
+        if (k_hi < n) {
+            const int64_t c1 = cseg + 1;
+#pragma unroll
+            for (int s = 0; s < N; ++s) X[s] = p.ck_x[c1 * p.state_total + nd.state_off + s * B + i];
+            t = p.ck_t[c1 * p.traj_total + g];
+        }
+        uint32_t tword = 0u;
+        int tword_idx = -1;
+        for (int k = k_hi - 1; k >= k_lo; --k) {
+            if (fold_left == 0) {
+#pragma unroll
+                for (int s = 0; s < N; ++s) {
+                    lam[s] += (double)dlam[s];
+                    dlam[s] = 0.f;
+                    lam32[s] = (float)lam[s];
+                }
+#pragma unroll
+                for (int j = 0; j < M; ++j) { dth[j] += (double)dth32[j]; dth32[j] = 0.f; }
+                fold_left = kFold;
+            }
+            fold_left -= 1;
+            if (k >= n) continue;
+            int j;
+            if (p.recompute) {
+                j = s_tape[wid][k - k_lo][lane];
+            } else {
+                const int widx = k >> tshift;
+                if (widx != tword_idx) {
+                    tword = p.tape[(int64_t)widx * p.traj_total + g];
+                    tword_idx = widx;
+                }
+                j = (int)((tword >> (p.tape_bits * (k & (spw - 1)))) & tmask);
+            }
+            int Xn[NOBS > 0 ? NOBS : 1];
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) Xn[o] = X[NET::OBS[o]];
+            apply<NET>(X, j, -1);        // X_{k+1} -> X_k
+
+            float a[M], A1[M], A2[M];
+            const float a0 = propensities<NET, true>(c, X, a, A1, A2);
+            uint32_t wd[Blocks<NET>::W];
+            words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, wd);
+            const float rcp_a0 = fast_rcp(a0);
+            const float tau = neglog_u(wd[0]) * rcp_a0;
+            const double t_k = t - (double)tau;
+
+            // direct dL/dt_{k+1}
+            if (bins && rbin < n_bins) {
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o)
+                    lam_t += dob[o] * (double)(X[NET::OBS[o]] - Xn[o]) * inv_dt;
+            }
+            // soft sample y~ in ratio form: y~_q ~ (r_min / r_q)^(1/T)
+            float r[M], ra[M];
+            float rmin = INFINITY;
+            int jmin = 0;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                const bool on = a[q] > 0.f;
+                ra[q] = on ? fast_rcp(a[q]) : 0.f;
+                r[q] = on ? neglog_u(wd[1 + q]) * ra[q] : INFINITY;
+                jmin = r[q] < rmin ? q : jmin;
+                rmin = fminf(rmin, r[q]);
+            }
+            float y[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) y[q] = rmin * fast_rcp(r[q]);
+            if (invT_is_2) {
+#pragma unroll
+                for (int q = 0; q < M; ++q) y[q] = y[q] * y[q];
+            } else if (!invT_is_1) {
+#pragma unroll
+                for (int q = 0; q < M; ++q) y[q] = y[q] > 0.f ? exp2f(log2f(y[q]) * invT) : 0.f;
+            }
+            float ysum = 0.f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) ysum += y[q];
+            const float rys = fast_rcp(ysum);
+            // w_q = v_q . lambda(k+1)
+            float wv[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                float s = 0.f;
+#pragma unroll
+                for (int sp = 0; sp < N; ++sp)
+                    if (NET::V[q][sp] != 0) s += (float)NET::V[q][sp] * (lam32[sp] + dlam[sp]);
+                wv[q] = s;
+            }
+            float wref = 0.f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) wref = (q == jmin) ? wv[q] : wref;
+            float wbar = 0.f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                y[q] *= rys;
+                wbar += y[q] * (wv[q] - wref);
+            }
+            const float cc = (float)(lam_t * (double)(-tau * rcp_a0));
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                const float gq = y[q] * ((wv[q] - wref) - wbar) * invT;
+                dth32[q] += gq + cc * a[q];
+                const float coef = gq * ra[q] + cc;
+                if (NET::S1[q] < N) dlam[NET::S1[q]] += coef * A2[q];
+                if (NET::S2[q] < N) dlam[NET::S2[q]] += coef * A1[q];
+            }
+            // direct dL/dX_k over [t_k, t_{k+1})
+            if (bins) {
+                double hi = fmin(t, t_obs);
+                while (t_k < rlo && rbin > 0) {
+                    if (rbin < n_bins) {
+                        const double seg = fmax(hi - rlo, 0.0);
+#pragma unroll
+                        for (int o = 0; o < NOBS; ++o)
+                            dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
+                    }
+                    hi = fmin(hi, rlo);
+                    rbin -= 1;
+                    rlo = bin_edge(t_obs, rbin, n_bins);
+#pragma unroll
+                    for (int o = 0; o < NO; ++o)
+                        dob[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] : 0.0;
+                }
+                if (rbin < n_bins) {
+                    const double seg = fmax(hi - t_k, 0.0);
+#pragma unroll
+                    for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
+                }
+            }
+            if (!(a0 > 0.f) || !(tau >= 0.f)) flags |= kFlagNonFinite;
+            t = t_k;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) dth[j] += (double)dth32[j];
+    if (!valid) return;
+#pragma unroll
+    for (int q = 0; q < M; ++q) p.partials[nd.part_off + q * B + i] = dth[q];
+    if (flags) atomicOr(p.flags, flags);
+}
+
+}  // namespace spec
+}  // namespace ssa
