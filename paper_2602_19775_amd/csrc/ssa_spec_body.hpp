@@ -165,14 +165,22 @@ __device__ void forward(const RunParams &p)
     int ck_left = 0;
     int64_t ck_idx = 0;
 
-    for (int k = 0; k < p.n_steps; ++k) {
+    // The step body is one straight-line block for every lane: the state
+    // updates are predicated on `fire`, and the Philox words of step k+1 are
+    // generated inside step k, so the scheduler can interleave that chain
+    // with the dependent propensity -> race -> update chain of step k.
+    uint32_t wd[Blocks<NET>::W];
+    words<NET>(0u, tid, pe, p.seed_lo, p.seed_hi, wd);
+    int k = 0;
+    for (; k < p.n_steps; ++k) {
         if (ballot(active) == 0ull) break;
-        if (!active) continue;
         if (p.ck_x) {
             if (ck_left == 0) {
+                if (active) {
 #pragma unroll
-                for (int s = 0; s < N; ++s) p.ck_x[ck_idx * p.state_total + nd.state_off + s * B + i] = X[s];
-                p.ck_t[ck_idx * p.traj_total + g] = t;
+                    for (int s = 0; s < N; ++s) p.ck_x[ck_idx * p.state_total + nd.state_off + s * B + i] = X[s];
+                    p.ck_t[ck_idx * p.traj_total + g] = t;
+                }
                 ck_idx += 1;
                 ck_left = p.K;
             }
@@ -180,24 +188,8 @@ __device__ void forward(const RunParams &p)
         }
         float a[M], A1[M], A2[M];
         const float a0 = propensities<NET, false>(c, X, a, A1, A2);
-        if (!(a0 > 0.f)) {
-            if (!(a0 == 0.f)) flags |= kFlagNonFinite;
-            active = false;
-            continue;
-        }
-        uint32_t wd[Blocks<NET>::W];
-        words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, wd);
         const float tau = neglog_u(wd[0]) * fast_rcp(a0);
         const double tn = t + (double)tau;
-        if (has_t_end) {
-            const bool fire = tn <= p.t_end;
-            if (fabs(tn - p.t_end) <= kClockTieLog * p.t_end)
-                log_tie(p, (uint32_t)g, k, fire ? 1 : 0, 0, (float)((tn - p.t_end) / p.t_end), 1);
-            if (!fire) {
-                active = false;
-                continue;
-            }
-        }
         // exponential race: smallest and second smallest E_j / a_j
         float r[M];
         float r1 = INFINITY, r2 = INFINITY;
@@ -210,19 +202,32 @@ __device__ void forward(const RunParams &p)
             j1 = lt ? j : j1;
             r1 = fminf(r1, r[j]);
         }
-        if (r2 <= r1 * (1.f + kTieLog)) {
-            int j2 = -1;
-            float best = INFINITY;
+        uint32_t wn[Blocks<NET>::W];
+        words<NET>((uint32_t)(k + 1), tid, pe, p.seed_lo, p.seed_hi, wn);
+
+        const bool live = active && a0 > 0.f;           // a0 = 0: absorbing state
+        const bool fire = live && (!has_t_end || tn <= p.t_end);
+        const bool in_bin = fire && tn <= bin_hi;       // the interval ends inside the current bin
+        const double w_obs = in_bin ? (double)tau : 0.0;
 #pragma unroll
-            for (int j = 0; j < M; ++j)
-                if (j != j1 && r[j] < best) { best = r[j]; j2 = j; }
-            log_tie(p, (uint32_t)g, k, j1, j2, (r2 - r1) / r1, 0);
-        }
-        if (bin < n_bins) {
-            if (tn <= bin_hi) {
+        for (int o = 0; o < NO; ++o) acc[o] += (double)X[NET::OBS[o]] * w_obs;
+        const bool clock_tie = live && has_t_end && fabs(tn - p.t_end) <= kClockTieLog * p.t_end;
+        const bool near_tie = fire && r2 <= r1 * (1.f + kTieLog);
+        const bool crossing = fire && !in_bin && bin < n_bins;
+        const bool odd = active && !(a0 >= 0.f);
+        if (ballot(clock_tie || near_tie || crossing || odd) != 0ull) {
+            if (odd) flags |= kFlagNonFinite;
+            if (clock_tie)
+                log_tie(p, (uint32_t)g, k, fire ? 1 : 0, 0, (float)((tn - p.t_end) / p.t_end), 1);
+            if (near_tie) {
+                int j2 = -1;
+                float best = INFINITY;
 #pragma unroll
-                for (int o = 0; o < NO; ++o) acc[o] += (double)X[NET::OBS[o]] * (double)tau;
-            } else {
+                for (int j = 0; j < M; ++j)
+                    if (j != j1 && r[j] < best) { best = r[j]; j2 = j; }
+                log_tie(p, (uint32_t)g, k, j1, j2, (r2 - r1) / r1, 0);
+            }
+            if (crossing) {
                 double t0 = t;
                 while (bin < n_bins) {
                     const double hi = bin_hi;
@@ -245,18 +250,21 @@ __device__ void forward(const RunParams &p)
         }
         if (spw) {
             const int pos = k & (spw - 1);
-            tword |= (uint32_t)j1 << (p.tape_bits * pos);
+            tword |= fire ? (uint32_t)j1 << (p.tape_bits * pos) : 0u;
             if (pos == spw - 1) {
-                p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
+                if (valid) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
                 tword = 0u;
             }
         }
-        apply<NET>(X, j1, +1);
-        t = tn;
-        n_done = k + 1;
+        apply<NET>(X, fire ? j1 : -1, +1);
+        t = fire ? tn : t;
+        n_done += fire ? 1 : 0;
+        active = fire;
+#pragma unroll
+        for (int q = 0; q < Blocks<NET>::W; ++q) wd[q] = wn[q];
     }
     if (!valid) return;
-    if (spw && (n_done & (spw - 1)) != 0) p.tape[(int64_t)(n_done >> tshift) * p.traj_total + g] = tword;
+    if (spw && (k & (spw - 1)) != 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
     if (bin < n_bins) {
         // hold the last state up to t_obs
         double t0 = t;
@@ -320,6 +328,11 @@ __device__ void backward(const RunParams &p)
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) kmax = max(kmax, __shfl_xor(kmax, off));
     kmax = uniform_i(kmax);
+    // smallest step count of the wave's valid lanes (lanes past the tile count nothing)
+    int nmin = valid ? n : kmax;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) nmin = min(nmin, __shfl_xor(nmin, off));
+    nmin = uniform_i(nmin);
 
     int X[N + 1];
 #pragma unroll
@@ -419,7 +432,116 @@ __device__ void backward(const RunParams &p)
         }
         uint32_t tword = 0u;
         int tword_idx = -1;
-        for (int k = k_hi - 1; k >= k_lo; --k) {
+        // one reverse step k for a lane that fired it: X_{k+1} -> X_k and the
+        // adjoint recursion; w holds the Philox words of step k
+        auto sweep = [&](int k, int j, const uint32_t (&w)[Blocks<NET>::W]) {
+                int Xn[NOBS > 0 ? NOBS : 1];
+    #pragma unroll
+                for (int o = 0; o < NOBS; ++o) Xn[o] = X[NET::OBS[o]];
+                apply<NET>(X, j, -1);        // X_{k+1} -> X_k
+
+                float a[M], A1[M], A2[M];
+                const float a0 = propensities<NET, true>(c, X, a, A1, A2);
+                const float rcp_a0 = fast_rcp(a0);
+                const float tau = neglog_u(w[0]) * rcp_a0;
+                const double t_k = t - (double)tau;
+
+                // direct dL/dt_{k+1}
+                if (bins && rbin < n_bins) {
+    #pragma unroll
+                    for (int o = 0; o < NOBS; ++o)
+                        lam_t += dob[o] * (double)(X[NET::OBS[o]] - Xn[o]) * inv_dt;
+                }
+                // soft sample y~ in ratio form: y~_q ~ (r_min / r_q)^(1/T)
+                float r[M], ra[M];
+                float rmin = INFINITY;
+                int jmin = 0;
+    #pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    const bool on = a[q] > 0.f;
+                    ra[q] = on ? fast_rcp(a[q]) : 0.f;
+                    r[q] = on ? neglog_u(w[1 + q]) * ra[q] : INFINITY;
+                    jmin = r[q] < rmin ? q : jmin;
+                    rmin = fminf(rmin, r[q]);
+                }
+                float y[M];
+    #pragma unroll
+                for (int q = 0; q < M; ++q) y[q] = rmin * fast_rcp(r[q]);
+                if (invT_is_2) {
+    #pragma unroll
+                    for (int q = 0; q < M; ++q) y[q] = y[q] * y[q];
+                } else if (!invT_is_1) {
+    #pragma unroll
+                    for (int q = 0; q < M; ++q) y[q] = y[q] > 0.f ? exp2f(log2f(y[q]) * invT) : 0.f;
+                }
+                float ysum = 0.f;
+    #pragma unroll
+                for (int q = 0; q < M; ++q) ysum += y[q];
+                const float rys = fast_rcp(ysum);
+                // w_q = v_q . lambda(k+1)
+                float wv[M];
+    #pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    float s = 0.f;
+    #pragma unroll
+                    for (int sp = 0; sp < N; ++sp)
+                        if (NET::V[q][sp] != 0) s += (float)NET::V[q][sp] * (lam32[sp] + dlam[sp]);
+                    wv[q] = s;
+                }
+                float wref = 0.f;
+    #pragma unroll
+                for (int q = 0; q < M; ++q) wref = (q == jmin) ? wv[q] : wref;
+                float wbar = 0.f;
+    #pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    y[q] *= rys;
+                    wbar += y[q] * (wv[q] - wref);
+                }
+                const float cc = (float)(lam_t * (double)(-tau * rcp_a0));
+    #pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    const float gq = y[q] * ((wv[q] - wref) - wbar) * invT;
+                    dth32[q] += gq + cc * a[q];
+                    const float coef = gq * ra[q] + cc;
+                    if (NET::S1[q] < N) dlam[NET::S1[q]] += coef * A2[q];
+                    if (NET::S2[q] < N) dlam[NET::S2[q]] += coef * A1[q];
+                }
+                // direct dL/dX_k over [t_k, t_{k+1})
+                if (bins) {
+                    double hi = fmin(t, t_obs);
+                    while (t_k < rlo && rbin > 0) {
+                        if (rbin < n_bins) {
+                            const double seg = fmax(hi - rlo, 0.0);
+    #pragma unroll
+                            for (int o = 0; o < NOBS; ++o)
+                                dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
+                        }
+                        hi = fmin(hi, rlo);
+                        rbin -= 1;
+                        rlo = bin_edge(t_obs, rbin, n_bins);
+    #pragma unroll
+                        for (int o = 0; o < NO; ++o)
+                            dob[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] : 0.0;
+                    }
+                    if (rbin < n_bins) {
+                        const double seg = fmax(hi - t_k, 0.0);
+    #pragma unroll
+                        for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
+                    }
+                }
+            if (!(a0 > 0.f) || !(tau >= 0.f)) flags |= kFlagNonFinite;
+            t = t_k;
+        };
+        auto choice = [&](int k) -> int {
+            if (p.recompute) return s_tape[wid][k - k_lo][lane];
+            const int widx = k >> tshift;
+            if (widx != tword_idx) {
+                tword = p.tape[(int64_t)widx * p.traj_total + g];
+                tword_idx = widx;
+            }
+            return (int)((tword >> (p.tape_bits * (k & (spw - 1)))) & tmask);
+        };
+        auto fold = [&]() {
             if (fold_left == 0) {
 #pragma unroll
                 for (int s = 0; s < N; ++s) {
@@ -432,116 +554,32 @@ __device__ void backward(const RunParams &p)
                 fold_left = kFold;
             }
             fold_left -= 1;
-            if (k >= n) continue;
-            int j;
-            if (p.recompute) {
-                j = s_tape[wid][k - k_lo][lane];
-            } else {
-                const int widx = k >> tshift;
-                if (widx != tword_idx) {
-                    tword = p.tape[(int64_t)widx * p.traj_total + g];
-                    tword_idx = widx;
-                }
-                j = (int)((tword >> (p.tape_bits * (k & (spw - 1)))) & tmask);
+        };
+        // steps some lanes of the wave never fired (they ended early): masked
+        const int k_split = max(min(k_hi, nmin), k_lo);
+        for (int k = k_hi - 1; k >= k_split; --k) {
+            fold();
+            const int j = choice(k);
+            if (k < n) {
+                uint32_t w[Blocks<NET>::W];
+                words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, w);
+                sweep(k, j, w);
             }
-            int Xn[NOBS > 0 ? NOBS : 1];
-#pragma unroll
-            for (int o = 0; o < NOBS; ++o) Xn[o] = X[NET::OBS[o]];
-            apply<NET>(X, j, -1);        // X_{k+1} -> X_k
-
-            float a[M], A1[M], A2[M];
-            const float a0 = propensities<NET, true>(c, X, a, A1, A2);
+        }
+        // steps every lane fired: straight-line body, Philox words of step
+        // k-1 generated while step k is swept
+        if (k_split > k_lo) {
             uint32_t wd[Blocks<NET>::W];
-            words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, wd);
-            const float rcp_a0 = fast_rcp(a0);
-            const float tau = neglog_u(wd[0]) * rcp_a0;
-            const double t_k = t - (double)tau;
-
-            // direct dL/dt_{k+1}
-            if (bins && rbin < n_bins) {
+            words<NET>((uint32_t)(k_split - 1), tid, pe, p.seed_lo, p.seed_hi, wd);
+            for (int k = k_split - 1; k >= k_lo; --k) {
+                fold();
+                const int j = choice(k);
+                uint32_t wn[Blocks<NET>::W];
+                words<NET>((uint32_t)(k - 1), tid, pe, p.seed_lo, p.seed_hi, wn);
+                sweep(k, j, wd);
 #pragma unroll
-                for (int o = 0; o < NOBS; ++o)
-                    lam_t += dob[o] * (double)(X[NET::OBS[o]] - Xn[o]) * inv_dt;
+                for (int q = 0; q < Blocks<NET>::W; ++q) wd[q] = wn[q];
             }
-            // soft sample y~ in ratio form: y~_q ~ (r_min / r_q)^(1/T)
-            float r[M], ra[M];
-            float rmin = INFINITY;
-            int jmin = 0;
-#pragma unroll
-            for (int q = 0; q < M; ++q) {
-                const bool on = a[q] > 0.f;
-                ra[q] = on ? fast_rcp(a[q]) : 0.f;
-                r[q] = on ? neglog_u(wd[1 + q]) * ra[q] : INFINITY;
-                jmin = r[q] < rmin ? q : jmin;
-                rmin = fminf(rmin, r[q]);
-            }
-            float y[M];
-#pragma unroll
-            for (int q = 0; q < M; ++q) y[q] = rmin * fast_rcp(r[q]);
-            if (invT_is_2) {
-#pragma unroll
-                for (int q = 0; q < M; ++q) y[q] = y[q] * y[q];
-            } else if (!invT_is_1) {
-#pragma unroll
-                for (int q = 0; q < M; ++q) y[q] = y[q] > 0.f ? exp2f(log2f(y[q]) * invT) : 0.f;
-            }
-            float ysum = 0.f;
-#pragma unroll
-            for (int q = 0; q < M; ++q) ysum += y[q];
-            const float rys = fast_rcp(ysum);
-            // w_q = v_q . lambda(k+1)
-            float wv[M];
-#pragma unroll
-            for (int q = 0; q < M; ++q) {
-                float s = 0.f;
-#pragma unroll
-                for (int sp = 0; sp < N; ++sp)
-                    if (NET::V[q][sp] != 0) s += (float)NET::V[q][sp] * (lam32[sp] + dlam[sp]);
-                wv[q] = s;
-            }
-            float wref = 0.f;
-#pragma unroll
-            for (int q = 0; q < M; ++q) wref = (q == jmin) ? wv[q] : wref;
-            float wbar = 0.f;
-#pragma unroll
-            for (int q = 0; q < M; ++q) {
-                y[q] *= rys;
-                wbar += y[q] * (wv[q] - wref);
-            }
-            const float cc = (float)(lam_t * (double)(-tau * rcp_a0));
-#pragma unroll
-            for (int q = 0; q < M; ++q) {
-                const float gq = y[q] * ((wv[q] - wref) - wbar) * invT;
-                dth32[q] += gq + cc * a[q];
-                const float coef = gq * ra[q] + cc;
-                if (NET::S1[q] < N) dlam[NET::S1[q]] += coef * A2[q];
-                if (NET::S2[q] < N) dlam[NET::S2[q]] += coef * A1[q];
-            }
-            // direct dL/dX_k over [t_k, t_{k+1})
-            if (bins) {
-                double hi = fmin(t, t_obs);
-                while (t_k < rlo && rbin > 0) {
-                    if (rbin < n_bins) {
-                        const double seg = fmax(hi - rlo, 0.0);
-#pragma unroll
-                        for (int o = 0; o < NOBS; ++o)
-                            dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
-                    }
-                    hi = fmin(hi, rlo);
-                    rbin -= 1;
-                    rlo = bin_edge(t_obs, rbin, n_bins);
-#pragma unroll
-                    for (int o = 0; o < NO; ++o)
-                        dob[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] : 0.0;
-                }
-                if (rbin < n_bins) {
-                    const double seg = fmax(hi - t_k, 0.0);
-#pragma unroll
-                    for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
-                }
-            }
-            if (!(a0 > 0.f) || !(tau >= 0.f)) flags |= kFlagNonFinite;
-            t = t_k;
         }
     }
 #pragma unroll
