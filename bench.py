@@ -27,23 +27,61 @@ METRIC = "SSA steps/sec fwd and fwd+bwd on 1 MI355X; grad rel-err vs FP64 oracle
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per clock x clock
 
 
-def alu_slots_per_step(M: int, N: int, nnz_total: int, n_obs: int, backward: bool, inv_t_is_2=True) -> int:
-    """Algorithmic VALU issue slots of one step of one trajectory (full-rate
-    op = 1 slot, quarter-rate 32-bit multiply / reciprocal / log = 4 slots)."""
+def alu_ops_per_step(M: int, N: int, nnz_total: int, n_obs: int, backward: bool, inv_t_is_2=True) -> dict:
+    """Algorithmic vector-ALU operations of one step of one trajectory, by kind:
+    mad = 32x32->64-bit product, int = 32-bit integer add/logic/shift,
+    fp32 = FP32 add/mul/FMA/compare/select, cvt = int<->float conversion,
+    log / rcp = transcendentals, f64 = FP64 add or FMA."""
     nb = (M + 1 + 3) // 4
-    rng = nb * 10 * (2 * 4 + 2)             # Philox4x32-10: two 32x32->64 products, two xor3 a round
-    neglog = (M + 1) * (3 + 4 + 1)          # word -> lattice uniform, log, scale
+    w = M + 1                                        # Philox words used
+    ops = {"mad": 20 * nb,                           # Philox4x32-10: two products a round
+           "int": 40 * nb + 2 * w,                   # four xors a round; word -> odd 24-bit integer
+           "cvt": w, "fp32": 2 * w,                  # lattice u = int * 2^-24, E = log2(u) * -ln 2
+           "log": w, "rcp": 0, "f64": 0}
     if not backward:
-        prop = M * 5 + M                    # two conversions, subtract, two products; a0 sum
-        tau = 4 + 1
-        race = M * (4 + 1 + 3)              # reciprocal, product, compare/min/select
-        upd = N + 1 + n_obs                 # state update, FP64 clock, FP64 bin integral
-        return rng + neglog + prop + tau + race + upd
-    prop = M * 7 + M                        # propensities and their two partial derivatives
-    tau = 4 + 1 + 1                         # waiting time and the reversed FP64 clock
-    soft = M * (5 + 5 + (1 if inv_t_is_2 else 8) + 1) + 4 + M   # ratios, rho, rho^(1/T), sum, normalise
-    adj = 2 * nnz_total + M * (2 + 3 + 2 + 2 + 4)              # w_j, wbar, g_j, dtheta, coef, lambda
-    return rng + neglog + prop + tau + soft + adj + N + 2 * n_obs
+        ops["cvt"] += 2 * M + 1 + n_obs              # propensity factors, clock, bin value
+        ops["int"] += M + N                          # homodimer X-1, state update
+        ops["fp32"] += 2 * M + M + 1 + M + 3 * M     # products, a0 sum, tau, r_j, race compare/min/select
+        ops["rcp"] += 1 + M                          # 1/a0 and 1/a_j
+        ops["f64"] += 1 + n_obs                      # clock, bin integral
+        return ops
+    ops["cvt"] += 2 * M + 2 + 2 * n_obs              # propensity factors, clock, time-path and bin terms
+    ops["int"] += M + N                              # homodimer X-1, reversed state update
+    ops["rcp"] += 1 + M + M + 1                      # 1/a0, 1/a_j, 1/r_j, 1/sum
+    ops["fp32"] += (3 * M + M + 1                    # products with partials, a0, tau
+                    + M + M + (M if inv_t_is_2 else 0) + M + M      # r_j, rho, rho^(1/T), sum, normalise
+                    + 2 * nnz_total + 2 * M + 3 * M + 2 * M + 2 * M + 4 * M)   # w, wbar, g, dtheta, coef, lambda
+    if not inv_t_is_2:
+        ops["log"] += M
+        ops["fp32"] += 3 * M
+    ops["f64"] += 2 + 2 * n_obs                      # reversed clock, time path, direct terms
+    return ops
+
+
+def measure_issue_costs():
+    """Issue cost of each operation kind in full-rate lane slots (one FP32 FMA
+    per lane per clock on every CU), measured on this GPU by the
+    instruction-throughput probes of libssa_ubench.so."""
+    import ctypes as C
+    L = C.CDLL(os.path.join(ROOT, "paper_2602_19775_amd", "libssa_ubench.so"))
+    L.ubench_run.restype = C.c_float
+    L.ubench_run.argtypes = [C.c_int, C.c_int, C.c_int]
+    blocks, iters = 2048, 4096
+    lanes = blocks * 256
+    t = {}
+    for kind in range(7):
+        ms = L.ubench_run(kind, iters, blocks)
+        if ms <= 0:
+            raise RuntimeError("instruction probe failed")
+        t[kind] = ms * 1e-3 * PEAK_LANE_SLOTS / (lanes * 8 * iters)   # slots per chain step
+    i32 = t[4] / 2                  # xor + add
+    f32 = t[3]                      # fma
+    return {"int": i32, "fp32": f32, "mad": t[0] - i32, "log": t[1] - f32, "rcp": t[2] - f32,
+            "cvt": t[6] - i32, "f64": t[5]}
+
+
+def slots(ops: dict, cost: dict) -> float:
+    return sum(n * cost[k] for k, n in ops.items())
 
 
 def main():
@@ -51,10 +89,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator"],
+                    help="dimer: 2A<->A2, 65,536 x 10,000 steps (default); "
+                         "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps")
     ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
     ap.add_argument("--n-traj", type=int, default=65536)
-    ap.add_argument("--n-steps", type=int, default=10000)
-    ap.add_argument("--ckpt-every", type=int, default=256)
+    ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")
+    ap.add_argument("--ckpt-every", type=int, default=0, help="checkpoint interval (0: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -84,8 +125,11 @@ def main():
         print(json.dumps({"copy_bytes": n * 4, "launches": 3}))
         return
 
-    wl = W.dimer_fwdbwd_64k(args.n_traj, args.n_steps)
-    cfg = wl.cfg.replace(ckpt_every=args.ckpt_every)
+    if args.workload == "dimer":
+        wl = W.dimer_fwdbwd_64k(args.n_traj, args.n_steps or 10000)
+    else:
+        wl = W.oscillator_fwdbwd_64k(args.n_traj, args.n_steps or 200000)
+    cfg = wl.cfg.replace(ckpt_every=args.ckpt_every or wl.cfg.ckpt_every)
     net, B = wl.net, wl.n_traj
     nb, nob = cfg.n_bins, len(net.obs_species)
     h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
@@ -94,23 +138,36 @@ def main():
 
     # targets: a seeded run at the target rates (separate stream purpose), untimed
     tcfg = cfg.replace(purpose=W.PURPOSE_TARGET)
-    theta_t = torch.tensor(np.log(np.array(W.DIMER_TARGET_RATES)).astype(np.float32), device=dev)
+    if args.workload == "dimer":
+        theta_t = torch.tensor(np.log(np.array(W.DIMER_TARGET_RATES)).astype(np.float32), device=dev)
+    else:
+        theta_t = torch.tensor(wl.extra["target_net"].theta0, device=dev)
     tf = ssa.forward(h, tcfg, theta_t, x0, keep_ckpt=False, tie_capacity=0)
-    tm, tv = losses.bin_moments(tf.obs, nb, nob, B)
-    tm, tv = tm.clone(), tv.clone()
+    if args.workload == "dimer":
+        tm, tv = losses.bin_moments(tf.obs, nb, nob, B)
+        tm, tv = tm.clone(), tv.clone()
+
+        def loss_fn(obs):
+            return losses.moment_mse(obs, tm, tv, nb, nob, B)
+    else:
+        tac = losses.mean_autocorrelation(tf.obs, nb, B, 64).clone()
+
+        def loss_fn(obs):
+            return losses.autocorrelation_mse(obs, tac, nb, B, 64)
     del tf
 
-    bufs = ssa.forward(h, cfg, theta, x0, tie_capacity=1 << 16, bwd_mode=args.bwd_mode)
+    tie_cap = 1 << 16 if args.workload == "dimer" else 1 << 22
+    bufs = ssa.forward(h, cfg, theta, x0, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
     d_params = torch.empty(net.n_params, dtype=torch.float32, device=dev)
 
     def step(record=None):
         if record is not None:
             record[0].record()
-        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=1 << 16, bwd_mode=args.bwd_mode)
+        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
         if record is not None:
             record[1].record()
         obs = bufs.obs.detach().requires_grad_(True)
-        loss = losses.moment_mse(obs, tm, tv, nb, nob, B)
+        loss = loss_fn(obs)
         (d_obs,) = torch.autograd.grad(loss, obs)
         if record is not None:
             record[2].record()
@@ -138,11 +195,11 @@ def main():
 
     # forward-only rate of the same forward call
     for _ in range(args.warmup):
-        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=1 << 16, bwd_mode=args.bwd_mode)
+        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
     torch.cuda.synchronize()
     f0 = time.perf_counter()
     for _ in range(args.steps):
-        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=1 << 16, bwd_mode=args.bwd_mode)
+        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
     torch.cuda.synchronize()
     f1 = time.perf_counter()
     fwd_rate = fired * args.steps / (f1 - f0)
@@ -152,10 +209,11 @@ def main():
     # gradient relative error against the oracle on a sample of trajectories
     import oracle
     obs = bufs.obs.detach().requires_grad_(True)
-    loss = losses.moment_mse(obs, tm, tv, nb, nob, B)
+    loss = loss_fn(obs)
     (d_obs,) = torch.autograd.grad(loss, obs)
     _, ppt = ssa.backward(h, cfg, theta, x0, bufs, d_obs, per_traj=True)
-    sample = np.arange(0, B, max(1, B // 64))[:64]
+    n_sample = 64 if args.workload == "dimer" else 16
+    sample = np.arange(0, B, max(1, B // n_sample))[:n_sample]
     dob = d_obs.cpu().numpy().reshape(nb, nob, B).transpose(2, 0, 1)[sample]
     ties = bufs.tie_records()
     idx = {int(q): k for k, q in enumerate(sample)}
@@ -167,23 +225,30 @@ def main():
     counts_exact = bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
     grad_rel_err = float(np.linalg.norm(g_gpu.sum(0) - r.grad.sum(0)) / np.linalg.norm(r.grad.sum(0)))
 
-    # roofline of the dominant kernel (ALU-bound: algorithmic VALU issue slots)
+    # roofline of the dominant kernel (ALU-bound): algorithmic operations of a
+    # launch weighted by their measured issue cost, over the kernel's time,
+    # against the full-rate issue limit of the vector ALUs
     nnz = int(np.count_nonzero(net.stoich))
-    per_step_b = alu_slots_per_step(net.n_reactions, net.n_species, nnz, nob, True)
-    per_step_f = alu_slots_per_step(net.n_reactions, net.n_species, nnz, nob, False)
+    cost = measure_issue_costs()
+    inv2 = abs(1.0 / cfg.temperature - 2.0) < 1e-12
+    ops_b = alu_ops_per_step(net.n_reactions, net.n_species, nnz, nob, True, inv2)
+    ops_f = alu_ops_per_step(net.n_reactions, net.n_species, nnz, nob, False)
     if bwd_ms >= fwd_ms:
-        dom, dom_ms, slots = "bwd_lane_kernel", bwd_ms, per_step_b
+        dom, dom_ms, ops = "ssa_spec_bwd", bwd_ms, ops_b
     else:
-        dom, dom_ms, slots = "fwd_lane_kernel", fwd_ms, per_step_f
-    achieved = fired * slots / (dom_ms * 1e-3)
+        dom, dom_ms, ops = "ssa_spec_fwd", fwd_ms, ops_f
+    per_step = slots(ops, cost)
+    achieved = fired * per_step / (dom_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
                 "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
-                "slots_per_step": slots, "kernel_ms": dom_ms}
+                "slots_per_step": per_step, "ops_per_step": ops, "issue_cost_slots": cost,
+                "kernel_ms": dom_ms,
+                "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
 
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        n_try = 32
+        n_try = 32 if args.workload == "dimer" else 4
         c0 = time.perf_counter()
         oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n_try), d_obs=np.zeros((n_try, nb, nob)),
                    n_threads=threads)

@@ -290,8 +290,18 @@ def dimer_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 10000) -> Workload:
     return Workload(f"dimer_2A_{n_traj}traj_{n_steps}steps_20bins", net, n_traj, cfg)
 
 
-def oscillator_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 200000, t_obs: float = None) -> Workload:
+# Observation window of the oscillator workload: 0.9 x the 1st percentile of the
+# clock after 200,000 steps in a 64-trajectory pilot run of the FP64 oracle
+# (pilot stream, initial rates); tests/golden/oscillator_pilot.py recomputes it.
+OSC_T_OBS = 124299.29021959605
+
+
+def oscillator_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 200000, t_obs: float = OSC_T_OBS) -> Workload:
+    """Activator-repressor oscillator with seeded rates: 65,536 trajectories x
+    200,000 steps, 256 exact bin averages of R on [0, t_obs], temperature 0.5,
+    checkpoints every 1,024 steps.  Targets come from a second seeded rate vector."""
     net = oscillator(rate_seed=0)
-    cfg = RunConfig(seed=0, n_steps=n_steps, obs_kind=OBS_BINS, n_bins=256,
-                    t_obs=t_obs if t_obs is not None else 0.0, temperature=0.5, ckpt_every=1024)
-    return Workload(f"oscillator_{n_traj}traj_{n_steps}steps_256bins", net, n_traj, cfg)
+    cfg = RunConfig(seed=0, n_steps=n_steps, obs_kind=OBS_BINS, n_bins=256, t_obs=t_obs,
+                    temperature=0.5, ckpt_every=1024)
+    return Workload(f"oscillator_{n_traj}traj_{n_steps}steps_256bins", net, n_traj, cfg,
+                    extra={"target_net": oscillator(rate_seed=1)})
