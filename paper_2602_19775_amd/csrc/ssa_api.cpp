@@ -16,6 +16,7 @@
 
 #include "ssa_jit.hpp"
 #include "ssa_lane.hpp"
+#include "ssa_wave.hpp"
 #include "ssa_misc.hpp"
 #include "ssa_plan.hpp"
 
@@ -66,10 +67,14 @@ struct ssa_net {
     int32_t *pmap_off_d = nullptr;
     int32_t *pmap_ch_d = nullptr;
     int32_t *param_net_d = nullptr;
+    int32_t *inc_ptr_d = nullptr;
+    int32_t *inc_ent_d = nullptr;
     // one launch per group: a generic lane class, or a topology-specialised kernel pair
     struct Group {
         bool spec = false;
         int lane_class = -1;
+        int wave_class = -1;     // persistent wave-mode launch
+        int wave_blocks = 0;
         SpecKernels kernels;
         LaneItem *items_d = nullptr;
         int n_items = 0;
@@ -191,6 +196,8 @@ RunParams base_params(const ssa_net *net, const ssa_config *cfg)
     p.traj_total = net->traj_total;
     p.temperature = cfg->temperature;
     p.recompute = resolve_bwd_mode(cfg) == SSA_BWD_RECOMPUTE ? 1 : 0;
+    p.inc_ptr = net->inc_ptr_d;
+    p.inc_ent = net->inc_ent_d;
     return p;
 }
 
@@ -200,11 +207,26 @@ ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hi
         if (!gr.n_items) continue;
         p.items = gr.items_d;
         p.n_items = gr.n_items;
-        hipError_t e = gr.spec ? spec_launch(gr.kernels, p, backward, stream)
-                               : lane_launch(gr.lane_class, p, backward, stream);
+        hipError_t e;
+        if (gr.wave_class >= 0) {
+            // the persistent kernel pulls work from a counter that starts at 0
+            e = launch_fill_u32(p.work_counter, 1, 0u, stream);
+            if (e == hipSuccess) e = wave_launch(gr.wave_class, p, backward, gr.wave_blocks, stream);
+        } else {
+            e = gr.spec ? spec_launch(gr.kernels, p, backward, stream) : lane_launch(gr.lane_class, p, backward, stream);
+        }
         if (e != hipSuccess) return hip_fail(e, backward ? "backward launch" : "forward launch");
     }
     return SSA_OK;
+}
+
+// Execution mode: SSA_EXEC=spec|lane|wave forces one (for tests and tuning).
+int forced_exec_mode()
+{
+    const char *e = std::getenv("SSA_EXEC");
+    if (!e) return 0;
+    const std::string v(e);
+    return v == "spec" ? 1 : v == "lane" ? 2 : v == "wave" ? 3 : 0;
 }
 
 // Topology-specialised kernels are used unless SSA_SPECIALIZE=0, for networks
@@ -271,64 +293,101 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
 
     ssa_net *net = new ssa_net();
     net->n_networks = nn;
+    auto bail = [&](ssa_status st, const std::string &m) {
+        ssa_net_destroy(net);
+        return fail(st, m);
+    };
+
+    // ---- validation and the execution plan -------------------------------
+    enum { kSpec = 1, kLane = 2, kWave = 3 };
+    int max_M = 0, max_N = 0;
+    bool all_spec_fit = true, all_lane_fit = true;
+    std::vector<std::string> srcs(nn);
+    std::map<std::string, SpecKernels> spec_kernels;
+    {
+        int64_t roff = 0, soff = 0, ooff = 0;
+        for (int n = 0; n < nn; ++n) {
+            const int N = d->n_species[n], M = d->n_reactions[n], P = d->n_params[n], B = d->n_traj[n];
+            const int nob = d->n_obs[n];
+            const std::string tag = "network " + std::to_string(n);
+            if (N < 1 || M < 1 || P < 1 || B < 0 || nob < 0) return bail(SSA_EINVAL, tag + ": sizes must be positive");
+            if (nob > 4) return bail(SSA_ESHAPE, tag + ": at most 4 observed species per network");
+            if (nob > 0 && !d->obs_species) return bail(SSA_EINVAL, "obs_species is NULL");
+            if (N > 254) return bail(SSA_ESHAPE, tag + ": at most 254 species");
+            for (int j = 0; j < M; ++j) {
+                const int s1 = d->reactant[2 * (roff + j)], s2 = d->reactant[2 * (roff + j) + 1];
+                const int ri = d->rate_index[roff + j];
+                if (s1 < -1 || s1 >= N || s2 < -1 || s2 >= N || (s1 < 0 && s2 >= 0))
+                    return bail(SSA_EINVAL, tag + ": bad reactant of channel " + std::to_string(j));
+                if (ri < 0 || ri >= P) return bail(SSA_EINVAL, tag + ": rate_index out of range");
+                int cnt = 0;
+                for (int q = 0; q < N; ++q) {
+                    const int v = d->stoich[soff + (int64_t)j * N + q];
+                    if (v < -8 || v > 7) return bail(SSA_EINVAL, tag + ": change vector entry out of [-8,7]");
+                    cnt += v != 0;
+                }
+                if (cnt > 255) return bail(SSA_ESHAPE, tag + ": change vector too long");
+            }
+            for (int o = 0; o < nob; ++o) {
+                const int sp = d->obs_species[ooff + o];
+                if (sp < 0 || sp >= N) return bail(SSA_EINVAL, tag + ": observed species out of range");
+            }
+            max_M = std::max(max_M, M);
+            max_N = std::max(max_N, N);
+            if (N > kSpecMaxSpecies || M > kSpecMaxChannels) all_spec_fit = false;
+            if (lane_class_for(N, M) < 0) all_lane_fit = false;
+            if (all_spec_fit) {
+                srcs[n] = spec_source(N, M, d->reactant + 2 * roff, d->rate_index + roff, d->stoich + soff, nob,
+                                      d->obs_species ? d->obs_species + ooff : nullptr);
+                spec_kernels.emplace(srcs[n], SpecKernels());
+                if ((int)spec_kernels.size() > kSpecMaxTopologies) all_spec_fit = false;
+            }
+            roff += M;
+            soff += (int64_t)M * N;
+            ooff += nob;
+        }
+    }
+    const bool wave_fit = max_N <= kWaveMaxSpecies && wave_class_for(max_M) >= 0;
+    int mode = forced_exec_mode();
+    if (mode == kSpec && !all_spec_fit) return bail(SSA_ESHAPE, "specialised lane mode does not fit this batch");
+    if (mode == kLane && !all_lane_fit) return bail(SSA_ESHAPE, "generic lane mode does not fit this batch");
+    if (mode == kWave && !wave_fit) return bail(SSA_ESHAPE, "wave mode does not fit this batch");
+    if (mode == 0) {
+        if (all_spec_fit && specialisation_enabled()) mode = kSpec;
+        else if (all_lane_fit && nn <= 64) mode = kLane;
+        else if (wave_fit) mode = kWave;
+        else if (all_lane_fit) mode = kLane;
+        else return bail(SSA_ESHAPE, "no execution mode fits this batch (at most 64 species and 511 channels)");
+    }
+    if (mode == kSpec) {
+        for (auto &kv : spec_kernels) {
+            std::string log;
+            if (!spec_compile(kv.first, &kv.second, &log)) return bail(SSA_EHIP, log);
+        }
+    }
+    const int wave_cls = mode == kWave ? wave_class_for(max_M) : -1;
+
+    // ---- device tables ---------------------------------------------------
     std::vector<ReactDesc> rd;
     std::vector<uint32_t> rows;
-    std::vector<int32_t> csr, obs_sp, pmap_off, pmap_ch, param_net;
-    std::vector<LaneItem> items[kLaneClassCount];
+    std::vector<int32_t> csr, obs_sp, pmap_off, pmap_ch, param_net, inc_ptr, inc_ent;
+    std::vector<LaneItem> items[kLaneClassCount], wave_items;
     std::map<std::string, std::vector<LaneItem>> spec_items;
-    std::map<std::string, SpecKernels> spec_kernels;
-    const bool try_spec = specialisation_enabled();
     int64_t roff = 0, soff = 0, ooff = 0;
-    auto bail = [&](ssa_status s, const std::string &m) {
-        ssa_net_destroy(net);
-        return fail(s, m);
-    };
     for (int n = 0; n < nn; ++n) {
         const int N = d->n_species[n], M = d->n_reactions[n], P = d->n_params[n], B = d->n_traj[n];
         const int nob = d->n_obs[n];
-        if (N < 1 || M < 1 || P < 1 || B < 0 || nob < 0)
-            return bail(SSA_EINVAL, "network " + std::to_string(n) + ": sizes must be positive");
-        if (nob > 4) return bail(SSA_ESHAPE, "at most 4 observed species per network");
-        if (nob > 0 && !d->obs_species) return bail(SSA_EINVAL, "obs_species is NULL");
-        const int cls_generic = lane_class_for(N, M);
-        std::string src;
-        bool use_spec = false;
-        if (try_spec && N <= kSpecMaxSpecies && M <= kSpecMaxChannels) {
-            bool ok_tables = true;
-            for (int q = 0; q < M * N; ++q) {
-                const int v = d->stoich[soff + q];
-                if (v < -8 || v > 7) ok_tables = false;
-            }
-            if (ok_tables) {
-                src = spec_source(N, M, d->reactant + 2 * roff, d->rate_index + roff, d->stoich + soff, nob,
-                                  d->obs_species ? d->obs_species + ooff : nullptr);
-                if (spec_kernels.count(src)) {
-                    use_spec = true;
-                } else if ((int)spec_kernels.size() < kSpecMaxTopologies) {
-                    SpecKernels k;
-                    std::string log;
-                    if (spec_compile(src, &k, &log)) {
-                        spec_kernels[src] = k;
-                        use_spec = true;
-                    } else if (cls_generic < 0) {
-                        return bail(SSA_EHIP, "network " + std::to_string(n) + ": " + log);
-                    }
-                }
-            }
-        }
-        const int cls = use_spec ? kLane_N16_M32 : cls_generic;
-        if (!use_spec && cls < 0)
-            return bail(SSA_ESHAPE, "network " + std::to_string(n) + " (N=" + std::to_string(N) +
-                                        ", M=" + std::to_string(M) + ") exceeds the lane-mode bounds");
+        const int cls = mode == kLane ? lane_class_for(N, M) : -1;
         NetDev nd;
         std::memset(&nd, 0, sizeof(nd));
         nd.N = N; nd.M = M; nd.P = P; nd.n_obs = nob; nd.B = B;
-        const int nmax = use_spec ? N : lane_class_nmax(cls);
+        const int nmax = mode == kLane ? lane_class_nmax(cls) : N;
         nd.wpr = (nmax + 7) / 8;
         nd.react_off = (int32_t)rd.size();
         nd.rows_off = (int32_t)rows.size();
         nd.obs_sp_off = (int32_t)obs_sp.size();
-        nd.mode = use_spec ? -1 : cls;
+        nd.mode = mode == kLane ? cls : mode == kSpec ? -1 : -2;
+        nd.inc_off = (int32_t)inc_ptr.size();
         nd.traj_off = net->traj_total;
         nd.state_off = net->state_total;
         nd.param_off = net->param_total;
@@ -336,55 +395,58 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         nd.part_off = net->part_total;
         nd.ppt_off = net->ppt_total;
         nd.t_obs = d->t_obs ? d->t_obs[n] : 0.0;
+        std::vector<std::vector<int32_t>> incid(N);
         for (int j = 0; j < M; ++j) {
             const int s1 = d->reactant[2 * (roff + j)], s2 = d->reactant[2 * (roff + j) + 1];
-            const int ri = d->rate_index[roff + j];
-            if (s1 < -1 || s1 >= N || s2 < -1 || s2 >= N || (s1 < 0 && s2 >= 0))
-                return bail(SSA_EINVAL, "network " + std::to_string(n) + ": bad reactant of channel " +
-                                            std::to_string(j));
-            if (ri < 0 || ri >= P)
-                return bail(SSA_EINVAL, "network " + std::to_string(n) + ": rate_index out of range");
             ReactDesc r;
             std::memset(&r, 0, sizeof(r));
             r.s1 = (uint8_t)(s1 < 0 ? kNoSpecies : s1);
             r.s2 = (uint8_t)(s2 < 0 ? kNoSpecies : s2);
             r.homodimer = (uint8_t)(s1 >= 0 && s1 == s2);
-            r.rate = ri;
+            r.rate = d->rate_index[roff + j];
             r.mult = r.homodimer ? 0.5f : 1.0f;
             const int beg = (int)csr.size();
             std::vector<uint32_t> packed(nd.wpr, 0u);
-            for (int s = 0; s < N; ++s) {
-                const int v = d->stoich[soff + (int64_t)j * N + s];
-                if (v < -8 || v > 7)
-                    return bail(SSA_EINVAL, "network " + std::to_string(n) + ": change vector entry out of [-8,7]");
+            for (int q = 0; q < N; ++q) {
+                const int v = d->stoich[soff + (int64_t)j * N + q];
                 if (v != 0) {
-                    csr.push_back((int32_t)((uint32_t)s | ((uint32_t)(v & 0xFFFF) << 16)));
-                    packed[s / 8] |= (uint32_t)(v & 0xF) << (4 * (s % 8));
+                    csr.push_back((int32_t)((uint32_t)q | ((uint32_t)(v & 0xFFFF) << 16)));
+                    if (q < nmax) packed[q / 8] |= (uint32_t)(v & 0xF) << (4 * (q % 8));
                 }
             }
-            const int cnt = (int)csr.size() - beg;
-            if (cnt > 255) return bail(SSA_ESHAPE, "change vector too long");
-            r.csr = beg | (cnt << 24);
+            r.csr = beg | (((int)csr.size() - beg) << 24);
             rd.push_back(r);
             rows.insert(rows.end(), packed.begin(), packed.end());
+            // channel j contributes coef*A2 to dlambda[s1] (role 1) and coef*A1 to dlambda[s2] (role 2)
+            if (s1 >= 0) incid[s1].push_back(j | (1 << 16));
+            if (s2 >= 0) incid[s2].push_back(j | (2 << 16));
         }
-        for (int o = 0; o < nob; ++o) {
-            const int s = d->obs_species[ooff + o];
-            if (s < 0 || s >= N) return bail(SSA_EINVAL, "observed species out of range");
-            obs_sp.push_back(s);
+        for (int q = 0; q < N; ++q) {
+            inc_ptr.push_back((int32_t)inc_ent.size());
+            inc_ent.insert(inc_ent.end(), incid[q].begin(), incid[q].end());
         }
+        inc_ptr.push_back((int32_t)inc_ent.size());
+        for (int o = 0; o < nob; ++o) obs_sp.push_back(d->obs_species[ooff + o]);
         // parameter -> channels map for the gradient reduction
-        for (int p = 0; p < P; ++p) {
+        for (int pp = 0; pp < P; ++pp) {
             pmap_off.push_back((int32_t)pmap_ch.size());
             for (int j = 0; j < M; ++j)
-                if (d->rate_index[roff + j] == p) pmap_ch.push_back(j);
+                if (d->rate_index[roff + j] == pp) pmap_ch.push_back(j);
             param_net.push_back(n);
         }
-        for (int first = 0; first < B; first += 64) {
-            LaneItem it;
-            it.net = n; it.first = first; it.count = std::min(64, B - first); it.pad = M;
-            if (use_spec) spec_items[src].push_back(it);
-            else items[cls].push_back(it);
+        if (mode == kWave) {
+            for (int i = 0; i < B; ++i) {
+                LaneItem it;
+                it.net = n; it.first = i; it.count = 1; it.pad = M;
+                wave_items.push_back(it);
+            }
+        } else {
+            for (int first = 0; first < B; first += 64) {
+                LaneItem it;
+                it.net = n; it.first = first; it.count = std::min(64, B - first); it.pad = M;
+                if (mode == kSpec) spec_items[srcs[n]].push_back(it);
+                else items[cls].push_back(it);
+            }
         }
         net->traj_total += B;
         net->state_total += (int64_t)N * B;
@@ -399,13 +461,12 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         ooff += nob;
     }
     pmap_off.push_back((int32_t)pmap_ch.size());
-    if (net->traj_total > 0xFFFFFFFFll) return bail(SSA_ESHAPE, "too many trajectories");
-    // more channels first: longer work items start early
-    for (auto &kv : spec_items)
-        std::stable_sort(kv.second.begin(), kv.second.end(),
-                         [](const LaneItem &a, const LaneItem &b) { return a.pad > b.pad; });
-    for (auto &v : items)
-        std::stable_sort(v.begin(), v.end(), [](const LaneItem &a, const LaneItem &b) { return a.pad > b.pad; });
+    if (net->traj_total > 0x7FFFFFFFll) return bail(SSA_ESHAPE, "too many trajectories");
+    // longest work first (channels are the per-step cost)
+    auto by_cost = [](const LaneItem &a, const LaneItem &b) { return a.pad > b.pad; };
+    for (auto &kv : spec_items) std::stable_sort(kv.second.begin(), kv.second.end(), by_cost);
+    for (auto &v : items) std::stable_sort(v.begin(), v.end(), by_cost);
+    std::stable_sort(wave_items.begin(), wave_items.end(), by_cost);
 
     hipError_t e = hipGetDevice(&net->device);
     if (e == hipSuccess) e = upload(&net->nets_d, net->nets_h);
@@ -416,6 +477,8 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     if (e == hipSuccess) e = upload(&net->pmap_off_d, pmap_off);
     if (e == hipSuccess) e = upload(&net->pmap_ch_d, pmap_ch.empty() ? std::vector<int32_t>{0} : pmap_ch);
     if (e == hipSuccess) e = upload(&net->param_net_d, param_net);
+    if (e == hipSuccess) e = upload(&net->inc_ptr_d, inc_ptr);
+    if (e == hipSuccess) e = upload(&net->inc_ent_d, inc_ent.empty() ? std::vector<int32_t>{0} : inc_ent);
     for (auto &kv : spec_items) {
         if (e != hipSuccess) break;
         ssa_net::Group gr;
@@ -433,14 +496,24 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         e = upload(&gr.items_d, items[c]);
         net->groups.push_back(gr);
     }
+    if (e == hipSuccess && !wave_items.empty()) {
+        ssa_net::Group gr;
+        gr.wave_class = wave_cls;
+        gr.n_items = (int)wave_items.size();
+        const int per_wave = 64 / wave_class_lanes(wave_cls);
+        const int64_t blocks_needed = ((int64_t)gr.n_items + 4 * per_wave - 1) / (4 * per_wave);
+        gr.wave_blocks = (int)std::min<int64_t>(blocks_needed, 2048);
+        e = upload(&gr.items_d, wave_items);
+        net->groups.push_back(gr);
+    }
     if (e == hipSuccess) e = hipMalloc((void **)&net->flags_d, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(net->flags_d, 0, sizeof(uint32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        ssa_status s = hip_fail(e, "ssa_net_create");
+        ssa_status st = hip_fail(e, "ssa_net_create");
         std::string m = g_last_error;
         ssa_net_destroy(net);
-        return fail(s, m);
+        return fail(st, m);
     }
     *out = net;
     return SSA_OK;
@@ -457,6 +530,8 @@ void ssa_net_destroy(ssa_net *net)
     (void)hipFree(net->pmap_off_d);
     (void)hipFree(net->pmap_ch_d);
     (void)hipFree(net->param_net_d);
+    (void)hipFree(net->inc_ptr_d);
+    (void)hipFree(net->inc_ent_d);
     for (auto &gr : net->groups) (void)hipFree(gr.items_d);
     (void)hipFree(net->flags_d);
     delete net;
@@ -530,6 +605,7 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
         p.tape_bits = L.tape_words ? L.tape_bits : 0;
         p.tape_words = L.tape_words;
     }
+    p.work_counter = (uint32_t *)((char *)work + 64);
     p.ties = reinterpret_cast<TieRec *>(ties);
     p.n_ties = n_ties;
     p.tie_cap = (uint32_t)cfg->tie_capacity;
@@ -571,6 +647,7 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
     p.tape_bits = L.tape_words ? L.tape_bits : 0;
     p.tape_words = L.tape_words;
     p.partials = (double *)((char *)work + kWorkHeader);
+    p.work_counter = (uint32_t *)((char *)work + 64);
     s = launch_all_classes(net, p, true, stream);
     if (s != SSA_OK) return s;
     hipError_t e = launch_reduce_params(net->nets_d, net->n_networks, net->pmap_off_d, net->pmap_ch_d,

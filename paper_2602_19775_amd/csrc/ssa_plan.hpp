@@ -44,6 +44,8 @@ struct NetDev {
     int32_t rows_off;    // first packed change-vector word
     int32_t obs_sp_off;  // first observed-species entry
     int32_t mode;        // execution class chosen at plan time
+    int32_t inc_off;     // first species-incidence offset (wave mode: N+1 entries)
+    int32_t pad0;
     int64_t traj_off;    // sum of B over earlier networks
     int64_t state_off;   // sum of N*B
     int64_t param_off;   // sum of P
@@ -125,6 +127,11 @@ struct RunParams {
     int64_t traj_total;
     float temperature;
     int32_t recompute;      // backward: recover choices by re-running segments
+
+    // wave mode: species -> (channel, role) incidence lists and the work counter
+    const int32_t *inc_ptr;
+    const int32_t *inc_ent;
+    uint32_t *work_counter;
 };
 
 }  // namespace ssa

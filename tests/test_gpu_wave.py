@@ -1,0 +1,174 @@
+"""Parity of the wave-mode kernels (one trajectory per group of lanes, one
+persistent launch for a whole batch of networks) with the FP64 oracle."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_19775_amd import workloads as W
+
+from test_gpu_parity import (_ties_for_oracle, _x0, assert_forward_parity, assert_grad_parity, edge_safe,
+                             run_pair)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_19775_amd import ssa as m
+    m.lib()
+    return m
+
+
+@pytest.fixture
+def wave_mode():
+    old = os.environ.get("SSA_EXEC")
+    os.environ["SSA_EXEC"] = "wave"
+    yield
+    if old is None:
+        del os.environ["SSA_EXEC"]
+    else:
+        os.environ["SSA_EXEC"] = old
+
+
+def run_batch(ssa, nets, B, cfg, d_obs_fn=None, bwd_mode="auto", t_obs=None):
+    h = ssa.Net(nets, B, t_obs=t_obs)
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    x0 = _x0(nets, B)
+    fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 16, bwd_mode=bwd_mode)
+    d_obs = None
+    ppt = None
+    if d_obs_fn is not None:
+        d_obs = d_obs_fn(h)
+        dp, ppt = ssa.backward(h, cfg, th, x0, fwd, torch.tensor(d_obs, device="cuda"), per_traj=True)
+        ppt = ppt.cpu().numpy()
+    torch.cuda.synchronize()
+    assert ssa.device_status(h) == 0
+    return h, fwd, d_obs, ppt
+
+
+def check_batch(h, fwd, nets, B, cfg, d_obs=None, ppt=None):
+    ties = fwd.tie_records()
+    xf = fwd.x_final.cpu().numpy()
+    sd = fwd.steps_done.cpu().numpy()
+    tf = fwd.t_final.cpu().numpy()
+    obs = fwd.obs.cpu().numpy()
+    bins = cfg.obs_kind == W.OBS_BINS
+    for n, (net, b) in enumerate(zip(nets, B)):
+        L = h.layout(n, cfg.obs_kind, cfg.n_bins)
+        nob = len(net.obs_species)
+        ov = _ties_for_oracle([t for t in ties if L.traj_offset <= t["traj"] < L.traj_offset + b], L.traj_offset)
+        dob = None
+        if d_obs is not None:
+            blk = d_obs[L.obs_offset: L.obs_offset + (cfg.n_bins if bins else 1) * nob * b]
+            dob = (blk.reshape(cfg.n_bins, nob, b).transpose(2, 0, 1) if bins else blk.reshape(nob, b).T)
+        r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=L.traj_offset + np.arange(b), ties=ov, d_obs=dob)
+        ob = obs[L.obs_offset: L.obs_offset + (cfg.n_bins if bins else 1) * nob * b]
+        gpu = {"x_final": xf[L.state_offset: L.state_offset + net.n_species * b].reshape(net.n_species, b).T,
+               "t_final": tf[L.traj_offset: L.traj_offset + b],
+               "steps_done": sd[L.traj_offset: L.traj_offset + b],
+               "obs": ob.reshape(cfg.n_bins, nob, b).transpose(2, 0, 1) if bins else ob.reshape(nob, b).T}
+        ids = np.arange(b)
+        assert_forward_parity(gpu, r, ids, cfg)
+        if ppt is not None:
+            g = ppt[L.ppt_offset: L.ppt_offset + net.n_params * b].reshape(net.n_params, b).T
+            keep = edge_safe(gpu, r, ids) if bins else np.ones(b, bool)
+            assert keep.mean() > 0.7
+            assert_grad_parity(g, r.grad, keep, rtol=1e-5)
+
+
+def test_wave_small_batch_forward(ssa, wave_mode):
+    nets = W.random_network_batch(6, seed=5, n_range=(4, 16), m_range=(8, 32))
+    B = [64, 37, 128, 1, 90, 65]
+    cfg = W.RunConfig(seed=9, n_steps=400, obs_kind=W.OBS_FINAL)
+    h, fwd, _, _ = run_batch(ssa, nets, B, cfg)
+    check_batch(h, fwd, nets, B, cfg)
+
+
+def test_wave_large_networks_forward(ssa, wave_mode):
+    nets = W.random_network_batch(5, seed=21, n_range=(40, 64), m_range=(200, 256))
+    B = [17, 8, 33, 5, 12]
+    cfg = W.RunConfig(seed=4, n_steps=300, obs_kind=W.OBS_FINAL)
+    h, fwd, _, _ = run_batch(ssa, nets, B, cfg)
+    check_batch(h, fwd, nets, B, cfg)
+
+
+@pytest.mark.parametrize("mode", ["tape", "recompute"])
+def test_wave_gradients_random_batch(ssa, wave_mode, mode):
+    nets = W.random_network_batch(4, seed=13, n_range=(4, 24), m_range=(8, 100))
+    B = [40, 23, 64, 9]
+    pilot = [oracle.run(n, W.RunConfig(seed=1, n_steps=300, purpose=2), n.theta0, n.x0,
+                        traj_ids=np.arange(8)) for n in nets]
+    t_obs = [float(np.min(r.t_final)) * 0.8 for r in pilot]
+    cfg = W.RunConfig(seed=3, n_steps=300, obs_kind=W.OBS_BINS, n_bins=4, t_obs=1.0, temperature=0.5,
+                      ckpt_every=64)
+    g = np.random.default_rng(8)
+
+    def d_obs_fn(h):
+        return g.normal(size=h.obs_total(cfg.obs_kind, cfg.n_bins))
+
+    h, fwd, d_obs, ppt = run_batch(ssa, nets, B, cfg, d_obs_fn, bwd_mode=mode, t_obs=t_obs)
+    check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt)
+
+
+def check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt):
+    """check_batch with a per-network observation window (the oracle runs
+    network by network, each with its own window)."""
+    ties = fwd.tie_records()
+    xf = fwd.x_final.cpu().numpy()
+    sd = fwd.steps_done.cpu().numpy()
+    tf = fwd.t_final.cpu().numpy()
+    obs = fwd.obs.cpu().numpy()
+    for n, (net, b) in enumerate(zip(nets, B)):
+        c = cfg.replace(t_obs=t_obs[n])
+        L = h.layout(n, c.obs_kind, c.n_bins)
+        nob = len(net.obs_species)
+        ov = _ties_for_oracle([t for t in ties if L.traj_offset <= t["traj"] < L.traj_offset + b], L.traj_offset)
+        blk = d_obs[L.obs_offset: L.obs_offset + c.n_bins * nob * b]
+        dob = blk.reshape(c.n_bins, nob, b).transpose(2, 0, 1)
+        r = oracle.run(net, c, net.theta0, net.x0, traj_ids=L.traj_offset + np.arange(b), ties=ov, d_obs=dob)
+        ob = obs[L.obs_offset: L.obs_offset + c.n_bins * nob * b]
+        gpu = {"x_final": xf[L.state_offset: L.state_offset + net.n_species * b].reshape(net.n_species, b).T,
+               "t_final": tf[L.traj_offset: L.traj_offset + b],
+               "steps_done": sd[L.traj_offset: L.traj_offset + b],
+               "obs": ob.reshape(c.n_bins, nob, b).transpose(2, 0, 1)}
+        ids = np.arange(b)
+        assert_forward_parity(gpu, r, ids, c)
+        gg = ppt[L.ppt_offset: L.ppt_offset + net.n_params * b].reshape(net.n_params, b).T
+        keep = edge_safe(gpu, r, ids)
+        assert keep.mean() > 0.7
+        assert_grad_parity(gg, r.grad, keep, rtol=1e-5)
+
+
+def test_wave_dimer_gradients(ssa, wave_mode):
+    net = W.dimerization_2a()
+    B = 200
+    cfg = W.RunConfig(seed=1, n_steps=1500, obs_kind=W.OBS_BINS, n_bins=20, t_obs=300.0,
+                      temperature=0.5, ckpt_every=64)
+    g = np.random.default_rng(2)
+    d_obs = g.normal(size=(cfg.n_bins, 1, B))
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs)
+    assert_forward_parity(gpu, r, ids, cfg)
+    keep = edge_safe(gpu, r, ids)
+    assert_grad_parity(gpu["ppt"], r.grad, keep)
+
+
+def test_wave_backward_deterministic(ssa, wave_mode):
+    nets = W.random_network_batch(3, seed=2, n_range=(8, 32), m_range=(40, 120))
+    B = [50, 50, 50]
+    cfg = W.RunConfig(seed=5, n_steps=200, obs_kind=W.OBS_FINAL, ckpt_every=32)
+    h = ssa.Net(nets, B)
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    x0 = _x0(nets, B)
+    d = torch.randn(h.obs_total(cfg.obs_kind, 0), dtype=torch.float64, device="cuda")
+    outs = []
+    for _ in range(2):
+        f = ssa.forward(h, cfg, th, x0)
+        dp, ppt = ssa.backward(h, cfg, th, x0, f, d, per_traj=True)
+        outs.append((f.x_final.clone(), dp.clone(), ppt.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
