@@ -89,9 +89,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator"],
+    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator", "uneven"],
                     help="dimer: 2A<->A2, 65,536 x 10,000 steps (default); "
-                         "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps")
+                         "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps; "
+                         "uneven: 4,096 random networks x 256 trajectories x 5,000 steps")
     ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
     ap.add_argument("--n-traj", type=int, default=65536)
     ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")
@@ -125,23 +126,33 @@ def main():
         print(json.dumps({"copy_bytes": n * 4, "launches": 3}))
         return
 
-    if args.workload == "dimer":
-        wl = W.dimer_fwdbwd_64k(args.n_traj, args.n_steps or 10000)
+    if args.workload in ("dimer", "oscillator"):
+        if args.workload == "dimer":
+            wl = W.dimer_fwdbwd_64k(args.n_traj, args.n_steps or 10000)
+        else:
+            wl = W.oscillator_fwdbwd_64k(args.n_traj, args.n_steps or 200000)
+        cfg = wl.cfg.replace(ckpt_every=args.ckpt_every or wl.cfg.ckpt_every)
+        nets, Bs, name = [wl.net], [wl.n_traj], wl.name
+        h = ssa.Net(nets, Bs, t_obs=[cfg.t_obs])
+        theta = torch.tensor(wl.net.theta0, device=dev)
+        x0 = torch.tensor(wl.x0_soa().reshape(-1), device=dev)
+        if args.workload == "dimer":
+            theta_t = torch.tensor(np.log(np.array(W.DIMER_TARGET_RATES)).astype(np.float32), device=dev)
+        else:
+            theta_t = torch.tensor(wl.extra["target_net"].theta0, device=dev)
     else:
-        wl = W.oscillator_fwdbwd_64k(args.n_traj, args.n_steps or 200000)
-    cfg = wl.cfg.replace(ckpt_every=args.ckpt_every or wl.cfg.ckpt_every)
-    net, B = wl.net, wl.n_traj
+        bw = W.uneven_batch(n_steps=args.n_steps or 5000)
+        cfg = bw.cfg.replace(ckpt_every=args.ckpt_every or bw.cfg.ckpt_every)
+        nets, Bs, name = bw.nets, bw.n_traj, bw.name
+        h = ssa.Net(nets, Bs)
+        theta = torch.tensor(bw.theta(), device=dev)
+        x0 = torch.tensor(bw.x0_packed(), device=dev)
+        theta_t = torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device=dev)
+    net, B = nets[0], Bs[0]
     nb, nob = cfg.n_bins, len(net.obs_species)
-    h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
-    theta = torch.tensor(net.theta0, device=dev)
-    x0 = torch.tensor(wl.x0_soa().reshape(-1), device=dev)
 
     # targets: a seeded run at the target rates (separate stream purpose), untimed
     tcfg = cfg.replace(purpose=W.PURPOSE_TARGET)
-    if args.workload == "dimer":
-        theta_t = torch.tensor(np.log(np.array(W.DIMER_TARGET_RATES)).astype(np.float32), device=dev)
-    else:
-        theta_t = torch.tensor(wl.extra["target_net"].theta0, device=dev)
     tf = ssa.forward(h, tcfg, theta_t, x0, keep_ckpt=False, tie_capacity=0)
     if args.workload == "dimer":
         tm, tv = losses.bin_moments(tf.obs, nb, nob, B)
@@ -149,16 +160,23 @@ def main():
 
         def loss_fn(obs):
             return losses.moment_mse(obs, tm, tv, nb, nob, B)
-    else:
+    elif args.workload == "oscillator":
         tac = losses.mean_autocorrelation(tf.obs, nb, B, 64).clone()
 
         def loss_fn(obs):
             return losses.autocorrelation_mse(obs, tac, nb, B, 64)
+    else:
+        # final counts, [sum n_obs][256]: ensemble mean of every observed species
+        rows = sum(len(n.obs_species) for n in nets)
+        tmean = tf.obs[: rows * B].view(rows, B).mean(dim=1).clone()
+
+        def loss_fn(obs):
+            return ((obs[: rows * B].view(rows, B).mean(dim=1) - tmean) ** 2).mean()
     del tf
 
-    tie_cap = 1 << 16 if args.workload == "dimer" else 1 << 22
+    tie_cap = {"dimer": 1 << 16, "oscillator": 1 << 22, "uneven": 1 << 23}[args.workload]
     bufs = ssa.forward(h, cfg, theta, x0, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
-    d_params = torch.empty(net.n_params, dtype=torch.float32, device=dev)
+    d_params = torch.empty(h.param_total, dtype=torch.float32, device=dev)
 
     def step(record=None):
         if record is not None:
@@ -207,36 +225,48 @@ def main():
     assert ssa.device_status(h) == 0
 
     # gradient relative error against the oracle on a sample of trajectories
+    # (of the first network of the batch)
     import oracle
     obs = bufs.obs.detach().requires_grad_(True)
     loss = loss_fn(obs)
     (d_obs,) = torch.autograd.grad(loss, obs)
     _, ppt = ssa.backward(h, cfg, theta, x0, bufs, d_obs, per_traj=True)
-    n_sample = 64 if args.workload == "dimer" else 16
+    n_sample = {"dimer": 64, "oscillator": 16, "uneven": 64}[args.workload]
     sample = np.arange(0, B, max(1, B // n_sample))[:n_sample]
-    dob = d_obs.cpu().numpy().reshape(nb, nob, B).transpose(2, 0, 1)[sample]
+    bins = cfg.obs_kind == W.OBS_BINS
+    dnp = d_obs.cpu().numpy()
+    dob = (dnp[: nb * nob * B].reshape(nb, nob, B).transpose(2, 0, 1)[sample] if bins
+           else dnp[: nob * B].reshape(nob, B).T[sample])
     ties = bufs.tie_records()
     idx = {int(q): k for k, q in enumerate(sample)}
     ov = [(idx[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
           for t in ties if int(t["traj"]) in idx]
     r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=sample, ties=ov, d_obs=dob)
-    g_gpu = ppt.cpu().numpy().reshape(net.n_params, B).T[sample].astype(np.float64)
-    xf = bufs.x_final.cpu().numpy().reshape(net.n_species, B).T[sample]
+    g_gpu = ppt.cpu().numpy()[: net.n_params * B].reshape(net.n_params, B).T[sample].astype(np.float64)
+    xf = bufs.x_final.cpu().numpy()[: net.n_species * B].reshape(net.n_species, B).T[sample]
     counts_exact = bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
     grad_rel_err = float(np.linalg.norm(g_gpu.sum(0) - r.grad.sum(0)) / np.linalg.norm(r.grad.sum(0)))
 
     # roofline of the dominant kernel (ALU-bound): algorithmic operations of a
     # launch weighted by their measured issue cost, over the kernel's time,
     # against the full-rate issue limit of the vector ALUs
-    nnz = int(np.count_nonzero(net.stoich))
-    cost = measure_issue_costs()
     inv2 = abs(1.0 / cfg.temperature - 2.0) < 1e-12
-    ops_b = alu_ops_per_step(net.n_reactions, net.n_species, nnz, nob, True, inv2)
-    ops_f = alu_ops_per_step(net.n_reactions, net.n_species, nnz, nob, False)
+    cost = measure_issue_costs()
+    wsum = float(sum(Bs))
+
+    def avg_ops(backward):
+        tot = {}
+        for n_, b_ in zip(nets, Bs):
+            o = alu_ops_per_step(n_.n_reactions, n_.n_species, int(np.count_nonzero(n_.stoich)),
+                                 len(n_.obs_species), backward, inv2)
+            for k_, v_ in o.items():
+                tot[k_] = tot.get(k_, 0.0) + v_ * b_ / wsum
+        return tot
+    ops_b, ops_f = avg_ops(True), avg_ops(False)
     if bwd_ms >= fwd_ms:
-        dom, dom_ms, ops = "ssa_spec_bwd", bwd_ms, ops_b
+        dom, dom_ms, ops = "backward", bwd_ms, ops_b
     else:
-        dom, dom_ms, ops = "ssa_spec_fwd", fwd_ms, ops_f
+        dom, dom_ms, ops = "forward", fwd_ms, ops_f
     per_step = slots(ops, cost)
     achieved = fired * per_step / (dom_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
@@ -248,15 +278,15 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        n_try = 32 if args.workload == "dimer" else 4
+        n_try = {"dimer": 32, "oscillator": 4, "uneven": 16}[args.workload]
         c0 = time.perf_counter()
-        oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n_try), d_obs=np.zeros((n_try, nb, nob)),
+        oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n_try), d_obs=np.zeros((n_try, nb, nob) if bins else (n_try, nob)),
                    n_threads=threads)
         dt = time.perf_counter() - c0
         n_cpu = int(min(B, max(n_try, n_try * args.cpu_seconds / max(dt, 1e-3))))
         c0 = time.perf_counter()
         rc = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n_cpu),
-                        d_obs=np.zeros((n_cpu, nb, nob)), n_threads=threads)
+                        d_obs=np.zeros((n_cpu, nb, nob) if bins else (n_cpu, nob)), n_threads=threads)
         dt = time.perf_counter() - c0
         cpu = {"value": float(rc.steps_done.sum() / dt), "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{n_cpu} of the {B} trajectories, full {cfg.n_steps} steps, forward+adjoint in FP64"}
@@ -265,7 +295,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl.name, "n_traj": B, "steps_per_traj": cfg.n_steps, "n_bins": nb,
+        "config": {"workload": name, "n_traj": int(sum(Bs)), "n_networks": len(nets), "steps_per_traj": cfg.n_steps, "n_bins": nb,
                    "t_obs": cfg.t_obs, "temperature": cfg.temperature, "ckpt_every": cfg.ckpt_every,
                    "bwd_mode": args.bwd_mode},
         "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate,

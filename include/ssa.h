@@ -104,7 +104,23 @@ typedef struct ssa_network_desc {
     const int8_t *stoich;          /* [sum M_n * N_n] */
     const int32_t *obs_species;    /* [sum n_obs_n] */
     const double *t_obs;           /* [n_networks] bin observations split [0, t_obs[n]] */
+    int32_t exec_mode;             /* SSA_EXEC_*: how trajectories map onto lanes */
+    int32_t wave_split;            /* wave mode: -1 library's choice, 0 one persistent launch
+                                      for the whole batch, 1 one launch per lane-group width */
 } ssa_network_desc;
+
+/* Execution modes.
+ *   SSA_EXEC_SPEC: one trajectory per lane, kernels compiled at plan time for
+ *                  each network topology (channel tables become constants);
+ *                  networks up to 64 species and 64 channels, at most 16
+ *                  distinct topologies per handle.
+ *   SSA_EXEC_LANE: one trajectory per lane, generic kernels reading the tables
+ *                  (up to 16 species and 32 channels).
+ *   SSA_EXEC_WAVE: one trajectory per group of 8-64 lanes sharing its channels
+ *                  (up to 64 species and 511 channels); persistent launches
+ *                  pulling trajectories from a work counter in cost order.
+ *   SSA_EXEC_AUTO: the library picks (SPEC, else LANE for small batches, else WAVE). */
+enum { SSA_EXEC_AUTO = 0, SSA_EXEC_SPEC = 1, SSA_EXEC_LANE = 2, SSA_EXEC_WAVE = 3 };
 
 typedef struct ssa_net ssa_net;    /* opaque handle: device-resident tables */
 

@@ -7,7 +7,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
 #include <map>
 #include <cstdio>
 #include <cstring>
@@ -75,6 +74,7 @@ struct ssa_net {
         int lane_class = -1;
         int wave_class = -1;     // persistent wave-mode launch
         int wave_blocks = 0;
+        int tab_m = 0, tab_nnz = 0, tab_inc = 0;   // per-group LDS table capacities
         SpecKernels kernels;
         LaneItem *items_d = nullptr;
         int n_items = 0;
@@ -209,6 +209,10 @@ ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hi
         p.n_items = gr.n_items;
         hipError_t e;
         if (gr.wave_class >= 0) {
+            p.tab_m = gr.tab_m;
+            p.tab_nnz = gr.tab_nnz;
+            p.tab_inc = gr.tab_inc;
+            p.tab_words = gr.tab_m + gr.tab_nnz + (kWaveMaxSpecies + 1) + gr.tab_inc;
             // the persistent kernel pulls work from a counter that starts at 0
             e = launch_fill_u32(p.work_counter, 1, 0u, stream);
             if (e == hipSuccess) e = wave_launch(gr.wave_class, p, backward, gr.wave_blocks, stream);
@@ -220,27 +224,16 @@ ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hi
     return SSA_OK;
 }
 
-// Execution mode: SSA_EXEC=spec|lane|wave forces one (for tests and tuning).
-int forced_exec_mode()
-{
-    const char *e = std::getenv("SSA_EXEC");
-    if (!e) return 0;
-    const std::string v(e);
-    return v == "spec" ? 1 : v == "lane" ? 2 : v == "wave" ? 3 : 0;
-}
 
-// Topology-specialised kernels are used unless SSA_SPECIALIZE=0, for networks
-// small enough to keep their state in registers, and only while a batch has
-// few distinct topologies (each costs one runtime compilation).
+
+// Topology-specialised kernels are used for networks small enough to keep
+// their state in registers, and only while a batch has few distinct
+// topologies (each costs one runtime compilation).
 constexpr int kSpecMaxSpecies = 64;
 constexpr int kSpecMaxChannels = 64;
 constexpr int kSpecMaxTopologies = 16;
 
-bool specialisation_enabled()
-{
-    const char *e = std::getenv("SSA_SPECIALIZE");
-    return !(e && e[0] == '0');
-}
+
 
 }  // namespace
 
@@ -348,12 +341,13 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         }
     }
     const bool wave_fit = max_N <= kWaveMaxSpecies && wave_class_for(max_M) >= 0;
-    int mode = forced_exec_mode();
+    if (d->exec_mode < SSA_EXEC_AUTO || d->exec_mode > SSA_EXEC_WAVE) return bail(SSA_EINVAL, "unknown exec_mode");
+    int mode = d->exec_mode;
     if (mode == kSpec && !all_spec_fit) return bail(SSA_ESHAPE, "specialised lane mode does not fit this batch");
     if (mode == kLane && !all_lane_fit) return bail(SSA_ESHAPE, "generic lane mode does not fit this batch");
     if (mode == kWave && !wave_fit) return bail(SSA_ESHAPE, "wave mode does not fit this batch");
     if (mode == 0) {
-        if (all_spec_fit && specialisation_enabled()) mode = kSpec;
+        if (all_spec_fit) mode = kSpec;
         else if (all_lane_fit && nn <= 64) mode = kLane;
         else if (wave_fit) mode = kWave;
         else if (all_lane_fit) mode = kLane;
@@ -366,12 +360,18 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         }
     }
     const int wave_cls = mode == kWave ? wave_class_for(max_M) : -1;
+    // wave mode: one persistent launch for the whole batch, or one per
+    // lane-group width with each network in the narrowest group that fits it
+    // (the library's choice: one launch per width, which keeps lanes busy)
+    const bool wave_split = d->wave_split != 0;
 
     // ---- device tables ---------------------------------------------------
     std::vector<ReactDesc> rd;
     std::vector<uint32_t> rows;
     std::vector<int32_t> csr, obs_sp, pmap_off, pmap_ch, param_net, inc_ptr, inc_ent;
-    std::vector<LaneItem> items[kLaneClassCount], wave_items;
+    std::vector<LaneItem> items[kLaneClassCount];
+    std::map<int, std::vector<LaneItem>> wave_items;   // by wave class
+    std::vector<int> net_nnz, net_inc;
     std::map<std::string, std::vector<LaneItem>> spec_items;
     int64_t roff = 0, soff = 0, ooff = 0;
     for (int n = 0; n < nn; ++n) {
@@ -421,11 +421,14 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
             if (s1 >= 0) incid[s1].push_back(j | (1 << 16));
             if (s2 >= 0) incid[s2].push_back(j | (2 << 16));
         }
+        const size_t inc_before = inc_ent.size();
         for (int q = 0; q < N; ++q) {
             inc_ptr.push_back((int32_t)inc_ent.size());
             inc_ent.insert(inc_ent.end(), incid[q].begin(), incid[q].end());
         }
         inc_ptr.push_back((int32_t)inc_ent.size());
+        net_nnz.push_back((int)(csr.size() - (rd[nd.react_off].csr & 0xFFFFFF)));
+        net_inc.push_back((int)(inc_ent.size() - inc_before));
         for (int o = 0; o < nob; ++o) obs_sp.push_back(d->obs_species[ooff + o]);
         // parameter -> channels map for the gradient reduction
         for (int pp = 0; pp < P; ++pp) {
@@ -435,10 +438,11 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
             param_net.push_back(n);
         }
         if (mode == kWave) {
+            const int wc = wave_split ? wave_class_for(M) : wave_cls;
             for (int i = 0; i < B; ++i) {
                 LaneItem it;
                 it.net = n; it.first = i; it.count = 1; it.pad = M;
-                wave_items.push_back(it);
+                wave_items[wc].push_back(it);
             }
         } else {
             for (int first = 0; first < B; first += 64) {
@@ -466,7 +470,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     auto by_cost = [](const LaneItem &a, const LaneItem &b) { return a.pad > b.pad; };
     for (auto &kv : spec_items) std::stable_sort(kv.second.begin(), kv.second.end(), by_cost);
     for (auto &v : items) std::stable_sort(v.begin(), v.end(), by_cost);
-    std::stable_sort(wave_items.begin(), wave_items.end(), by_cost);
+    for (auto &kv : wave_items) std::stable_sort(kv.second.begin(), kv.second.end(), by_cost);
 
     hipError_t e = hipGetDevice(&net->device);
     if (e == hipSuccess) e = upload(&net->nets_d, net->nets_h);
@@ -496,14 +500,25 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         e = upload(&gr.items_d, items[c]);
         net->groups.push_back(gr);
     }
-    if (e == hipSuccess && !wave_items.empty()) {
+    for (auto &kv : wave_items) {
+        if (e != hipSuccess) break;
         ssa_net::Group gr;
-        gr.wave_class = wave_cls;
-        gr.n_items = (int)wave_items.size();
-        const int per_wave = 64 / wave_class_lanes(wave_cls);
+        gr.wave_class = kv.first;
+        gr.n_items = (int)kv.second.size();
+        for (const LaneItem &it : kv.second) {
+            gr.tab_m = std::max(gr.tab_m, d->n_reactions[it.net]);
+            gr.tab_nnz = std::max(gr.tab_nnz, net_nnz[it.net]);
+            gr.tab_inc = std::max(gr.tab_inc, net_inc[it.net]);
+        }
+        const int per_wave = 64 / wave_class_lanes(gr.wave_class);
+        const size_t tab_bytes = sizeof(int32_t) * (size_t)(gr.tab_m + gr.tab_nnz + kWaveMaxSpecies + 1 + gr.tab_inc);
+        const size_t lds = std::max(wave_static_lds(gr.wave_class, true), wave_static_lds(gr.wave_class, false)) +
+                           tab_bytes * 4 * per_wave;
+        if (lds > kLdsPerBlock)
+            return bail(SSA_ESHAPE, "network tables do not fit the LDS of a wave-mode block");
         const int64_t blocks_needed = ((int64_t)gr.n_items + 4 * per_wave - 1) / (4 * per_wave);
         gr.wave_blocks = (int)std::min<int64_t>(blocks_needed, 2048);
-        e = upload(&gr.items_d, wave_items);
+        e = upload(&gr.items_d, kv.second);
         net->groups.push_back(gr);
     }
     if (e == hipSuccess) e = hipMalloc((void **)&net->flags_d, sizeof(uint32_t));

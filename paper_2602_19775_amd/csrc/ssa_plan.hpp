@@ -132,6 +132,9 @@ struct RunParams {
     const int32_t *inc_ptr;
     const int32_t *inc_ent;
     uint32_t *work_counter;
+    // wave mode: per-group LDS copy of a network's change vectors and
+    // incidence lists (capacities in 32-bit words)
+    int32_t tab_m, tab_nnz, tab_inc, tab_words;
 };
 
 }  // namespace ssa

@@ -118,6 +118,41 @@ struct LaneChannels {
     }
 };
 
+// A network's tables staged in the group's LDS slot:
+//   desc[tab_m]        channel j: first entry (relative) | entry count << 24
+//   ent[tab_nnz]       change-vector entries, species | delta << 16
+//   inc_ptr[kMaxN+1]   species -> range of incidence entries (relative)
+//   inc[tab_inc]       channel | role << 16
+struct GroupTab {
+    int32_t *desc, *ent, *inc_ptr, *inc;
+
+    __device__ GroupTab(int32_t *base, const RunParams &p)
+    {
+        desc = base;
+        ent = desc + p.tab_m;
+        inc_ptr = ent + p.tab_nnz;
+        inc = inc_ptr + (kMaxN + 1);
+    }
+
+    __device__ void load(const RunParams &p, const NetDev &nd, int gl, int L)
+    {
+        const ReactDesc *rd = p.rd + nd.react_off;
+        const int base_e = rd[0].csr & 0xFFFFFF;
+        const int last = rd[nd.M - 1].csr;
+        const int n_ent = (last & 0xFFFFFF) + (int)((uint32_t)last >> 24) - base_e;
+        for (int q = gl; q < nd.M; q += L) {
+            const int c = rd[q].csr;
+            desc[q] = ((c & 0xFFFFFF) - base_e) | (c & (int)0xFF000000);
+        }
+        for (int e = gl; e < n_ent; e += L) ent[e] = p.csr[base_e + e];
+        const int *ip = p.inc_ptr + nd.inc_off;
+        const int base_i = ip[0];
+        const int n_inc = ip[nd.N] - base_i;
+        for (int s = gl; s <= nd.N; s += L) inc_ptr[s] = ip[s] - base_i;
+        for (int e = gl; e < n_inc; e += L) inc[e] = p.inc_ent[base_i + e];
+    }
+};
+
 __device__ __forceinline__ int xval(const int *sx, int s)
 {
     return s == kNoSpecies ? 1 : sx[s];
@@ -141,13 +176,12 @@ __device__ __forceinline__ void group_words(int M, int gl, uint32_t k, uint32_t 
 
 // X += sign * v_j through the sparse change vector (lane e applies entry e).
 template <int L>
-__device__ __forceinline__ void group_apply(const RunParams &p, const NetDev &nd, int *sx, int j, int sign, int gl,
-                                            bool act)
+__device__ __forceinline__ void group_apply(const GroupTab &tab, int *sx, int j, int sign, int gl, bool act)
 {
-    const int csr = p.rd[nd.react_off + j].csr;
+    const int csr = tab.desc[j];
     const int beg = csr & 0xFFFFFF, cnt = (int)((uint32_t)csr >> 24);
     for (int e = gl; e < cnt; e += L) {
-        const int32_t ent = p.csr[beg + e];
+        const int32_t ent = tab.ent[beg + e];
         if (act) sx[csr_species(ent)] += sign * csr_delta(ent);
     }
     wave_sync();
@@ -160,10 +194,12 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
     constexpr int G = 64 / L;                 // trajectories per wavefront
     constexpr int C = 4 * BPL;
     __shared__ int s_x[kWaves][G][kMaxN];
+    extern __shared__ int32_t s_dyn[];
     const int wid = uniform_i((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane & (L - 1);
     int *sx = s_x[wid][grp];
+    GroupTab tab(s_dyn + (wid * G + grp) * p.tab_words, p);
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
     const bool has_t_end = p.t_end < INFINITY;
@@ -181,6 +217,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
         const NetDev nd = p.nets[it.net];
         if (it.net != cached_net) {
             ch.load(p, nd, gl);
+            tab.load(p, nd, gl, L);
             cached_net = it.net;
         }
         const int N = nd.N, M = nd.M;
@@ -303,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
                     tword = 0u;
                 }
             }
-            group_apply<L>(p, nd, sx, fire ? j1 : 0, +1, gl, fire);
+            group_apply<L>(tab, sx, fire ? j1 : 0, +1, gl, fire);
             t = fire ? tn : t;
             n_done += fire ? 1 : 0;
             active = fire;
@@ -356,6 +393,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
     __shared__ float s_lam32[kWaves][G][kMaxN];      // FP32 view of lambda (base + increments)
     __shared__ float s_contrib[kWaves][G][2][MMAX];  // per-channel contributions to dlambda[s1], dlambda[s2]
     __shared__ uint8_t s_tape[kWaves][G][KREC];
+    extern __shared__ int32_t s_dyn[];
     const int wid = uniform_i((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int grp = lane / L, gl = lane & (L - 1);
@@ -364,6 +402,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
     float *scon1 = s_contrib[wid][grp][0];
     float *scon2 = s_contrib[wid][grp][1];
     uint8_t *stape = s_tape[wid][grp];
+    GroupTab tab(s_dyn + (wid * G + grp) * p.tab_words, p);
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
     const float invT = 1.0f / p.temperature;
@@ -382,6 +421,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
         const NetDev nd = p.nets[it.net];
         if (it.net != cached_net) {
             ch.load(p, nd, gl);
+            tab.load(p, nd, gl, L);
             cached_net = it.net;
         }
         const int N = nd.N, M = nd.M;
@@ -459,8 +499,6 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
         const int n_seg = (kmax + p.K - 1) / p.K;
         uint32_t flags = 0u;
         int fold_left = kFold;
-        // incidence list of the lane's species
-        const int *inc_ptr = p.inc_ptr + nd.inc_off;
 
         for (int cseg = n_seg - 1; cseg >= 0; --cseg) {
             const int k_lo = cseg * p.K;
@@ -500,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                     }
                     grace<L>(r1, j1, r2);
                     if (on_k && gl == 0) stape[k - k_lo] = (uint8_t)j1;
-                    group_apply<L>(p, nd, sx, on_k ? j1 : 0, +1, gl, on_k);
+                    group_apply<L>(tab, sx, on_k ? j1 : 0, +1, gl, on_k);
                 }
                 // back to the state at the segment's end
 #pragma unroll
@@ -516,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                 t = p.ck_t[c1 * p.traj_total + g];
                 wave_sync();
             }
-            uint32_t tword = 0u;
+            uint32_t tword = 0u, tnext = 0u;
             int tword_idx = -1;
             for (int k = k_hi - 1; k >= k_lo; --k) {
                 if (fold_left == 0) {
@@ -540,10 +578,13 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                     wave_sync();
                     j = stape[k - k_lo];
                 } else {
+                    // the word of the next (earlier) steps is fetched one word ahead
                     const int widx = k >> tshift;
                     if (widx != tword_idx) {
-                        tword = have ? p.tape[(int64_t)widx * p.traj_total + g] : 0u;
+                        tword = (widx == tword_idx - 1) ? tnext
+                                                        : (have ? p.tape[(int64_t)widx * p.traj_total + g] : 0u);
                         tword_idx = widx;
+                        tnext = (have && widx > 0) ? p.tape[(int64_t)(widx - 1) * p.traj_total + g] : 0u;
                     }
                     j = (int)((tword >> (p.tape_bits * (k & (spw - 1)))) & tmask);
                 }
@@ -552,7 +593,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
 #pragma unroll
                 for (int o = 0; o < kObsMax; ++o) xn[o] = o < nd.n_obs ? sx[osp[o]] : 0;
                 wave_sync();
-                group_apply<L>(p, nd, sx, on_k ? j : 0, -1, gl, on_k);
+                group_apply<L>(tab, sx, on_k ? j : 0, -1, gl, on_k);
 
                 float a[C], A1[C], A2[C];
                 float a0 = 0.f;
@@ -613,9 +654,10 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                 for (int q = 0; q < C; ++q) {
                     float s = 0.f;
                     if (ch.on[q]) {
-                        const int beg = ch.csr[q] & 0xFFFFFF, cnt = (int)((uint32_t)ch.csr[q] >> 24);
+                        const int d = tab.desc[ch.j[q]];
+                        const int beg = d & 0xFFFFFF, cnt = (int)((uint32_t)d >> 24);
                         for (int e = 0; e < cnt; ++e) {
-                            const int32_t ent = p.csr[beg + e];
+                            const int32_t ent = tab.ent[beg + e];
                             s += (float)csr_delta(ent) * slam[csr_species(ent)];
                         }
                     }
@@ -653,8 +695,8 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                         const int s = gl + L * m;
                         if (s < N) {
                             float d = 0.f;
-                            for (int e = inc_ptr[s]; e < inc_ptr[s + 1]; ++e) {
-                                const int32_t ent = p.inc_ent[e];
+                            for (int e = tab.inc_ptr[s]; e < tab.inc_ptr[s + 1]; ++e) {
+                                const int32_t ent = tab.inc[e];
                                 d += (ent >> 16) == 1 ? scon1[ent & 0xFFFF] : scon2[ent & 0xFFFF];
                             }
                             dlam[m] += d;
@@ -735,11 +777,24 @@ int wave_class_lanes(int cls)
 template <int L, int BPL>
 static hipError_t launch_wave(const RunParams &p, bool backward, int n_blocks, hipStream_t stream)
 {
+    const size_t dyn = sizeof(int32_t) * (size_t)p.tab_words * wave::kWaves * (64 / L);
     if (backward)
-        hipLaunchKernelGGL((wave::bwd_kernel<L, BPL>), dim3(n_blocks), dim3(wave::kBlock), 0, stream, p);
+        hipLaunchKernelGGL((wave::bwd_kernel<L, BPL>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
     else
-        hipLaunchKernelGGL((wave::fwd_kernel<L, BPL>), dim3(n_blocks), dim3(wave::kBlock), 0, stream, p);
+        hipLaunchKernelGGL((wave::fwd_kernel<L, BPL>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
     return hipGetLastError();
+}
+
+size_t wave_static_lds(int cls, bool backward)
+{
+    const int L = wave_class_lanes(cls);
+    const int G = 64 / L;
+    const int bpl = cls == kWave_L64x2 ? 2 : 1;
+    size_t b = sizeof(int) * wave::kWaves * G * wave::kMaxN;
+    if (backward)
+        b += sizeof(float) * wave::kWaves * G * wave::kMaxN + sizeof(float) * wave::kWaves * G * 2 * 4 * bpl * L +
+             wave::kWaves * G * 64;
+    return b;
 }
 
 hipError_t wave_launch(int cls, const RunParams &p, bool backward, int n_blocks, hipStream_t stream)

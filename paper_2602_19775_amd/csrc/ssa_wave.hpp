@@ -24,5 +24,8 @@ int wave_class_for(int max_M);
 int wave_class_lanes(int cls);
 // Persistent launch over p.items (one trajectory each); p.work_counter must be 0.
 hipError_t wave_launch(int cls, const RunParams &p, bool backward, int n_blocks, hipStream_t stream);
+// LDS bytes of a block besides the per-group network tables.
+size_t wave_static_lds(int cls, bool backward);
+constexpr size_t kLdsPerBlock = 160 * 1024;
 
 }  // namespace ssa

@@ -35,7 +35,8 @@ class _Desc(C.Structure):
     _fields_ = [("n_networks", C.c_int32), ("n_species", C.c_void_p), ("n_reactions", C.c_void_p),
                 ("n_params", C.c_void_p), ("n_traj", C.c_void_p), ("n_obs", C.c_void_p),
                 ("reactant", C.c_void_p), ("rate_index", C.c_void_p), ("stoich", C.c_void_p),
-                ("obs_species", C.c_void_p), ("t_obs", C.c_void_p)]
+                ("obs_species", C.c_void_p), ("t_obs", C.c_void_p), ("exec_mode", C.c_int32),
+                ("wave_split", C.c_int32)]
 
 
 class _Layout(C.Structure):
@@ -110,8 +111,11 @@ def _stream(stream=None):
 class Net:
     """Device-resident tables of one or more networks (see include/ssa.h)."""
 
+    EXEC = {"auto": 0, "spec": 1, "lane": 2, "wave": 3}
+
     def __init__(self, networks: Sequence[W.Network], n_traj: Sequence[int],
-                 t_obs: Optional[Sequence[float]] = None, obs_species: Optional[Sequence] = None):
+                 t_obs: Optional[Sequence[float]] = None, obs_species: Optional[Sequence] = None,
+                 exec_mode: str = "auto", wave_split: int = -1):
         self.networks = list(networks)
         self.n_traj = [int(b) for b in n_traj]
         nn = len(self.networks)
@@ -131,7 +135,8 @@ class Net:
             np.ascontiguousarray(t_obs if t_obs is not None else np.zeros(nn), np.float64),
         ]
         k = self._keep
-        d = _Desc(nn, *[a.ctypes.data_as(C.c_void_p).value for a in k])
+        d = _Desc(nn, *[a.ctypes.data_as(C.c_void_p).value for a in k], self.EXEC[exec_mode], int(wave_split))
+        self.exec_mode, self.wave_split = exec_mode, wave_split
         h = C.c_void_p()
         _check(lib().ssa_net_create(C.byref(d), C.byref(h)), "ssa_net_create")
         self.handle = h

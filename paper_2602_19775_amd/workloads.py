@@ -305,3 +305,40 @@ def oscillator_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 200000, t_obs: flo
                     temperature=0.5, ckpt_every=1024)
     return Workload(f"oscillator_{n_traj}traj_{n_steps}steps_256bins", net, n_traj, cfg,
                     extra={"target_net": oscillator(rate_seed=1)})
+
+
+@dataclass
+class BatchWorkload:
+    """Several networks run together in one launch."""
+    name: str
+    nets: List[Network]
+    n_traj: List[int]
+    cfg: RunConfig
+    target_nets: List[Network] = None
+
+    def theta(self) -> np.ndarray:
+        return np.concatenate([n.theta0 for n in self.nets]).astype(np.float32)
+
+    def x0_packed(self) -> np.ndarray:
+        return np.concatenate([np.repeat(n.x0[:, None], b, axis=1).reshape(-1)
+                               for n, b in zip(self.nets, self.n_traj)]).astype(np.int32)
+
+
+def uneven_batch(n_networks: int = 4096, traj_per_network: int = 256, n_steps: int = 5000,
+                 seed: int = 0) -> BatchWorkload:
+    """4,096 random mass-action networks (4-64 species, 8-256 channels, orders
+    0-2, change vectors in {-2..2}, log-uniform rates in [1e-3, 1e2], Poisson(50)
+    initial counts), 256 trajectories each, 5,000 steps, final counts of up to 4
+    species observed, temperature 0.5, checkpoints every 256 steps.  Targets use
+    the same networks with every rate scaled by a seeded factor in [0.5, 2]."""
+    nets = random_network_batch(n_networks, seed=seed)
+    g = np.random.default_rng(np.random.SeedSequence([seed, 4]))
+    targets = []
+    for n in nets:
+        t = Network(n.name, n.species, n.reactant, n.rate_index, n.stoich, n.n_params,
+                    (n.theta0 + np.log(g.uniform(0.5, 2.0, size=n.n_params))).astype(np.float32),
+                    n.x0, n.obs_species, n.param_names)
+        targets.append(t)
+    cfg = RunConfig(seed=seed, n_steps=n_steps, obs_kind=OBS_FINAL, temperature=0.5, ckpt_every=256)
+    return BatchWorkload(f"uneven_{n_networks}nets_{traj_per_network}traj_{n_steps}steps", nets,
+                         [traj_per_network] * n_networks, cfg, targets)

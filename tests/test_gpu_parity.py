@@ -50,11 +50,12 @@ def _ties_for_oracle(recs, traj_offset=0, traj_index=None):
     return out
 
 
-def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=None, per_traj=True):
+def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=None, per_traj=True,
+             exec_mode="auto"):
     """GPU forward (+backward) over B trajectories and the oracle on `sample`
     trajectory ids (default: all)."""
     theta = net.theta0 if theta is None else theta
-    h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
+    h = ssa.Net([net], [B], t_obs=[cfg.t_obs], exec_mode=exec_mode)
     th = torch.tensor(theta, dtype=torch.float32, device="cuda")
     x0 = _x0([net], [B])
     fwd = ssa.forward(h, cfg, th, x0, keep_ckpt=d_obs is not None, tie_capacity=1 << 16,
@@ -210,15 +211,16 @@ def test_zero_steps_and_absorbing(ssa):
     assert np.all(gpu["x_final"][:, 2] == 2) and np.all(gpu["steps_done"] < 500)
 
 
+@pytest.mark.parametrize("exec_mode", ["spec", "lane"])
 @pytest.mark.parametrize("mode", ["tape", "recompute"])
-def test_dimer_gradients_small(ssa, mode):
+def test_dimer_gradients_small(ssa, mode, exec_mode):
     net = W.dimerization_2a()
     B = 300
     cfg = W.RunConfig(seed=1, n_steps=1500, obs_kind=W.OBS_BINS, n_bins=20, t_obs=300.0,
                       temperature=0.5, ckpt_every=64)
     g = np.random.default_rng(2)
     d_obs = g.normal(size=(cfg.n_bins, 1, B))
-    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode=mode)
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode=mode, exec_mode=exec_mode)
     assert_forward_parity(gpu, r, ids, cfg)
     keep = edge_safe(gpu, r, ids)
     assert keep.mean() > 0.8
@@ -243,11 +245,12 @@ def test_oscillator_gradients_small(ssa):
     assert_grad_parity(gpu["ppt"], r.grad, keep, rtol=1e-5)
 
 
-def test_random_networks_batch_forward(ssa):
+@pytest.mark.parametrize("exec_mode", ["spec", "lane"])
+def test_random_networks_batch_forward(ssa, exec_mode):
     nets = W.random_network_batch(6, seed=5, n_range=(4, 16), m_range=(8, 32))
     B = [64, 37, 128, 1, 90, 65]
     cfg = W.RunConfig(seed=9, n_steps=400, obs_kind=W.OBS_FINAL)
-    h = ssa.Net(nets, B)
+    h = ssa.Net(nets, B, exec_mode=exec_mode)
     th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
     x0 = _x0(nets, B)
     fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 12)

@@ -1,7 +1,5 @@
 """Parity of the wave-mode kernels (one trajectory per group of lanes, one
 persistent launch for a whole batch of networks) with the FP64 oracle."""
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -24,19 +22,14 @@ def ssa():
     return m
 
 
-@pytest.fixture
-def wave_mode():
-    old = os.environ.get("SSA_EXEC")
-    os.environ["SSA_EXEC"] = "wave"
-    yield
-    if old is None:
-        del os.environ["SSA_EXEC"]
-    else:
-        os.environ["SSA_EXEC"] = old
+@pytest.fixture(params=[1, 0], ids=["split", "one_launch"])
+def wave_mode(request):
+    """Wave mode, one launch per lane-group width or one launch for the batch."""
+    return request.param
 
 
-def run_batch(ssa, nets, B, cfg, d_obs_fn=None, bwd_mode="auto", t_obs=None):
-    h = ssa.Net(nets, B, t_obs=t_obs)
+def run_batch(ssa, nets, B, cfg, d_obs_fn=None, bwd_mode="auto", t_obs=None, wave_split=-1):
+    h = ssa.Net(nets, B, t_obs=t_obs, exec_mode="wave", wave_split=wave_split)
     th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
     x0 = _x0(nets, B)
     fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 16, bwd_mode=bwd_mode)
@@ -85,7 +78,7 @@ def test_wave_small_batch_forward(ssa, wave_mode):
     nets = W.random_network_batch(6, seed=5, n_range=(4, 16), m_range=(8, 32))
     B = [64, 37, 128, 1, 90, 65]
     cfg = W.RunConfig(seed=9, n_steps=400, obs_kind=W.OBS_FINAL)
-    h, fwd, _, _ = run_batch(ssa, nets, B, cfg)
+    h, fwd, _, _ = run_batch(ssa, nets, B, cfg, wave_split=wave_mode)
     check_batch(h, fwd, nets, B, cfg)
 
 
@@ -93,7 +86,7 @@ def test_wave_large_networks_forward(ssa, wave_mode):
     nets = W.random_network_batch(5, seed=21, n_range=(40, 64), m_range=(200, 256))
     B = [17, 8, 33, 5, 12]
     cfg = W.RunConfig(seed=4, n_steps=300, obs_kind=W.OBS_FINAL)
-    h, fwd, _, _ = run_batch(ssa, nets, B, cfg)
+    h, fwd, _, _ = run_batch(ssa, nets, B, cfg, wave_split=wave_mode)
     check_batch(h, fwd, nets, B, cfg)
 
 
@@ -111,7 +104,8 @@ def test_wave_gradients_random_batch(ssa, wave_mode, mode):
     def d_obs_fn(h):
         return g.normal(size=h.obs_total(cfg.obs_kind, cfg.n_bins))
 
-    h, fwd, d_obs, ppt = run_batch(ssa, nets, B, cfg, d_obs_fn, bwd_mode=mode, t_obs=t_obs)
+    h, fwd, d_obs, ppt = run_batch(ssa, nets, B, cfg, d_obs_fn, bwd_mode=mode, t_obs=t_obs,
+                                   wave_split=wave_mode)
     check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt)
 
 
@@ -151,7 +145,7 @@ def test_wave_dimer_gradients(ssa, wave_mode):
                       temperature=0.5, ckpt_every=64)
     g = np.random.default_rng(2)
     d_obs = g.normal(size=(cfg.n_bins, 1, B))
-    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs)
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, exec_mode="wave")
     assert_forward_parity(gpu, r, ids, cfg)
     keep = edge_safe(gpu, r, ids)
     assert_grad_parity(gpu["ppt"], r.grad, keep)
@@ -161,7 +155,7 @@ def test_wave_backward_deterministic(ssa, wave_mode):
     nets = W.random_network_batch(3, seed=2, n_range=(8, 32), m_range=(40, 120))
     B = [50, 50, 50]
     cfg = W.RunConfig(seed=5, n_steps=200, obs_kind=W.OBS_FINAL, ckpt_every=32)
-    h = ssa.Net(nets, B)
+    h = ssa.Net(nets, B, exec_mode="wave", wave_split=wave_mode)
     th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
     x0 = _x0(nets, B)
     d = torch.randn(h.obs_total(cfg.obs_kind, 0), dtype=torch.float64, device="cuda")
