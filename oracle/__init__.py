@@ -18,6 +18,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ssa_oracle.c")
+SOURCES = [SRC, os.path.join(HERE, "ssa_oracle_grn.c")]
+HEADER = os.path.join(HERE, "ssa_oracle.h")
 LIB = os.path.join(HERE, "liboracle.so")
 
 _lib = None
@@ -25,13 +27,20 @@ _lib = None
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if force or _stale():
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-Wall", "-Wextra", "-Wno-unused-parameter",
-                               SRC, "-o", tmp, "-lm"])
+                               *SOURCES, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
+
+
+def _stale() -> bool:
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(f) > t for f in SOURCES + [HEADER])
 
 
 class _Net(C.Structure):
@@ -47,6 +56,11 @@ class _Cfg(C.Structure):
                 ("tie_threshold", C.c_double), ("clock_tol", C.c_double)]
 
 
+class _Grn(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hid", C.c_int32), ("n_out", C.c_int32),
+                ("beta", C.c_double), ("delta_min", C.c_double)]
+
+
 class _Ov(C.Structure):
     _fields_ = [("off", C.c_void_p), ("step", C.c_void_p), ("kind", C.c_void_p), ("val", C.c_void_p)]
 
@@ -59,7 +73,7 @@ class _Stats(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if _stale():
             build(force=True)
         L = C.CDLL(LIB)
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -76,6 +90,21 @@ def lib():
         L.orc_trace.argtypes = [C.POINTER(_Net), C.POINTER(_Cfg), C.c_void_p, C.c_uint32,
                                 C.c_void_p, C.c_int64] + [C.c_void_p] * 7
         L.orc_trace.restype = C.c_int64
+        L.orc_bf16.argtypes = [C.c_float]
+        L.orc_bf16.restype = C.c_float
+        L.orc_grn_n_params.argtypes = [C.POINTER(_Grn)]
+        L.orc_grn_n_params.restype = C.c_int64
+        L.orc_grn_n_compact.argtypes = [C.POINTER(_Grn)]
+        L.orc_grn_n_compact.restype = C.c_int64
+        L.orc_grn_hidden_input.argtypes = [C.POINTER(_Grn), C.c_void_p, C.c_void_p, C.c_int64,
+                                           C.c_void_p]
+        L.orc_grn_run.argtypes = [C.POINTER(_Grn), C.POINTER(_Cfg), C.c_void_p, C.c_void_p,
+                                  C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Ov),
+                                  C.c_void_p] + [C.c_void_p] * 5 + [C.POINTER(_Stats), C.c_int]
+        L.orc_grn_run.restype = C.c_int
+        L.orc_grn_trace.argtypes = [C.POINTER(_Grn), C.POINTER(_Cfg), C.c_void_p, C.c_void_p,
+                                    C.c_uint32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.orc_grn_trace.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -231,3 +260,114 @@ def trace(net, cfg, theta, x0, traj_id: int = 0, cap: int = 1000) -> Trace:
     if k < 0:
         raise RuntimeError("oracle rejected its arguments")
     return Trace(X[:k + 1], t[:k + 1], tau[:k], j[:k], a[:k], u[:k], mg[:k])
+
+
+# ---------------------------------------------------------------------------
+# Gene-regulatory network classifier
+# ---------------------------------------------------------------------------
+def _grn(net) -> _Grn:
+    return _Grn(net.n_in, net.n_hid, net.n_out, float(net.beta), float(net.delta_min))
+
+
+def bf16(x) -> np.ndarray:
+    """The oracle's bfloat16 rounding (nearest even) of FP32 values, elementwise."""
+    L = lib()
+    x = np.asarray(x, np.float32)
+    return np.array([L.orc_bf16(float(v)) for v in x.reshape(-1)], np.float32).reshape(x.shape)
+
+
+def grn_hidden_input(net, theta, images) -> np.ndarray:
+    """u [n_images, n_hid] = b + bf16(W) bf16(x), exact in FP64."""
+    keep = _Keep()
+    g = _grn(net)
+    th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
+    x = keep(np.ascontiguousarray(np.asarray(images, np.float32).astype(np.float64)))
+    n_img = x.shape[0]
+    u = np.zeros((n_img, net.n_hid))
+    lib().orc_grn_hidden_input(C.byref(g), _p(th), _p(x), n_img, _p(u))
+    return u
+
+
+@dataclass
+class GrnResult:
+    x_final: np.ndarray        # [n_traj, n_hid + n_out]
+    t_final: np.ndarray
+    steps_done: np.ndarray
+    obs: np.ndarray            # [n_traj, n_out]
+    min_margin: np.ndarray
+    n_near: np.ndarray
+    n_resync: np.ndarray
+    n_bad: np.ndarray
+    grad_c: Optional[np.ndarray] = None   # [n_traj, n_compact]
+
+
+def grn_run(net, cfg, theta, u_hid, image_of, x0=None, traj_ids=None, ties=None, d_obs=None,
+            tie_threshold: float = 1e-6, clock_tol: float = 1e-5, n_threads: int = 0) -> GrnResult:
+    """Simulate (and with d_obs [n_traj, n_out], differentiate) GRN trajectories.
+    u_hid: [n_images, n_hid] hidden pre-activations (the oracle's own from
+    grn_hidden_input, or another implementation's, for split parity)."""
+    keep = _Keep()
+    g = _grn(net)
+    image_of = keep(np.ascontiguousarray(image_of, np.int32))
+    n_traj = len(image_of)
+    N = net.n_hid + net.n_out
+    if traj_ids is None:
+        traj_ids = np.arange(n_traj, dtype=np.uint32)
+    traj_ids = keep(np.ascontiguousarray(traj_ids, np.uint32))
+    x0 = np.zeros((n_traj, N), np.int32) if x0 is None else np.asarray(x0, np.int32)
+    x0 = keep(np.ascontiguousarray(np.broadcast_to(x0, (n_traj, N)), np.int32))
+    u = keep(np.ascontiguousarray(u_hid, np.float64))
+    th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
+    c = _Cfg(cfg.seed, cfg.purpose, cfg.epoch, min(int(cfg.n_steps), 2 ** 62), float(cfg.t_end),
+             0, 0, 0.0, 0, None, float(cfg.temperature), tie_threshold, clock_tol)
+    ov = _overrides(n_traj, ties, keep)
+    res = GrnResult(np.zeros((n_traj, N), np.int32), np.zeros(n_traj), np.zeros(n_traj, np.int32),
+                    np.zeros((n_traj, net.n_out)), np.zeros(n_traj), np.zeros(n_traj, np.int32),
+                    np.zeros(n_traj, np.int32), np.zeros(n_traj, np.int32))
+    st = _Stats(_p(res.min_margin).value, _p(res.n_near).value, _p(res.n_resync).value,
+                _p(res.n_bad).value, None)
+    dp = None
+    if d_obs is not None:
+        d = keep(np.ascontiguousarray(np.broadcast_to(d_obs, (n_traj, net.n_out)), np.float64))
+        res.grad_c = np.zeros((n_traj, net.n_compact))
+        dp = _p(d)
+    rc = lib().orc_grn_run(C.byref(g), C.byref(c), _p(th), _p(u), n_traj, _p(traj_ids),
+                           _p(image_of), _p(x0), C.byref(ov) if ov is not None else None, dp,
+                           _p(res.x_final), _p(res.t_final), _p(res.steps_done), _p(res.obs),
+                           _p(res.grad_c) if res.grad_c is not None else None, C.byref(st),
+                           n_threads)
+    if rc != 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return res
+
+
+def grn_full_gradient(net, res_grad_c, images, image_of) -> np.ndarray:
+    """Assemble dL/dtheta [P] from the compact per-trajectory gradients:
+    dW = sum_q du_q x_{image(q)}^T (x as the contraction sees it, bfloat16),
+    the other blocks are sums over trajectories."""
+    H, O = net.n_hid, net.n_out
+    gc = np.asarray(res_grad_c, np.float64)
+    du = gc[:, :H]
+    x = bf16(np.asarray(images, np.float32)).astype(np.float64)[np.asarray(image_of)]
+    dW = du.T @ x
+    rest = gc.sum(axis=0)
+    return np.concatenate([dW.reshape(-1), rest[:H], rest[H:H + O * H], rest[H + O * H:H + O * H + O],
+                           rest[H + O * H + O:]])
+
+
+def grn_trace(net, cfg, theta, u_row, traj_id: int = 0, x0=None, cap: int = 1000):
+    """Fired channels [n] and clock [n+1] of one trajectory."""
+    keep = _Keep()
+    g = _grn(net)
+    N = net.n_hid + net.n_out
+    x = keep(np.ascontiguousarray(np.zeros(N, np.int32) if x0 is None else x0, np.int32))
+    u = keep(np.ascontiguousarray(u_row, np.float64))
+    th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
+    c = _Cfg(cfg.seed, cfg.purpose, cfg.epoch, min(int(cfg.n_steps), 2 ** 62), float(cfg.t_end),
+             0, 0, 0.0, 0, None, float(cfg.temperature), 1e-6, 1e-5)
+    j = np.zeros(cap, np.int32)
+    t = np.zeros(cap + 1)
+    n = lib().orc_grn_trace(C.byref(g), C.byref(c), _p(th), _p(u), traj_id, _p(x), cap, _p(j), _p(t))
+    if n < 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return j[:n], t[:n + 1]

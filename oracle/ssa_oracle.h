@@ -111,3 +111,64 @@ int64_t orc_trace(const orc_net *net, const orc_cfg *cfg, const double *theta,
 }
 #endif
 #endif
+
+#ifndef SSA_ORACLE_GRN_H
+#define SSA_ORACLE_GRN_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Gene-regulatory network classifier (Sec. 4.3, Fig. 4A): fixed input factors
+ * x (the n_in pixel intensities of an image), n_hid hidden genes H and n_out
+ * output genes O, each gene switched ON with probability sigmoid(b + sum w x)
+ * of its regulators.  Species order: H_0..H_{n_hid-1}, O_0..O_{n_out-1}.
+ * Channels, in this order (channel j uses Philox word 1+j):
+ *   hidden production  0 -> H_h  a = beta sigmoid(u_h),   u_h = b_h + sum_i W_hi x_i
+ *   hidden decay       H_h -> 0  a = delta_h H_h,         delta_h = delta_min + exp(psi_h)
+ *   output production  0 -> O_o  a = beta sigmoid(v_o),   v_o = c_o + sum_h U_oh H_h
+ *   output decay       O_o -> 0  a = delta_o O_o,         delta_o = delta_min + exp(psi_{n_hid+o})
+ * Parameters theta = [W (n_hid x n_in, row-major) | b (n_hid) | U (n_out x n_hid,
+ * row-major) | c (n_out) | psi (n_hid + n_out)].
+ * Observation: final counts of the output genes. */
+typedef struct orc_grn {
+    int32_t n_in, n_hid, n_out;
+    double beta, delta_min;
+} orc_grn;
+
+/* Number of parameters, and the width of the compact per-trajectory gradient
+ * [du (n_hid) | dU (n_out x n_hid) | dc (n_out) | dpsi (n_hid + n_out)],
+ * where du_h = dL/du_h (= dL/db_h).  dL/dW_hi = sum over trajectories of
+ * du_h x_i of the trajectory's image. */
+int64_t orc_grn_n_params(const orc_grn *net);
+int64_t orc_grn_n_compact(const orc_grn *net);
+
+/* bfloat16 rounding (nearest even, NaN kept quiet) of an FP32 value. */
+float orc_bf16(float x);
+
+/* u[m][h] = b_h + sum_i bf16(W_hi) bf16(x_mi), the products and the sum exact
+ * in FP64 (theta holds FP32 values; x_img [n_images][n_in] FP32 values). */
+void orc_grn_hidden_input(const orc_grn *net, const double *theta, const double *x_img,
+                          int64_t n_images, double *u);
+
+/* Forward (and, if d_obs != NULL, the straight-through adjoint) of n_traj
+ * trajectories; trajectory q runs on the hidden pre-activations
+ * u_hid[image_of[q]] ([n_images][n_hid]).  cfg: seed, purpose, epoch, n_steps,
+ * t_end, temperature, tie_threshold, clock_tol are used (obs is always the
+ * final output counts).  x0, x_final [n_traj][n_hid+n_out];
+ * obs, d_obs [n_traj][n_out]; grad_c [n_traj][orc_grn_n_compact]. */
+int orc_grn_run(const orc_grn *net, const orc_cfg *cfg, const double *theta,
+                const double *u_hid, int64_t n_traj, const uint32_t *traj_ids,
+                const int32_t *image_of, const int32_t *x0, const orc_overrides *ov,
+                const double *d_obs, int32_t *x_final, double *t_final, int32_t *steps_done,
+                double *obs, double *grad_c, const orc_stats *stats, int n_threads);
+
+/* Fired channels j [cap] and clock t [cap+1] of one trajectory (u_row: its
+ * n_hid pre-activations).  Returns the number of fired steps. */
+int64_t orc_grn_trace(const orc_grn *net, const orc_cfg *cfg, const double *theta,
+                      const double *u_row, uint32_t traj_id, const int32_t *x0, int64_t cap,
+                      int32_t *j, double *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -342,3 +342,126 @@ def uneven_batch(n_networks: int = 4096, traj_per_network: int = 256, n_steps: i
     cfg = RunConfig(seed=seed, n_steps=n_steps, obs_kind=OBS_FINAL, temperature=0.5, ckpt_every=256)
     return BatchWorkload(f"uneven_{n_networks}nets_{traj_per_network}traj_{n_steps}steps", nets,
                          [traj_per_network] * n_networks, cfg, targets)
+
+
+# --------------------------------------------------------------------------
+# Gene-regulatory network classifier (Sec. 4.3, Fig. 4A)
+# --------------------------------------------------------------------------
+
+@dataclass
+class GrnNet:
+    """Feed-forward gene network: n_in fixed input factors (an image's pixels),
+    n_hid hidden genes, n_out output genes.  Every gene is produced at
+    beta * P(ON) with P(ON) = sigmoid(bias + sum of weighted regulator levels)
+    and decays at delta = delta_min + exp(psi).  Parameters, packed:
+    [W (n_hid x n_in) | b (n_hid) | U (n_out x n_hid) | c (n_out) | psi (n_hid + n_out)]."""
+    n_in: int = 784
+    n_hid: int = 256
+    n_out: int = 10
+    beta: float = 10.0
+    delta_min: float = 0.25
+
+    @property
+    def n_species(self) -> int:
+        return self.n_hid + self.n_out
+
+    @property
+    def n_reactions(self) -> int:
+        return 2 * (self.n_hid + self.n_out)
+
+    @property
+    def n_params(self) -> int:
+        return self.n_hid * self.n_in + self.n_hid + self.n_out * self.n_hid + self.n_out + self.n_hid + self.n_out
+
+    @property
+    def n_compact(self) -> int:
+        """Width of a trajectory's compact gradient [du | dU | dc | dpsi]."""
+        return self.n_hid + self.n_out * self.n_hid + self.n_out + self.n_hid + self.n_out
+
+    def offsets(self) -> dict:
+        I, H, O = self.n_in, self.n_hid, self.n_out
+        o = {"W": 0, "b": H * I}
+        o["U"] = o["b"] + H
+        o["c"] = o["U"] + O * H
+        o["psi"] = o["c"] + O
+        return o
+
+    def split(self, theta: np.ndarray) -> dict:
+        """Views of a packed parameter vector."""
+        I, H, O = self.n_in, self.n_hid, self.n_out
+        o = self.offsets()
+        return {"W": theta[o["W"]:o["b"]].reshape(H, I), "b": theta[o["b"]:o["U"]],
+                "U": theta[o["U"]:o["c"]].reshape(O, H), "c": theta[o["c"]:o["psi"]],
+                "psi": theta[o["psi"]:]}
+
+
+def grn_init_params(net: GrnNet, seed: int = 0, delta0: float = 1.0) -> np.ndarray:
+    """Glorot-uniform W and U, zero biases, every decay rate delta0
+    (psi = ln(delta0 - delta_min)).  float32."""
+    g = np.random.default_rng(np.random.SeedSequence([seed, 5]))
+    I, H, O = net.n_in, net.n_hid, net.n_out
+    lim_w = np.sqrt(6.0 / (I + H))
+    lim_u = np.sqrt(6.0 / (H + O))
+    W = g.uniform(-lim_w, lim_w, size=(H, I))
+    U = g.uniform(-lim_u, lim_u, size=(O, H))
+    psi = np.full(H + O, np.log(delta0 - net.delta_min))
+    return np.concatenate([W.reshape(-1), np.zeros(H), U.reshape(-1), np.zeros(O), psi]).astype(np.float32)
+
+
+def grn_images(n_images: int, seed: int = 0, side: int = 28, n_classes: int = 10):
+    """Synthetic stand-ins with the shape of handwritten-digit images: each of
+    n_classes prototypes is a sum of 3 Gaussian blobs (centres uniform in
+    [4, side-4]^2, widths uniform in [1.5, 3.5] px); an image is its class
+    prototype plus N(0, 0.15^2) pixel noise, clipped to [0, 1] and quantised to
+    levels p/256 (p integer), which bfloat16 represents exactly.
+    Image m has class m mod n_classes.  Returns (float32 [n_images, side*side],
+    int64 labels)."""
+    g = np.random.default_rng(np.random.SeedSequence([seed, 3]))
+    yy, xx = np.mgrid[0:side, 0:side].astype(np.float64)
+    protos = []
+    for _ in range(n_classes):
+        img = np.zeros((side, side))
+        for _ in range(3):
+            cy, cx = g.uniform(4.0, side - 4.0, size=2)
+            s = g.uniform(1.5, 3.5)
+            img += np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * s * s))
+        protos.append(np.clip(img, 0.0, 1.0))
+    labels = np.arange(n_images) % n_classes
+    imgs = np.stack([protos[c] for c in labels]) + g.normal(0.0, 0.15, size=(n_images, side, side))
+    imgs = np.round(np.clip(imgs, 0.0, 1.0) * 256.0) / 256.0
+    return imgs.reshape(n_images, side * side).astype(np.float32), labels.astype(np.int64)
+
+
+@dataclass
+class GrnWorkload:
+    name: str
+    net: GrnNet
+    n_images: int
+    n_rep: int                    # trajectories per image (trajectory q runs image q // n_rep)
+    cfg: RunConfig
+    theta: np.ndarray
+    images: np.ndarray            # [n_images, n_in] float32
+    labels: np.ndarray            # [n_images]
+
+    @property
+    def n_traj(self) -> int:
+        return self.n_images * self.n_rep
+
+    def image_of(self) -> np.ndarray:
+        return np.arange(self.n_traj) // self.n_rep
+
+    def x0_soa(self) -> np.ndarray:
+        return np.zeros((self.net.n_species, self.n_traj), np.int32)
+
+
+def grn_classifier(n_images: int = 512, n_rep: int = 32, n_steps: int = 2000, seed: int = 0,
+                   net: GrnNet = None) -> GrnWorkload:
+    """784 -> 256 -> 10 gene network on synthetic 28x28 images: 512 images x 32
+    trajectories, 2,000 steps from zero counts, final output counts observed,
+    temperature 1.0."""
+    net = net or GrnNet()
+    side = int(round(np.sqrt(net.n_in)))
+    imgs, labels = grn_images(n_images, seed=seed, side=side)
+    cfg = RunConfig(seed=seed, n_steps=n_steps, obs_kind=OBS_FINAL, temperature=1.0)
+    return GrnWorkload(f"grn_{net.n_in}x{net.n_hid}x{net.n_out}_{n_images}img_{n_rep}rep_{n_steps}steps",
+                       net, n_images, n_rep, cfg, grn_init_params(net, seed), imgs, labels)
