@@ -228,6 +228,82 @@ const char *ssa_status_string(ssa_status s);
 /* Detail of the last failing call on this thread ("" if none). */
 const char *ssa_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Gene-regulatory network classifier (Sec. 4.3, Fig. 4A).
+ *
+ * The pixels x of an image are fixed input factors.  Each of n_hid = 256
+ * hidden genes H_h and n_out output genes O_o is ON with probability
+ * sigmoid(bias + sum of weighted regulator levels) and produced at beta times
+ * that probability; every gene decays at delta = delta_min + exp(psi), which
+ * keeps the decay rate above delta_min.  Channels (word 1+j drives channel j):
+ *   j = h                 0 -> H_h   a = beta sigmoid(u_h),  u_h = b_h + sum_i W_hi x_i
+ *   j = n_hid + h         H_h -> 0   a = delta_h H_h
+ *   j = 2 n_hid + o       0 -> O_o   a = beta sigmoid(v_o),  v_o = c_o + sum_h U_oh H_h
+ *   j = 2 n_hid + n_out + o  O_o -> 0  a = delta_{n_hid+o} O_o
+ * The contraction W x runs on bf16 matrix cores: W and x are rounded to
+ * bfloat16 (nearest even), products are summed in FP32.  v_o is kept in FP64
+ * and updated by +-U_oh whenever H_h changes.
+ *
+ * Layouts (device memory, caller-owned):
+ *   theta, d_params  float  [P]: W [n_hid][n_in] | b [n_hid] | U [n_out][n_hid] |
+ *                    c [n_out] | psi [n_hid + n_out],
+ *                    P = n_hid*n_in + n_hid + n_out*n_hid + n_out + n_hid + n_out
+ *   x_img            float  [n_images][n_in]
+ *   u_hid            float  [n_images][n_hid]   (written by the forward)
+ *   x0, x_final      int32  [n_hid + n_out][B]  (species-major; B = n_images*n_rep,
+ *                    trajectory q runs image q / n_rep)
+ *   t_final          double [B];  steps_done int32 [B]
+ *   obs, d_obs       double [n_out][B]          (final output counts)
+ *   d_compact        double [B][C], C = n_hid + n_out*n_hid + n_out + n_hid + n_out:
+ *                    per trajectory [dL/du (n_hid) | dL/dU | dL/dc | dL/dpsi]
+ *                    (dL/db = dL/du; dL/dW = sum_q dL/du_q bf16(x_{image q})^T)
+ * Runs use cfg->seed, purpose, epoch, d_epoch, traj_ids, n_steps, temperature
+ * and tie_capacity; the observation is always the final output counts, and
+ * cfg->t_end must be +INFINITY (SSA_ENOTSUP otherwise).
+ * ------------------------------------------------------------------------ */
+typedef struct ssa_grn_desc {
+    int32_t n_in;                  /* input factors per image (>= 1) */
+    int32_t n_hid;                 /* hidden genes: 256 */
+    int32_t n_out;                 /* output genes: 1..16 */
+    int32_t n_images;              /* images per run */
+    int32_t n_rep;                 /* trajectories per image */
+    float beta;                    /* production rate of a gene that is ON (> 0) */
+    float delta_min;               /* floor of every decay rate (>= 0) */
+} ssa_grn_desc;
+
+typedef struct ssa_grn ssa_grn;    /* opaque handle */
+
+/* Validates the shape and allocates the handle's device status word. */
+ssa_status ssa_grn_create(const ssa_grn_desc *desc, ssa_grn **out);
+void ssa_grn_destroy(ssa_grn *grn);
+
+/* Device bytes the caller provides: tape_bytes (fired channels, written by the
+ * forward and read by the backward) and work_bytes (backward scratch). */
+ssa_status ssa_grn_buffer_sizes(const ssa_grn *grn, const ssa_config *cfg, size_t *tape_bytes,
+                                size_t *work_bytes);
+
+/* Hidden pre-activations u_hid and the forward simulation of every
+ * trajectory.  tape may be NULL (then no backward is possible); ties/n_ties
+ * as for ssa_forward. */
+ssa_status ssa_grn_forward(const ssa_grn *grn, const ssa_config *cfg, const float *theta,
+                           const float *x_img, const int32_t *x0, float *u_hid,
+                           int32_t *x_final, double *t_final, int32_t *steps_done, double *obs,
+                           void *tape, size_t tape_bytes, ssa_tie *ties, uint32_t *n_ties,
+                           hipStream_t stream);
+
+/* Straight-through backward: overwrites d_params with dL/dtheta (per-trajectory
+ * FP64 partials, summed per image and then over images in a fixed order; dW on
+ * FP64 matrix cores).  d_compact (optional) receives the per-trajectory
+ * partials.  Inputs are the forward's inputs and outputs with the same cfg. */
+ssa_status ssa_grn_backward(const ssa_grn *grn, const ssa_config *cfg, const float *theta,
+                            const float *x_img, const float *u_hid, const int32_t *x_final,
+                            const int32_t *steps_done, const void *tape, size_t tape_bytes,
+                            const double *d_obs, float *d_params, double *d_compact,
+                            void *work, size_t work_bytes, hipStream_t stream);
+
+/* Sticky device flags of the handle, as ssa_device_status.  Synchronises `stream`. */
+ssa_status ssa_grn_device_status(const ssa_grn *grn, hipStream_t stream, uint32_t *flags);
+
 /* Device primitives exposed for verification.
  * ssa_selftest_philox: n blocks; ctr_key [n][6] = (c0,c1,c2,c3,k0,k1), out [n][4].
  * ssa_selftest_neglog: out[i] = the library's FP32 -ln(u) for lattice point

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "ssa_host.hpp"
 #include "ssa_jit.hpp"
 #include "ssa_lane.hpp"
 #include "ssa_wave.hpp"
@@ -23,7 +24,7 @@ using namespace ssa;
 
 static_assert(sizeof(TieRec) == sizeof(ssa_tie), "tie record layout");
 
-namespace {
+namespace ssa {
 
 thread_local std::string g_last_error;
 
@@ -37,6 +38,10 @@ ssa_status hip_fail(hipError_t e, const char *what)
 {
     return fail(SSA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+}  // namespace ssa
+
+namespace {
 
 template <typename T>
 hipError_t upload(T **dst, const std::vector<T> &src)

@@ -55,9 +55,16 @@ class _Cfg(C.Structure):
 TIE_DTYPE = np.dtype([("traj", np.uint32), ("step", np.uint32), ("chosen", np.int32),
                       ("second", np.int32), ("margin", np.float32), ("kind", np.int32)])
 
+class _GrnDesc(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hid", C.c_int32), ("n_out", C.c_int32), ("n_images", C.c_int32),
+                ("n_rep", C.c_int32), ("beta", C.c_float), ("delta_min", C.c_float)]
+
+
 EXPORTS = ["ssa_config_default", "ssa_net_create", "ssa_net_destroy", "ssa_net_sizes", "ssa_net_layout",
            "ssa_buffer_sizes", "ssa_forward", "ssa_backward", "ssa_step_batch", "ssa_device_status",
-           "ssa_status_string", "ssa_last_error", "ssa_selftest_philox", "ssa_selftest_neglog"]
+           "ssa_status_string", "ssa_last_error", "ssa_selftest_philox", "ssa_selftest_neglog",
+           "ssa_grn_create", "ssa_grn_destroy", "ssa_grn_buffer_sizes", "ssa_grn_forward",
+           "ssa_grn_backward", "ssa_grn_device_status"]
 
 
 def lib():
@@ -85,9 +92,17 @@ def lib():
         L.ssa_last_error.restype = C.c_char_p
         L.ssa_selftest_philox.argtypes = [V, V, C.c_int64, V]
         L.ssa_selftest_neglog.argtypes = [C.c_uint32, C.c_int64, V, V]
+        L.ssa_grn_create.argtypes = [C.POINTER(_GrnDesc), C.POINTER(V)]
+        L.ssa_grn_destroy.argtypes = [V]
+        L.ssa_grn_buffer_sizes.argtypes = [V, C.POINTER(_Cfg), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        L.ssa_grn_forward.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, V, V, V, C.c_size_t, V, V, V]
+        L.ssa_grn_backward.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, C.c_size_t, V, V, V, V,
+                                       C.c_size_t, V]
+        L.ssa_grn_device_status.argtypes = [V, V, C.POINTER(C.c_uint32)]
         for name in EXPORTS:
             f = getattr(L, name)
-            if name not in ("ssa_net_destroy", "ssa_config_default", "ssa_status_string", "ssa_last_error"):
+            if name not in ("ssa_net_destroy", "ssa_grn_destroy", "ssa_config_default", "ssa_status_string",
+                            "ssa_last_error"):
                 f.restype = C.c_int
         _lib = L
     return _lib
@@ -312,3 +327,114 @@ class SimulateST(torch.autograd.Function):
 def simulate(theta: torch.Tensor, net: Net, cfg: W.RunConfig, x0: torch.Tensor,
              bwd_mode: str = "auto", tie_capacity: int = 0) -> torch.Tensor:
     return SimulateST.apply(theta, net, cfg, x0, bwd_mode, tie_capacity)
+
+
+# ---------------------------------------------------------------------------
+# Gene-regulatory network classifier
+# ---------------------------------------------------------------------------
+class Grn:
+    """Handle of a gene-network classifier run shape (see include/ssa.h)."""
+
+    def __init__(self, net: W.GrnNet, n_images: int, n_rep: int):
+        self.net = net
+        self.n_images, self.n_rep = int(n_images), int(n_rep)
+        self.B = self.n_images * self.n_rep
+        d = _GrnDesc(net.n_in, net.n_hid, net.n_out, self.n_images, self.n_rep, float(net.beta),
+                     float(net.delta_min))
+        h = C.c_void_p()
+        _check(lib().ssa_grn_create(C.byref(d), C.byref(h)), "ssa_grn_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.ssa_grn_destroy(h)
+            self.handle = None
+
+
+@dataclass
+class GrnForward:
+    u_hid: torch.Tensor        # float32 [n_images, n_hid]
+    x_final: torch.Tensor      # int32 [n_hid + n_out, B]
+    t_final: torch.Tensor      # float64 [B]
+    steps_done: torch.Tensor   # int32 [B]
+    obs: torch.Tensor          # float64 [n_out, B]
+    tape: Optional[torch.Tensor]
+    ties: Optional[torch.Tensor]
+    n_ties: Optional[torch.Tensor]
+    ccfg: _Cfg
+
+    tie_records = Forward.tie_records
+
+
+def grn_buffer_sizes(g: Grn, ccfg: _Cfg):
+    tb, wb = C.c_size_t(), C.c_size_t()
+    _check(lib().ssa_grn_buffer_sizes(g.handle, C.byref(ccfg), C.byref(tb), C.byref(wb)), "ssa_grn_buffer_sizes")
+    return tb.value, wb.value
+
+
+def grn_forward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tensor,
+                x0: Optional[torch.Tensor] = None, *, keep_tape: bool = True, tie_capacity: int = 4096,
+                traj_ids: Optional[torch.Tensor] = None, d_epoch: Optional[torch.Tensor] = None,
+                buffers: Optional[GrnForward] = None, stream=None) -> GrnForward:
+    """Runs ssa_grn_forward.  theta float32 [P], x_img float32 [n_images, n_in] (CUDA)."""
+    dev = theta.device
+    n = g.net
+    assert theta.dtype == torch.float32 and theta.is_cuda and theta.numel() == n.n_params
+    assert x_img.dtype == torch.float32 and x_img.is_cuda and x_img.shape == (g.n_images, n.n_in)
+    if x0 is None:
+        x0 = torch.zeros((n.n_species, g.B), dtype=torch.int32, device=dev)
+    assert x0.dtype == torch.int32 and x0.is_cuda and x0.numel() == n.n_species * g.B
+    ccfg = make_cfg(cfg, tie_capacity, "auto", traj_ids, d_epoch)
+    tb, _ = grn_buffer_sizes(g, ccfg)
+    if buffers is None:
+        buffers = GrnForward(
+            torch.empty((g.n_images, n.n_hid), dtype=torch.float32, device=dev),
+            torch.empty((n.n_species, g.B), dtype=torch.int32, device=dev),
+            torch.empty(g.B, dtype=torch.float64, device=dev),
+            torch.empty(g.B, dtype=torch.int32, device=dev),
+            torch.empty((n.n_out, g.B), dtype=torch.float64, device=dev),
+            torch.empty(max(tb, 1), dtype=torch.uint8, device=dev) if keep_tape else None,
+            torch.empty(max(tie_capacity, 1) * TIE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+            if tie_capacity else None,
+            torch.zeros(1, dtype=torch.int32, device=dev) if tie_capacity else None,
+            ccfg)
+    else:
+        buffers.ccfg = ccfg
+    b = buffers
+    rc = lib().ssa_grn_forward(g.handle, C.byref(ccfg), _ptr(theta), _ptr(x_img.contiguous()),
+                               _ptr(x0.contiguous()), _ptr(b.u_hid), _ptr(b.x_final), _ptr(b.t_final),
+                               _ptr(b.steps_done), _ptr(b.obs), _ptr(b.tape),
+                               b.tape.numel() if b.tape is not None else 0, _ptr(b.ties), _ptr(b.n_ties),
+                               _stream(stream))
+    _check(rc, "ssa_grn_forward")
+    return b
+
+
+def grn_backward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tensor, fwd: GrnForward,
+                 d_obs: torch.Tensor, per_traj: bool = False, d_params: Optional[torch.Tensor] = None,
+                 work: Optional[torch.Tensor] = None, stream=None):
+    """Runs ssa_grn_backward; returns d_params float32 [P] and, if asked, the
+    compact per-trajectory gradients float64 [B, C]."""
+    assert fwd.tape is not None, "the forward kept no tape"
+    assert d_obs.dtype == torch.float64 and d_obs.is_cuda and d_obs.numel() == g.net.n_out * g.B
+    dev = theta.device
+    _, wb = grn_buffer_sizes(g, fwd.ccfg)
+    if work is None:
+        work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    if d_params is None:
+        d_params = torch.empty(g.net.n_params, dtype=torch.float32, device=dev)
+    comp = torch.empty((g.B, g.net.n_compact), dtype=torch.float64, device=dev) if per_traj else None
+    rc = lib().ssa_grn_backward(g.handle, C.byref(fwd.ccfg), _ptr(theta), _ptr(x_img.contiguous()),
+                                _ptr(fwd.u_hid), _ptr(fwd.x_final), _ptr(fwd.steps_done), _ptr(fwd.tape),
+                                fwd.tape.numel(), _ptr(d_obs.contiguous()), _ptr(d_params), _ptr(comp),
+                                _ptr(work), work.numel(), _stream(stream))
+    _check(rc, "ssa_grn_backward")
+    return (d_params, comp) if per_traj else d_params
+
+
+def grn_device_status(g: Grn, stream=None) -> int:
+    flags = C.c_uint32()
+    rc = lib().ssa_grn_device_status(g.handle, _stream(stream), C.byref(flags))
+    _check(rc, "ssa_grn_device_status")
+    return flags.value

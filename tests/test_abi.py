@@ -70,3 +70,24 @@ def test_struct_sizes_match_header(L):
     assert C.sizeof(ssa._Cfg) == 72
     assert ssa.TIE_DTYPE.itemsize == 24
     assert C.sizeof(ssa._Layout) == 40
+
+
+def test_grn_host_side_checks(L):
+    from paper_2602_19775_amd import ssa
+    assert C.sizeof(ssa._GrnDesc) == 28
+    h = C.c_void_p()
+    d = ssa._GrnDesc(784, 128, 10, 4, 2, 10.0, 0.25)
+    assert L.ssa_grn_create(C.byref(d), C.byref(h)) == -2          # hidden layer must be 256 wide
+    assert b"256" in L.ssa_last_error()
+    d = ssa._GrnDesc(784, 256, 17, 4, 2, 10.0, 0.25)
+    assert L.ssa_grn_create(C.byref(d), C.byref(h)) == -2          # at most 16 output genes
+    d = ssa._GrnDesc(784, 256, 10, 0, 2, 10.0, 0.25)
+    assert L.ssa_grn_create(C.byref(d), C.byref(h)) == -1
+    d = ssa._GrnDesc(784, 256, 10, 4, 2, -1.0, 0.25)
+    assert L.ssa_grn_create(C.byref(d), C.byref(h)) == -1
+    cfg = ssa._Cfg()
+    L.ssa_config_default(C.byref(cfg))
+    tb, wb = C.c_size_t(), C.c_size_t()
+    assert L.ssa_grn_buffer_sizes(None, C.byref(cfg), C.byref(tb), C.byref(wb)) == -1
+    assert L.ssa_grn_forward(None, C.byref(cfg), *([None] * 9), 0, None, None, None) == -1
+    assert L.ssa_grn_backward(None, C.byref(cfg), *([None] * 6), 0, None, None, None, None, 0, None) == -1
