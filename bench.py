@@ -1,11 +1,16 @@
 #!/usr/bin/env python3
 """Throughput of the batched exact SSA step, forward and forward+backward, on one MI355X.
 
-Workload: reversible dimerisation 2A <-> A2 (kf = 1e-3, kb = 0.1, A(0) = 100),
+Default workload: reversible dimerisation 2A <-> A2 (kf = 1e-3, kb = 0.1, A(0) = 100),
 65,536 trajectories x 10,000 steps each, observation = exact bin averages of A
 over 20 bins on [0, 2500], loss = MSE of per-bin ensemble mean and variance
 against targets from a seeded run at kf = 2e-3, kb = 0.05, Gumbel-Softmax
 temperature 0.5, checkpoints every 256 steps, gradients with respect to ln k.
+
+Other workloads (--workload): the oscillator (9 species, 16 channels, 65,536
+trajectories x 200,000 steps), an uneven batch of 4,096 random networks in one
+launch, and the 784 -> 256 -> 10 gene-network classifier (512 images x 32
+trajectories x 2,000 steps, cross-entropy on the final output counts).
 
 One timed step = ssa_forward + loss (PyTorch FP64) + ssa_backward (+ the FP64
 gradient reduction).  `value` counts fired reactions per second of that step;
@@ -84,15 +89,186 @@ def slots(ops: dict, cost: dict) -> float:
     return sum(n * cost[k] for k, n in ops.items())
 
 
+def alu_ops_per_step_grn(n_hid: int, n_out: int, backward: bool, hidden_frac: float) -> dict:
+    """Algorithmic vector-ALU operations of one gene-network step of one
+    trajectory (same kinds as alu_ops_per_step).  hidden_frac: share of the
+    steps that change a hidden gene (each updates the n_out output
+    pre-activations and their production rates)."""
+    M = 2 * (n_hid + n_out)
+    nb = (M + 1 + 3) // 4
+    w = M + 1
+    ops = {"mad": 20 * nb, "int": 40 * nb + 2 * w, "cvt": w, "fp32": 2 * w, "log": w, "rcp": 0, "f64": 0}
+    ops["cvt"] += n_hid + n_out                      # decay propensities delta * count
+    ops["fp32"] += n_hid + n_out + M                 # their products, a0 sum
+    # a hidden event: v_o += U_oh in FP64 and beta sigmoid(v_o) (FP64 range
+    # reduction, exp2, reciprocal)
+    ev = {"f64": 4 * n_out, "cvt": 2 * n_out, "log": n_out, "rcp": n_out, "fp32": 3 * n_out}
+    for k, v in ev.items():
+        ops[k] += hidden_frac * v
+    if not backward:
+        ops["rcp"] += M + 1                          # 1/a_j, 1/a0
+        ops["fp32"] += M + 3 * M + 1                 # r_j, race compare/min/select, tau
+        ops["f64"] += 1                              # clock
+        ops["int"] += 1
+        return ops
+    ops["rcp"] += M + n_hid + n_out                  # 1/E_j, 1/count of the decay terms
+    ops["fp32"] += (2 * M                            # rho = r_ref a_j / E_j
+                    + 2 * M                          # sums of rho and rho (w_j - w_ref)
+                    + M + 3 * M                      # w_j - w_ref, g_j
+                    + 2 * n_hid + n_hid + 2 * n_out  # production/decay sums, decay adjoint, dL/dv
+                    + n_hid * n_out)                 # lambda_H += sum_o dL/dv_o U_oh
+    ops["cvt"] += n_hid + n_out
+    ops["f64"] += n_hid + 2 * n_out + hidden_frac * n_out   # lambda, dL/dc, dU on hidden events
+    ops["int"] += 1
+    return ops
+
+
+def bench_grn(args, torch, dev):
+    """Gene-network classifier: ssa_grn_forward (bf16 MFMA contraction +
+    simulation) + cross-entropy (PyTorch FP64) + ssa_grn_backward (adjoint,
+    FP64 reductions, dW on FP64 MFMA)."""
+    from paper_2602_19775_amd import losses, ssa
+    from paper_2602_19775_amd import workloads as W
+    import oracle
+
+    wl = W.grn_classifier(n_steps=args.n_steps or 2000)
+    net, cfg = wl.net, wl.cfg
+    g = ssa.Grn(net, wl.n_images, wl.n_rep)
+    theta = torch.tensor(wl.theta, device=dev)
+    x_img = torch.tensor(wl.images, device=dev)
+    labels = torch.tensor(wl.labels, device=dev)[torch.arange(wl.n_traj, device=dev) // wl.n_rep]
+    tie_cap = 1 << 20
+    bufs = ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap)
+    d_params = torch.empty(net.n_params, dtype=torch.float32, device=dev)
+    _, wb = ssa.grn_buffer_sizes(g, bufs.ccfg)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+
+    def step(record=None):
+        if record is not None:
+            record[0].record()
+        ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=bufs)
+        if record is not None:
+            record[1].record()
+        obs = bufs.obs.detach().requires_grad_(True)
+        loss = losses.count_cross_entropy(obs, labels)
+        (d_obs,) = torch.autograd.grad(loss, obs)
+        if record is not None:
+            record[2].record()
+        ssa.grn_backward(g, cfg, theta, x_img, bufs, d_obs, d_params=d_params, work=work)
+        if record is not None:
+            record[3].record()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        loss = step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fired = int(bufs.steps_done.sum().item())
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    loss_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    value = fired / (ms_step * 1e-3)
+
+    for _ in range(args.warmup):
+        ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=bufs)
+    torch.cuda.synchronize()
+    f0 = time.perf_counter()
+    for _ in range(args.steps):
+        ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=bufs)
+    torch.cuda.synchronize()
+    f1 = time.perf_counter()
+    fwd_rate = fired * args.steps / (f1 - f0)
+    n_ties = int(bufs.n_ties.item())
+    assert ssa.grn_device_status(g) == 0
+
+    # gradient relative error on a sample of trajectories: the oracle runs on
+    # the GPU's hidden pre-activations (the bf16 contraction is checked on its
+    # own by the parity tests)
+    obs = bufs.obs.detach().requires_grad_(True)
+    loss = losses.count_cross_entropy(obs, labels)
+    (d_obs,) = torch.autograd.grad(loss, obs)
+    _, comp = ssa.grn_backward(g, cfg, theta, x_img, bufs, d_obs, per_traj=True, work=work)
+    sample = np.arange(0, wl.n_traj, wl.n_traj // 32)[:32]
+    ties = bufs.tie_records()
+    idx = {int(q): k for k, q in enumerate(sample)}
+    ov = [(idx[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
+          for t in ties if int(t["traj"]) in idx]
+    u_gpu = bufs.u_hid.cpu().numpy().astype(np.float64)
+    dnp = d_obs.cpu().numpy().T[sample]
+    r = oracle.grn_run(net, cfg, wl.theta, u_gpu, sample // wl.n_rep, traj_ids=sample, ties=ov, d_obs=dnp,
+                       tie_threshold=2e-6)
+    cg = comp[torch.from_numpy(sample).to(dev)].cpu().numpy()
+    xf = bufs.x_final.cpu().numpy().T[sample]
+    counts_exact = bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
+    grad_rel_err = float(np.linalg.norm(cg.sum(0) - r.grad_c.sum(0)) / np.linalg.norm(r.grad_c.sum(0)))
+    # share of steps that change a hidden gene, from the oracle's traces
+    hid = []
+    for q in sample[:4]:
+        jk, _ = oracle.grn_trace(net, cfg, wl.theta, u_gpu[q // wl.n_rep], traj_id=int(q), cap=cfg.n_steps)
+        hid.append(np.mean(jk < 2 * net.n_hid))
+    hidden_frac = float(np.mean(hid))
+
+    cost = measure_issue_costs()
+    ops_f = alu_ops_per_step_grn(net.n_hid, net.n_out, False, hidden_frac)
+    ops_b = alu_ops_per_step_grn(net.n_hid, net.n_out, True, hidden_frac)
+    dom, dom_ms, ops = ("backward", bwd_ms, ops_b) if bwd_ms >= fwd_ms else ("forward", fwd_ms, ops_f)
+    per_step = slots(ops, cost)
+    achieved = fired * per_step / (dom_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
+                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
+                "slots_per_step": per_step, "ops_per_step": ops, "issue_cost_slots": cost,
+                "kernel_ms": dom_ms, "hidden_event_share": hidden_frac,
+                "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        n_try = 32
+        c0 = time.perf_counter()
+        ids = np.arange(n_try)
+        oracle.grn_run(net, cfg, wl.theta, u_gpu, ids // wl.n_rep, traj_ids=ids,
+                       d_obs=np.zeros((n_try, net.n_out)), n_threads=threads)
+        dt = time.perf_counter() - c0
+        n_cpu = int(min(wl.n_traj, max(n_try, n_try * args.cpu_seconds / max(dt, 1e-3))))
+        ids = np.arange(n_cpu)
+        c0 = time.perf_counter()
+        rc = oracle.grn_run(net, cfg, wl.theta, u_gpu, ids // wl.n_rep, traj_ids=ids,
+                            d_obs=np.zeros((n_cpu, net.n_out)), n_threads=threads)
+        dt = time.perf_counter() - c0
+        cpu = {"value": float(rc.steps_done.sum() / dt), "unit": "steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{n_cpu} of the {wl.n_traj} trajectories, full {cfg.n_steps} steps, "
+                         "forward+adjoint in FP64 on the GPU's hidden pre-activations"}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "n_traj": wl.n_traj, "n_images": wl.n_images, "n_rep": wl.n_rep,
+                   "steps_per_traj": cfg.n_steps, "n_params": net.n_params, "temperature": cfg.temperature},
+        "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate,
+        "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
+        "grad_rel_err": grad_rel_err, "counts_bit_exact_sample": counts_exact, "near_ties": n_ties,
+        "loss": float(loss.item()), "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator", "uneven"],
+    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator", "uneven", "grn"],
                     help="dimer: 2A<->A2, 65,536 x 10,000 steps (default); "
                          "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps; "
-                         "uneven: 4,096 random networks x 256 trajectories x 5,000 steps")
+                         "uneven: 4,096 random networks x 256 trajectories x 5,000 steps; "
+                         "grn: 784->256->10 gene-network classifier, 512 images x 32 trajectories x 2,000 steps")
     ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
     ap.add_argument("--n-traj", type=int, default=65536)
     ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")
@@ -115,6 +291,9 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
+
+    if args.workload == "grn":
+        return bench_grn(args, torch, dev)
 
     if args.copy_bytes:
         n = args.copy_bytes // 4

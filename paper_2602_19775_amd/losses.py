@@ -35,3 +35,10 @@ def mean_autocorrelation(obs: torch.Tensor, n_bins: int, B: int, max_lag: int, e
 
 def autocorrelation_mse(obs: torch.Tensor, target: torch.Tensor, n_bins: int, B: int, max_lag: int = 64):
     return ((mean_autocorrelation(obs, n_bins, B, max_lag) - target) ** 2).mean()
+
+
+def count_cross_entropy(obs: torch.Tensor, labels: torch.Tensor) -> torch.Tensor:
+    """Cross-entropy of the softmax over final output-gene counts (Sec. 4.3),
+    averaged over trajectories.  obs: [n_out, B] float64, labels: [B]."""
+    logits = obs.t()
+    return torch.nn.functional.cross_entropy(logits, labels)
