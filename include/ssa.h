@@ -296,7 +296,8 @@ ssa_status ssa_grn_forward(const ssa_grn *grn, const ssa_config *cfg, const floa
  * FP64 matrix cores).  d_compact (optional) receives the per-trajectory
  * partials.  Inputs are the forward's inputs and outputs with the same cfg. */
 ssa_status ssa_grn_backward(const ssa_grn *grn, const ssa_config *cfg, const float *theta,
-                            const float *x_img, const float *u_hid, const int32_t *x_final,
+                            const float *x_img, const int32_t *x0, const float *u_hid,
+                            const int32_t *x_final,
                             const int32_t *steps_done, const void *tape, size_t tape_bytes,
                             const double *d_obs, float *d_params, double *d_compact,
                             void *work, size_t work_bytes, hipStream_t stream);

@@ -42,6 +42,7 @@ struct GrnParams {
     float temperature;
     const double *d_obs;        // [n_out][B]
     double *part;               // [B][C] compact per-trajectory gradient
+    float *e_hist;              // [B][n_steps][n_out] dL/dv_o of every step (backward scratch)
     int32_t C;                  // kHid + n_out*kHid + n_out + kHid + n_out
     double *g_img;              // [n_images][C]
     float *d_params;            // [P]
@@ -49,6 +50,7 @@ struct GrnParams {
 
 hipError_t launch_hidden_input(const GrnParams &p, hipStream_t stream);
 hipError_t launch_forward(const GrnParams &p, hipStream_t stream);
+// backward sweep, then the dL/dU and dL/dc pass
 hipError_t launch_backward(const GrnParams &p, hipStream_t stream);
 hipError_t launch_reduce(const GrnParams &p, hipStream_t stream);
 

@@ -54,10 +54,13 @@ size_t tape_bytes_for(const ssa_grn *g, const ssa_config *cfg)
     return align_up(sizeof(uint32_t) * tape_words(cfg) * (size_t)g->B);
 }
 
-size_t work_bytes_for(const ssa_grn *g)
+// Backward scratch: per-trajectory partials [B][C], per-image sums
+// [n_images][C] (FP64), and dL/dv_o of every step [B][n_steps][n_out] (FP32).
+size_t work_bytes_for(const ssa_grn *g, const ssa_config *cfg)
 {
     return align_up(sizeof(double) * (size_t)g->B * g->C) +
-           align_up(sizeof(double) * (size_t)g->d.n_images * g->C);
+           align_up(sizeof(double) * (size_t)g->d.n_images * g->C) +
+           align_up(sizeof(float) * (size_t)g->B * (size_t)cfg->n_steps * g->d.n_out);
 }
 
 grn::GrnParams base_params(const ssa_grn *g, const ssa_config *cfg, const float *theta, const float *x_img)
@@ -138,7 +141,7 @@ ssa_status ssa_grn_buffer_sizes(const ssa_grn *g, const ssa_config *cfg, size_t 
     ssa_status s = check_cfg(g, cfg);
     if (s != SSA_OK) return s;
     if (tape_bytes) *tape_bytes = tape_bytes_for(g, cfg);
-    if (work_bytes) *work_bytes = work_bytes_for(g);
+    if (work_bytes) *work_bytes = work_bytes_for(g, cfg);
     return SSA_OK;
 }
 
@@ -178,19 +181,21 @@ ssa_status ssa_grn_forward(const ssa_grn *g, const ssa_config *cfg, const float 
 }
 
 ssa_status ssa_grn_backward(const ssa_grn *g, const ssa_config *cfg, const float *theta, const float *x_img,
-                            const float *u_hid, const int32_t *x_final, const int32_t *steps_done,
+                            const int32_t *x0, const float *u_hid, const int32_t *x_final,
+                            const int32_t *steps_done,
                             const void *tape, size_t tape_bytes, const double *d_obs, float *d_params,
                             double *d_compact, void *work, size_t work_bytes, hipStream_t stream)
 {
     g_last_error.clear();
     ssa_status s = check_cfg(g, cfg);
     if (s != SSA_OK) return s;
-    if (!theta || !x_img || !u_hid || !x_final || !steps_done || !d_obs || !d_params)
-        return fail(SSA_EINVAL, "theta, x_img, u_hid, x_final, steps_done, d_obs and d_params are required");
+    if (!theta || !x_img || !x0 || !u_hid || !x_final || !steps_done || !d_obs || !d_params)
+        return fail(SSA_EINVAL, "theta, x_img, x0, u_hid, x_final, steps_done, d_obs and d_params are required");
     if (!tape || tape_bytes < tape_bytes_for(g, cfg)) return fail(SSA_EWORKSPACE, "tape buffer too small");
-    if (!work || work_bytes < work_bytes_for(g)) return fail(SSA_EWORKSPACE, "work buffer too small");
+    if (!work || work_bytes < work_bytes_for(g, cfg)) return fail(SSA_EWORKSPACE, "work buffer too small");
     grn::GrnParams p = base_params(g, cfg, theta, x_img);
     p.u_hid = const_cast<float *>(u_hid);
+    p.x0 = x0;
     p.x_final = const_cast<int32_t *>(x_final);
     p.steps_done = const_cast<int32_t *>(steps_done);
     p.tape = (uint32_t *)const_cast<void *>(tape);
@@ -198,6 +203,7 @@ ssa_status ssa_grn_backward(const ssa_grn *g, const ssa_config *cfg, const float
     char *w = (char *)work;
     p.part = d_compact ? d_compact : (double *)w;
     p.g_img = (double *)(w + align_up(sizeof(double) * (size_t)g->B * g->C));
+    p.e_hist = (float *)((char *)p.g_img + align_up(sizeof(double) * (size_t)g->d.n_images * g->C));
     p.d_params = d_params;
     hipError_t e = grn::launch_backward(p, stream);
     if (e != hipSuccess) return hip_fail(e, "backward launch");

@@ -96,7 +96,7 @@ def lib():
         L.ssa_grn_destroy.argtypes = [V]
         L.ssa_grn_buffer_sizes.argtypes = [V, C.POINTER(_Cfg), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.ssa_grn_forward.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, V, V, V, C.c_size_t, V, V, V]
-        L.ssa_grn_backward.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, C.c_size_t, V, V, V, V,
+        L.ssa_grn_backward.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, V, C.c_size_t, V, V, V, V,
                                        C.c_size_t, V]
         L.ssa_grn_device_status.argtypes = [V, V, C.POINTER(C.c_uint32)]
         for name in EXPORTS:
@@ -354,6 +354,7 @@ class Grn:
 
 @dataclass
 class GrnForward:
+    x0: torch.Tensor           # int32 [n_hid + n_out, B] (the forward's input)
     u_hid: torch.Tensor        # float32 [n_images, n_hid]
     x_final: torch.Tensor      # int32 [n_hid + n_out, B]
     t_final: torch.Tensor      # float64 [B]
@@ -389,6 +390,7 @@ def grn_forward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tens
     tb, _ = grn_buffer_sizes(g, ccfg)
     if buffers is None:
         buffers = GrnForward(
+            x0,
             torch.empty((g.n_images, n.n_hid), dtype=torch.float32, device=dev),
             torch.empty((n.n_species, g.B), dtype=torch.int32, device=dev),
             torch.empty(g.B, dtype=torch.float64, device=dev),
@@ -401,6 +403,7 @@ def grn_forward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tens
             ccfg)
     else:
         buffers.ccfg = ccfg
+        buffers.x0 = x0
     b = buffers
     rc = lib().ssa_grn_forward(g.handle, C.byref(ccfg), _ptr(theta), _ptr(x_img.contiguous()),
                                _ptr(x0.contiguous()), _ptr(b.u_hid), _ptr(b.x_final), _ptr(b.t_final),
@@ -426,7 +429,7 @@ def grn_backward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Ten
         d_params = torch.empty(g.net.n_params, dtype=torch.float32, device=dev)
     comp = torch.empty((g.B, g.net.n_compact), dtype=torch.float64, device=dev) if per_traj else None
     rc = lib().ssa_grn_backward(g.handle, C.byref(fwd.ccfg), _ptr(theta), _ptr(x_img.contiguous()),
-                                _ptr(fwd.u_hid), _ptr(fwd.x_final), _ptr(fwd.steps_done), _ptr(fwd.tape),
+                                _ptr(fwd.x0.contiguous()), _ptr(fwd.u_hid), _ptr(fwd.x_final), _ptr(fwd.steps_done), _ptr(fwd.tape),
                                 fwd.tape.numel(), _ptr(d_obs.contiguous()), _ptr(d_params), _ptr(comp),
                                 _ptr(work), work.numel(), _stream(stream))
     _check(rc, "ssa_grn_backward")

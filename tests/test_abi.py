@@ -90,4 +90,4 @@ def test_grn_host_side_checks(L):
     tb, wb = C.c_size_t(), C.c_size_t()
     assert L.ssa_grn_buffer_sizes(None, C.byref(cfg), C.byref(tb), C.byref(wb)) == -1
     assert L.ssa_grn_forward(None, C.byref(cfg), *([None] * 9), 0, None, None, None) == -1
-    assert L.ssa_grn_backward(None, C.byref(cfg), *([None] * 6), 0, None, None, None, None, 0, None) == -1
+    assert L.ssa_grn_backward(None, C.byref(cfg), *([None] * 7), 0, None, None, None, None, 0, None) == -1
