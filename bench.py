@@ -187,6 +187,30 @@ def bench_grn(args, torch, dev):
     n_ties = int(bufs.n_ties.item())
     assert ssa.grn_device_status(g) == 0
 
+    graph = None
+    if not args.no_graph:
+        from paper_2602_19775_amd.graph import CapturedStep
+        ep = torch.zeros(1, dtype=torch.int32, device=dev)
+        gbufs = ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=0, d_epoch=ep)
+        gdp = torch.empty_like(d_params)
+        gwork = torch.empty_like(work)
+
+        def gstep():
+            ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=0, d_epoch=ep, buffers=gbufs)
+            gobs = gbufs.obs.detach().requires_grad_(True)
+            (gd,) = torch.autograd.grad(losses.count_cross_entropy(gobs, labels), gobs)
+            ssa.grn_backward(g, cfg, theta, x_img, gbufs, gd, d_params=gdp, work=gwork)
+            ep.add_(1)
+        cap = CapturedStep(gstep, warmup=args.warmup)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.steps):
+            cap.replay()
+        torch.cuda.synchronize()
+        g1 = time.perf_counter()
+        graph = {"steps_per_s": fired * args.steps / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / args.steps}
+        del cap, gbufs, gwork
+
     # gradient relative error on a sample of trajectories: the oracle runs on
     # the GPU's hidden pre-activations (the bf16 contraction is checked on its
     # own by the parity tests)
@@ -251,7 +275,7 @@ def bench_grn(args, torch, dev):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "n_traj": wl.n_traj, "n_images": wl.n_images, "n_rep": wl.n_rep,
                    "steps_per_traj": cfg.n_steps, "n_params": net.n_params, "temperature": cfg.temperature},
-        "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate,
+        "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate, "graph_replay": graph,
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
         "grad_rel_err": grad_rel_err, "counts_bit_exact_sample": counts_exact, "near_ties": n_ties,
         "loss": float(loss.item()), "roofline": roofline, "cpu_baseline": cpu,
@@ -273,6 +297,9 @@ def main():
     ap.add_argument("--n-traj", type=int, default=65536)
     ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")
     ap.add_argument("--ckpt-every", type=int, default=0, help="checkpoint interval (0: the workload's)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the execution plan with the autotuner (untimed; cached under ~/.cache)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -327,6 +354,14 @@ def main():
         theta = torch.tensor(bw.theta(), device=dev)
         x0 = torch.tensor(bw.x0_packed(), device=dev)
         theta_t = torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device=dev)
+    plan = None
+    if args.autotune:
+        from paper_2602_19775_amd import autotune
+        t_obs_l = [cfg.t_obs] * len(nets) if cfg.obs_kind == W.OBS_BINS else None
+        plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l)
+        h = plan.net(nets, Bs, t_obs_l)
+        cfg = plan.config(cfg)
+        args.bwd_mode = plan.bwd_mode
     net, B = nets[0], Bs[0]
     nb, nob = cfg.n_bins, len(net.obs_species)
 
@@ -403,6 +438,32 @@ def main():
     n_ties = int(bufs.n_ties.item())
     assert ssa.device_status(h) == 0
 
+    # the same step captured into one HIP graph (the epoch advances on the
+    # device, so every replay draws a fresh stream), replayed
+    graph = None
+    if not args.no_graph:
+        from paper_2602_19775_amd.graph import CapturedStep
+        ep = torch.zeros(1, dtype=torch.int32, device=dev)
+        gbufs = ssa.forward(h, cfg, theta, x0, tie_capacity=0, bwd_mode=args.bwd_mode, d_epoch=ep)
+        gdp = torch.empty_like(d_params)
+
+        def gstep():
+            ssa.forward(h, cfg, theta, x0, buffers=gbufs, tie_capacity=0, bwd_mode=args.bwd_mode, d_epoch=ep)
+            gobs = gbufs.obs.detach().requires_grad_(True)
+            (gd,) = torch.autograd.grad(loss_fn(gobs), gobs)
+            ssa.backward(h, cfg, theta, x0, gbufs, gd, d_params=gdp)
+            ep.add_(1)
+        cap = CapturedStep(gstep, warmup=args.warmup)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.steps):
+            cap.replay()
+        torch.cuda.synchronize()
+        g1 = time.perf_counter()
+        gfired = int(gbufs.steps_done.sum().item())
+        graph = {"steps_per_s": gfired * args.steps / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / args.steps}
+        del cap, gbufs
+
     # gradient relative error against the oracle on a sample of trajectories
     # (of the first network of the batch)
     import oracle
@@ -476,8 +537,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": name, "n_traj": int(sum(Bs)), "n_networks": len(nets), "steps_per_traj": cfg.n_steps, "n_bins": nb,
                    "t_obs": cfg.t_obs, "temperature": cfg.temperature, "ckpt_every": cfg.ckpt_every,
-                   "bwd_mode": args.bwd_mode},
-        "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate,
+                   "bwd_mode": args.bwd_mode,
+                   "plan": None if plan is None else {"exec_mode": plan.exec_mode, "wave_split": plan.wave_split}},
+        "forward_steps_per_s": fwd_rate, "graph_replay": graph, "fwdbwd_over_forward": value / fwd_rate,
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
         "grad_rel_err": grad_rel_err, "counts_bit_exact_sample": counts_exact, "near_ties": n_ties,
         "loss": float(loss.item()), "roofline": roofline, "cpu_baseline": cpu,
