@@ -1,0 +1,149 @@
+"""Parity at the benchmarked sizes, in the launch configuration bench.py times.
+
+The GPU runs the whole workload; the oracle recomputes a sample of
+trajectories one by one (same global trajectory ids, so the same random
+streams), with the GPU's near-tie log.  dL/dobs comes from the workload's own
+loss on the GPU's observation, as in the benchmark.
+
+- counts and step counts bit-exact, clocks within 1e-5 relative;
+- per-trajectory gradients within 1e-5 (bin observations: the trajectories
+  whose event times stay clear of every bin edge, see test_gpu_parity);
+- the sample's summed gradient within 1e-5;
+- the reduced d_params equal the FP64 sum of the (FP32) per-trajectory
+  gradients, up to their rounding.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_19775_amd import losses
+from paper_2602_19775_amd import workloads as W
+
+from test_gpu_parity import _ties_for_oracle, _x0, assert_forward_parity, assert_grad_parity, edge_safe
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_19775_amd import ssa as m
+    m.lib()
+    return m
+
+
+def _single_network(ssa, wl, loss_of, sample):
+    net, B, cfg = wl.net, wl.n_traj, wl.cfg
+    h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = _x0([net], [B])
+    tf = ssa.forward(h, cfg.replace(purpose=W.PURPOSE_TARGET), loss_of["target_theta"], x0, keep_ckpt=False,
+                     tie_capacity=0)
+    loss_fn = loss_of["make"](tf.obs)
+    del tf
+    fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 22)
+    obs = fwd.obs.detach().requires_grad_(True)
+    (d_obs,) = torch.autograd.grad(loss_fn(obs), obs)
+    dp, ppt = ssa.backward(h, cfg, th, x0, fwd, d_obs, per_traj=True)
+    torch.cuda.synchronize()
+    assert ssa.device_status(h) == 0
+    nb, nob, N = cfg.n_bins, len(net.obs_species), net.n_species
+    ids = np.asarray(sample)
+    gpu = {"x_final": fwd.x_final.cpu().numpy().reshape(N, B).T,
+           "t_final": fwd.t_final.cpu().numpy(), "steps_done": fwd.steps_done.cpu().numpy(),
+           "obs": fwd.obs.cpu().numpy()[: nb * nob * B].reshape(nb, nob, B).transpose(2, 0, 1)}
+    ppt = ppt.cpu().numpy().reshape(net.n_params, B).T
+    dnp = d_obs.cpu().numpy()[: nb * nob * B].reshape(nb, nob, B).transpose(2, 0, 1)
+    index = {int(q): k for k, q in enumerate(ids)}
+    r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=ids, ties=_ties_for_oracle(fwd.tie_records(), 0, index),
+                   d_obs=dnp[ids])
+    assert_forward_parity(gpu, r, ids, cfg)
+    keep = edge_safe(gpu, r, ids)
+    for k in np.flatnonzero(keep):
+        assert_grad_parity(ppt[ids[k]], r.grad[k])
+    gs, rs = ppt[ids].sum(0), r.grad.sum(0)
+    assert np.linalg.norm(gs - rs) <= 1e-5 * np.linalg.norm(rs)
+    # the per-trajectory gradients are handed out in FP32: their sum carries
+    # that rounding, relative to the sum of magnitudes
+    total = ppt.astype(np.float64).sum(0)
+    mag = np.abs(ppt.astype(np.float64)).sum(0)
+    assert np.all(np.abs(dp.cpu().numpy() - total) <= 1e-5 * np.abs(total) + 1e-6 * mag)
+    return keep
+
+
+def test_dimer_65536x10000(ssa):
+    wl = W.dimer_fwdbwd_64k()
+    B, nb = wl.n_traj, wl.cfg.n_bins
+
+    def make(tobs):
+        tm, tv = losses.bin_moments(tobs, nb, 1, B)
+        tm, tv = tm.clone(), tv.clone()
+        return lambda obs: losses.moment_mse(obs, tm, tv, nb, 1, B)
+    target = torch.tensor(np.log(np.array(W.DIMER_TARGET_RATES)).astype(np.float32), device="cuda")
+    g = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([[0, B - 1], g.choice(B, 62, replace=False)]))
+    keep = _single_network(ssa, wl, {"make": make, "target_theta": target}, sample)
+    assert keep.mean() > 0.5
+
+
+def test_oscillator_65536x200000(ssa):
+    wl = W.oscillator_fwdbwd_64k()
+    B, nb = wl.n_traj, wl.cfg.n_bins
+
+    def make(tobs):
+        tac = losses.mean_autocorrelation(tobs, nb, B, 64).clone()
+        return lambda obs: losses.autocorrelation_mse(obs, tac, nb, B, 64)
+    target = torch.tensor(wl.extra["target_net"].theta0, device="cuda")
+    sample = np.array([0, 4097, 33333, B - 1])
+    _single_network(ssa, wl, {"make": make, "target_theta": target}, sample)
+
+
+def test_uneven_batch_4096x256x5000(ssa):
+    bw = W.uneven_batch()
+    nets, Bs, cfg = bw.nets, bw.n_traj, bw.cfg
+    h = ssa.Net(nets, Bs)
+    th = torch.tensor(bw.theta(), device="cuda")
+    x0 = torch.tensor(bw.x0_packed(), device="cuda")
+    rows = sum(len(n.obs_species) for n in nets)
+    Bn = Bs[0]
+    tf = ssa.forward(h, cfg.replace(purpose=W.PURPOSE_TARGET),
+                     torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device="cuda"), x0,
+                     keep_ckpt=False, tie_capacity=0)
+    tmean = tf.obs[: rows * Bn].view(rows, Bn).mean(dim=1).clone()
+    del tf
+    fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 23)
+    obs = fwd.obs.detach().requires_grad_(True)
+    loss = ((obs[: rows * Bn].view(rows, Bn).mean(dim=1) - tmean) ** 2).mean()
+    (d_obs,) = torch.autograd.grad(loss, obs)
+    dp, ppt = ssa.backward(h, cfg, th, x0, fwd, d_obs, per_traj=True)
+    torch.cuda.synchronize()
+    assert ssa.device_status(h) == 0
+    ties = fwd.tie_records()
+    xf, tfin, sd = fwd.x_final.cpu().numpy(), fwd.t_final.cpu().numpy(), fwd.steps_done.cpu().numpy()
+    ob, dob, pp = fwd.obs.cpu().numpy(), d_obs.cpu().numpy(), ppt.cpu().numpy()
+    g = np.random.default_rng(5)
+    picks = np.unique(np.concatenate([[0, len(nets) - 1], g.choice(len(nets), 14, replace=False)]))
+    for n in picks:
+        net = nets[n]
+        L = h.layout(int(n), cfg.obs_kind, cfg.n_bins)
+        nob, N, P = len(net.obs_species), net.n_species, net.n_params
+        ids = np.array([0, 1, 129, Bn - 1])
+        index = {int(L.traj_offset + q): k for k, q in enumerate(ids)}
+        ov = [(index[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
+              for t in ties if int(t["traj"]) in index]
+        dn = dob[L.obs_offset: L.obs_offset + nob * Bn].reshape(nob, Bn).T[ids]
+        r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=L.traj_offset + ids, ties=ov, d_obs=dn)
+        gpu = {"x_final": xf[L.state_offset: L.state_offset + N * Bn].reshape(N, Bn).T,
+               "t_final": tfin[L.traj_offset: L.traj_offset + Bn],
+               "steps_done": sd[L.traj_offset: L.traj_offset + Bn],
+               "obs": ob[L.obs_offset: L.obs_offset + nob * Bn].reshape(nob, Bn).T}
+        assert_forward_parity(gpu, r, ids, cfg)
+        gq = pp[L.ppt_offset: L.ppt_offset + P * Bn].reshape(P, Bn).T
+        for k, q in enumerate(ids):
+            assert_grad_parity(gq[q], r.grad[k])
+        tot = gq.astype(np.float64).sum(0)
+        mag = np.abs(gq.astype(np.float64)).sum(0)
+        dpn = dp.cpu().numpy()[L.param_offset: L.param_offset + P]
+        assert np.all(np.abs(dpn - tot) <= 1e-5 * np.abs(tot) + 1e-6 * mag)
