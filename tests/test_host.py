@@ -1,0 +1,55 @@
+"""Host-side logic that needs no GPU: the autotuner's plan space, batch
+signature and cache, and the benchmark's single-GPU contract."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+from paper_2602_19775_amd import autotune as A
+from paper_2602_19775_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_candidate_plans():
+    plans = A.candidate_plans(10000)
+    assert len(plans) == len(set(plans))
+    assert {p.exec_mode for p in plans} == {"spec", "lane", "wave"}
+    assert all(p.ckpt_every <= 64 for p in plans if p.bwd_mode == "recompute")
+    assert {p.wave_split for p in plans if p.exec_mode == "wave"} == {0, 1}
+    short = A.candidate_plans(100)
+    assert max(p.ckpt_every for p in short) == 64
+
+
+def test_signature_separates_batches():
+    net = W.dimerization_2a()
+    cfg = W.RunConfig(n_steps=10000, obs_kind=W.OBS_BINS, n_bins=20)
+    s = A.signature([net], [1024], cfg)
+    assert s == A.signature([net], [1024], cfg)
+    assert s == A.signature([net], [1024], cfg.replace(n_steps=9000))       # same power-of-two bucket
+    assert s != A.signature([net], [2048], cfg)
+    assert s != A.signature([net], [1024], cfg.replace(n_steps=40000))
+    assert s != A.signature([net], [1024], cfg.replace(obs_kind=W.OBS_FINAL, n_bins=0))
+    assert s != A.signature([W.isomerization()], [1024], cfg)
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "sub" / "tune.json")
+    c = A.Cache(path)
+    assert c.get("k") is None
+    p = A.Plan("wave", 1, "recompute", 64)
+    c.put("k", p, {"wave/split1/recompute/K64": 1.5, "spec/split-1/tape/K256": None})
+    assert A.Cache(path).get("k") == p
+    assert json.load(open(path))["k"]["timings_ms"]["spec/split-1/tape/K256"] is None
+    with open(path, "w") as f:
+        f.write("{not json")
+    assert A.Cache(path).get("k") is None
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
