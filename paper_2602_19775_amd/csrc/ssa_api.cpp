@@ -89,6 +89,7 @@ struct ssa_net {
     int64_t traj_total = 0, state_total = 0, param_total = 0, obsb_total = 0, part_total = 0,
             ppt_total = 0;
     int max_M = 0;
+    int64_t max_B = 0;
     int device = 0;
 };
 
@@ -143,12 +144,19 @@ CkptLayout ckpt_layout(const ssa_net *net, const ssa_config *cfg)
     return L;
 }
 
-// Work buffer: [tie counter | flags scratch] then FP64 per-channel partials.
+// Work buffer: [header: work counter] then FP64 per-channel partials, then
+// the per-chunk sums of the gradient reduction.
 constexpr size_t kWorkHeader = 256;
+
+size_t partials_bytes(const ssa_net *net)
+{
+    return align_up(sizeof(double) * (size_t)net->part_total, 256);
+}
 
 size_t work_bytes_for(const ssa_net *net)
 {
-    return kWorkHeader + align_up(sizeof(double) * (size_t)net->part_total, 256);
+    return kWorkHeader + partials_bytes(net) +
+           align_up(sizeof(double) * (size_t)net->param_total * reduce_chunks(net->max_B), 256);
 }
 
 ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
@@ -464,6 +472,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         net->part_total += (int64_t)M * B;
         net->ppt_total += (int64_t)P * B;
         net->max_M = std::max(net->max_M, M);
+        net->max_B = std::max<int64_t>(net->max_B, B);
         net->nets_h.push_back(nd);
         roff += M;
         soff += (int64_t)M * N;
@@ -670,8 +679,9 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
     p.work_counter = (uint32_t *)((char *)work + 64);
     s = launch_all_classes(net, p, true, stream);
     if (s != SSA_OK) return s;
-    hipError_t e = launch_reduce_params(net->nets_d, net->n_networks, net->pmap_off_d, net->pmap_ch_d,
-                                        net->param_net_d, net->param_total, p.partials, d_params,
+    double *chunk_sums = (double *)((char *)work + kWorkHeader + partials_bytes(net));
+    hipError_t e = launch_reduce_params(net->nets_d, net->pmap_off_d, net->pmap_ch_d, net->param_net_d,
+                                        net->param_total, net->max_B, p.partials, chunk_sums, d_params,
                                         d_params_per_traj, stream);
     if (e != hipSuccess) return hip_fail(e, "gradient reduction");
     return SSA_OK;

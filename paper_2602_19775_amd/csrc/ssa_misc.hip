@@ -4,6 +4,8 @@
 #include "ssa_device.hpp"
 #include "ssa_misc.hpp"
 
+#include <algorithm>
+
 #include <math.h>
 
 namespace ssa {
@@ -87,19 +89,25 @@ __global__ void step_batch_kernel(RunParams p, int n_networks, uint32_t step, in
 // of partials[j][i], summed in a fixed order (thread-strided FP64 sums, then
 // a fixed LDS tree), so repeated runs give identical bits.
 constexpr int kRedThreads = 256;
+constexpr int64_t kRedChunk = 4096;   // trajectories per block of the first reduction pass
 
-__global__ __launch_bounds__(kRedThreads) void reduce_params_kernel(
-    const NetDev *nets, int n_networks, const int32_t *pmap_off, const int32_t *pmap_ch,
-    const int32_t *param_net, const double *partials, float *d_params, float *d_ppt)
+// Pass 1: the sum of each parameter's per-trajectory partials over one chunk
+// of kRedChunk trajectories (channels sharing a parameter are added first),
+// in a fixed tree order; also the per-trajectory gradient if asked for.
+__global__ __launch_bounds__(kRedThreads) void reduce_chunks_kernel(
+    const NetDev *nets, const int32_t *pmap_off, const int32_t *pmap_ch, const int32_t *param_net,
+    const double *partials, int n_chunks, double *chunk_sums, float *d_ppt)
 {
     __shared__ double s[kRedThreads];
     const int pg = blockIdx.x;                   // global parameter index
+    const int chunk = blockIdx.y;
     const int n = param_net[pg];
     const NetDev nd = nets[n];
     const int pl = (int)(pg - nd.param_off);
     const int64_t B = nd.B;
+    const int64_t lo = (int64_t)chunk * kRedChunk, hi = min(B, lo + kRedChunk);
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < B; i += kRedThreads) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kRedThreads) {
         double v = 0.0;
         for (int e = pmap_off[pg]; e < pmap_off[pg + 1]; ++e)
             v += partials[nd.part_off + (int64_t)pmap_ch[e] * B + i];
@@ -112,7 +120,21 @@ __global__ __launch_bounds__(kRedThreads) void reduce_params_kernel(
         if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) d_params[pg] = (float)s[0];
+    if (threadIdx.x == 0) chunk_sums[(int64_t)pg * n_chunks + chunk] = s[0];
+}
+
+// Pass 2: the chunk sums of each parameter, in chunk order.
+__global__ __launch_bounds__(256) void reduce_total_kernel(const NetDev *nets, const int32_t *param_net,
+                                                           int64_t param_total, int n_chunks,
+                                                           const double *chunk_sums, float *d_params)
+{
+    const int64_t pg = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (pg >= param_total) return;
+    const int64_t B = nets[param_net[pg]].B;
+    const int used = (int)((B + kRedChunk - 1) / kRedChunk);
+    double acc = 0.0;
+    for (int c = 0; c < used && c < n_chunks; ++c) acc += chunk_sums[pg * n_chunks + c];
+    d_params[pg] = (float)acc;
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v)
@@ -157,13 +179,24 @@ hipError_t launch_step_batch(const RunParams &p, int n_networks, uint32_t step, 
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_params(const NetDev *nets, int n_networks, const int32_t *pmap_off,
-                                const int32_t *pmap_ch, const int32_t *param_net, int64_t param_total,
-                                const double *partials, float *d_params, float *d_ppt, hipStream_t stream)
+int reduce_chunks(int64_t max_traj)
+{
+    return (int)std::max<int64_t>(1, (max_traj + kRedChunk - 1) / kRedChunk);
+}
+
+hipError_t launch_reduce_params(const NetDev *nets, const int32_t *pmap_off, const int32_t *pmap_ch,
+                                const int32_t *param_net, int64_t param_total, int64_t max_traj,
+                                const double *partials, double *chunk_sums, float *d_params, float *d_ppt,
+                                hipStream_t stream)
 {
     if (param_total == 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_params_kernel, dim3((unsigned)param_total), dim3(kRedThreads), 0, stream,
-                       nets, n_networks, pmap_off, pmap_ch, param_net, partials, d_params, d_ppt);
+    const int nc = reduce_chunks(max_traj);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)param_total, (unsigned)nc), dim3(kRedThreads), 0,
+                       stream, nets, pmap_off, pmap_ch, param_net, partials, nc, chunk_sums, d_ppt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_total_kernel, dim3((unsigned)((param_total + 255) / 256)), dim3(256), 0, stream,
+                       nets, param_net, param_total, nc, chunk_sums, d_params);
     return hipGetLastError();
 }
 

@@ -9,9 +9,14 @@ namespace ssa {
 
 hipError_t launch_step_batch(const RunParams &p, int n_networks, uint32_t step, int32_t *x, double *t,
                              int32_t *chosen, float *tau, float *a, hipStream_t stream);
-hipError_t launch_reduce_params(const NetDev *nets, int n_networks, const int32_t *pmap_off,
-                                const int32_t *pmap_ch, const int32_t *param_net, int64_t param_total,
-                                const double *partials, float *d_params, float *d_ppt, hipStream_t stream);
+// Deterministic gradient reduction in two passes (chunks of trajectories in a
+// fixed tree order, then the chunks in order); chunk_sums holds
+// param_total * reduce_chunks(max_traj) doubles.
+int reduce_chunks(int64_t max_traj);
+hipError_t launch_reduce_params(const NetDev *nets, const int32_t *pmap_off, const int32_t *pmap_ch,
+                                const int32_t *param_net, int64_t param_total, int64_t max_traj,
+                                const double *partials, double *chunk_sums, float *d_params, float *d_ppt,
+                                hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_selftest_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t stream);
 hipError_t launch_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream);

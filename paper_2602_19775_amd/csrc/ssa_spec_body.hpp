@@ -357,12 +357,13 @@ __device__ void backward(const RunParams &p)
 #pragma unroll
     for (int j = 0; j < M; ++j) { dth[j] = 0.0; dth32[j] = 0.f; }
 
-    // reverse-time bin tracker
+    // reverse-time bin tracker; doi = dL/dobs of the current bin / bin width
     int rbin = n_bins;
     double rlo = t_obs;
-    double dob[NO];
+    double doi[NO];
+    float doi32[NO];
 #pragma unroll
-    for (int o = 0; o < NO; ++o) dob[o] = 0.0;
+    for (int o = 0; o < NO; ++o) { doi[o] = 0.0; doi32[o] = 0.f; }
     if (valid) {
         if (bins) {
             double hi = t_obs;
@@ -370,11 +371,13 @@ __device__ void backward(const RunParams &p)
                 rbin -= 1;
                 rlo = bin_edge(t_obs, rbin, n_bins);
 #pragma unroll
-                for (int o = 0; o < NO; ++o)
-                    dob[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] : 0.0;
+                for (int o = 0; o < NO; ++o) {
+                    doi[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] * inv_dt : 0.0;
+                    doi32[o] = (float)doi[o];
+                }
                 const double seg = hi - fmax(t, rlo);
 #pragma unroll
-                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dob[o] * seg * inv_dt;
+                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += doi[o] * seg;
                 hi = rlo;
             }
         } else if (p.obs_kind == 0) {
@@ -450,23 +453,24 @@ __device__ void backward(const RunParams &p)
                 if (bins && rbin < n_bins) {
     #pragma unroll
                     for (int o = 0; o < NOBS; ++o)
-                        lam_t += dob[o] * (double)(X[NET::OBS[o]] - Xn[o]) * inv_dt;
+                        lam_t += doi[o] * (double)(X[NET::OBS[o]] - Xn[o]);
                 }
-                // soft sample y~ in ratio form: y~_q ~ (r_min / r_q)^(1/T)
+                // soft sample y~ in ratio form: y~_q ~ (r_j / r_q)^(1/T) with j
+                // the fired channel; a_q = 0 gives r_q = +inf and y~_q = 0
+                // without a branch
                 float r[M], ra[M];
-                float rmin = INFINITY;
-                int jmin = 0;
     #pragma unroll
                 for (int q = 0; q < M; ++q) {
-                    const bool on = a[q] > 0.f;
-                    ra[q] = on ? fast_rcp(a[q]) : 0.f;
-                    r[q] = on ? neglog_u(w[1 + q]) * ra[q] : INFINITY;
-                    jmin = r[q] < rmin ? q : jmin;
-                    rmin = fminf(rmin, r[q]);
+                    const float rq = fast_rcp(a[q]);
+                    ra[q] = a[q] > 0.f ? rq : 0.f;
+                    r[q] = neglog_u(w[1 + q]) * rq;
                 }
+                float rref = r[0];
+    #pragma unroll
+                for (int q = 1; q < M; ++q) rref = (q == j) ? r[q] : rref;
                 float y[M];
     #pragma unroll
-                for (int q = 0; q < M; ++q) y[q] = rmin * fast_rcp(r[q]);
+                for (int q = 0; q < M; ++q) y[q] = rref * fast_rcp(r[q]);
                 if (invT_is_2) {
     #pragma unroll
                     for (int q = 0; q < M; ++q) y[q] = y[q] * y[q];
@@ -488,16 +492,16 @@ __device__ void backward(const RunParams &p)
                         if (NET::V[q][sp] != 0) s += (float)NET::V[q][sp] * (lam32[sp] + dlam[sp]);
                     wv[q] = s;
                 }
-                float wref = 0.f;
+                float wref = wv[0];
     #pragma unroll
-                for (int q = 0; q < M; ++q) wref = (q == jmin) ? wv[q] : wref;
+                for (int q = 1; q < M; ++q) wref = (q == j) ? wv[q] : wref;
                 float wbar = 0.f;
     #pragma unroll
                 for (int q = 0; q < M; ++q) {
                     y[q] *= rys;
                     wbar += y[q] * (wv[q] - wref);
                 }
-                const float cc = (float)(lam_t * (double)(-tau * rcp_a0));
+                const float cc = (float)lam_t * (-tau * rcp_a0);
     #pragma unroll
                 for (int q = 0; q < M; ++q) {
                     const float gq = y[q] * ((wv[q] - wref) - wbar) * invT;
@@ -508,25 +512,26 @@ __device__ void backward(const RunParams &p)
                 }
                 // direct dL/dX_k over [t_k, t_{k+1})
                 if (bins) {
-                    double hi = fmin(t, t_obs);
+                    double hi = t < t_obs ? t : t_obs;
                     while (t_k < rlo && rbin > 0) {
                         if (rbin < n_bins) {
                             const double seg = fmax(hi - rlo, 0.0);
     #pragma unroll
-                            for (int o = 0; o < NOBS; ++o)
-                                dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
+                            for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += (float)(doi[o] * seg);
                         }
                         hi = fmin(hi, rlo);
                         rbin -= 1;
                         rlo = bin_edge(t_obs, rbin, n_bins);
     #pragma unroll
-                        for (int o = 0; o < NO; ++o)
-                            dob[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] : 0.0;
+                        for (int o = 0; o < NO; ++o) {
+                            doi[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] * inv_dt : 0.0;
+                            doi32[o] = (float)doi[o];
+                        }
                     }
                     if (rbin < n_bins) {
-                        const double seg = fmax(hi - t_k, 0.0);
+                        const float seg = (float)(hi - t_k);
     #pragma unroll
-                        for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += (float)(dob[o] * seg * inv_dt);
+                        for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += seg > 0.f ? seg * doi32[o] : 0.f;
                     }
                 }
             if (!(a0 > 0.f) || !(tau >= 0.f)) flags |= kFlagNonFinite;
