@@ -115,8 +115,8 @@ __device__ __forceinline__ void rates(const RunParams &p, const NetDev &nd, floa
 constexpr int obs_cap(int n) { return n > 0 ? n : 1; }
 
 // --------------------------------------------------------------------------
-template <class NET>
-__device__ void forward(const RunParams &p)
+template <class NET, bool HAS_T_END>
+__device__ void forward_run(const RunParams &p)
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
     const int wid = uniform_i((int)(threadIdx.x >> 6));
@@ -153,39 +153,42 @@ __device__ void forward(const RunParams &p)
     double *obs_lane = p.obs + nd.obsb_off * (p.obs_kind == 1 ? n_bins : 1) + i;
     const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
 
-    const int spw = p.tape_bits ? 32 / p.tape_bits : 0;
+    const int bits = p.tape_bits;
+    const int spw = bits ? 32 / bits : 0;
     const int tshift = spw ? __builtin_ctz(spw) : 0;
     uint32_t tword = 0u;
-    const bool has_t_end = p.t_end < INFINITY;
 
     double t = 0.0;
     bool active = valid;
     int n_done = 0;
     uint32_t flags = 0u;
-    int ck_left = 0;
     int64_t ck_idx = 0;
 
     // The step body is one straight-line block for every lane: the state
     // updates are predicated on `fire`, and the Philox words of step k+1 are
     // generated inside step k, so the scheduler can interleave that chain
     // with the dependent propensity -> race -> update chain of step k.
+    // Per-step bookkeeping stays out of the body: checkpoints are written
+    // per segment, the tape word is stored per word, and lanes that stop
+    // (absorbing state, t_end) go through the rare path.
     uint32_t wd[Blocks<NET>::W];
     words<NET>(0u, tid, pe, p.seed_lo, p.seed_hi, wd);
     int k = 0;
-    for (; k < p.n_steps; ++k) {
-        if (ballot(active) == 0ull) break;
-        if (p.ck_x) {
-            if (ck_left == 0) {
-                if (active) {
+    bool any = ballot(active) != 0ull;
+    while (any && k < p.n_steps) {
+      if (p.ck_x) {
+          if (active) {
 #pragma unroll
-                    for (int s = 0; s < N; ++s) p.ck_x[ck_idx * p.state_total + nd.state_off + s * B + i] = X[s];
-                    p.ck_t[ck_idx * p.traj_total + g] = t;
-                }
-                ck_idx += 1;
-                ck_left = p.K;
-            }
-            ck_left -= 1;
-        }
+              for (int s = 0; s < N; ++s) p.ck_x[ck_idx * p.state_total + nd.state_off + s * B + i] = X[s];
+              p.ck_t[ck_idx * p.traj_total + g] = t;
+          }
+          ck_idx += 1;
+      }
+      const int seg_end = p.ck_x ? min(k + p.K, p.n_steps) : p.n_steps;
+      while (any && k < seg_end) {
+        const int word_end = spw ? min((k | (spw - 1)) + 1, seg_end) : seg_end;
+        uint32_t shift = spw ? (uint32_t)(bits * (k & (spw - 1))) : 0u;
+        for (; k < word_end; ++k) {
         float a[M], A1[M], A2[M];
         const float a0 = propensities<NET, false>(c, X, a, A1, A2);
         const float tau = neglog_u(wd[0]) * fast_rcp(a0);
@@ -206,16 +209,18 @@ __device__ void forward(const RunParams &p)
         words<NET>((uint32_t)(k + 1), tid, pe, p.seed_lo, p.seed_hi, wn);
 
         const bool live = active && a0 > 0.f;           // a0 = 0: absorbing state
-        const bool fire = live && (!has_t_end || tn <= p.t_end);
+        const bool fire = live && (!HAS_T_END || tn <= p.t_end);
         const bool in_bin = fire && tn <= bin_hi;       // the interval ends inside the current bin
         const double w_obs = in_bin ? (double)tau : 0.0;
 #pragma unroll
         for (int o = 0; o < NO; ++o) acc[o] += (double)X[NET::OBS[o]] * w_obs;
-        const bool clock_tie = live && has_t_end && fabs(tn - p.t_end) <= kClockTieLog * p.t_end;
+        const bool clock_tie = HAS_T_END && live && fabs(tn - p.t_end) <= kClockTieLog * p.t_end;
         const bool near_tie = fire && r2 <= r1 * (1.f + kTieLog);
         const bool crossing = fire && !in_bin && bin < n_bins;
         const bool odd = active && !(a0 >= 0.f);
-        if (ballot(clock_tie || near_tie || crossing || odd) != 0ull) {
+        const bool stop = active && !fire;
+        if (ballot(clock_tie || near_tie || crossing || odd || stop) != 0ull) {
+            if (ballot(stop) != 0ull) any = ballot(fire) != 0ull;
             if (odd) flags |= kFlagNonFinite;
             if (clock_tie)
                 log_tie(p, (uint32_t)g, k, fire ? 1 : 0, 0, (float)((tn - p.t_end) / p.t_end), 1);
@@ -248,20 +253,25 @@ __device__ void forward(const RunParams &p)
                 }
             }
         }
-        if (spw) {
-            const int pos = k & (spw - 1);
-            tword |= fire ? (uint32_t)j1 << (p.tape_bits * pos) : 0u;
-            if (pos == spw - 1) {
-                if (valid) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
-                tword = 0u;
-            }
-        }
+        tword |= fire ? (uint32_t)j1 << shift : 0u;
+        shift += (uint32_t)bits;
         apply<NET>(X, fire ? j1 : -1, +1);
         t = fire ? tn : t;
         n_done += fire ? 1 : 0;
         active = fire;
 #pragma unroll
         for (int q = 0; q < Blocks<NET>::W; ++q) wd[q] = wn[q];
+        if (!any) {
+            ++k;
+            break;
+        }
+        }
+        // a completed tape word
+        if (spw && (k & (spw - 1)) == 0) {
+            if (valid) p.tape[(int64_t)((k - 1) >> tshift) * p.traj_total + g] = tword;
+            tword = 0u;
+        }
+      }
     }
     if (!valid) return;
     if (spw && (k & (spw - 1)) != 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
@@ -293,6 +303,13 @@ __device__ void forward(const RunParams &p)
     p.t_final[g] = t;
     p.steps_done[g] = n_done;
     if (flags) atomicOr(p.flags, flags);
+}
+
+template <class NET>
+__device__ void forward(const RunParams &p)
+{
+    if (p.t_end < INFINITY) forward_run<NET, true>(p);
+    else forward_run<NET, false>(p);
 }
 
 // --------------------------------------------------------------------------
@@ -546,8 +563,11 @@ __device__ void backward(const RunParams &p)
             }
             return (int)((tword >> (p.tape_bits * (k & (spw - 1)))) & tmask);
         };
-        auto fold = [&]() {
-            if (fold_left == 0) {
+        // the FP32 increments go into the FP64 accumulators once kFold steps
+        // have been swept since the last fold
+        auto fold = [&](int steps) {
+            fold_left -= steps;
+            if (fold_left <= 0) {
 #pragma unroll
                 for (int s = 0; s < N; ++s) {
                     lam[s] += (double)dlam[s];
@@ -558,32 +578,40 @@ __device__ void backward(const RunParams &p)
                 for (int j = 0; j < M; ++j) { dth[j] += (double)dth32[j]; dth32[j] = 0.f; }
                 fold_left = kFold;
             }
-            fold_left -= 1;
         };
         // steps some lanes of the wave never fired (they ended early): masked
         const int k_split = max(min(k_hi, nmin), k_lo);
         for (int k = k_hi - 1; k >= k_split; --k) {
-            fold();
             const int j = choice(k);
             if (k < n) {
                 uint32_t w[Blocks<NET>::W];
                 words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, w);
                 sweep(k, j, w);
             }
+            fold(1);
         }
         // steps every lane fired: straight-line body, Philox words of step
-        // k-1 generated while step k is swept
+        // k-1 generated while step k is swept; the choices are read one tape
+        // word (or, recomputing, one segment) at a time
         if (k_split > k_lo) {
             uint32_t wd[Blocks<NET>::W];
             words<NET>((uint32_t)(k_split - 1), tid, pe, p.seed_lo, p.seed_hi, wd);
-            for (int k = k_split - 1; k >= k_lo; --k) {
-                fold();
-                const int j = choice(k);
-                uint32_t wn[Blocks<NET>::W];
-                words<NET>((uint32_t)(k - 1), tid, pe, p.seed_lo, p.seed_hi, wn);
-                sweep(k, j, wd);
+            int k = k_split - 1;
+            while (k >= k_lo) {
+                const int w_lo = p.recompute ? k_lo : max(k & ~(spw - 1), k_lo);
+                const uint32_t tw = p.recompute ? 0u : p.tape[(int64_t)(k >> tshift) * p.traj_total + g];
+                int shift = p.recompute ? 0 : p.tape_bits * (k & (spw - 1));
+                const int steps = k - w_lo + 1;
+                for (; k >= w_lo; --k) {
+                    const int j = p.recompute ? (int)s_tape[wid][k - k_lo][lane] : (int)((tw >> shift) & tmask);
+                    shift -= p.tape_bits;
+                    uint32_t wn[Blocks<NET>::W];
+                    words<NET>((uint32_t)(k - 1), tid, pe, p.seed_lo, p.seed_hi, wn);
+                    sweep(k, j, wd);
 #pragma unroll
-                for (int q = 0; q < Blocks<NET>::W; ++q) wd[q] = wn[q];
+                    for (int q = 0; q < Blocks<NET>::W; ++q) wd[q] = wn[q];
+                }
+                fold(steps);
             }
         }
     }
