@@ -313,12 +313,15 @@ __device__ void forward(const RunParams &p)
 }
 
 // --------------------------------------------------------------------------
-template <class NET>
-__device__ void backward(const RunParams &p)
+// TMODE: 2 -> T = 1/2 (y~ ~ rho^2), 1 -> T = 1 (y~ ~ rho), 0 -> y~ ~ rho^(1/T).
+// RECOMPUTE: the choices of a segment come from re-running it into LDS
+// instead of the tape.
+constexpr int kRecSteps = 64;   // recompute mode: steps of a segment kept in LDS
+
+template <class NET, int TMODE, bool RECOMPUTE>
+__device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64])
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
-    constexpr int KREC = 64;     // recompute mode: steps of a segment kept in LDS
-    __shared__ uint8_t s_tape[kWaves][KREC][64];
 
     const int wid = uniform_i((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -338,7 +341,6 @@ __device__ void backward(const RunParams &p)
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
     const float invT = 1.0f / p.temperature;
-    const bool invT_is_2 = invT == 2.0f, invT_is_1 = invT == 1.0f;
 
     const int n = valid ? p.steps_done[g] : 0;
     int kmax = n;
@@ -409,13 +411,12 @@ __device__ void backward(const RunParams &p)
     const int tshift = __builtin_ctz(spw);
     const uint32_t tmask = p.tape_bits ? ((1u << p.tape_bits) - 1u) : 0u;
     const int n_seg = (kmax + p.K - 1) / p.K;
-    uint32_t flags = 0u;
     int fold_left = kFold;
 
     for (int cseg = n_seg - 1; cseg >= 0; --cseg) {
         const int k_lo = cseg * p.K;
         const int k_hi = min(k_lo + p.K, kmax);
-        if (p.recompute) {
+        if (RECOMPUTE) {
             int Xr[N + 1];
             if (k_lo < n) {
 #pragma unroll
@@ -488,10 +489,10 @@ __device__ void backward(const RunParams &p)
                 float y[M];
     #pragma unroll
                 for (int q = 0; q < M; ++q) y[q] = rref * fast_rcp(r[q]);
-                if (invT_is_2) {
+                if (TMODE == 2) {
     #pragma unroll
                     for (int q = 0; q < M; ++q) y[q] = y[q] * y[q];
-                } else if (!invT_is_1) {
+                } else if (TMODE == 0) {
     #pragma unroll
                     for (int q = 0; q < M; ++q) y[q] = y[q] > 0.f ? exp2f(log2f(y[q]) * invT) : 0.f;
                 }
@@ -527,9 +528,10 @@ __device__ void backward(const RunParams &p)
                     if (NET::S1[q] < N) dlam[NET::S1[q]] += coef * A2[q];
                     if (NET::S2[q] < N) dlam[NET::S2[q]] += coef * A1[q];
                 }
-                // direct dL/dX_k over [t_k, t_{k+1})
+                // direct dL/dX_k over [t_k, t_{k+1}); crossing a bin edge is rare
                 if (bins) {
                     double hi = t < t_obs ? t : t_obs;
+                    if (ballot(t_k < rlo && rbin > 0) != 0ull)
                     while (t_k < rlo && rbin > 0) {
                         if (rbin < n_bins) {
                             const double seg = fmax(hi - rlo, 0.0);
@@ -545,17 +547,15 @@ __device__ void backward(const RunParams &p)
                             doi32[o] = (float)doi[o];
                         }
                     }
-                    if (rbin < n_bins) {
-                        const float seg = (float)(hi - t_k);
+                    const float seg = (float)(hi - t_k);
+                    const bool inb = rbin < n_bins && seg > 0.f;
     #pragma unroll
-                        for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += seg > 0.f ? seg * doi32[o] : 0.f;
-                    }
+                    for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += inb ? seg * doi32[o] : 0.f;
                 }
-            if (!(a0 > 0.f) || !(tau >= 0.f)) flags |= kFlagNonFinite;
             t = t_k;
         };
         auto choice = [&](int k) -> int {
-            if (p.recompute) return s_tape[wid][k - k_lo][lane];
+            if (RECOMPUTE) return (int)s_tape[wid][k - k_lo][lane];
             const int widx = k >> tshift;
             if (widx != tword_idx) {
                 tword = p.tape[(int64_t)widx * p.traj_total + g];
@@ -598,12 +598,12 @@ __device__ void backward(const RunParams &p)
             words<NET>((uint32_t)(k_split - 1), tid, pe, p.seed_lo, p.seed_hi, wd);
             int k = k_split - 1;
             while (k >= k_lo) {
-                const int w_lo = p.recompute ? k_lo : max(k & ~(spw - 1), k_lo);
-                const uint32_t tw = p.recompute ? 0u : p.tape[(int64_t)(k >> tshift) * p.traj_total + g];
-                int shift = p.recompute ? 0 : p.tape_bits * (k & (spw - 1));
+                const int w_lo = RECOMPUTE ? k_lo : max(k & ~(spw - 1), k_lo);
+                const uint32_t tw = RECOMPUTE ? 0u : p.tape[(int64_t)(k >> tshift) * p.traj_total + g];
+                int shift = RECOMPUTE ? 0 : p.tape_bits * (k & (spw - 1));
                 const int steps = k - w_lo + 1;
                 for (; k >= w_lo; --k) {
-                    const int j = p.recompute ? (int)s_tape[wid][k - k_lo][lane] : (int)((tw >> shift) & tmask);
+                    const int j = RECOMPUTE ? (int)s_tape[wid][k - k_lo][lane] : (int)((tw >> shift) & tmask);
                     shift -= p.tape_bits;
                     uint32_t wn[Blocks<NET>::W];
                     words<NET>((uint32_t)(k - 1), tid, pe, p.seed_lo, p.seed_hi, wn);
@@ -620,7 +620,22 @@ __device__ void backward(const RunParams &p)
     if (!valid) return;
 #pragma unroll
     for (int q = 0; q < M; ++q) p.partials[nd.part_off + q * B + i] = dth[q];
-    if (flags) atomicOr(p.flags, flags);
+}
+
+template <class NET>
+__device__ void backward(const RunParams &p)
+{
+    __shared__ uint8_t s_tape[kWaves][kRecSteps][64];
+    const float invT = 1.0f / p.temperature;
+    if (p.recompute) {
+        if (invT == 2.0f) backward_run<NET, 2, true>(p, s_tape);
+        else if (invT == 1.0f) backward_run<NET, 1, true>(p, s_tape);
+        else backward_run<NET, 0, true>(p, s_tape);
+    } else {
+        if (invT == 2.0f) backward_run<NET, 2, false>(p, s_tape);
+        else if (invT == 1.0f) backward_run<NET, 1, false>(p, s_tape);
+        else backward_run<NET, 0, false>(p, s_tape);
+    }
 }
 
 }  // namespace spec
