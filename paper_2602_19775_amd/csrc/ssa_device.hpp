@@ -81,9 +81,10 @@ __device__ __forceinline__ int uniform_i(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Lanes of the wavefront whose predicate holds (the compare mask itself).
 __device__ __forceinline__ uint64_t ballot(bool p)
 {
-    return __ballot(p);
+    return __builtin_amdgcn_ballot_w64(p);
 }
 
 }  // namespace ssa

@@ -597,9 +597,13 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
             uint32_t wd[Blocks<NET>::W];
             words<NET>((uint32_t)(k_split - 1), tid, pe, p.seed_lo, p.seed_hi, wd);
             int k = k_split - 1;
+            // the tape word of the next (lower) block is loaded one block ahead
+            uint32_t tw_next = RECOMPUTE ? 0u : p.tape[(int64_t)(k >> tshift) * p.traj_total + g];
             while (k >= k_lo) {
                 const int w_lo = RECOMPUTE ? k_lo : max(k & ~(spw - 1), k_lo);
-                const uint32_t tw = RECOMPUTE ? 0u : p.tape[(int64_t)(k >> tshift) * p.traj_total + g];
+                const uint32_t tw = tw_next;
+                if (!RECOMPUTE && w_lo > k_lo)
+                    tw_next = p.tape[(int64_t)((w_lo - 1) >> tshift) * p.traj_total + g];
                 int shift = RECOMPUTE ? 0 : p.tape_bits * (k & (spw - 1));
                 const int steps = k - w_lo + 1;
                 for (; k >= w_lo; --k) {
