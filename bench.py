@@ -175,15 +175,18 @@ def bench_grn(args, torch, dev):
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
     value = fired / (ms_step * 1e-3)
 
+    # forward-only rate of the plain forward (no choice tape)
+    pbufs = ssa.grn_forward(g, cfg, theta, x_img, keep_tape=False, tie_capacity=tie_cap)
     for _ in range(args.warmup):
-        ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=bufs)
+        ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=pbufs)
     torch.cuda.synchronize()
     f0 = time.perf_counter()
     for _ in range(args.steps):
-        ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=bufs)
+        ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=pbufs)
     torch.cuda.synchronize()
     f1 = time.perf_counter()
-    fwd_rate = fired * args.steps / (f1 - f0)
+    fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
+    del pbufs
     n_ties = int(bufs.n_ties.item())
     assert ssa.grn_device_status(g) == 0
 
@@ -425,16 +428,18 @@ def main():
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
     value = fired / (ms_step * 1e-3)
 
-    # forward-only rate of the same forward call
+    # forward-only rate of the plain forward (no checkpoints, no choice tape)
+    pbufs = ssa.forward(h, cfg, theta, x0, keep_ckpt=False, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
     for _ in range(args.warmup):
-        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
+        ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
     torch.cuda.synchronize()
     f0 = time.perf_counter()
     for _ in range(args.steps):
-        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
+        ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
     torch.cuda.synchronize()
     f1 = time.perf_counter()
-    fwd_rate = fired * args.steps / (f1 - f0)
+    fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
+    del pbufs
     n_ties = int(bufs.n_ties.item())
     assert ssa.device_status(h) == 0
 

@@ -388,7 +388,7 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
             double hi = t_obs;
             while (rbin > 0 && t < rlo) {
                 rbin -= 1;
-                rlo = bin_edge(t_obs, rbin, n_bins);
+                rlo = rbin > 0 ? bin_edge(t_obs, rbin, n_bins) : -INFINITY;
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
                     doi[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] * inv_dt : 0.0;
@@ -467,8 +467,8 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                 const float tau = neglog_u(w[0]) * rcp_a0;
                 const double t_k = t - (double)tau;
 
-                // direct dL/dt_{k+1}
-                if (bins && rbin < n_bins) {
+                // direct dL/dt_{k+1} (doi is 0 past the observation window)
+                if (bins) {
     #pragma unroll
                     for (int o = 0; o < NOBS; ++o)
                         lam_t += doi[o] * (double)(X[NET::OBS[o]] - Xn[o]);
@@ -531,8 +531,9 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                 // direct dL/dX_k over [t_k, t_{k+1}); crossing a bin edge is rare
                 if (bins) {
                     double hi = t < t_obs ? t : t_obs;
-                    if (ballot(t_k < rlo && rbin > 0) != 0ull)
-                    while (t_k < rlo && rbin > 0) {
+                    // below the first bin's edge rlo is -inf: nothing left to cross
+                    if (ballot(t_k < rlo) != 0ull)
+                    while (t_k < rlo) {
                         if (rbin < n_bins) {
                             const double seg = fmax(hi - rlo, 0.0);
     #pragma unroll
@@ -540,17 +541,16 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                         }
                         hi = fmin(hi, rlo);
                         rbin -= 1;
-                        rlo = bin_edge(t_obs, rbin, n_bins);
+                        rlo = rbin > 0 ? bin_edge(t_obs, rbin, n_bins) : -INFINITY;
     #pragma unroll
                         for (int o = 0; o < NO; ++o) {
                             doi[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] * inv_dt : 0.0;
                             doi32[o] = (float)doi[o];
                         }
                     }
-                    const float seg = (float)(hi - t_k);
-                    const bool inb = rbin < n_bins && seg > 0.f;
+                    const float seg = fmaxf((float)(hi - t_k), 0.f);
     #pragma unroll
-                    for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += inb ? seg * doi32[o] : 0.f;
+                    for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += seg * doi32[o];
                 }
             t = t_k;
         };

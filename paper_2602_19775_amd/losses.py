@@ -11,8 +11,7 @@ def bin_moments(obs: torch.Tensor, n_bins: int, n_obs: int, B: int):
     """Per-bin ensemble mean and population variance of bin averages laid out
     [n_bins][n_obs][B] (the library's layout for one network)."""
     o = obs[: n_bins * n_obs * B].view(n_bins, n_obs, B)
-    m = o.mean(dim=2)
-    v = ((o - m[:, :, None]) ** 2).mean(dim=2)
+    v, m = torch.var_mean(o, dim=2, correction=0)
     return m, v
 
 
