@@ -87,4 +87,169 @@ __device__ __forceinline__ uint64_t ballot(bool p)
     return __builtin_amdgcn_ballot_w64(p);
 }
 
+// --------------------------------------------------------------------------
+// Reductions over aligned groups of L lanes (L = 8, 16, 32, 64) without LDS:
+// DPP lane permutations inside rows of 16 lanes (pairs at xor 1 and 2, then
+// mirrors of 8 and 16 lanes) and the gfx950 row swaps across rows and halves.
+// Each step combines a lane's value with its partner's by a commutative
+// operation, so every lane of a group ends with bitwise the same result.
+// All lanes of the wavefront must be active.
+namespace lanes {
+
+constexpr int kXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kHalfMirror = 0x141;
+constexpr int kMirror = 0x140;
+constexpr int kRowBcast0 = 0x150;  // lane 0 of each row
+constexpr int kRowBcast8 = 0x158;  // lane 8 of each row
+
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(dpp<CTRL>(__float_as_int(v)));
+}
+
+// (value of the even row, value of the odd row) of each pair of rows
+__device__ __forceinline__ void rows16(int v, int &even, int &odd)
+{
+    const auto p = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    even = (int)p[0];
+    odd = (int)p[1];
+}
+
+// (value of the lower half, value of the upper half)
+__device__ __forceinline__ void halves(int v, int &lo, int &hi)
+{
+    const auto p = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    lo = (int)p[0];
+    hi = (int)p[1];
+}
+
+__device__ __forceinline__ void rows16(float v, float &even, float &odd)
+{
+    int e, o;
+    rows16(__float_as_int(v), e, o);
+    even = __int_as_float(e);
+    odd = __int_as_float(o);
+}
+
+__device__ __forceinline__ void halves(float v, float &lo, float &hi)
+{
+    int a, b;
+    halves(__float_as_int(v), a, b);
+    lo = __int_as_float(a);
+    hi = __int_as_float(b);
+}
+
+}  // namespace lanes
+
+template <int L>
+__device__ __forceinline__ float group_sum(float v)
+{
+    static_assert(L == 8 || L == 16 || L == 32 || L == 64, "group width");
+    v += lanes::dpp<lanes::kXor1>(v);
+    v += lanes::dpp<lanes::kXor2>(v);
+    v += lanes::dpp<lanes::kHalfMirror>(v);
+    if (L >= 16) v += lanes::dpp<lanes::kMirror>(v);
+    if (L >= 32) {
+        float e, o;
+        lanes::rows16(v, e, o);
+        v = e + o;
+    }
+    if (L >= 64) {
+        float lo, hi;
+        lanes::halves(v, lo, hi);
+        v = lo + hi;
+    }
+    return v;
+}
+
+template <int L>
+__device__ __forceinline__ float group_min(float v)
+{
+    static_assert(L == 8 || L == 16 || L == 32 || L == 64, "group width");
+    v = fminf(v, lanes::dpp<lanes::kXor1>(v));
+    v = fminf(v, lanes::dpp<lanes::kXor2>(v));
+    v = fminf(v, lanes::dpp<lanes::kHalfMirror>(v));
+    if (L >= 16) v = fminf(v, lanes::dpp<lanes::kMirror>(v));
+    if (L >= 32) {
+        float e, o;
+        lanes::rows16(v, e, o);
+        v = fminf(e, o);
+    }
+    if (L >= 64) {
+        float lo, hi;
+        lanes::halves(v, lo, hi);
+        v = fminf(lo, hi);
+    }
+    return v;
+}
+
+// Race state (smallest ratio r1, its channel j1, second smallest r2) merged
+// with another lane's: the smaller (r1, j1) pair wins, r2 is the smallest of
+// the rest.  Symmetric in its arguments.
+__device__ __forceinline__ void race_merge(float a1, int aj, float a2, float b1, int bj, float b2,
+                                           float &r1, int &j1, float &r2)
+{
+    const bool b_wins = b1 < a1 || (b1 == a1 && bj < aj);
+    r2 = fminf(fminf(a2, b2), fmaxf(a1, b1));
+    r1 = b_wins ? b1 : a1;
+    j1 = b_wins ? bj : aj;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void race_step(float &r1, int &j1, float &r2)
+{
+    race_merge(r1, j1, r2, lanes::dpp<CTRL>(r1), lanes::dpp<CTRL>(j1), lanes::dpp<CTRL>(r2), r1, j1, r2);
+}
+
+template <int L>
+__device__ __forceinline__ void group_race(float &r1, int &j1, float &r2)
+{
+    static_assert(L == 8 || L == 16 || L == 32 || L == 64, "group width");
+    race_step<lanes::kXor1>(r1, j1, r2);
+    race_step<lanes::kXor2>(r1, j1, r2);
+    race_step<lanes::kHalfMirror>(r1, j1, r2);
+    if (L >= 16) race_step<lanes::kMirror>(r1, j1, r2);
+    if (L >= 32) {
+        float e1, o1, e2, o2;
+        int ej, oj;
+        lanes::rows16(r1, e1, o1);
+        lanes::rows16(j1, ej, oj);
+        lanes::rows16(r2, e2, o2);
+        race_merge(e1, ej, e2, o1, oj, o2, r1, j1, r2);
+    }
+    if (L >= 64) {
+        float l1, h1, l2, h2;
+        int lj, hj;
+        lanes::halves(r1, l1, h1);
+        lanes::halves(j1, lj, hj);
+        lanes::halves(r2, l2, h2);
+        race_merge(l1, lj, l2, h1, hj, h2, r1, j1, r2);
+    }
+}
+
+// The value of the first lane of each group.
+template <int L>
+__device__ __forceinline__ float group_first(float v)
+{
+    static_assert(L == 8 || L == 16 || L == 32 || L == 64, "group width");
+    if (L == 64) return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+    const float b0 = lanes::dpp<lanes::kRowBcast0>(v);
+    if (L == 16) return b0;
+    if (L == 32) {
+        float e, o;
+        lanes::rows16(b0, e, o);
+        return e;
+    }
+    const float b8 = lanes::dpp<lanes::kRowBcast8>(v);
+    return (__lane_id() & 8) ? b8 : b0;
+}
+
 }  // namespace ssa

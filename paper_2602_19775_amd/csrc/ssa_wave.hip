@@ -41,17 +41,7 @@ __device__ __forceinline__ void wave_sync()
 template <int L>
 __device__ __forceinline__ float gsum(float v)
 {
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-template <int L>
-__device__ __forceinline__ float gmin(float v)
-{
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
+    return group_sum<L>(v);
 }
 
 // (r1, j1, r2) = smallest ratio, its channel (lowest index on exact ties) and
@@ -59,17 +49,7 @@ __device__ __forceinline__ float gmin(float v)
 template <int L>
 __device__ __forceinline__ void grace(float &r1, int &j1, float &r2)
 {
-#pragma unroll
-    for (int o = L / 2; o > 0; o >>= 1) {
-        const float o1 = __shfl_xor(r1, o);
-        const int oj = __shfl_xor(j1, o);
-        const float o2 = __shfl_xor(r2, o);
-        const float nr2 = fminf(fminf(r2, o2), fmaxf(r1, o1));
-        const bool other = o1 < r1 || (o1 == r1 && oj < j1);
-        r1 = other ? o1 : r1;
-        j1 = other ? oj : j1;
-        r2 = nr2;
-    }
+    group_race<L>(r1, j1, r2);
 }
 
 __device__ void log_tie(const RunParams &p, uint32_t g, int k, int chosen, int second, float margin, int kind)
@@ -285,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
                 r1 = fminf(r1, rq);
             }
             grace<L>(r1, j1, r2);
-            const float e0 = __shfl(neglog_u(wd[0]), lane & ~(L - 1));
+            const float e0 = group_first<L>(neglog_u(wd[0]));
             const float tau = e0 * fast_rcp(a0);
             const double tn = t + (double)tau;
             const bool live = active && a0 > 0.f;
@@ -611,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                 uint32_t wd[C];
                 group_words<L, BPL>(M, gl, (uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, wd);
                 const float rcp_a0 = fast_rcp(a0);
-                const float e0 = __shfl(neglog_u(wd[0]), lane & ~(L - 1));
+                const float e0 = group_first<L>(neglog_u(wd[0]));
                 const float tau = e0 * rcp_a0;
                 const double t_k = t - (double)tau;
                 if (on_k && bins && rbin < n_bins) {
