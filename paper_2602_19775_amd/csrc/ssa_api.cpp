@@ -72,14 +72,15 @@ struct ssa_net {
     int32_t *pmap_ch_d = nullptr;
     int32_t *param_net_d = nullptr;
     int32_t *inc_ptr_d = nullptr;
-    int32_t *inc_ent_d = nullptr;
+    int32_t *chan_inc_d = nullptr;
     // one launch per group: a generic lane class, or a topology-specialised kernel pair
     struct Group {
         bool spec = false;
         int lane_class = -1;
         int wave_class = -1;     // persistent wave-mode launch
         int wave_blocks = 0;
-        int tab_m = 0, tab_nnz = 0, tab_inc = 0;   // per-group LDS table capacities
+        int tab_m = 0, tab_nnz = 0;   // per-group LDS table capacities
+        int wide_ve = 0;              // a channel changes more than kVecSlots species
         SpecKernels kernels;
         LaneItem *items_d = nullptr;
         int n_items = 0;
@@ -210,7 +211,7 @@ RunParams base_params(const ssa_net *net, const ssa_config *cfg)
     p.temperature = cfg->temperature;
     p.recompute = resolve_bwd_mode(cfg) == SSA_BWD_RECOMPUTE ? 1 : 0;
     p.inc_ptr = net->inc_ptr_d;
-    p.inc_ent = net->inc_ent_d;
+    p.chan_inc = net->chan_inc_d;
     return p;
 }
 
@@ -224,8 +225,8 @@ ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hi
         if (gr.wave_class >= 0) {
             p.tab_m = gr.tab_m;
             p.tab_nnz = gr.tab_nnz;
-            p.tab_inc = gr.tab_inc;
-            p.tab_words = gr.tab_m + gr.tab_nnz + (kWaveMaxSpecies + 1) + gr.tab_inc;
+            p.tab_words = gr.tab_m + gr.tab_nnz + (kWaveMaxSpecies + 1);
+            p.wide_ve = gr.wide_ve;
             // the persistent kernel pulls work from a counter that starts at 0
             e = launch_fill_u32(p.work_counter, 1, 0u, stream);
             if (e == hipSuccess) e = wave_launch(gr.wave_class, p, backward, gr.wave_blocks, stream);
@@ -381,10 +382,10 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     // ---- device tables ---------------------------------------------------
     std::vector<ReactDesc> rd;
     std::vector<uint32_t> rows;
-    std::vector<int32_t> csr, obs_sp, pmap_off, pmap_ch, param_net, inc_ptr, inc_ent;
+    std::vector<int32_t> csr, obs_sp, pmap_off, pmap_ch, param_net, inc_ptr, chan_inc;
     std::vector<LaneItem> items[kLaneClassCount];
     std::map<int, std::vector<LaneItem>> wave_items;   // by wave class
-    std::vector<int> net_nnz, net_inc;
+    std::vector<int> net_nnz, net_ve;
     std::map<std::string, std::vector<LaneItem>> spec_items;
     int64_t roff = 0, soff = 0, ooff = 0;
     for (int n = 0; n < nn; ++n) {
@@ -409,6 +410,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         nd.ppt_off = net->ppt_total;
         nd.t_obs = d->t_obs ? d->t_obs[n] : 0.0;
         std::vector<std::vector<int32_t>> incid(N);
+        int max_ve = 0;
         for (int j = 0; j < M; ++j) {
             const int s1 = d->reactant[2 * (roff + j)], s2 = d->reactant[2 * (roff + j) + 1];
             ReactDesc r;
@@ -433,15 +435,19 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
             // channel j contributes coef*A2 to dlambda[s1] (role 1) and coef*A1 to dlambda[s2] (role 2)
             if (s1 >= 0) incid[s1].push_back(j | (1 << 16));
             if (s2 >= 0) incid[s2].push_back(j | (2 << 16));
+            max_ve = std::max(max_ve, (int)csr.size() - beg);
         }
-        const size_t inc_before = inc_ent.size();
+        // incidence slots grouped by species; each channel keeps its two slots
+        std::vector<int32_t> pos(2 * (size_t)M, 0xFFFF);
+        int slot = 0;
         for (int q = 0; q < N; ++q) {
-            inc_ptr.push_back((int32_t)inc_ent.size());
-            inc_ent.insert(inc_ent.end(), incid[q].begin(), incid[q].end());
+            inc_ptr.push_back(slot);
+            for (int32_t ent : incid[q]) pos[2 * (ent & 0xFFFF) + ((ent >> 16) - 1)] = slot++;
         }
-        inc_ptr.push_back((int32_t)inc_ent.size());
+        inc_ptr.push_back(slot);
+        for (int j = 0; j < M; ++j) chan_inc.push_back(pos[2 * j] | (pos[2 * j + 1] << 16));
         net_nnz.push_back((int)(csr.size() - (rd[nd.react_off].csr & 0xFFFFFF)));
-        net_inc.push_back((int)(inc_ent.size() - inc_before));
+        net_ve.push_back(max_ve);
         for (int o = 0; o < nob; ++o) obs_sp.push_back(d->obs_species[ooff + o]);
         // parameter -> channels map for the gradient reduction
         for (int pp = 0; pp < P; ++pp) {
@@ -496,7 +502,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     if (e == hipSuccess) e = upload(&net->pmap_ch_d, pmap_ch.empty() ? std::vector<int32_t>{0} : pmap_ch);
     if (e == hipSuccess) e = upload(&net->param_net_d, param_net);
     if (e == hipSuccess) e = upload(&net->inc_ptr_d, inc_ptr);
-    if (e == hipSuccess) e = upload(&net->inc_ent_d, inc_ent.empty() ? std::vector<int32_t>{0} : inc_ent);
+    if (e == hipSuccess) e = upload(&net->chan_inc_d, chan_inc.empty() ? std::vector<int32_t>{0} : chan_inc);
     for (auto &kv : spec_items) {
         if (e != hipSuccess) break;
         ssa_net::Group gr;
@@ -522,10 +528,10 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         for (const LaneItem &it : kv.second) {
             gr.tab_m = std::max(gr.tab_m, d->n_reactions[it.net]);
             gr.tab_nnz = std::max(gr.tab_nnz, net_nnz[it.net]);
-            gr.tab_inc = std::max(gr.tab_inc, net_inc[it.net]);
+            if (net_ve[it.net] > kVecSlots) gr.wide_ve = 1;
         }
         const int per_wave = 64 / wave_class_lanes(gr.wave_class);
-        const size_t tab_bytes = sizeof(int32_t) * (size_t)(gr.tab_m + gr.tab_nnz + kWaveMaxSpecies + 1 + gr.tab_inc);
+        const size_t tab_bytes = sizeof(int32_t) * (size_t)(gr.tab_m + gr.tab_nnz + kWaveMaxSpecies + 1);
         const size_t lds = std::max(wave_static_lds(gr.wave_class, true), wave_static_lds(gr.wave_class, false)) +
                            tab_bytes * 4 * per_wave;
         if (lds > kLdsPerBlock)
@@ -560,7 +566,7 @@ void ssa_net_destroy(ssa_net *net)
     (void)hipFree(net->pmap_ch_d);
     (void)hipFree(net->param_net_d);
     (void)hipFree(net->inc_ptr_d);
-    (void)hipFree(net->inc_ent_d);
+    (void)hipFree(net->chan_inc_d);
     for (auto &gr : net->groups) (void)hipFree(gr.items_d);
     (void)hipFree(net->flags_d);
     delete net;

@@ -128,13 +128,18 @@ struct RunParams {
     float temperature;
     int32_t recompute;      // backward: recover choices by re-running segments
 
-    // wave mode: species -> (channel, role) incidence lists and the work counter
+    // wave mode: species -> range of incidence slots, and per channel the
+    // slots of its (role 1, role 2) contributions: pos1 | pos2 << 16 with
+    // 0xFFFF for none (incidence slots are grouped by species, channels in
+    // increasing order, role 1 before role 2)
     const int32_t *inc_ptr;
-    const int32_t *inc_ent;
+    const int32_t *chan_inc;
     uint32_t *work_counter;
     // wave mode: per-group LDS copy of a network's change vectors and
-    // incidence lists (capacities in 32-bit words)
-    int32_t tab_m, tab_nnz, tab_inc, tab_words;
+    // incidence ranges (capacities in 32-bit words); wide_ve is set when a
+    // channel of the group changes more than kVecSlots species
+    int32_t tab_m, tab_nnz, tab_words;
+    int32_t wide_ve;
 };
 
 }  // namespace ssa

@@ -64,13 +64,19 @@ __device__ void log_tie(const RunParams &p, uint32_t g, int k, int chosen, int s
     }
 }
 
-// The channels a lane owns, read once per network.
+// The channels a lane owns, read once per network.  For the backward also
+// the first kVecSlots change-vector entries of each, two per word as
+// species | delta << 8 in 16 bits (zero-padded), and its two incidence slots
+// as pos1 | pos2 << 16.
 template <int L, int BPL>
 struct LaneChannels {
     static constexpr int C = 4 * BPL;
     int s1[C], s2[C], homo[C], csr[C], j[C];
     float c[C];
     bool on[C];
+    uint32_t ve[C][kVecSlots / 2];
+    uint32_t pos[C];
+    static constexpr uint32_t kSink = 8 * BPL * L;   // incidence slot that nothing reads
 
     __device__ void load(const RunParams &p, const NetDev &nd, int gl)
     {
@@ -86,6 +92,9 @@ struct LaneChannels {
             homo[q] = 0;
             csr[q] = 0;
             c[q] = 0.f;
+            pos[q] = kSink | (kSink << 16);
+#pragma unroll
+            for (int e = 0; e < kVecSlots / 2; ++e) ve[q][e] = 0u;
             if (on[q]) {
                 const ReactDesc r = rd[jj];
                 s1[q] = r.s1;
@@ -93,6 +102,16 @@ struct LaneChannels {
                 homo[q] = r.homodimer;
                 csr[q] = r.csr;
                 c[q] = expf(p.theta[nd.param_off + r.rate]) * r.mult;
+                const int beg = r.csr & 0xFFFFFF, cnt = (int)((uint32_t)r.csr >> 24);
+#pragma unroll
+                for (int e = 0; e < kVecSlots; ++e) {
+                    const int32_t ent = e < cnt ? p.csr[beg + e] : 0;
+                    const uint32_t h = ((uint32_t)csr_species(ent) & 0xFFu) | (((uint32_t)csr_delta(ent) & 0xFFu) << 8);
+                    ve[q][e >> 1] |= h << (16 * (e & 1));
+                }
+                const uint32_t pi = (uint32_t)p.chan_inc[nd.react_off + jj];
+                const uint32_t p1 = pi & 0xFFFFu, p2 = pi >> 16;
+                pos[q] = (p1 == 0xFFFFu ? kSink : p1) | ((p2 == 0xFFFFu ? kSink : p2) << 16);
             }
         }
     }
@@ -101,17 +120,15 @@ struct LaneChannels {
 // A network's tables staged in the group's LDS slot:
 //   desc[tab_m]        channel j: first entry (relative) | entry count << 24
 //   ent[tab_nnz]       change-vector entries, species | delta << 16
-//   inc_ptr[kMaxN+1]   species -> range of incidence entries (relative)
-//   inc[tab_inc]       channel | role << 16
+//   inc_ptr[kMaxN+1]   species -> range of its incidence slots
 struct GroupTab {
-    int32_t *desc, *ent, *inc_ptr, *inc;
+    int32_t *desc, *ent, *inc_ptr;
 
     __device__ GroupTab(int32_t *base, const RunParams &p)
     {
         desc = base;
         ent = desc + p.tab_m;
         inc_ptr = ent + p.tab_nnz;
-        inc = inc_ptr + (kMaxN + 1);
     }
 
     __device__ void load(const RunParams &p, const NetDev &nd, int gl, int L)
@@ -126,10 +143,7 @@ struct GroupTab {
         }
         for (int e = gl; e < n_ent; e += L) ent[e] = p.csr[base_e + e];
         const int *ip = p.inc_ptr + nd.inc_off;
-        const int base_i = ip[0];
-        const int n_inc = ip[nd.N] - base_i;
-        for (int s = gl; s <= nd.N; s += L) inc_ptr[s] = ip[s] - base_i;
-        for (int e = gl; e < n_inc; e += L) inc[e] = p.inc_ent[base_i + e];
+        for (int s = gl; s <= nd.N; s += L) inc_ptr[s] = ip[s];
     }
 };
 
@@ -362,8 +376,13 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
 }
 
 // --------------------------------------------------------------------------
+// waves per SIMD the backward's registers are held to
 template <int L, int BPL>
-__global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
+constexpr int bwd_waves() { return BPL == 1 && L == 64 ? 3 : 2; }
+
+template <int L, int BPL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(bwd_waves<L, BPL>())))
+void bwd_kernel(RunParams p)
 {
     constexpr int G = 64 / L;
     constexpr int C = 4 * BPL;
@@ -371,7 +390,8 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
     constexpr int KREC = 64;
     __shared__ int s_x[kWaves][G][kMaxN];
     __shared__ float s_lam32[kWaves][G][kMaxN];      // FP32 view of lambda (base + increments)
-    __shared__ float s_contrib[kWaves][G][2][MMAX];  // per-channel contributions to dlambda[s1], dlambda[s2]
+    __shared__ float s_inc[kWaves][G][2 * MMAX + 1];  // per-channel contributions to dlambda[s1], dlambda[s2],
+                                                      // in incidence-slot order, + a sink slot
     __shared__ uint8_t s_tape[kWaves][G][KREC];
     extern __shared__ int32_t s_dyn[];
     const int wid = uniform_i((int)(threadIdx.x >> 6));
@@ -379,8 +399,7 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
     const int grp = lane / L, gl = lane & (L - 1);
     int *sx = s_x[wid][grp];
     float *slam = s_lam32[wid][grp];
-    float *scon1 = s_contrib[wid][grp][0];
-    float *scon2 = s_contrib[wid][grp][1];
+    float *sinc = s_inc[wid][grp];
     uint8_t *stape = s_tape[wid][grp];
     GroupTab tab(s_dyn + (wid * G + grp) * p.tab_words, p);
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
@@ -633,12 +652,26 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     float s = 0.f;
-                    if (ch.on[q]) {
-                        const int d = tab.desc[ch.j[q]];
-                        const int beg = d & 0xFFFFFF, cnt = (int)((uint32_t)d >> 24);
-                        for (int e = 0; e < cnt; ++e) {
-                            const int32_t ent = tab.ent[beg + e];
-                            s += (float)csr_delta(ent) * slam[csr_species(ent)];
+                    if (p.wide_ve) {
+                        if (ch.on[q]) {
+                            const int d = tab.desc[ch.j[q]];
+                            const int beg = d & 0xFFFFFF, cnt = (int)((uint32_t)d >> 24);
+                            for (int e = 0; e < cnt; ++e) {
+                                const int32_t ent = tab.ent[beg + e];
+                                s += (float)csr_delta(ent) * slam[csr_species(ent)];
+                            }
+                        }
+                    } else {
+                        // padding entries are species 0 with delta 0
+#pragma unroll
+                        for (int e = 0; e < kVecSlots; ++e) {
+                            // decoded per step (kept packed across the loop to save registers)
+                            uint32_t w = ch.ve[q][e >> 1];
+                            asm volatile("" : "+v"(w));
+                            const uint32_t h = w >> (16 * (e & 1));
+                            const int sp = (int)(h & 0xFFu);
+                            const int dl = (int)(int8_t)(uint8_t)((h >> 8) & 0xFFu);
+                            s += (float)dl * slam[sp];
                         }
                     }
                     wv[q] = s;
@@ -663,8 +696,10 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                     const float coef = gq * ra[q] + cc;
                     if (on_k && ch.on[q]) {
                         dth32[q] += gq + cc * a[q];
-                        scon1[ch.j[q]] = coef * A2[q];
-                        scon2[ch.j[q]] = coef * A1[q];
+                        uint32_t ps = ch.pos[q];
+                        asm volatile("" : "+v"(ps));
+                        sinc[ps & 0xFFFFu] = coef * A2[q];
+                        sinc[ps >> 16] = coef * A1[q];
                     }
                 }
                 wave_sync();
@@ -674,11 +709,15 @@ __global__ __launch_bounds__(kBlock) void bwd_kernel(RunParams p)
                     for (int m = 0; m < SPL; ++m) {
                         const int s = gl + L * m;
                         if (s < N) {
+                            // the species' slots in order, four reads in flight
+                            const int end = tab.inc_ptr[s + 1];
+                            int e = tab.inc_ptr[s];
                             float d = 0.f;
-                            for (int e = tab.inc_ptr[s]; e < tab.inc_ptr[s + 1]; ++e) {
-                                const int32_t ent = tab.inc[e];
-                                d += (ent >> 16) == 1 ? scon1[ent & 0xFFFF] : scon2[ent & 0xFFFF];
+                            for (; e + 4 <= end; e += 4) {
+                                const float v0 = sinc[e], v1 = sinc[e + 1], v2 = sinc[e + 2], v3 = sinc[e + 3];
+                                d = (((d + v0) + v1) + v2) + v3;
                             }
+                            for (; e < end; ++e) d += sinc[e];
                             dlam[m] += d;
                         }
                     }
@@ -772,7 +811,7 @@ size_t wave_static_lds(int cls, bool backward)
     const int bpl = cls == kWave_L64x2 ? 2 : 1;
     size_t b = sizeof(int) * wave::kWaves * G * wave::kMaxN;
     if (backward)
-        b += sizeof(float) * wave::kWaves * G * wave::kMaxN + sizeof(float) * wave::kWaves * G * 2 * 4 * bpl * L +
+        b += sizeof(float) * wave::kWaves * G * wave::kMaxN + sizeof(float) * wave::kWaves * G * (2 * 4 * bpl * L + 1) +
              wave::kWaves * G * 64;
     return b;
 }

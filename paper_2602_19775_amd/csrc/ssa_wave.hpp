@@ -17,6 +17,9 @@ enum WaveClass : int {
 };
 
 constexpr int kWaveMaxSpecies = 64;
+// Change-vector entries a channel slot keeps in registers for the backward's
+// w = v_j . lambda (channels with more use the table in LDS).
+constexpr int kVecSlots = 4;
 
 // Smallest class whose group covers every Philox block of a network with
 // max_M channels, or -1.
