@@ -106,7 +106,9 @@ constexpr int kRowBcast8 = 0x158;  // lane 8 of each row
 template <int CTRL>
 __device__ __forceinline__ int dpp(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    // every control used here reads a valid lane, so bound_ctrl only spares
+    // the copy of the old value
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 
 template <int CTRL>
@@ -191,48 +193,68 @@ __device__ __forceinline__ float group_min(float v)
     return v;
 }
 
-// Race state (smallest ratio r1, its channel j1, second smallest r2) merged
-// with another lane's: the smaller (r1, j1) pair wins, r2 is the smallest of
-// the rest.  Symmetric in its arguments.
-__device__ __forceinline__ void race_merge(float a1, int aj, float a2, float b1, int bj, float b2,
-                                           float &r1, int &j1, float &r2)
+// Race state (smallest ratio r1, its channel j1, second smallest r2) over a
+// group of lanes.  Ratios are non-negative, so the bit pattern of r1 (with
+// -0 made +0) orders like the value, and (r1, j1) packs into one 64-bit key
+// whose unsigned minimum is the smaller ratio with the lowest channel on
+// exact ties.  r2 is the smallest of the rest: min(a2, b2, max(a1, b1)).
+namespace racekey {
+
+__device__ __forceinline__ uint64_t pack(float r1, int j1)
 {
-    const bool b_wins = b1 < a1 || (b1 == a1 && bj < aj);
-    r2 = fminf(fminf(a2, b2), fmaxf(a1, b1));
-    r1 = b_wins ? b1 : a1;
-    j1 = b_wins ? bj : aj;
+    const uint32_t bits = (uint32_t)__float_as_int(r1 + 0.0f);
+    return ((uint64_t)bits << 32) | (uint32_t)j1;
+}
+
+__device__ __forceinline__ float ratio(uint64_t k) { return __int_as_float((int)(uint32_t)(k >> 32)); }
+
+__device__ __forceinline__ void merge(uint64_t &k, float &r2, uint64_t ko, float o2)
+{
+    r2 = fminf(fminf(r2, o2), fmaxf(ratio(k), ratio(ko)));
+    k = ko < k ? ko : k;
 }
 
 template <int CTRL>
-__device__ __forceinline__ void race_step(float &r1, int &j1, float &r2)
+__device__ __forceinline__ void step(uint64_t &k, float &r2)
 {
-    race_merge(r1, j1, r2, lanes::dpp<CTRL>(r1), lanes::dpp<CTRL>(j1), lanes::dpp<CTRL>(r2), r1, j1, r2);
+    const int lo = lanes::dpp<CTRL>((int)(uint32_t)k);
+    const int hi = lanes::dpp<CTRL>((int)(uint32_t)(k >> 32));
+    merge(k, r2, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo, lanes::dpp<CTRL>(r2));
 }
+
+}  // namespace racekey
 
 template <int L>
 __device__ __forceinline__ void group_race(float &r1, int &j1, float &r2)
 {
     static_assert(L == 8 || L == 16 || L == 32 || L == 64, "group width");
-    race_step<lanes::kXor1>(r1, j1, r2);
-    race_step<lanes::kXor2>(r1, j1, r2);
-    race_step<lanes::kHalfMirror>(r1, j1, r2);
-    if (L >= 16) race_step<lanes::kMirror>(r1, j1, r2);
+    uint64_t k = racekey::pack(r1, j1);
+    racekey::step<lanes::kXor1>(k, r2);
+    racekey::step<lanes::kXor2>(k, r2);
+    racekey::step<lanes::kHalfMirror>(k, r2);
+    if (L >= 16) racekey::step<lanes::kMirror>(k, r2);
     if (L >= 32) {
-        float e1, o1, e2, o2;
-        int ej, oj;
-        lanes::rows16(r1, e1, o1);
-        lanes::rows16(j1, ej, oj);
+        int elo, olo, ehi, ohi;
+        float e2, o2;
+        lanes::rows16((int)(uint32_t)k, elo, olo);
+        lanes::rows16((int)(uint32_t)(k >> 32), ehi, ohi);
         lanes::rows16(r2, e2, o2);
-        race_merge(e1, ej, e2, o1, oj, o2, r1, j1, r2);
+        k = ((uint64_t)(uint32_t)ehi << 32) | (uint32_t)elo;
+        r2 = e2;
+        racekey::merge(k, r2, ((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo, o2);
     }
     if (L >= 64) {
-        float l1, h1, l2, h2;
-        int lj, hj;
-        lanes::halves(r1, l1, h1);
-        lanes::halves(j1, lj, hj);
+        int llo, hlo, lhi, hhi;
+        float l2, h2;
+        lanes::halves((int)(uint32_t)k, llo, hlo);
+        lanes::halves((int)(uint32_t)(k >> 32), lhi, hhi);
         lanes::halves(r2, l2, h2);
-        race_merge(l1, lj, l2, h1, hj, h2, r1, j1, r2);
+        k = ((uint64_t)(uint32_t)lhi << 32) | (uint32_t)llo;
+        r2 = l2;
+        racekey::merge(k, r2, ((uint64_t)(uint32_t)hhi << 32) | (uint32_t)hlo, h2);
     }
+    r1 = racekey::ratio(k);
+    j1 = (int)(uint32_t)k;
 }
 
 // The value of the first lane of each group.

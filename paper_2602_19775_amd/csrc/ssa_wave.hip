@@ -380,7 +380,8 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
 template <int L, int BPL>
 constexpr int bwd_waves() { return BPL == 1 && L == 64 ? 3 : 2; }
 
-template <int L, int BPL>
+// TMODE: 0 for 1/T = 2, 1 for 1/T = 1, 2 for any other temperature
+template <int L, int BPL, int TMODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(bwd_waves<L, BPL>())))
 void bwd_kernel(RunParams p)
 {
@@ -405,7 +406,6 @@ void bwd_kernel(RunParams p)
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
     const float invT = 1.0f / p.temperature;
-    const bool invT_is_2 = invT == 2.0f, invT_is_1 = invT == 1.0f;
 
     LaneChannels<L, BPL> ch;
     int cached_net = -1;
@@ -640,8 +640,8 @@ void bwd_kernel(RunParams p)
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     float v = rmin * fast_rcp(r[q]);
-                    if (invT_is_2) v = v * v;
-                    else if (!invT_is_1) v = v > 0.f ? exp2f(log2f(v) * invT) : 0.f;
+                    if (TMODE == 0) v = v * v;
+                    else if (TMODE == 2) v = v > 0.f ? exp2f(log2f(v) * invT) : 0.f;
                     y[q] = v;
                     ys += v;
                 }
@@ -797,9 +797,15 @@ template <int L, int BPL>
 static hipError_t launch_wave(const RunParams &p, bool backward, int n_blocks, hipStream_t stream)
 {
     const size_t dyn = sizeof(int32_t) * (size_t)p.tab_words * wave::kWaves * (64 / L);
-    if (backward)
-        hipLaunchKernelGGL((wave::bwd_kernel<L, BPL>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
-    else
+    if (backward) {
+        const float invT = 1.0f / p.temperature;
+        if (invT == 2.0f)
+            hipLaunchKernelGGL((wave::bwd_kernel<L, BPL, 0>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
+        else if (invT == 1.0f)
+            hipLaunchKernelGGL((wave::bwd_kernel<L, BPL, 1>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
+        else
+            hipLaunchKernelGGL((wave::bwd_kernel<L, BPL, 2>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
+    } else
         hipLaunchKernelGGL((wave::fwd_kernel<L, BPL>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
     return hipGetLastError();
 }
