@@ -30,6 +30,25 @@ __device__ __forceinline__ double bin_edge(double t_obs, int b, int n_bins)
     return t_obs * (double)b / (double)n_bins;
 }
 
+// Checkpoints and the choice tape are kept trajectory-major in this mode: a
+// group works on one trajectory at a time, so its successive tape words and
+// its checkpointed counts share cache lines instead of each touching a line of
+// its own.
+__device__ __forceinline__ int64_t tape_at(const RunParams &p, int64_t g, int64_t w)
+{
+    return g * p.tape_words + w;
+}
+
+__device__ __forceinline__ int64_t ckx_at(const RunParams &p, const NetDev &nd, int64_t c, int64_t i, int s)
+{
+    return c * p.state_total + nd.state_off + i * nd.N + s;
+}
+
+__device__ __forceinline__ int64_t ckt_at(const RunParams &p, int64_t g, int64_t c)
+{
+    return g * p.n_ckpt + c;
+}
+
 // LDS writes of one lane become visible to the other lanes of its wavefront.
 __device__ __forceinline__ void wave_sync()
 {
@@ -247,8 +266,8 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
             if (p.ck_x) {
                 if (ck_left == 0) {
                     if (active) {
-                        for (int s = gl; s < N; s += L) p.ck_x[ck_idx * p.state_total + nd.state_off + s * B + i] = sx[s];
-                        if (gl == 0) p.ck_t[ck_idx * p.traj_total + g] = t;
+                        for (int s = gl; s < N; s += L) p.ck_x[ckx_at(p, nd, ck_idx, i, s)] = sx[s];
+                        if (gl == 0) p.ck_t[ckt_at(p, g, ck_idx)] = t;
                     }
                     ck_idx += 1;
                     ck_left = p.K;
@@ -330,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
                 const int pos = k & (spw - 1);
                 tword |= fire ? (uint32_t)j1 << (p.tape_bits * pos) : 0u;
                 if (pos == spw - 1) {
-                    if (have && gl == 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
+                    if (have && gl == 0) p.tape[tape_at(p, g, k >> tshift)] = tword;
                     tword = 0u;
                 }
             }
@@ -340,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
             active = fire;
         }
         if (have) {
-            if (spw && (k & (spw - 1)) != 0 && gl == 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
+            if (spw && (k & (spw - 1)) != 0 && gl == 0) p.tape[tape_at(p, g, k >> tshift)] = tword;
             if (bin < n_bins) {
                 double xo[kObsMax];
 #pragma unroll
@@ -512,7 +531,7 @@ void bwd_kernel(RunParams p)
                 }
                 if (k_lo < n)
                     for (int s = gl; s < N; s += L)
-                        sx[s] = p.ck_x[(int64_t)cseg * p.state_total + nd.state_off + s * B + i];
+                        sx[s] = p.ck_x[ckx_at(p, nd, cseg, i, s)];
                 wave_sync();
                 for (int k = k_lo; k < k_hi; ++k) {
                     const bool on_k = k < n;
@@ -549,8 +568,8 @@ void bwd_kernel(RunParams p)
             }
             if (k_hi < n) {
                 const int64_t c1 = cseg + 1;
-                for (int s = gl; s < N; s += L) sx[s] = p.ck_x[c1 * p.state_total + nd.state_off + s * B + i];
-                t = p.ck_t[c1 * p.traj_total + g];
+                for (int s = gl; s < N; s += L) sx[s] = p.ck_x[ckx_at(p, nd, c1, i, s)];
+                t = p.ck_t[ckt_at(p, g, c1)];
                 wave_sync();
             }
             uint32_t tword = 0u, tnext = 0u;
@@ -581,9 +600,9 @@ void bwd_kernel(RunParams p)
                     const int widx = k >> tshift;
                     if (widx != tword_idx) {
                         tword = (widx == tword_idx - 1) ? tnext
-                                                        : (have ? p.tape[(int64_t)widx * p.traj_total + g] : 0u);
+                                                        : (have ? p.tape[tape_at(p, g, widx)] : 0u);
                         tword_idx = widx;
-                        tnext = (have && widx > 0) ? p.tape[(int64_t)(widx - 1) * p.traj_total + g] : 0u;
+                        tnext = (have && widx > 0) ? p.tape[tape_at(p, g, widx - 1)] : 0u;
                     }
                     j = (int)((tword >> (p.tape_bits * (k & (spw - 1)))) & tmask);
                 }
