@@ -6,6 +6,7 @@ import subprocess
 import sys
 
 import numpy as np
+import torch
 
 from paper_2602_19775_amd import autotune as A
 from paper_2602_19775_amd import workloads as W
@@ -53,3 +54,33 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_moment_mse_gradient_matches_autograd():
+    from paper_2602_19775_amd import losses
+    g = torch.Generator().manual_seed(3)
+    nb, no, B = 5, 2, 37
+    obs = (torch.rand(nb * no * B + 7, generator=g, dtype=torch.float64) * 50).requires_grad_(True)
+    tm = torch.rand(nb, no, generator=g, dtype=torch.float64) * 50
+    tv = torch.rand(nb, no, generator=g, dtype=torch.float64) * 200
+    l1 = losses.moment_mse(obs, tm, tv, nb, no, B)
+    (g1,) = torch.autograd.grad(l1, obs)
+    l2 = losses.moment_mse_autograd(obs, tm, tv, nb, no, B)
+    (g2,) = torch.autograd.grad(l2, obs)
+    assert abs(l1.item() - l2.item()) <= 1e-12 * abs(l2.item())
+    assert torch.allclose(g1, g2, rtol=1e-10, atol=1e-14)
+    assert torch.all(g1[nb * no * B:] == 0)
+
+
+def test_autocorrelation_fft_matches_lag_sums():
+    from paper_2602_19775_amd import losses
+    g = torch.Generator().manual_seed(4)
+    nb, B, lag = 40, 9, 12
+    obs = (torch.rand(nb * B, generator=g, dtype=torch.float64) * 30).requires_grad_(True)
+    r1 = losses.mean_autocorrelation(obs, nb, B, lag)
+    r2 = losses.mean_autocorrelation_direct(obs, nb, B, lag)
+    assert torch.allclose(r1, r2, rtol=0, atol=1e-13)
+    w = torch.rand(lag, generator=g, dtype=torch.float64)
+    (g1,) = torch.autograd.grad((r1 * w).sum(), obs)
+    (g2,) = torch.autograd.grad((r2 * w).sum(), obs)
+    assert torch.allclose(g1, g2, rtol=0, atol=1e-13)
