@@ -32,30 +32,45 @@ METRIC = "SSA steps/sec fwd and fwd+bwd on 1 MI355X; grad rel-err vs FP64 oracle
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per clock x clock
 
 
-def alu_ops_per_step(M: int, N: int, nnz_total: int, n_obs: int, backward: bool, inv_t_is_2=True) -> dict:
-    """Algorithmic vector-ALU operations of one step of one trajectory, by kind:
-    mad = 32x32->64-bit product, int = 32-bit integer add/logic/shift,
-    fp32 = FP32 add/mul/FMA/compare/select, cvt = int<->float conversion,
-    log / rcp = transcendentals, f64 = FP64 add or FMA."""
+def alu_ops_per_step(net, backward: bool, inv_t_is_2=True) -> dict:
+    """Algorithmic vector-ALU operations of one step of one trajectory of a
+    mass-action network, by kind: mad = 32x32->64-bit product, int = 32-bit
+    integer add/logic/shift, fp32 = FP32 add/mul/FMA/compare/select, cvt =
+    int<->float conversion, log / rcp = transcendentals, f64 = FP64 add or FMA.
+    Propensity work follows each channel's order: a zero-order channel's
+    propensity is its rate, a first-order one costs one product and has a
+    constant partial derivative, a second-order one costs two products and
+    two partials (a homodimer also forms X - 1)."""
+    M, N = net.n_reactions, net.n_species
+    n_obs = len(net.obs_species)
+    r = np.asarray(net.reactant)
+    order = (r >= 0).sum(axis=1)
+    n1, n2 = int((order == 1).sum()), int((order == 2).sum())
+    homo = int(((r[:, 0] >= 0) & (r[:, 0] == r[:, 1])).sum())
+    factors = n1 + 2 * n2                           # reactant factors (int -> float)
+    nnz = int(np.count_nonzero(net.stoich))
     nb = (M + 1 + 3) // 4
     w = M + 1                                        # Philox words used
     ops = {"mad": 20 * nb,                           # Philox4x32-10: two products a round
            "int": 40 * nb + 2 * w,                   # four xors a round; word -> odd 24-bit integer
-           "cvt": w, "fp32": 2 * w,                  # lattice u = int * 2^-24, E = log2(u) * -ln 2
+           "cvt": w + factors, "fp32": 2 * w,        # lattice u = int * 2^-24, E = log2(u) * -ln 2
            "log": w, "rcp": 0, "f64": 0}
+    ops["int"] += homo                               # X - 1 of homodimers
+    ops["fp32"] += factors + (M - 1) + 1             # propensities, a0, tau
+    ops["rcp"] += 1 + M                              # 1/a0, 1/a_j
     if not backward:
-        ops["cvt"] += 2 * M + 1 + n_obs              # propensity factors, clock, bin value
-        ops["int"] += M + N                          # homodimer X-1, state update
-        ops["fp32"] += 2 * M + M + 1 + M + 3 * M     # products, a0 sum, tau, r_j, race compare/min/select
-        ops["rcp"] += 1 + M                          # 1/a0 and 1/a_j
+        ops["cvt"] += 1 + n_obs                      # clock, bin value
+        ops["int"] += nnz                            # state update (select of the fired change vector)
+        ops["fp32"] += M + 3 * M                     # r_j, race compare/min/select
         ops["f64"] += 1 + n_obs                      # clock, bin integral
         return ops
-    ops["cvt"] += 2 * M + 2 + 2 * n_obs              # propensity factors, clock, time-path and bin terms
-    ops["int"] += M + N                              # homodimer X-1, reversed state update
-    ops["rcp"] += 1 + M + M + 1                      # 1/a0, 1/a_j, 1/r_j, 1/sum
-    ops["fp32"] += (3 * M + M + 1                    # products with partials, a0, tau
+    ops["cvt"] += 1 + 2 * n_obs                      # clock, time-path and bin terms
+    ops["int"] += nnz                                # reversed state update
+    ops["rcp"] += M + 1                              # 1/r_j, 1/sum
+    ops["fp32"] += (2 * n2                           # partials of second-order channels
                     + M + M + (M if inv_t_is_2 else 0) + M + M      # r_j, rho, rho^(1/T), sum, normalise
-                    + 2 * nnz_total + 2 * M + 3 * M + 2 * M + 2 * M + 4 * M)   # w, wbar, g, dtheta, coef, lambda
+                    + nnz + 2 * M + 3 * M + 2 * M + M              # w, w - w_ref and wbar, g, dtheta, coef
+                    + factors)                                      # lambda updates
     if not inv_t_is_2:
         ops["log"] += M
         ops["fp32"] += 3 * M
@@ -83,6 +98,40 @@ def measure_issue_costs():
     f32 = t[3]                      # fma
     return {"int": i32, "fp32": f32, "mad": t[0] - i32, "log": t[1] - f32, "rcp": t[2] - f32,
             "cvt": t[6] - i32, "f64": t[5]}
+
+
+def sources_sha1() -> str:
+    """Digest of the library sources (the profile summaries record the one
+    their counters were taken with)."""
+    import hashlib
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_2602_19775_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of a workload's forward or backward from the
+    FETCH_SIZE / WRITE_SIZE passes summarised under profiles/, scaled by the
+    copy calibration; None when no summary covers it or the library sources
+    changed since the counters were taken."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    sha = sources_sha1()
+    for f in sorted(os.listdir(d)):
+        if not f.endswith(".md"):
+            continue
+        with open(os.path.join(d, f)) as fh:
+            for line in fh:
+                p = line.split()
+                if len(p) == 5 and p[0] == "traffic_bytes_per_launch" and p[1] == workload and p[2] == kernel:
+                    return float(p[3]) if p[4] == f"sources={sha}" else None
+    return None
 
 
 def slots(ops: dict, cost: dict) -> float:
@@ -248,7 +297,7 @@ def bench_grn(args, torch, dev):
     per_step = slots(ops, cost)
     achieved = fired * per_step / (dom_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
+                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": profiled_traffic("grn", dom),
                 "slots_per_step": per_step, "ops_per_step": ops, "issue_cost_slots": cost,
                 "kernel_ms": dom_ms, "hidden_event_share": hidden_frac,
                 "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
@@ -502,8 +551,7 @@ def main():
     def avg_ops(backward):
         tot = {}
         for n_, b_ in zip(nets, Bs):
-            o = alu_ops_per_step(n_.n_reactions, n_.n_species, int(np.count_nonzero(n_.stoich)),
-                                 len(n_.obs_species), backward, inv2)
+            o = alu_ops_per_step(n_, backward, inv2)
             for k_, v_ in o.items():
                 tot[k_] = tot.get(k_, 0.0) + v_ * b_ / wsum
         return tot
@@ -515,7 +563,7 @@ def main():
     per_step = slots(ops, cost)
     achieved = fired * per_step / (dom_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
+                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": profiled_traffic(args.workload, dom),
                 "slots_per_step": per_step, "ops_per_step": ops, "issue_cost_slots": cost,
                 "kernel_ms": dom_ms,
                 "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
