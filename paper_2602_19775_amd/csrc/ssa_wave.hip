@@ -187,6 +187,44 @@ __device__ __forceinline__ void group_words(int M, int gl, uint32_t k, uint32_t 
     }
 }
 
+// Lane of a group and channel slot that hold channel j: word j + 1 lies in
+// Philox block b = (j + 1) / 4, which lane b mod L generates as its slot
+// 4 (b / L) + (j + 1) mod 4.
+struct Owner {
+    int lane;   // lane of the wavefront
+    int slot;
+};
+
+template <int L, int BPL>
+__device__ __forceinline__ Owner owner_of(int j, int grp)
+{
+    if (L == 64) j = __builtin_amdgcn_readfirstlane(j);   // one trajectory per wave: j is uniform
+    const int w = j + 1, b = w >> 2;
+    return Owner{grp * L + (b & (L - 1)), 4 * (b / L) + (w & 3)};
+}
+
+// v[o.slot] of lane o.lane, for every lane of the group.
+template <int L, int C>
+__device__ __forceinline__ float from_owner(const float (&v)[C], Owner o)
+{
+    if (L == 64) {
+        // owner and slot are uniform: read every slot of the owner lane into
+        // scalars and pick one (a select on the lane's own slots with a
+        // uniform index would be lowered to an indexed private array)
+        int pick = 0;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int x = __builtin_amdgcn_readlane(__float_as_int(v[q]), o.lane);
+            pick = (q == o.slot) ? x : pick;
+        }
+        return __int_as_float(pick);
+    }
+    float mine = v[0];
+#pragma unroll
+    for (int q = 1; q < C; ++q) mine = (q == o.slot) ? v[q] : mine;
+    return __shfl(mine, o.lane);
+}
+
 // X += sign * v_j through the sparse change vector (lane e applies entry e).
 template <int L>
 __device__ __forceinline__ void group_apply(const GroupTab &tab, int *sx, int j, int sign, int gl, bool act)
@@ -637,28 +675,22 @@ void bwd_kernel(RunParams p)
                     for (int o = 0; o < kObsMax; ++o)
                         if (o < nd.n_obs) lam_t += dob[o] * (double)(sx[osp[o]] - xn[o]) * inv_dt;
                 }
-                // soft sample in ratio form
+                // soft sample in ratio form, relative to the fired channel j
+                // (the race's winner, so every ratio is at most 1)
                 float r[C], ra[C];
-                float rmin = INFINITY;
-                int jmin = 0x7FFFFFFF;
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     const bool onq = ch.on[q] && a[q] > 0.f;
                     ra[q] = onq ? fast_rcp(a[q]) : 0.f;
                     r[q] = onq ? neglog_u(wd[q]) * ra[q] : INFINITY;
-                    const bool lt = r[q] < rmin;
-                    jmin = lt ? ch.j[q] : jmin;
-                    rmin = fminf(rmin, r[q]);
                 }
-                {
-                    float dummy = INFINITY;
-                    grace<L>(rmin, jmin, dummy);
-                }
+                const Owner own = owner_of<L, BPL>(j, grp);
+                const float rref = from_owner<L, C>(r, own);
                 float y[C];
                 float ys = 0.f;
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
-                    float v = rmin * fast_rcp(r[q]);
+                    float v = rref * fast_rcp(r[q]);
                     if (TMODE == 0) v = v * v;
                     else if (TMODE == 2) v = v > 0.f ? exp2f(log2f(v) * invT) : 0.f;
                     y[q] = v;
@@ -695,11 +727,8 @@ void bwd_kernel(RunParams p)
                     }
                     wv[q] = s;
                 }
-                // reference value w_jmin, broadcast from the lane owning jmin
-                float wref_l = 0.f;
-#pragma unroll
-                for (int q = 0; q < C; ++q) wref_l = (ch.on[q] && ch.j[q] == jmin) ? wv[q] : wref_l;
-                const float wref = gsum<L>(wref_l);
+                // reference value w_j from the lane owning channel j
+                const float wref = from_owner<L, C>(wv, own);
                 float wb = 0.f;
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
