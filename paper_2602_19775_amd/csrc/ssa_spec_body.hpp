@@ -454,8 +454,9 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
         uint32_t tword = 0u;
         int tword_idx = -1;
         // one reverse step k for a lane that fired it: X_{k+1} -> X_k and the
-        // adjoint recursion; w holds the Philox words of step k
-        auto sweep = [&](int k, int j, const uint32_t (&w)[Blocks<NET>::W]) {
+        // adjoint recursion; e holds -ln u of the words of step k (e[0] for
+        // the waiting time, e[1 + q] for channel q)
+        auto sweep = [&](int k, int j, const float (&e)[M + 1]) {
                 int Xn[NOBS > 0 ? NOBS : 1];
     #pragma unroll
                 for (int o = 0; o < NOBS; ++o) Xn[o] = X[NET::OBS[o]];
@@ -464,7 +465,7 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                 float a[M], A1[M], A2[M];
                 const float a0 = propensities<NET, true>(c, X, a, A1, A2);
                 const float rcp_a0 = fast_rcp(a0);
-                const float tau = neglog_u(w[0]) * rcp_a0;
+                const float tau = e[0] * rcp_a0;
                 const double t_k = t - (double)tau;
 
                 // direct dL/dt_{k+1} (doi is 0 past the observation window)
@@ -481,7 +482,7 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                 for (int q = 0; q < M; ++q) {
                     const float rq = fast_rcp(a[q]);
                     ra[q] = a[q] > 0.f ? rq : 0.f;
-                    r[q] = neglog_u(w[1 + q]) * rq;
+                    r[q] = e[1 + q] * rq;
                 }
                 float rref = r[0];
     #pragma unroll
@@ -586,16 +587,25 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
             if (k < n) {
                 uint32_t w[Blocks<NET>::W];
                 words<NET>((uint32_t)k, tid, pe, p.seed_lo, p.seed_hi, w);
-                sweep(k, j, w);
+                float e[M + 1];
+#pragma unroll
+                for (int q = 0; q <= M; ++q) e[q] = neglog_u(w[q]);
+                sweep(k, j, e);
             }
             fold(1);
         }
-        // steps every lane fired: straight-line body, Philox words of step
-        // k-1 generated while step k is swept; the choices are read one tape
-        // word (or, recomputing, one segment) at a time
+        // steps every lane fired: straight-line body, the noise of step k-1
+        // (Philox words and their logarithms) computed while step k is swept;
+        // the choices are read one tape word (or, recomputing, one segment)
+        // at a time
         if (k_split > k_lo) {
-            uint32_t wd[Blocks<NET>::W];
-            words<NET>((uint32_t)(k_split - 1), tid, pe, p.seed_lo, p.seed_hi, wd);
+            float ed[M + 1];
+            {
+                uint32_t wd[Blocks<NET>::W];
+                words<NET>((uint32_t)(k_split - 1), tid, pe, p.seed_lo, p.seed_hi, wd);
+#pragma unroll
+                for (int q = 0; q <= M; ++q) ed[q] = neglog_u(wd[q]);
+            }
             int k = k_split - 1;
             // the tape word of the next (lower) block is loaded one block ahead
             uint32_t tw_next = RECOMPUTE ? 0u : p.tape[(int64_t)(k >> tshift) * p.traj_total + g];
@@ -611,9 +621,12 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                     shift -= p.tape_bits;
                     uint32_t wn[Blocks<NET>::W];
                     words<NET>((uint32_t)(k - 1), tid, pe, p.seed_lo, p.seed_hi, wn);
-                    sweep(k, j, wd);
+                    float en[M + 1];
 #pragma unroll
-                    for (int q = 0; q < Blocks<NET>::W; ++q) wd[q] = wn[q];
+                    for (int q = 0; q <= M; ++q) en[q] = neglog_u(wn[q]);
+                    sweep(k, j, ed);
+#pragma unroll
+                    for (int q = 0; q <= M; ++q) ed[q] = en[q];
                 }
                 fold(steps);
             }
