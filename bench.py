@@ -134,6 +134,12 @@ def profiled_traffic(workload: str, kernel: str):
     return None
 
 
+def spread(ms) -> dict:
+    """Median, minimum and maximum of per-step times (ms)."""
+    a = np.asarray(ms, dtype=np.float64)
+    return {"median": float(np.median(a)), "min": float(a.min()), "max": float(a.max())}
+
+
 def slots(ops: dict, cost: dict) -> float:
     return sum(n * cost[k] for k, n in ops.items())
 
@@ -222,6 +228,7 @@ def bench_grn(args, torch, dev):
     fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     loss_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    step_stats = spread([e[0].elapsed_time(e[3]) for e in evs])
     value = fired / (ms_step * 1e-3)
 
     # forward-only rate of the plain forward (no choice tape)
@@ -229,12 +236,16 @@ def bench_grn(args, torch, dev):
     for _ in range(args.warmup):
         ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=pbufs)
     torch.cuda.synchronize()
+    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     f0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        fevs[k][0].record()
         ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=pbufs)
+        fevs[k][1].record()
     torch.cuda.synchronize()
     f1 = time.perf_counter()
     fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
+    fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
     del pbufs
     n_ties = int(bufs.n_ties.item())
     assert ssa.grn_device_status(g) == 0
@@ -329,6 +340,7 @@ def bench_grn(args, torch, dev):
                    "steps_per_traj": cfg.n_steps, "n_params": net.n_params, "temperature": cfg.temperature},
         "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate, "graph_replay": graph,
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
+        "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
         "grad_rel_err": grad_rel_err, "counts_bit_exact_sample": counts_exact, "near_ties": n_ties,
         "loss": float(loss.item()), "roofline": roofline, "cpu_baseline": cpu,
     }
@@ -475,6 +487,7 @@ def main():
     fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     loss_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    step_stats = spread([e[0].elapsed_time(e[3]) for e in evs])
     value = fired / (ms_step * 1e-3)
 
     # forward-only rate of the plain forward (no checkpoints, no choice tape)
@@ -482,12 +495,16 @@ def main():
     for _ in range(args.warmup):
         ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
     torch.cuda.synchronize()
+    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     f0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        fevs[k][0].record()
         ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
+        fevs[k][1].record()
     torch.cuda.synchronize()
     f1 = time.perf_counter()
     fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
+    fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
     del pbufs
     n_ties = int(bufs.n_ties.item())
     assert ssa.device_status(h) == 0
@@ -594,6 +611,7 @@ def main():
                    "plan": None if plan is None else {"exec_mode": plan.exec_mode, "wave_split": plan.wave_split}},
         "forward_steps_per_s": fwd_rate, "graph_replay": graph, "fwdbwd_over_forward": value / fwd_rate,
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
+        "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
         "grad_rel_err": grad_rel_err, "counts_bit_exact_sample": counts_exact, "near_ties": n_ties,
         "loss": float(loss.item()), "roofline": roofline, "cpu_baseline": cpu,
     }
