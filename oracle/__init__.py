@@ -208,7 +208,7 @@ def run(net, cfg, theta, x0: np.ndarray, traj_ids=None, ties=None, d_obs=None,
     th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
     ov = _overrides(n_traj, ties, keep)
     n_obs = c.n_obs
-    obs_shape = (n_traj, cfg.n_bins, n_obs) if cfg.obs_kind == 1 else (n_traj, n_obs)
+    obs_shape = (n_traj, cfg.n_bins, n_obs) if cfg.obs_kind in (1, 2) else (n_traj, n_obs)
     res = OracleResult(np.zeros((n_traj, N), np.int32), np.zeros(n_traj), np.zeros(n_traj, np.int32),
                        np.zeros(obs_shape), np.zeros(n_traj), np.zeros(n_traj, np.int32),
                        np.zeros(n_traj, np.int32), np.zeros(n_traj, np.int32), np.zeros(n_traj))

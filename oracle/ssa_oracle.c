@@ -23,7 +23,8 @@
  *   - Reverse recursion for dL/dX_k (Fig. 1 caption), extended with the clock
  *     adjoint dL/dt_k because the observation depends on event times.
  *   - Observation by exact time averages of the piecewise-constant path over
- *     uniform bins (Sec. 4.4), or the final counts.
+ *     uniform bins (Sec. 4.4), by the path linearly interpolated between its
+ *     event points onto a uniform time grid (Sec. 4.1), or the final counts.
  * Readings where the paper is silent (random stream layout, uniform lattice,
  * tie handling, stop rules) are listed in the design notes of the repository.
  */
@@ -155,6 +156,22 @@ static void add_interval(const orc_cfg *cfg, double t0, double t1, const double 
             for (int o = 0; o < cfg->n_obs; ++o)
                 acc[(size_t)b * cfg->n_obs + o] += val_per_obs[o] * ov;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Observation helpers: the path linearly interpolated on a uniform grid.    */
+/* ------------------------------------------------------------------------ */
+static double grid_time(const orc_cfg *cfg, int g)
+{
+    return cfg->t_obs * (double)g / (double)(cfg->n_bins - 1);
+}
+
+/* First grid index whose time is >= t (n_bins if none). */
+static int grid_first_at_or_after(const orc_cfg *cfg, double t)
+{
+    int g = 0;
+    while (g < cfg->n_bins && grid_time(cfg, g) < t) ++g;
+    return g;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -320,6 +337,21 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
             for (int w = 0; w <= M; ++w) path->E[(size_t)k_step * (M + 1) + w] = -log(u[w]);
         }
 
+        /* grid times in [t, t + tau): linear interpolation between (t, X) and
+         * (t + tau, X + v_j) */
+        if (cfg->obs_kind == ORC_OBS_GRID) {
+            const int32_t *vj = net->stoich + (size_t)jbest * N;
+            for (int g = grid_first_at_or_after(cfg, t); g < cfg->n_bins; ++g) {
+                const double tg = grid_time(cfg, g);
+                if (!(tg < t + tau)) break;
+                const double f = (tg - t) / tau;
+                for (int o = 0; o < cfg->n_obs; ++o) {
+                    const int s = cfg->obs_species[o];
+                    obs_acc[(size_t)g * cfg->n_obs + o] = (double)X[s] + f * (double)vj[s];
+                }
+            }
+        }
+
         /* fire: X += v_j (Eq. 6), t += tau */
         const int32_t *v = net->stoich + (size_t)jbest * N;
         for (int s = 0; s < N; ++s) X[s] += v[s];
@@ -328,6 +360,11 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
         if (cfg->obs_kind == ORC_OBS_BINS)
             for (int b = 1; b <= cfg->n_bins; ++b) {
                 double d = fabs(t - bin_edge(cfg, b));
+                if (d < st->edge_dist) st->edge_dist = d;
+            }
+        if (cfg->obs_kind == ORC_OBS_GRID)
+            for (int g = 0; g < cfg->n_bins; ++g) {
+                double d = fabs(t - grid_time(cfg, g));
                 if (d < st->edge_dist) st->edge_dist = d;
             }
         if (path) {
@@ -345,17 +382,22 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
         for (int o = 0; o < cfg->n_obs; ++o) xo[o] = (double)X[cfg->obs_species[o]];
         add_interval(cfg, t, cfg->t_obs, xo, obs_acc);
     }
+    if (cfg->obs_kind == ORC_OBS_GRID)
+        for (int g = grid_first_at_or_after(cfg, t); g < cfg->n_bins; ++g)
+            for (int o = 0; o < cfg->n_obs; ++o)
+                obs_acc[(size_t)g * cfg->n_obs + o] = (double)X[cfg->obs_species[o]];
     *t_out = t;
     return k_step;
 }
 
 static int obs_width(const orc_cfg *cfg)
 {
-    return cfg->obs_kind == ORC_OBS_BINS ? cfg->n_bins * cfg->n_obs : cfg->n_obs;
+    return cfg->obs_kind == ORC_OBS_FINAL ? cfg->n_obs : cfg->n_bins * cfg->n_obs;
 }
 
 static void finish_obs(const orc_cfg *cfg, const int32_t *X, double *obs)
 {
+    if (cfg->obs_kind == ORC_OBS_GRID) return;
     if (cfg->obs_kind == ORC_OBS_BINS) {
         double inv = (double)cfg->n_bins / cfg->t_obs;
         for (int i = 0; i < cfg->n_bins * cfg->n_obs; ++i) obs[i] *= inv;
@@ -370,6 +412,9 @@ static int check_args(const orc_net *net, const orc_cfg *cfg)
         return -1;
     if (cfg->obs_kind == ORC_OBS_BINS && (cfg->n_bins <= 0 || !(cfg->t_obs > 0.0)))
         return -1;
+    if (cfg->obs_kind == ORC_OBS_GRID && (cfg->n_bins < 2 || !(cfg->t_obs > 0.0)))
+        return -1;
+    if (cfg->obs_kind < ORC_OBS_FINAL || cfg->obs_kind > ORC_OBS_GRID) return -1;
     if (cfg->n_obs < 0 || (cfg->n_obs > 0 && !cfg->obs_species)) return -1;
     if (!(cfg->temperature > 0.0)) return -1;
     for (int j = 0; j < net->n_reactions; ++j)
@@ -438,6 +483,7 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
     const int nobs = cfg->n_obs;
     const double T = cfg->temperature;
     const int bins = cfg->obs_kind == ORC_OBS_BINS;
+    const int grid = cfg->obs_kind == ORC_OBS_GRID;
     const double inv_dt = bins ? (double)cfg->n_bins / cfg->t_obs : 0.0;
     double *lamX = work;              /* [N] */
     double *dX = lamX + N;            /* [N] */
@@ -461,6 +507,10 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
             for (int o = 0; o < nobs; ++o)
                 lamX[cfg->obs_species[o]] += dobs[(size_t)b * nobs + o] * tmp[(size_t)b * nobs + o] * inv_dt;
         free(tmp);
+    } else if (grid) {
+        /* grid times at or after the last event see the final state */
+        for (int g = grid_first_at_or_after(cfg, p->t[n]); g < cfg->n_bins; ++g)
+            for (int o = 0; o < nobs; ++o) lamX[cfg->obs_species[o]] += dobs[(size_t)g * nobs + o];
     } else {
         for (int o = 0; o < nobs; ++o) lamX[cfg->obs_species[o]] += dobs[o];
     }
@@ -480,6 +530,24 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
                     int s = cfg->obs_species[o];
                     lamt += dobs[(size_t)b * nobs + o] * (double)(Xk[s] - Xk1[s]) * inv_dt;
                 }
+        }
+
+        /* grid times in [t_k, t_{k+1}): obs = X_k + f (X_{k+1} - X_k) with
+         * f = (t_g - t_k)/(t_{k+1} - t_k); the X_{k+1} and t_{k+1} parts
+         * enter the adjoints of step k+1 before this step uses them */
+        int g_lo = 0, g_hi = 0;
+        if (grid) {
+            g_lo = grid_first_at_or_after(cfg, tk);
+            g_hi = grid_first_at_or_after(cfg, tk1);
+            for (int g = g_lo; g < g_hi; ++g) {
+                const double f = (grid_time(cfg, g) - tk) / (tk1 - tk);
+                for (int o = 0; o < nobs; ++o) {
+                    const int s = cfg->obs_species[o];
+                    const double d = dobs[(size_t)g * nobs + o];
+                    lamX[s] += d * f;
+                    lamt += d * (double)(Xk1[s] - Xk[s]) * (-f / (tk1 - tk));
+                }
+            }
         }
 
         double a0 = 0.0;
@@ -533,6 +601,17 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
                 for (int o = 0; o < nobs; ++o)
                     dX[cfg->obs_species[o]] += dobs[(size_t)b * nobs + o] * tmp[(size_t)b * nobs + o] * inv_dt;
         }
+        /* the X_k and t_k parts of this interval's grid times */
+        if (grid)
+            for (int g = g_lo; g < g_hi; ++g) {
+                const double f = (grid_time(cfg, g) - tk) / (tk1 - tk);
+                for (int o = 0; o < nobs; ++o) {
+                    const int s = cfg->obs_species[o];
+                    const double d = dobs[(size_t)g * nobs + o];
+                    dX[s] += d * (1.0 - f);
+                    lamt += d * (double)(Xk1[s] - Xk[s]) * ((f - 1.0) / (tk1 - tk));
+                }
+            }
         for (int q = 0; q < N; ++q) lamX[q] += dX[q];
     }
     free(tmp);
@@ -599,7 +678,7 @@ int64_t orc_trace(const orc_net *net, const orc_cfg *cfg, const double *theta,
     if (c.n_steps > cap) c.n_steps = cap;
     double *k = malloc(sizeof(double) * M);
     double *scratch = malloc(sizeof(double) * (2 * M + 1 + c.n_obs + 1));
-    double *obs = calloc((size_t)(c.obs_kind == ORC_OBS_BINS ? c.n_bins * c.n_obs : 1) + 1,
+    double *obs = calloc((size_t)(c.obs_kind != ORC_OBS_FINAL ? c.n_bins * c.n_obs : 1) + 1,
                          sizeof(double));
     int32_t *Xw = malloc(sizeof(int32_t) * N);
     int64_t n = -1;

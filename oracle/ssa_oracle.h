@@ -31,7 +31,11 @@ typedef struct orc_net {
     const int32_t *stoich;      /* [M*N] */
 } orc_net;
 
-enum { ORC_OBS_FINAL = 0, ORC_OBS_BINS = 1 };
+/* FINAL: final counts.  BINS: exact time averages over n_bins uniform bins of
+ * [0, t_obs].  GRID: the path linearly interpolated between its event points
+ * (t_k, X_k) at n_bins uniform grid times t_obs g / (n_bins - 1), held at its
+ * last state after the last event (Sec. 4.1). */
+enum { ORC_OBS_FINAL = 0, ORC_OBS_BINS = 1, ORC_OBS_GRID = 2 };
 
 typedef struct orc_cfg {
     uint64_t seed;
@@ -39,9 +43,9 @@ typedef struct orc_cfg {
     uint32_t epoch;
     int64_t n_steps;        /* fire at most this many reactions */
     double t_end;           /* fire only while t + tau <= t_end (INFINITY: no limit) */
-    int32_t obs_kind;       /* ORC_OBS_FINAL or ORC_OBS_BINS */
-    int32_t n_bins;
-    double t_obs;           /* bins split [0, t_obs] uniformly */
+    int32_t obs_kind;       /* ORC_OBS_FINAL, ORC_OBS_BINS or ORC_OBS_GRID */
+    int32_t n_bins;         /* bins, or grid points */
+    double t_obs;           /* bins split [0, t_obs] uniformly; the grid spans it */
     int32_t n_obs;
     const int32_t *obs_species;  /* [n_obs] */
     double temperature;     /* Gumbel-Softmax temperature T of Eq. (3) */

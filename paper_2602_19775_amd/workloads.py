@@ -22,6 +22,8 @@ import numpy as np
 # Observation kinds.
 OBS_FINAL = 0   # final copy numbers of the observed species
 OBS_BINS = 1    # exact time average of the piecewise-constant path over uniform bins (Sec. 4.4)
+OBS_GRID = 2    # the path linearly interpolated between its event points at n_bins uniform
+                # times t_obs g / (n_bins - 1), held after the last event (Sec. 4.1)
 
 # Random-stream purposes (high byte of the fourth Philox counter word).
 PURPOSE_SIMULATE = 0

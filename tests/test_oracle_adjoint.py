@@ -43,6 +43,10 @@ def _overlaps(t0, t1, t_obs, nb):
     return np.clip(np.minimum(t1, e[1:]) - np.maximum(t0, e[:-1]), 0.0, None)
 
 
+def _grid(cfg):
+    return np.array([cfg.t_obs * g / (cfg.n_bins - 1) for g in range(cfg.n_bins)])
+
+
 def _softmax_masked(z, active):
     z = np.where(active, z, -np.inf)
     z = z - z[active].max()
@@ -66,18 +70,27 @@ def surrogate_F(net, cfg, theta, theta_ref, tr, d_obs):
     X = tr.X[0].astype(np.float64)
     t = 0.0
     bins = cfg.obs_kind == W.OBS_BINS
-    obs = np.zeros((cfg.n_bins, len(net.obs_species))) if bins else None
+    grid = cfg.obs_kind == W.OBS_GRID
+    obs = np.zeros((cfg.n_bins, len(net.obs_species))) if (bins or grid) else None
+    tg = _grid(cfg) if grid else None
     for s in range(n):
         a = k * _h(net, X)
         tau = E[s, 0] / a.sum()
         y = _softmax_masked((np.log(np.where(act[s], a, 1.0)) - np.log(E[s, 1:])) / T, act[s])
         if bins:
             obs += np.outer(_overlaps(t, t + tau, cfg.t_obs, cfg.n_bins), X[net.obs_species])
-        X = X + V[tr.j[s]] + (y - y_ref[s]) @ V
+        Xn = X + V[tr.j[s]] + (y - y_ref[s]) @ V
+        if grid:
+            for g in np.flatnonzero((tg >= t) & (tg < t + tau)):
+                f = (tg[g] - t) / tau
+                obs[g] = X[net.obs_species] + f * (Xn - X)[net.obs_species]
+        X = Xn
         t += tau
     if bins:
         obs += np.outer(_overlaps(t, cfg.t_obs, cfg.t_obs, cfg.n_bins), X[net.obs_species])
         obs *= cfg.n_bins / cfg.t_obs
+    elif grid:
+        obs[tg >= t] = X[net.obs_species]
     else:
         obs = X[net.obs_species]
     return float(np.sum(d_obs * obs))
@@ -95,9 +108,12 @@ def literal_st_grad(net, cfg, theta0, tr, d_obs):
     X = torch.tensor(tr.X[0], dtype=dt)
     t = torch.zeros((), dtype=dt)
     bins = cfg.obs_kind == W.OBS_BINS
+    grid = cfg.obs_kind == W.OBS_GRID
     osp = torch.tensor(net.obs_species, dtype=torch.long)
     edges = torch.linspace(0.0, cfg.t_obs, cfg.n_bins + 1, dtype=dt) if bins else None
     obs = torch.zeros((cfg.n_bins, len(net.obs_species)), dtype=dt) if bins else None
+    tg = _grid(cfg) if grid else None
+    gobs = [None] * cfg.n_bins if grid else None
 
     def h_of(X):
         hs = []
@@ -131,11 +147,18 @@ def literal_st_grad(net, cfg, theta0, tr, d_obs):
         if bins:
             obs = obs + torch.outer(ov(t, t + tau), X[osp])
         Xn = X + y_st @ V                                        # Eqs. (6)-(7)
-        X = Xn + (Xn.detach().round() - Xn.detach())             # value stays integer
+        Xn = Xn + (Xn.detach().round() - Xn.detach())            # value stays integer
+        if grid:                                                 # linear interpolation (Sec. 4.1)
+            t1 = t + tau
+            for g in np.flatnonzero((tg >= float(t.detach())) & (tg < float(t1.detach()))):
+                gobs[g] = X[osp] + (float(tg[g]) - t) / (t1 - t) * (Xn - X)[osp]
+        X = Xn
         t = t + tau
     if bins:
         obs = obs + torch.outer(ov(t, torch.tensor(cfg.t_obs, dtype=dt)), X[osp])
         obs = obs * (cfg.n_bins / cfg.t_obs)
+    elif grid:
+        obs = torch.stack([X[osp] if v is None else v for v in gobs])
     else:
         obs = X[osp]
     L = torch.sum(torch.tensor(d_obs, dtype=dt) * obs)
@@ -163,24 +186,34 @@ def _case(name):
     elif name == "channel_absorbing":
         net = W.ion_channel_coi()
         cfg = W.RunConfig(n_steps=50, obs_kind=W.OBS_BINS, n_bins=8, t_obs=4.0, temperature=0.3)
+    elif name == "abc_grid":
+        net = W.dimerization_abc()
+        cfg = W.RunConfig(n_steps=80, obs_kind=W.OBS_GRID, n_bins=12, t_obs=0.0, temperature=0.5)
+    elif name == "abc_grid_coldT":
+        net = W.dimerization_abc(0.125, 0.025)
+        cfg = W.RunConfig(n_steps=60, obs_kind=W.OBS_GRID, n_bins=9, t_obs=0.0, temperature=0.01)
+    elif name == "channel_grid_absorbing":
+        net = W.ion_channel_coi()
+        cfg = W.RunConfig(n_steps=50, obs_kind=W.OBS_GRID, n_bins=10, t_obs=6.0, temperature=0.3)
     else:
         raise KeyError(name)
     return net, cfg, g
 
 
 CASES = ["dimer_bins", "dimer_bins_coldT", "abc_final", "oscillator_bins", "random_bins",
-         "channel_absorbing"]
+         "channel_absorbing", "abc_grid", "abc_grid_coldT", "channel_grid_absorbing"]
 
 
 def _prepare(orc, name, traj_id=1):
     net, cfg, g = _case(name)
     theta0 = net.theta0.copy()
-    if cfg.obs_kind == W.OBS_BINS and cfg.t_obs == 0.0:
+    if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID) and cfg.t_obs == 0.0:
         tr0 = orc.trace(net, cfg.replace(obs_kind=W.OBS_FINAL), theta0, net.x0, traj_id=traj_id,
                         cap=cfg.n_steps)
         cfg = cfg.replace(t_obs=float(tr0.t[-1]) * 0.8)
     tr = orc.trace(net, cfg, theta0, net.x0, traj_id=traj_id, cap=cfg.n_steps)
-    shape = (cfg.n_bins, len(net.obs_species)) if cfg.obs_kind == W.OBS_BINS else (len(net.obs_species),)
+    shape = ((cfg.n_bins, len(net.obs_species)) if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID)
+             else (len(net.obs_species),))
     d_obs = g.normal(size=shape)
     r = orc.run(net, cfg, theta0, net.x0[None, :], traj_ids=[traj_id], d_obs=d_obs[None])
     assert r.steps_done[0] == len(tr.j)
@@ -240,3 +273,20 @@ def test_large_temperature_gives_pathwise_crn_derivative(orc):
         fd = ((rp.obs - rm.obs) * d_obs).sum((1, 2)) / (float(tp[p]) - float(tm[p]))
         ref = r.grad[:, p]
         assert np.allclose(fd[keep], ref[keep], rtol=1e-5, atol=1e-6 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name", ["abc_grid", "channel_grid_absorbing"])
+def test_grid_observation_is_linear_interpolation(orc, name):
+    """The grid observation is numpy's linear interpolation of the event
+    points (t_k, X_k), held at the last state after the last event."""
+    net, cfg, _ = _case(name)
+    if cfg.t_obs == 0.0:
+        tr0 = orc.trace(net, cfg.replace(obs_kind=W.OBS_FINAL), net.theta0, net.x0, traj_id=2, cap=cfg.n_steps)
+        cfg = cfg.replace(t_obs=float(tr0.t[-1]) * 0.8)
+    for q in range(4):
+        tr = orc.trace(net, cfg, net.theta0, net.x0, traj_id=q, cap=cfg.n_steps)
+        r = orc.run(net, cfg, net.theta0, net.x0[None, :], traj_ids=[q])
+        tg = _grid(cfg)
+        for o, sp in enumerate(net.obs_species):
+            ref = np.interp(tg, tr.t, tr.X[:, sp].astype(np.float64))
+            assert np.allclose(r.obs[0, :, o], ref, rtol=0, atol=1e-12), (q, o)
