@@ -347,16 +347,132 @@ def bench_grn(args, torch, dev):
     print(json.dumps(out))
 
 
+def bench_infer(args, torch, dev):
+    """Rate inference for A + B <-> C: 250 epochs of one captured optimisation
+    step (forward with the grid observation, loss gradient, backward, RMSprop
+    update) over 100,000 trajectories x 250 steps, from the paper's starting
+    guess; value = fired steps of the replayed epochs / their wall time."""
+    from paper_2602_19775_amd import infer, ssa
+    from paper_2602_19775_amd import workloads as W
+    import oracle
+
+    n_traj = args.n_traj if args.n_traj != 65536 else 100_000
+    n_steps = args.n_steps or 250
+    tr = infer.Trainer(infer.TRUE_RATES, n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
+    tr.capture()
+    res = tr.run()
+    value = res.steps_per_epoch * res.epochs / res.train_s
+
+    # kernel times of one step at the learned rates and the final temperature
+    T_end = float(tr.temp.item()) / tr.r_temp      # the temperature of the last epoch
+    cfg = tr.cfg.replace(temperature=T_end, epoch=res.epochs)
+    bufs = ssa.forward(tr.h, cfg, tr.theta, tr.x0, tie_capacity=1 << 16)
+    G, O, B = tr.n_grid, tr.n_obs, tr.B
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for k in range(args.warmup + args.steps):
+        e = evs[k - args.warmup] if k >= args.warmup else None
+        if e:
+            e[0].record()
+        ssa.forward(tr.h, cfg, tr.theta, tr.x0, buffers=bufs, tie_capacity=1 << 16)
+        if e:
+            e[1].record()
+        o = bufs.obs[: G * O * B].view(G, O, B)
+        d_obs = ((o.mean(dim=2) - tr.target) * (2.0 / (G * O * B))).unsqueeze(2).expand(G, O, B).reshape(-1)
+        d_obs = d_obs.contiguous()
+        ssa.backward(tr.h, cfg, tr.theta, tr.x0, bufs, d_obs, d_params=tr.d_params)
+        if e:
+            e[2].record()
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    fired = int(bufs.steps_done.sum().item())
+    pb = ssa.forward(tr.h, cfg, tr.theta, tr.x0, keep_ckpt=False, tie_capacity=0)
+    torch.cuda.synchronize()
+    f0 = time.perf_counter()
+    for _ in range(args.steps):
+        ssa.forward(tr.h, cfg, tr.theta, tr.x0, buffers=pb, tie_capacity=0)
+    torch.cuda.synchronize()
+    fwd_rate = int(pb.steps_done.sum().item()) * args.steps / (time.perf_counter() - f0)
+
+    # parity sample: per-trajectory gradients at the learned rates against the
+    # oracle, at temperatures across the annealing schedule (the FP32 soft
+    # weights carry a relative error of about 1e-7 / T)
+    n_sample = 32
+    sample = np.arange(0, B, B // n_sample)[:n_sample]
+    th = tr.theta.cpu().numpy()
+    dnp = d_obs.cpu().numpy().reshape(G, O, B).transpose(2, 0, 1)[sample]
+    idx = {int(q): k for k, q in enumerate(sample)}
+    err_by_T = {}
+    counts_exact = True
+    for T in (1.0, 0.1, 0.01, T_end):
+        c2 = cfg.replace(temperature=float(T))
+        b2 = ssa.forward(tr.h, c2, tr.theta, tr.x0, tie_capacity=1 << 16)
+        _, ppt = ssa.backward(tr.h, c2, tr.theta, tr.x0, b2, d_obs, per_traj=True)
+        ov = [(idx[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
+              for t in b2.tie_records() if int(t["traj"]) in idx]
+        r = oracle.run(tr.net, c2, th, tr.net.x0, traj_ids=sample, ties=ov, d_obs=dnp)
+        g_gpu = ppt.cpu().numpy().reshape(2, B).T[sample].astype(np.float64)
+        xf = b2.x_final.cpu().numpy().reshape(3, B).T[sample]
+        counts_exact = counts_exact and bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
+        err_by_T[f"{T:.3g}"] = float(np.linalg.norm(g_gpu.sum(0) - r.grad.sum(0)) / np.linalg.norm(r.grad.sum(0)))
+    grad_rel_err = max(err_by_T.values())
+
+    cost = measure_issue_costs()
+    inv2 = abs(1.0 / T_end - 2.0) < 1e-12
+    ops_f, ops_b = alu_ops_per_step(tr.net, False, inv2), alu_ops_per_step(tr.net, True, inv2)
+    dom, dom_ms, ops = ("backward", bwd_ms, ops_b) if bwd_ms >= fwd_ms else ("forward", fwd_ms, ops_f)
+    achieved = fired * slots(ops, cost) / (dom_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
+                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS,
+                "traffic": profiled_traffic("abc_infer", dom), "kernel_ms": dom_ms,
+                "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        n_cpu = 2048
+        c0 = time.perf_counter()
+        rc = oracle.run(tr.net, cfg, th, tr.net.x0, traj_ids=np.arange(n_cpu),
+                        d_obs=np.zeros((n_cpu, G, O)), n_threads=threads)
+        dt = time.perf_counter() - c0
+        cpu = {"value": float(rc.steps_done.sum()) / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{n_cpu} of the {B} trajectories, {n_steps} steps, forward+adjoint in FP64"}
+    sweep = None
+    if args.sweep:
+        sweep = []
+        for k2 in infer.K2_SWEEP:
+            rr = infer.infer((infer.TRUE_RATES[0], k2), n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
+            sweep.append({"k_true": rr.k_true.tolist(), "k_learned": rr.k_learned.tolist(),
+                          "ape_percent": rr.ape.tolist(), "loss_first": rr.loss_first, "loss_last": rr.loss_last})
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": res.epochs,
+        "warmup": 2, "ms_per_step": res.train_s * 1e3 / res.epochs, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"abc_inference_{B}traj_{n_steps}steps_{tr.n_grid}grid_{res.epochs}epochs",
+                   "n_traj": B, "steps_per_traj": n_steps, "n_grid": tr.n_grid, "t_obs": tr.t_obs,
+                   "epochs": res.epochs, "temperature": [tr.temp0, T_end], "optimizer": "rmsprop"},
+        "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate,
+        "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "grad_rel_err": grad_rel_err, "grad_rel_err_by_T": err_by_T,
+        "counts_bit_exact_sample": counts_exact,
+        "inference": {"k_true": res.k_true.tolist(), "k_start": list(infer.START_RATES),
+                      "k_learned": res.k_learned.tolist(), "ape_percent": res.ape.tolist(),
+                      "loss_first": res.loss_first, "loss_last": res.loss_last, "train_s": res.train_s},
+        "sweep": sweep, "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator", "uneven", "grn"],
+    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator", "uneven", "grn", "abc_infer"],
                     help="dimer: 2A<->A2, 65,536 x 10,000 steps (default); "
                          "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps; "
                          "uneven: 4,096 random networks x 256 trajectories x 5,000 steps; "
-                         "grn: 784->256->10 gene-network classifier, 512 images x 32 trajectories x 2,000 steps")
+                         "grn: 784->256->10 gene-network classifier, 512 images x 32 trajectories x 2,000 steps; "
+                         "abc_infer: rate inference for A+B<->C, 100,000 x 250 steps, 250 captured epochs")
+    ap.add_argument("--sweep", action="store_true", help="abc_infer: also run the k2 sweep (8 targets)")
     ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
     ap.add_argument("--n-traj", type=int, default=65536)
     ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")
@@ -385,6 +501,8 @@ def main():
 
     if args.workload == "grn":
         return bench_grn(args, torch, dev)
+    if args.workload == "abc_infer":
+        return bench_infer(args, torch, dev)
 
     if args.copy_bytes:
         n = args.copy_bytes // 4

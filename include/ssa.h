@@ -65,8 +65,18 @@ typedef enum ssa_status {
     SSA_ENOTSUP = -7       /* valid request this build does not implement */
 } ssa_status;
 
-/* Observation kinds. */
-enum { SSA_OBS_FINAL = 0, SSA_OBS_BINS = 1 };
+/* Observation kinds, per observed species o of a network with B trajectories:
+ *   SSA_OBS_FINAL  obs[o][B]: the final counts.
+ *   SSA_OBS_BINS   obs[b][o][B], b < n_bins: the exact time average of the
+ *                  piecewise-constant path over bin b of n_bins uniform bins
+ *                  of [0, t_obs] (the bin-averaged loss of Sec. 4.4).
+ *   SSA_OBS_GRID   obs[g][o][B], g < n_bins: the path linearly interpolated
+ *                  between its event points (t_k, X_k) at the grid time
+ *                  t_obs g / (n_bins - 1), held at the last state after the
+ *                  last event (the interpolated ensemble trajectories of
+ *                  Sec. 4.1).  Runs in the topology-specialised lane mode
+ *                  only: any other plan returns SSA_ENOTSUP. */
+enum { SSA_OBS_FINAL = 0, SSA_OBS_BINS = 1, SSA_OBS_GRID = 2 };
 
 /* How ssa_backward obtains the fired channel of each step.
  *   SSA_BWD_TAPE:      ssa_forward stores the fired channel index of every
@@ -90,7 +100,7 @@ enum { SSA_BWD_AUTO = 0, SSA_BWD_TAPE = 1, SSA_BWD_RECOMPUTE = 2 };
  *   stoich: dense change vectors, network n contributes M_n*N_n entries in
  *     [channel][species] order; every entry must be in [-8, 7].
  *   obs_species: local species observed, n_obs_n entries per network.
- *   t_obs: window of the bin observation of each network (may be NULL if no
+ *   t_obs: window of the bin or grid observation of each network (may be NULL if no
  *     run uses bins). */
 typedef struct ssa_network_desc {
     int32_t n_networks;
@@ -103,7 +113,7 @@ typedef struct ssa_network_desc {
     const int32_t *rate_index;     /* [sum M_n] */
     const int8_t *stoich;          /* [sum M_n * N_n] */
     const int32_t *obs_species;    /* [sum n_obs_n] */
-    const double *t_obs;           /* [n_networks] bin observations split [0, t_obs[n]] */
+    const double *t_obs;           /* [n_networks] bin or grid observations span [0, t_obs[n]] */
     int32_t exec_mode;             /* SSA_EXEC_*: how trajectories map onto lanes */
     int32_t wave_split;            /* wave mode: -1 library's choice, 0 one persistent launch
                                       for the whole batch, 1 one launch per lane-group width */
@@ -143,12 +153,15 @@ typedef struct ssa_config {
     const uint32_t *traj_ids;      /* optional DEVICE [sum B_n] global trajectory ids; NULL: 0..B-1 */
     int32_t n_steps;               /* fire at most this many channels per trajectory */
     double t_end;                  /* fire only while t + tau <= t_end; +INFINITY: no limit */
-    int32_t obs_kind;              /* SSA_OBS_FINAL or SSA_OBS_BINS */
-    int32_t n_bins;                /* bins per observed species (bins only) */
+    int32_t obs_kind;              /* SSA_OBS_FINAL, SSA_OBS_BINS or SSA_OBS_GRID */
+    int32_t n_bins;                /* bins (>= 1) or grid points (>= 2) per observed species */
     float temperature;             /* Gumbel-Softmax temperature T of Eq. (3), > 0 */
     int32_t ckpt_every;            /* K: steps between state checkpoints (>= 1) */
     int32_t bwd_mode;              /* SSA_BWD_* */
     int32_t tie_capacity;          /* entries the near-tie log can hold */
+    const float *d_temperature;    /* optional DEVICE scalar overriding temperature, read by the
+                                      backward when it runs (annealing T under graph replay);
+                                      it must then hold a finite value > 0.  NULL: temperature */
 } ssa_config;
 
 /* One logged step where the selection (kind 0) or the t_end stop decision

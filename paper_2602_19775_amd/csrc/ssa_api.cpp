@@ -166,13 +166,22 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
     if (!cfg) return fail(SSA_EINVAL, "config is NULL");
     if (cfg->n_steps < 0) return fail(SSA_EINVAL, "n_steps must be >= 0");
     if (!(cfg->t_end > 0.0)) return fail(SSA_EINVAL, "t_end must be > 0 (use INFINITY for no limit)");
-    if (cfg->obs_kind != SSA_OBS_FINAL && cfg->obs_kind != SSA_OBS_BINS)
-        return fail(SSA_EINVAL, "obs_kind must be SSA_OBS_FINAL or SSA_OBS_BINS");
+    if (cfg->obs_kind != SSA_OBS_FINAL && cfg->obs_kind != SSA_OBS_BINS && cfg->obs_kind != SSA_OBS_GRID)
+        return fail(SSA_EINVAL, "obs_kind must be SSA_OBS_FINAL, SSA_OBS_BINS or SSA_OBS_GRID");
     if (cfg->obs_kind == SSA_OBS_BINS) {
         if (cfg->n_bins < 1) return fail(SSA_EINVAL, "bin observation needs n_bins >= 1");
         for (const NetDev &nd : net->nets_h)
             if (nd.n_obs > 0 && !(nd.t_obs > 0.0) )
                 return fail(SSA_EINVAL, "bin observation needs t_obs > 0 for every observed network");
+    }
+    if (cfg->obs_kind == SSA_OBS_GRID) {
+        if (cfg->n_bins < 2) return fail(SSA_EINVAL, "grid observation needs n_bins >= 2 grid points");
+        for (const NetDev &nd : net->nets_h)
+            if (nd.n_obs > 0 && !(nd.t_obs > 0.0) )
+                return fail(SSA_EINVAL, "grid observation needs t_obs > 0 for every observed network");
+        for (const auto &gr : net->groups)
+            if (gr.n_items && !gr.spec)
+                return fail(SSA_ENOTSUP, "grid observation runs in the topology-specialised lane mode only");
     }
     if (!(cfg->temperature > 0.f) || !std::isfinite(cfg->temperature))
         return fail(SSA_EINVAL, "temperature must be finite and > 0");
@@ -204,11 +213,12 @@ RunParams base_params(const ssa_net *net, const ssa_config *cfg)
     p.n_steps = cfg->n_steps;
     p.t_end = cfg->t_end;
     p.obs_kind = cfg->obs_kind;
-    p.n_bins = cfg->obs_kind == SSA_OBS_BINS ? cfg->n_bins : 0;
+    p.n_bins = cfg->obs_kind != SSA_OBS_FINAL ? cfg->n_bins : 0;
     p.K = cfg->ckpt_every;
     p.state_total = net->state_total;
     p.traj_total = net->traj_total;
     p.temperature = cfg->temperature;
+    p.d_temperature = cfg->d_temperature;
     p.recompute = resolve_bwd_mode(cfg) == SSA_BWD_RECOMPUTE ? 1 : 0;
     p.inc_ptr = net->inc_ptr_d;
     p.chan_inc = net->chan_inc_d;
@@ -262,6 +272,7 @@ void ssa_config_default(ssa_config *cfg)
     cfg->obs_kind = SSA_OBS_FINAL;
     cfg->n_bins = 0;
     cfg->temperature = 0.5f;
+    cfg->d_temperature = nullptr;
     cfg->ckpt_every = 256;
     cfg->bwd_mode = SSA_BWD_AUTO;
     cfg->tie_capacity = 0;
@@ -592,7 +603,7 @@ ssa_status ssa_net_layout(const ssa_net *net, int32_t obs_kind, int32_t n_bins, 
     out->traj_offset = nd.traj_off;
     out->state_offset = nd.state_off;
     out->param_offset = nd.param_off;
-    out->obs_offset = nd.obsb_off * (obs_kind == SSA_OBS_BINS ? n_bins : 1);
+    out->obs_offset = nd.obsb_off * (obs_kind != SSA_OBS_FINAL ? n_bins : 1);
     out->ppt_offset = nd.ppt_off;
     return SSA_OK;
 }

@@ -257,6 +257,13 @@ __device__ __forceinline__ void group_race(float &r1, int &j1, float &r2)
     j1 = (int)(uint32_t)k;
 }
 
+// Gumbel-Softmax temperature of a run: the device scalar when one is given.
+template <class P>
+__device__ __forceinline__ float run_temperature(const P &p)
+{
+    return p.d_temperature ? *p.d_temperature : p.temperature;
+}
+
 // The value of the first lane of each group.
 template <int L>
 __device__ __forceinline__ float group_first(float v)

@@ -40,6 +40,7 @@ struct GrnParams {
     const uint32_t *traj_ids;
     int32_t n_steps;
     float temperature;
+    const float *d_temperature;   // when set, the temperature is read here on the device
     const double *d_obs;        // [n_out][B]
     double *part;               // [B][C] compact per-trajectory gradient
     float *e_hist;              // [B][n_steps][n_out] dL/dv_o of every step (backward scratch)

@@ -90,6 +90,7 @@ grn::GrnParams base_params(const ssa_grn *g, const ssa_config *cfg, const float 
     p.traj_ids = cfg->traj_ids;
     p.n_steps = cfg->n_steps;
     p.temperature = cfg->temperature;
+    p.d_temperature = cfg->d_temperature;
     p.C = g->C;
     return p;
 }

@@ -68,10 +68,14 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
     if (n_obs == 0) s << "0";
     for (int o = 0; o < n_obs; ++o) s << (o ? ", " : "") << obs_species[o];
     s << "};\n};\n";
-    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd(ssa::RunParams p)"
-         " { ssa::spec::forward<Net>(p); }\n";
-    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_bwd(ssa::RunParams p)"
-         " { ssa::spec::backward<Net>(p); }\n";
+    // one kernel pair for the final and bin observations, one for the grid
+    for (const char *g : {"false", "true"}) {
+        const std::string sfx = std::string(g) == "true" ? "_grid" : "";
+        s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd" << sfx
+          << "(ssa::RunParams p) { ssa::spec::forward<Net, " << g << ">(p); }\n";
+        s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_bwd" << sfx
+          << "(ssa::RunParams p) { ssa::spec::backward<Net, " << g << ">(p); }\n";
+    }
     return s.str();
 }
 
@@ -119,7 +123,9 @@ bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
     SpecKernels k;
     if (hipModuleLoadData(&k.module, code.data()) != hipSuccess ||
         hipModuleGetFunction(&k.fwd, k.module, "ssa_spec_fwd") != hipSuccess ||
-        hipModuleGetFunction(&k.bwd, k.module, "ssa_spec_bwd") != hipSuccess) {
+        hipModuleGetFunction(&k.bwd, k.module, "ssa_spec_bwd") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_grid, k.module, "ssa_spec_fwd_grid") != hipSuccess ||
+        hipModuleGetFunction(&k.bwd_grid, k.module, "ssa_spec_bwd_grid") != hipSuccess) {
         *log = "loading the compiled module failed";
         return false;
     }
@@ -134,8 +140,9 @@ hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, 
     if (blocks == 0) return hipSuccess;
     RunParams copy = p;
     void *args[] = {&copy};
-    return hipModuleLaunchKernel(backward ? k.bwd : k.fwd, blocks, 1, 1, 64 * spec_waves_per_block, 1, 1, 0,
-                                 stream, args, nullptr);
+    const bool grid = p.obs_kind == 2;
+    hipFunction_t f = backward ? (grid ? k.bwd_grid : k.bwd) : (grid ? k.fwd_grid : k.fwd);
+    return hipModuleLaunchKernel(f, blocks, 1, 1, 64 * spec_waves_per_block, 1, 1, 0, stream, args, nullptr);
 }
 
 }  // namespace ssa

@@ -13,8 +13,10 @@ constexpr int spec_waves_per_block = 4;   // matches spec::kWaves
 
 struct SpecKernels {
     hipModule_t module = nullptr;
-    hipFunction_t fwd = nullptr;
+    hipFunction_t fwd = nullptr;        // final and bin observations
     hipFunction_t bwd = nullptr;
+    hipFunction_t fwd_grid = nullptr;   // grid observation
+    hipFunction_t bwd_grid = nullptr;
 };
 
 // Source of the specialised kernel pair for one network (host tables).

@@ -430,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void bwd_lane_kernel(RunParams p)
     const uint32_t tid = p.traj_ids ? p.traj_ids[g] : (uint32_t)g;
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
-    const float invT = 1.0f / p.temperature;
+    const float invT = 1.0f / run_temperature(p);
     const bool invT_is_2 = invT == 2.0f, invT_is_1 = invT == 1.0f;
 
     const int n = valid ? p.steps_done[g] : 0;

@@ -126,6 +126,7 @@ struct RunParams {
     int64_t state_total;
     int64_t traj_total;
     float temperature;
+    const float *d_temperature;   // when set, the temperature is read here on the device
     int32_t recompute;      // backward: recover choices by re-running segments
 
     // wave mode: species -> range of incidence slots, and per channel the

@@ -13,8 +13,9 @@
 //
 // Forward (Sec. 2, Sec. 3.2): a_j, a0, tau = E_0/a0, j* = argmin_j E_j/a_j
 // (= argmax_j ln a_j + G_j with G_j = -ln E_j), X += v_j*, t += tau (FP64),
-// exact bin integrals of the observed species (Sec. 4.4), checkpoints every
-// K steps and the compact choice tape.
+// exact bin integrals of the observed species (Sec. 4.4) or the path linearly
+// interpolated between its event points on a uniform time grid (Sec. 4.1),
+// checkpoints every K steps and the compact choice tape.
 // Backward (Sec. 3.1, Eqs. 3-7, Fig. 1): reverse sweep with the noise,
 // propensities and waiting times regenerated from the Philox counters.
 #pragma once
@@ -32,6 +33,23 @@ constexpr int kFold = 32;   // FP32 adjoint increments are folded into FP64 this
 __device__ __forceinline__ double bin_edge(double t_obs, int b, int n_bins)
 {
     return t_obs * (double)b / (double)n_bins;
+}
+
+// Grid time g of an n-point grid spanning [0, t_obs].
+__device__ __forceinline__ double grid_time(double t_obs, int g, int n)
+{
+    return t_obs * (double)g / (double)(n - 1);
+}
+
+// v_j[s] for a runtime channel j.
+template <class NET>
+__device__ __forceinline__ int delta_of(int j, int s)
+{
+    int d = 0;
+#pragma unroll
+    for (int q = 0; q < NET::M; ++q)
+        if (NET::V[q][s] != 0) d = (j == q) ? NET::V[q][s] : d;
+    return d;
 }
 
 __device__ __forceinline__ void log_tie(const RunParams &p, uint32_t g, int k, int chosen, int second,
@@ -115,7 +133,8 @@ __device__ __forceinline__ void rates(const RunParams &p, const NetDev &nd, floa
 constexpr int obs_cap(int n) { return n > 0 ? n : 1; }
 
 // --------------------------------------------------------------------------
-template <class NET, bool HAS_T_END>
+// GRID: the grid observation (the other kinds are runtime cases of GRID = false)
+template <class NET, bool HAS_T_END, bool GRID>
 __device__ void forward_run(const RunParams &p)
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
@@ -142,7 +161,8 @@ __device__ void forward_run(const RunParams &p)
     for (int s = 0; s < N; ++s) X[s] = p.x0[nd.state_off + s * B + i];
     X[N] = 1;
 
-    const bool bins = p.obs_kind == 1 && NOBS > 0;
+    const bool bins = !GRID && p.obs_kind == 1 && NOBS > 0;
+    constexpr bool grid = GRID && NOBS > 0;
     const int n_bins = p.n_bins;
     const double t_obs = nd.t_obs;
     int bin = bins ? 0 : n_bins;
@@ -150,7 +170,10 @@ __device__ void forward_run(const RunParams &p)
     double acc[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) acc[o] = 0.0;
-    double *obs_lane = p.obs + nd.obsb_off * (p.obs_kind == 1 ? n_bins : 1) + i;
+    double *obs_lane = p.obs + nd.obsb_off * (p.obs_kind != 0 ? n_bins : 1) + i;
+    // grid observation: next grid point gi, at time grid_t >= t
+    int gi = 0;
+    double grid_t = grid ? 0.0 : INFINITY;
     const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
 
     const int bits = p.tape_bits;
@@ -217,9 +240,10 @@ __device__ void forward_run(const RunParams &p)
         const bool clock_tie = HAS_T_END && live && fabs(tn - p.t_end) <= kClockTieLog * p.t_end;
         const bool near_tie = fire && r2 <= r1 * (1.f + kTieLog);
         const bool crossing = fire && !in_bin && bin < n_bins;
+        const bool gcross = grid && fire && grid_t < tn;    // grid points in [t, t + tau)
         const bool odd = active && !(a0 >= 0.f);
         const bool stop = active && !fire;
-        if (ballot(clock_tie || near_tie || crossing || odd || stop) != 0ull) {
+        if (ballot(clock_tie || near_tie || crossing || gcross || odd || stop) != 0ull) {
             if (ballot(stop) != 0ull) any = ballot(fire) != 0ull;
             if (odd) flags |= kFlagNonFinite;
             if (clock_tie)
@@ -250,6 +274,18 @@ __device__ void forward_run(const RunParams &p)
                     t0 = fmax(t0, hi);
                     bin += 1;
                     bin_hi = bin < n_bins ? bin_edge(t_obs, bin + 1, n_bins) : INFINITY;
+                }
+            }
+            if (gcross) {
+                // interpolate between (t, X) and (t + tau, X + v_j)
+                while (grid_t < tn) {
+                    const double f = (grid_t - t) / (double)tau;
+#pragma unroll
+                    for (int o = 0; o < NOBS; ++o)
+                        obs_lane[((int64_t)gi * NOBS + o) * B] =
+                            (double)X[NET::OBS[o]] + f * (double)delta_of<NET>(j1, NET::OBS[o]);
+                    gi += 1;
+                    grid_t = gi < n_bins ? grid_time(t_obs, gi, n_bins) : INFINITY;
                 }
             }
         }
@@ -295,6 +331,11 @@ __device__ void forward_run(const RunParams &p)
 #pragma unroll
         for (int o = 0; o < NOBS; ++o) obs_lane[(int64_t)o * B] = (double)X[NET::OBS[o]];
     }
+    // grid points after the last event hold the last state
+    if (grid)
+        for (; gi < n_bins; ++gi)
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)gi * NOBS + o) * B] = (double)X[NET::OBS[o]];
 #pragma unroll
     for (int s = 0; s < N; ++s) {
         p.x_final[nd.state_off + s * B + i] = X[s];
@@ -305,11 +346,11 @@ __device__ void forward_run(const RunParams &p)
     if (flags) atomicOr(p.flags, flags);
 }
 
-template <class NET>
+template <class NET, bool GRID>
 __device__ void forward(const RunParams &p)
 {
-    if (p.t_end < INFINITY) forward_run<NET, true>(p);
-    else forward_run<NET, false>(p);
+    if (p.t_end < INFINITY) forward_run<NET, true, GRID>(p);
+    else forward_run<NET, false, GRID>(p);
 }
 
 // --------------------------------------------------------------------------
@@ -318,7 +359,7 @@ __device__ void forward(const RunParams &p)
 // instead of the tape.
 constexpr int kRecSteps = 64;   // recompute mode: steps of a segment kept in LDS
 
-template <class NET, int TMODE, bool RECOMPUTE>
+template <class NET, int TMODE, bool RECOMPUTE, bool GRID>
 __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64])
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
@@ -340,7 +381,7 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     const uint32_t tid = p.traj_ids ? p.traj_ids[g] : (uint32_t)g;
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
-    const float invT = 1.0f / p.temperature;
+    const float invT = 1.0f / run_temperature(p);
 
     const int n = valid ? p.steps_done[g] : 0;
     int kmax = n;
@@ -359,11 +400,12 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     X[N] = 1;
     double t = valid ? p.t_final[g] : 0.0;
 
-    const bool bins = p.obs_kind == 1 && NOBS > 0;
+    const bool bins = !GRID && p.obs_kind == 1 && NOBS > 0;
+    constexpr bool grid = GRID && NOBS > 0;
     const int n_bins = p.n_bins;
     const double t_obs = nd.t_obs;
     const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
-    const double *dobs_lane = p.d_obs + nd.obsb_off * (p.obs_kind == 1 ? n_bins : 1) + i;
+    const double *dobs_lane = p.d_obs + nd.obsb_off * (p.obs_kind != 0 ? n_bins : 1) + i;
 
     // adjoint of the state: FP64 accumulator, FP32 increments folded every kFold steps
     double lam[N];
@@ -403,6 +445,26 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
 #pragma unroll
             for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[(int64_t)o * B];
         }
+    }
+    // grid observation: the points at or after the last event see the final
+    // state; gh counts the points below the current clock, glo is the time of
+    // the highest of them (the next one the reverse sweep meets)
+    int gh = 0;
+    double glo = -INFINITY;
+    double gd[NO];                     // dL/dobs of grid point gh - 1, loaded ahead
+#pragma unroll
+    for (int o = 0; o < NO; ++o) gd[o] = 0.0;
+    if (grid) {
+        if (valid) {
+            while (gh < n_bins && grid_time(t_obs, gh, n_bins) < t) ++gh;
+            for (int g = gh; g < n_bins; ++g)
+#pragma unroll
+                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[((int64_t)g * NOBS + o) * B];
+        }
+        glo = gh > 0 ? grid_time(t_obs, gh - 1, n_bins) : -INFINITY;
+        if (gh > 0)
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) gd[o] = dobs_lane[((int64_t)(gh - 1) * NOBS + o) * B];
     }
 #pragma unroll
     for (int s = 0; s < N; ++s) lam32[s] = (float)lam[s];
@@ -473,6 +535,33 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     #pragma unroll
                     for (int o = 0; o < NOBS; ++o)
                         lam_t += doi[o] * (double)(X[NET::OBS[o]] - Xn[o]);
+                }
+                // grid points in [t_k, t_{k+1}) see X_k + f (X_{k+1} - X_k),
+                // f = (t_g - t_k) / tau: their X_{k+1} and t_{k+1} parts join
+                // the adjoints this step reads, the X_k and t_k parts are
+                // added after it
+                float gx[NO];
+    #pragma unroll
+                for (int o = 0; o < NO; ++o) gx[o] = 0.f;
+                double glt = 0.0;
+                if (grid && ballot(gh > 0 && glo >= t_k) != 0ull) {
+                    while (gh > 0 && glo >= t_k) {
+                        const double f = (glo - t_k) / (double)tau;
+    #pragma unroll
+                        for (int o = 0; o < NOBS; ++o) {
+                            const double d = gd[o];
+                            const double dv = (double)(Xn[o] - X[NET::OBS[o]]);
+                            dlam[NET::OBS[o]] += (float)(d * f);
+                            lam_t -= d * dv * f / (double)tau;
+                            gx[o] += (float)(d * (1.0 - f));
+                            glt += d * dv * (f - 1.0) / (double)tau;
+                        }
+                        gh -= 1;
+                        glo = gh > 0 ? grid_time(t_obs, gh - 1, n_bins) : -INFINITY;
+                        if (gh > 0)
+    #pragma unroll
+                            for (int o = 0; o < NOBS; ++o) gd[o] = dobs_lane[((int64_t)(gh - 1) * NOBS + o) * B];
+                    }
                 }
                 // soft sample y~ in ratio form: y~_q ~ (r_j / r_q)^(1/T) with j
                 // the fired channel; a_q = 0 gives r_q = +inf and y~_q = 0
@@ -552,6 +641,11 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                     const float seg = fmaxf((float)(hi - t_k), 0.f);
     #pragma unroll
                     for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += seg * doi32[o];
+                }
+                if (grid) {
+    #pragma unroll
+                    for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += gx[o];
+                    lam_t += glt;
                 }
             t = t_k;
         };
@@ -639,19 +733,19 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     for (int q = 0; q < M; ++q) p.partials[nd.part_off + q * B + i] = dth[q];
 }
 
-template <class NET>
+template <class NET, bool GRID>
 __device__ void backward(const RunParams &p)
 {
     __shared__ uint8_t s_tape[kWaves][kRecSteps][64];
-    const float invT = 1.0f / p.temperature;
+    const float invT = 1.0f / run_temperature(p);
     if (p.recompute) {
-        if (invT == 2.0f) backward_run<NET, 2, true>(p, s_tape);
-        else if (invT == 1.0f) backward_run<NET, 1, true>(p, s_tape);
-        else backward_run<NET, 0, true>(p, s_tape);
+        if (invT == 2.0f) backward_run<NET, 2, true, GRID>(p, s_tape);
+        else if (invT == 1.0f) backward_run<NET, 1, true, GRID>(p, s_tape);
+        else backward_run<NET, 0, true, GRID>(p, s_tape);
     } else {
-        if (invT == 2.0f) backward_run<NET, 2, false>(p, s_tape);
-        else if (invT == 1.0f) backward_run<NET, 1, false>(p, s_tape);
-        else backward_run<NET, 0, false>(p, s_tape);
+        if (invT == 2.0f) backward_run<NET, 2, false, GRID>(p, s_tape);
+        else if (invT == 1.0f) backward_run<NET, 1, false, GRID>(p, s_tape);
+        else backward_run<NET, 0, false, GRID>(p, s_tape);
     }
 }
 

@@ -462,7 +462,7 @@ void bwd_kernel(RunParams p)
     GroupTab tab(s_dyn + (wid * G + grp) * p.tab_words, p);
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
-    const float invT = 1.0f / p.temperature;
+    const float invT = 1.0f / run_temperature(p);
 
     LaneChannels<L, BPL> ch;
     int cached_net = -1;
@@ -846,7 +846,8 @@ static hipError_t launch_wave(const RunParams &p, bool backward, int n_blocks, h
 {
     const size_t dyn = sizeof(int32_t) * (size_t)p.tab_words * wave::kWaves * (64 / L);
     if (backward) {
-        const float invT = 1.0f / p.temperature;
+        // a temperature read on the device takes the general form
+        const float invT = p.d_temperature ? 0.f : 1.0f / p.temperature;
         if (invT == 2.0f)
             hipLaunchKernelGGL((wave::bwd_kernel<L, BPL, 0>), dim3(n_blocks), dim3(wave::kBlock), dyn, stream, p);
         else if (invT == 1.0f)

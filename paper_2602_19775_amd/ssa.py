@@ -49,7 +49,7 @@ class _Cfg(C.Structure):
                 ("d_epoch", C.c_void_p), ("traj_ids", C.c_void_p), ("n_steps", C.c_int32),
                 ("t_end", C.c_double), ("obs_kind", C.c_int32), ("n_bins", C.c_int32),
                 ("temperature", C.c_float), ("ckpt_every", C.c_int32), ("bwd_mode", C.c_int32),
-                ("tie_capacity", C.c_int32)]
+                ("tie_capacity", C.c_int32), ("d_temperature", C.c_void_p)]
 
 
 TIE_DTYPE = np.dtype([("traj", np.uint32), ("step", np.uint32), ("chosen", np.int32),
@@ -167,7 +167,7 @@ class Net:
 
     def obs_total(self, obs_kind: int, n_bins: int) -> int:
         per = sum(len(o) * b for o, b in zip(self.obs_species, self.n_traj))
-        return per * (n_bins if obs_kind == W.OBS_BINS else 1)
+        return per * (n_bins if obs_kind in (W.OBS_BINS, W.OBS_GRID) else 1)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -177,12 +177,13 @@ class Net:
 
 
 def make_cfg(cfg: W.RunConfig, tie_capacity: int = 0, bwd_mode: str = "auto",
-             traj_ids: Optional[torch.Tensor] = None, d_epoch: Optional[torch.Tensor] = None) -> _Cfg:
+             traj_ids: Optional[torch.Tensor] = None, d_epoch: Optional[torch.Tensor] = None,
+             d_temperature: Optional[torch.Tensor] = None) -> _Cfg:
     n_steps = int(min(cfg.n_steps, 2 ** 31 - 1))
     return _Cfg(int(cfg.seed) & (2 ** 64 - 1), int(cfg.purpose), int(cfg.epoch), _ptr(d_epoch),
                 _ptr(traj_ids), n_steps, float(cfg.t_end), int(cfg.obs_kind),
-                int(cfg.n_bins if cfg.obs_kind == W.OBS_BINS else 0), float(cfg.temperature),
-                int(cfg.ckpt_every), _BWD[bwd_mode], int(tie_capacity))
+                int(cfg.n_bins if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID) else 0), float(cfg.temperature),
+                int(cfg.ckpt_every), _BWD[bwd_mode], int(tie_capacity), _ptr(d_temperature))
 
 
 @dataclass
@@ -217,12 +218,17 @@ def buffer_sizes(net: Net, ccfg: _Cfg):
 def forward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, *,
             keep_ckpt: bool = True, tie_capacity: int = 4096, bwd_mode: str = "auto",
             traj_ids: Optional[torch.Tensor] = None, d_epoch: Optional[torch.Tensor] = None,
+            d_temperature: Optional[torch.Tensor] = None,
             buffers: Optional[Forward] = None, stream=None) -> Forward:
-    """Runs ssa_forward.  theta: float32 [param_total], x0: int32 [state_total] (CUDA)."""
+    """Runs ssa_forward.  theta: float32 [param_total], x0: int32 [state_total] (CUDA).
+    d_epoch (int32 [1]) and d_temperature (float32 [1]), if given, are read on the
+    device by this forward and by the backward that uses its buffers."""
+    if d_temperature is not None:
+        assert d_temperature.dtype == torch.float32 and d_temperature.is_cuda
     dev = theta.device
     assert theta.dtype == torch.float32 and theta.is_cuda and theta.numel() == net.param_total
     assert x0.dtype == torch.int32 and x0.is_cuda and x0.numel() == net.state_total
-    ccfg = make_cfg(cfg, tie_capacity, bwd_mode, traj_ids, d_epoch)
+    ccfg = make_cfg(cfg, tie_capacity, bwd_mode, traj_ids, d_epoch, d_temperature)
     ck_bytes, wk_bytes = buffer_sizes(net, ccfg)
     if buffers is None:
         obs_n = max(net.obs_total(cfg.obs_kind, cfg.n_bins), 1)
@@ -377,8 +383,10 @@ def grn_buffer_sizes(g: Grn, ccfg: _Cfg):
 def grn_forward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tensor,
                 x0: Optional[torch.Tensor] = None, *, keep_tape: bool = True, tie_capacity: int = 4096,
                 traj_ids: Optional[torch.Tensor] = None, d_epoch: Optional[torch.Tensor] = None,
+                d_temperature: Optional[torch.Tensor] = None,
                 buffers: Optional[GrnForward] = None, stream=None) -> GrnForward:
-    """Runs ssa_grn_forward.  theta float32 [P], x_img float32 [n_images, n_in] (CUDA)."""
+    """Runs ssa_grn_forward.  theta float32 [P], x_img float32 [n_images, n_in] (CUDA).
+    d_epoch / d_temperature: optional device scalars read by this forward and its backward."""
     dev = theta.device
     n = g.net
     assert theta.dtype == torch.float32 and theta.is_cuda and theta.numel() == n.n_params
@@ -386,7 +394,7 @@ def grn_forward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tens
     if x0 is None:
         x0 = torch.zeros((n.n_species, g.B), dtype=torch.int32, device=dev)
     assert x0.dtype == torch.int32 and x0.is_cuda and x0.numel() == n.n_species * g.B
-    ccfg = make_cfg(cfg, tie_capacity, "auto", traj_ids, d_epoch)
+    ccfg = make_cfg(cfg, tie_capacity, "auto", traj_ids, d_epoch, d_temperature)
     tb, _ = grn_buffer_sizes(g, ccfg)
     if buffers is None:
         buffers = GrnForward(

@@ -46,6 +46,7 @@ def test_status_strings_and_defaults(L):
     L.ssa_config_default(C.byref(cfg))
     assert cfg.n_steps == 2 ** 31 - 1 and math.isinf(cfg.t_end) and cfg.ckpt_every == 256
     assert abs(cfg.temperature - 0.5) < 1e-7
+    assert cfg.d_temperature is None and cfg.d_epoch is None
 
 
 def test_host_side_argument_errors(L):
@@ -64,12 +65,41 @@ def test_host_side_argument_errors(L):
     assert L.ssa_selftest_neglog(0, 1 << 24, None, None) == -1
 
 
-def test_struct_sizes_match_header(L):
-    """ctypes mirrors of the public structs have the C layout."""
+def test_struct_sizes_match_header(L, tmp_path):
+    """ctypes mirrors of the public structs have the C layout: a C program
+    built against include/ssa.h prints every size and field offset."""
+    import shutil
+    import subprocess
     from paper_2602_19775_amd import ssa
-    assert C.sizeof(ssa._Cfg) == 72
-    assert ssa.TIE_DTYPE.itemsize == 24
-    assert C.sizeof(ssa._Layout) == 40
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"ssa_network_desc": ssa._Desc, "ssa_net_layout_t": ssa._Layout, "ssa_config": ssa._Cfg,
+               "ssa_grn_desc": ssa._GrnDesc}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", "#define __HIP_PLATFORM_AMD__ 1", '#include "ssa.h"',
+             "int main(void) {"]
+    for name, st in mirrors.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    for f in ssa.TIE_DTYPE.names:
+        lines.append(f'printf("ssa_tie.{f} %zu\\n", offsetof(ssa_tie, {f}));')
+    lines.append('printf("ssa_tie %zu\\n", sizeof(ssa_tie));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for name, st in mirrors.items():
+        assert int(got[name]) == C.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, (name, f)
+    assert int(got["ssa_tie"]) == ssa.TIE_DTYPE.itemsize
+    for f in ssa.TIE_DTYPE.names:
+        assert int(got[f"ssa_tie.{f}"]) == ssa.TIE_DTYPE.fields[f][1], f
 
 
 def test_grn_host_side_checks(L):

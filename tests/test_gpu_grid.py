@@ -1,0 +1,80 @@
+"""Parity of the grid observation (the path linearly interpolated between its
+event points on a uniform time grid, Sec. 4.1) with the FP64 oracle, through
+the C ABI.  Same bars as the other parity tests; interpolated values are held
+to 1e-5 relative to the counts' scale, and per-trajectory gradients are
+compared where every event time stays clear of every grid time (there the
+interval a grid time falls in, and so the branch of its derivative, is the same
+for an FP32 and an FP64 clock)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_19775_amd import workloads as W
+
+from test_gpu_parity import assert_forward_parity, assert_grad_parity, edge_safe, run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_19775_amd import ssa as m
+    m.lib()
+    return m
+
+
+def _check(ssa, net, cfg, B, n_sample, bwd_mode="tape", seed=0):
+    g = np.random.default_rng(seed)
+    nob = len(net.obs_species)
+    d_obs = g.normal(size=(cfg.n_bins, nob, B))
+    sample = np.unique(np.concatenate([[0, B - 1], g.choice(B, n_sample, replace=False)]))
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode=bwd_mode, sample=sample)
+    assert_forward_parity(gpu, r, ids, cfg)
+    keep = edge_safe(gpu, r, ids)
+    assert keep.mean() > 0.5
+    for k in np.flatnonzero(keep):
+        assert_grad_parity(gpu["ppt"][ids[k]], r.grad[k])
+    assert_grad_parity(gpu["ppt"][ids][keep].sum(0), r.grad[keep].sum(0))
+    # the reduction is the FP64 sum of the per-trajectory gradients
+    tot = gpu["ppt"].astype(np.float64).sum(0)
+    mag = np.abs(gpu["ppt"].astype(np.float64)).sum(0)
+    assert np.all(np.abs(gpu["d_params"] - tot) <= 1e-5 * np.abs(tot) + 1e-6 * mag)
+    return gpu, r
+
+
+@pytest.mark.parametrize("bwd_mode", ["tape", "recompute"])
+def test_grid_parity_abc(ssa, bwd_mode):
+    net = W.dimerization_abc()
+    cfg = W.RunConfig(seed=9, n_steps=250, obs_kind=W.OBS_GRID, n_bins=32, t_obs=4.5, temperature=0.5,
+                      ckpt_every=64)
+    _check(ssa, net, cfg, 4096, 40, bwd_mode)
+
+
+def test_grid_parity_cold_start_rates(ssa):
+    # the inference's starting rates: the grid ends long before the paths do
+    net = W.dimerization_abc(0.125, 0.025)
+    cfg = W.RunConfig(seed=3, n_steps=250, obs_kind=W.OBS_GRID, n_bins=24, t_obs=4.5, temperature=0.05,
+                      ckpt_every=256)
+    _check(ssa, net, cfg, 2048, 30)
+
+
+def test_grid_parity_absorbing(ssa):
+    # paths that stop in the absorbing state hold it over the rest of the grid
+    net = W.ion_channel_coi(n_channels=5)
+    cfg = W.RunConfig(seed=4, n_steps=40, obs_kind=W.OBS_GRID, n_bins=20, t_obs=8.0, temperature=0.3,
+                      ckpt_every=16)
+    gpu, r = _check(ssa, net, cfg, 1024, 30)
+    assert (r.steps_done < cfg.n_steps).any()
+
+
+@pytest.mark.parametrize("mode", ["lane", "wave"])
+def test_grid_needs_the_specialised_mode(ssa, mode):
+    net = W.dimerization_abc()
+    cfg = W.RunConfig(seed=1, n_steps=10, obs_kind=W.OBS_GRID, n_bins=8, t_obs=1.0)
+    h = ssa.Net([net], [64], t_obs=[cfg.t_obs], exec_mode=mode)
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = torch.tensor(np.repeat(net.x0[:, None], 64, axis=1).reshape(-1), dtype=torch.int32, device="cuda")
+    with pytest.raises(ssa.SSAError, match="grid observation"):
+        ssa.forward(h, cfg, th, x0)

@@ -60,7 +60,7 @@ def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=N
     x0 = _x0([net], [B])
     fwd = ssa.forward(h, cfg, th, x0, keep_ckpt=d_obs is not None, tie_capacity=1 << 16,
                       bwd_mode=bwd_mode)
-    bins = cfg.obs_kind == W.OBS_BINS
+    bins = cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID)     # [n_bins][n_obs][B] layouts
     nob = len(net.obs_species)
     gpu = {}
     if d_obs is not None:
@@ -115,6 +115,10 @@ def assert_forward_parity(gpu, r, ids, cfg=None):
     if cfg is not None and cfg.obs_kind == W.OBS_BINS:
         jump = max(1.0, float(np.abs(r.x_final).max()))
         atol = 4.0 * jump * max(clock_drift(gpu, r, ids), 1e-15) * cfg.n_bins / cfg.t_obs + 1e-12
+    if cfg is not None and cfg.obs_kind == W.OBS_GRID:
+        # an interpolated value moves by (count jump) * (clock shift) / (waiting
+        # time) when the event times shift: relative to the counts' scale
+        atol = 1e-5 * float(np.abs(r.obs).max()) + 1e-12
     err = np.abs(o - r.obs)
     bad = err > 1e-5 * np.abs(r.obs) + atol
     assert not bad.any(), (int(bad.sum()), float(err.max()), atol, np.argwhere(bad)[:3])
