@@ -72,7 +72,7 @@ class Trainer:
 
     def __init__(self, k_true: Sequence[float], *, n_traj: int = 100_000, n_target: int = 100_000,
                  n_steps: int = 250, n_grid: int = 64, epochs: int = 250, t0: float = 1.0,
-                 t1: float = 1e-3, lr0: float = 0.1, lr1: float = 1e-4, rho: float = 0.9,
+                 t1: float = 1e-3, lr0: float = 0.15, lr1: float = 1e-4, rho: float = 0.9,
                  eps: float = 1e-7, seed: int = 0, k_start: Sequence[float] = START_RATES,
                  ckpt_every: int = 64):
         dev = torch.device("cuda")

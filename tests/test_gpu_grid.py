@@ -25,6 +25,13 @@ def ssa():
     return m
 
 
+def grad_rtol(T):
+    """Gradient bar at temperature T: the soft weights are rho^(1/T), so the
+    FP32 error of a ratio rho (two -ln u within 3e-7 each, two reciprocals:
+    at most about 8e-7) becomes 8e-7 / T in ln y~; 1e-5 holds for T >= 0.08."""
+    return max(1e-5, 8e-7 / T)
+
+
 def _check(ssa, net, cfg, B, n_sample, bwd_mode="tape", seed=0):
     g = np.random.default_rng(seed)
     nob = len(net.obs_species)
@@ -34,9 +41,10 @@ def _check(ssa, net, cfg, B, n_sample, bwd_mode="tape", seed=0):
     assert_forward_parity(gpu, r, ids, cfg)
     keep = edge_safe(gpu, r, ids)
     assert keep.mean() > 0.5
+    rtol = grad_rtol(cfg.temperature)
     for k in np.flatnonzero(keep):
-        assert_grad_parity(gpu["ppt"][ids[k]], r.grad[k])
-    assert_grad_parity(gpu["ppt"][ids][keep].sum(0), r.grad[keep].sum(0))
+        assert_grad_parity(gpu["ppt"][ids[k]], r.grad[k], rtol=rtol)
+    assert_grad_parity(gpu["ppt"][ids][keep].sum(0), r.grad[keep].sum(0), rtol=rtol)
     # the reduction is the FP64 sum of the per-trajectory gradients
     tot = gpu["ppt"].astype(np.float64).sum(0)
     mag = np.abs(gpu["ppt"].astype(np.float64)).sum(0)
@@ -78,3 +86,18 @@ def test_grid_needs_the_specialised_mode(ssa, mode):
     x0 = torch.tensor(np.repeat(net.x0[:, None], 64, axis=1).reshape(-1), dtype=torch.int32, device="cuda")
     with pytest.raises(ssa.SSAError, match="grid observation"):
         ssa.forward(h, cfg, th, x0)
+
+
+def test_grid_fullsize_inference_batch(ssa):
+    """The inference's model batch as the benchmark runs it (100,000 x 250
+    steps, 64 grid points on the target's span, the starting rates), at the
+    start and near the end of the temperature schedule; a sample of
+    trajectories against the oracle."""
+    from paper_2602_19775_amd import infer
+    true_net = W.dimerization_abc(*infer.TRUE_RATES)
+    t_obs = infer.grid_end(true_net, 100_000, 250, 0)
+    net = W.dimerization_abc(*infer.START_RATES)
+    for T in (1.0, 0.1, 0.01):
+        cfg = W.RunConfig(seed=0, epoch=7, n_steps=250, obs_kind=W.OBS_GRID, n_bins=64, t_obs=t_obs,
+                          temperature=T, ckpt_every=64)
+        _check(ssa, net, cfg, 100_000, 62, seed=int(1 / T))
