@@ -278,8 +278,9 @@ __device__ void forward_run(const RunParams &p)
             }
             if (gcross) {
                 // interpolate between (t, X) and (t + tau, X + v_j)
+                const double inv_tau = 1.0 / (double)tau;
                 while (grid_t < tn) {
-                    const double f = (grid_t - t) / (double)tau;
+                    const double f = (grid_t - t) * inv_tau;
 #pragma unroll
                     for (int o = 0; o < NOBS; ++o)
                         obs_lane[((int64_t)gi * NOBS + o) * B] =
@@ -456,6 +457,11 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     for (int o = 0; o < NO; ++o) gd[o] = 0.0;
     if (grid) {
         if (valid) {
+            // first grid index whose time is >= t: an estimate, then exact
+            // comparisons with the grid times themselves
+            const double est = ceil(t * (double)(n_bins - 1) / t_obs);
+            gh = est < 0.0 ? 0 : est > (double)n_bins ? n_bins : (int)est;
+            while (gh > 0 && grid_time(t_obs, gh - 1, n_bins) >= t) --gh;
             while (gh < n_bins && grid_time(t_obs, gh, n_bins) < t) ++gh;
             for (int g = gh; g < n_bins; ++g)
 #pragma unroll
@@ -545,16 +551,17 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                 for (int o = 0; o < NO; ++o) gx[o] = 0.f;
                 double glt = 0.0;
                 if (grid && ballot(gh > 0 && glo >= t_k) != 0ull) {
+                    const double inv_tau = 1.0 / (double)tau;
                     while (gh > 0 && glo >= t_k) {
-                        const double f = (glo - t_k) / (double)tau;
+                        const double f = (glo - t_k) * inv_tau;
     #pragma unroll
                         for (int o = 0; o < NOBS; ++o) {
                             const double d = gd[o];
-                            const double dv = (double)(Xn[o] - X[NET::OBS[o]]);
+                            const double ddv = d * (double)(Xn[o] - X[NET::OBS[o]]) * inv_tau;
                             dlam[NET::OBS[o]] += (float)(d * f);
-                            lam_t -= d * dv * f / (double)tau;
+                            lam_t -= ddv * f;
                             gx[o] += (float)(d * (1.0 - f));
-                            glt += d * dv * (f - 1.0) / (double)tau;
+                            glt += ddv * (f - 1.0);
                         }
                         gh -= 1;
                         glo = gh > 0 ? grid_time(t_obs, gh - 1, n_bins) : -INFINITY;
