@@ -460,7 +460,7 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
             // first grid index whose time is >= t: an estimate, then exact
             // comparisons with the grid times themselves
             const double est = ceil(t * (double)(n_bins - 1) / t_obs);
-            gh = est < 0.0 ? 0 : est > (double)n_bins ? n_bins : (int)est;
+            gh = !(est > 0.0) ? 0 : est > (double)n_bins ? n_bins : (int)est;
             while (gh > 0 && grid_time(t_obs, gh - 1, n_bins) >= t) --gh;
             while (gh < n_bins && grid_time(t_obs, gh, n_bins) < t) ++gh;
             for (int g = gh; g < n_bins; ++g)
