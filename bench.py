@@ -356,9 +356,17 @@ def bench_infer(args, torch, dev):
     from paper_2602_19775_amd import workloads as W
     import oracle
 
-    n_traj = args.n_traj if args.n_traj != 65536 else 100_000
-    n_steps = args.n_steps or 250
-    tr = infer.Trainer(infer.TRUE_RATES, n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
+    coi = args.workload == "coi_infer"
+    if coi:
+        n_traj = args.n_traj if args.n_traj != 65536 else 262_144
+        n_steps = args.n_steps or 20
+        tr = infer.ion_channel(n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
+        k_start = infer.COI_START
+    else:
+        n_traj = args.n_traj if args.n_traj != 65536 else 100_000
+        n_steps = args.n_steps or 250
+        tr = infer.dimerization(infer.TRUE_RATES, n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
+        k_start = infer.START_RATES
     tr.capture()
     res = tr.run()
     value = res.steps_per_epoch * res.epochs / res.train_s
@@ -367,7 +375,8 @@ def bench_infer(args, torch, dev):
     T_end = float(tr.temp.item()) / tr.r_temp      # the temperature of the last epoch
     cfg = tr.cfg.replace(temperature=T_end, epoch=res.epochs)
     bufs = ssa.forward(tr.h, cfg, tr.theta, tr.x0, tie_capacity=1 << 16)
-    G, O, B = tr.n_grid, tr.n_obs, tr.B
+    G, O, B = tr.n_pts, tr.n_obs, tr.B
+    NS, NP = tr.net.n_species, tr.net.n_params
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     for k in range(args.warmup + args.steps):
         e = evs[k - args.warmup] if k >= args.warmup else None
@@ -404,15 +413,15 @@ def bench_infer(args, torch, dev):
     idx = {int(q): k for k, q in enumerate(sample)}
     err_by_T = {}
     counts_exact = True
-    for T in (1.0, 0.1, 0.01, T_end):
+    for T in sorted({1.0, 0.1, 0.01, round(tr.temp0, 9), round(T_end, 9)}, reverse=True):
         c2 = cfg.replace(temperature=float(T))
         b2 = ssa.forward(tr.h, c2, tr.theta, tr.x0, tie_capacity=1 << 16)
         _, ppt = ssa.backward(tr.h, c2, tr.theta, tr.x0, b2, d_obs, per_traj=True)
         ov = [(idx[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
               for t in b2.tie_records() if int(t["traj"]) in idx]
         r = oracle.run(tr.net, c2, th, tr.net.x0, traj_ids=sample, ties=ov, d_obs=dnp)
-        g_gpu = ppt.cpu().numpy().reshape(2, B).T[sample].astype(np.float64)
-        xf = b2.x_final.cpu().numpy().reshape(3, B).T[sample]
+        g_gpu = ppt.cpu().numpy().reshape(NP, B).T[sample].astype(np.float64)
+        xf = b2.x_final.cpu().numpy().reshape(NS, B).T[sample]
         counts_exact = counts_exact and bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
         err_by_T[f"{T:.3g}"] = float(np.linalg.norm(g_gpu.sum(0) - r.grad.sum(0)) / np.linalg.norm(r.grad.sum(0)))
     grad_rel_err = max(err_by_T.values())
@@ -424,7 +433,7 @@ def bench_infer(args, torch, dev):
     achieved = fired * slots(ops, cost) / (dom_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
                 "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS,
-                "traffic": profiled_traffic("abc_infer", dom), "kernel_ms": dom_ms,
+                "traffic": profiled_traffic(args.workload, dom), "kernel_ms": dom_ms,
                 "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
     cpu = None
     if not args.no_cpu_baseline:
@@ -437,7 +446,7 @@ def bench_infer(args, torch, dev):
         cpu = {"value": float(rc.steps_done.sum()) / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{n_cpu} of the {B} trajectories, {n_steps} steps, forward+adjoint in FP64"}
     sweep = None
-    if args.sweep:
+    if args.sweep and not coi:
         sweep = []
         for k2 in infer.K2_SWEEP:
             rr = infer.infer((infer.TRUE_RATES[0], k2), n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
@@ -447,13 +456,14 @@ def bench_infer(args, torch, dev):
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": res.epochs,
         "warmup": 2, "ms_per_step": res.train_s * 1e3 / res.epochs, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"abc_inference_{B}traj_{n_steps}steps_{tr.n_grid}grid_{res.epochs}epochs",
-                   "n_traj": B, "steps_per_traj": n_steps, "n_grid": tr.n_grid, "t_obs": tr.t_obs,
+        "config": {"workload": (f"ion_channel_inference_{B}traj_{n_steps}steps_{G}bins_{res.epochs}epochs" if coi
+                                else f"abc_inference_{B}traj_{n_steps}steps_{G}grid_{res.epochs}epochs"),
+                   "n_traj": B, "steps_per_traj": n_steps, "n_obs_points": G, "t_obs": tr.t_obs,
                    "epochs": res.epochs, "temperature": [tr.temp0, T_end], "optimizer": "rmsprop"},
         "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate,
         "fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "grad_rel_err": grad_rel_err, "grad_rel_err_by_T": err_by_T,
         "counts_bit_exact_sample": counts_exact,
-        "inference": {"k_true": res.k_true.tolist(), "k_start": list(infer.START_RATES),
+        "inference": {"k_true": res.k_true.tolist(), "k_start": list(k_start),
                       "k_learned": res.k_learned.tolist(), "ape_percent": res.ape.tolist(),
                       "loss_first": res.loss_first, "loss_last": res.loss_last, "train_s": res.train_s},
         "sweep": sweep, "roofline": roofline, "cpu_baseline": cpu,
@@ -466,12 +476,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dimer", choices=["dimer", "oscillator", "uneven", "grn", "abc_infer"],
+    ap.add_argument("--workload", default="dimer",
+                    choices=["dimer", "oscillator", "uneven", "grn", "abc_infer", "coi_infer"],
                     help="dimer: 2A<->A2, 65,536 x 10,000 steps (default); "
                          "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps; "
                          "uneven: 4,096 random networks x 256 trajectories x 5,000 steps; "
                          "grn: 784->256->10 gene-network classifier, 512 images x 32 trajectories x 2,000 steps; "
-                         "abc_infer: rate inference for A+B<->C, 100,000 x 250 steps, 250 captured epochs")
+                         "abc_infer: rate inference for A+B<->C, 100,000 x 250 steps, 250 captured epochs; "
+                         "coi_infer: ion-channel rate inference, 262,144 x 20 steps, 800 bins, 400 captured epochs")
     ap.add_argument("--sweep", action="store_true", help="abc_infer: also run the k2 sweep (8 targets)")
     ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
     ap.add_argument("--n-traj", type=int, default=65536)
@@ -501,7 +513,7 @@ def main():
 
     if args.workload == "grn":
         return bench_grn(args, torch, dev)
-    if args.workload == "abc_infer":
+    if args.workload in ("abc_infer", "coi_infer"):
         return bench_infer(args, torch, dev)
 
     if args.copy_bytes:

@@ -1,16 +1,19 @@
-"""Rate inference for the reversible dimerisation A + B <-> C (Sec. 4.1).
+"""Rate inference on the library: the reversible dimerisation A + B <-> C
+(Sec. 4.1) and the closed/open/inactivated ion channel (Sec. 4.4).
 
-- **Target.** The ensemble-mean trajectories of A, B and C from `n_target`
-  trajectories at the true rates (their own random stream), each path linearly
-  interpolated between its event points onto a uniform time grid before the
-  average is taken (the library's grid observation).
-- **Model.** `n_traj` trajectories of `n_steps` steps at theta = ln k, observed
-  the same way. The loss is the mean over grid points and species of the
-  squared difference of the ensemble means.
+- **Target.** A target ensemble at the true rates (its own random stream),
+  observed like the model: for the dimerisation, A, B and C linearly
+  interpolated between event points onto a uniform time grid (the library's
+  grid observation); for the channel, the open count's exact bin averages.
+- **Model.** `n_traj` trajectories at theta = ln k. The loss is the mean over
+  observation points and observed species of the squared difference of the
+  ensemble means.
 - **Gradient.** The library's straight-through backward (Eqs. 3-7, Fig. 1).
 - **Optimiser.** RMSprop on theta (decay 0.9, eps 1e-7). The Gumbel-Softmax
-  temperature is annealed geometrically from 1.0 to 0.001 over the epochs
-  (Sec. 3.5), and the learning rate geometrically from `lr0` to `lr1`.
+  temperature is annealed geometrically over the epochs (Sec. 3.5: 1.0 to
+  0.001 for the dimerisation, 0.05 to 0.0005 for the channel), the learning
+  rate geometrically as well (the channel's in proportion to the
+  temperature, Sec. 4.4).
 - **Graph.** One optimisation step is captured once into a HIP graph and
   replayed per epoch. The step is: forward, loss gradient, backward, RMSprop
   update, schedule update and epoch count. The epoch, the temperature and the
@@ -67,45 +70,48 @@ def _x0(net: W.Network, n: int) -> torch.Tensor:
 
 
 class Trainer:
-    """The captured optimisation step for one target."""
+    """The captured optimisation step: a model ensemble started at
+    `theta_start`, observed like the target ensemble drawn at the true rates
+    of `true_net`; the loss is the mean over observation points and observed
+    species of the squared difference of the two ensembles' means."""
 
-    def __init__(self, k_true: Sequence[float], *, n_traj: int = 100_000, n_target: int = 100_000,
-                 n_steps: int = 250, n_grid: int = 64, epochs: int = 250, t0: float = 1.0,
-                 t1: float = 1e-3, lr0: float = 0.15, lr1: float = 1e-4, rho: float = 0.9,
-                 eps: float = 1e-7, seed: int = 0, k_start: Sequence[float] = START_RATES,
-                 ckpt_every: int = 64):
+    def __init__(self, true_net: W.Network, theta_start: Sequence[float], cfg: W.RunConfig, *,
+                 n_traj: int, n_target: int, epochs: int, t0: float, t1: float, lr0: float,
+                 lr1: Optional[float] = None, rho: float = 0.9, eps: float = 1e-7):
+        """lr1=None anneals the learning rate in proportion to the temperature."""
         dev = torch.device("cuda")
-        self.k_true = np.asarray(k_true, np.float64)
-        true_net = W.dimerization_abc(*k_true, x0=X0)
-        self.net = W.dimerization_abc(*k_start, x0=X0)
-        self.t_obs = grid_end(true_net, n_target, n_steps, seed)
+        self.true_net = true_net
+        self.k_true = np.exp(true_net.theta0.astype(np.float64))
+        self.net = true_net
+        self.t_obs = cfg.t_obs
         self.epochs = epochs
-        self.n_grid, self.n_obs, self.B = n_grid, 3, n_traj
-        self.cfg = W.RunConfig(seed=seed, n_steps=n_steps, obs_kind=W.OBS_GRID, n_bins=n_grid,
-                               t_obs=self.t_obs, temperature=t0, ckpt_every=ckpt_every)
-        # target ensemble means on the grid
+        self.n_pts = cfg.n_bins if cfg.obs_kind != W.OBS_FINAL else 1
+        self.n_obs, self.B = len(true_net.obs_species), n_traj
+        self.cfg = cfg.replace(temperature=t0)
+        P_, O_ = self.n_pts, self.n_obs
+        # target ensemble means
         ht = ssa.Net([true_net], [n_target], t_obs=[self.t_obs])
         tf = ssa.forward(ht, self.cfg.replace(purpose=W.PURPOSE_TARGET),
                          torch.tensor(true_net.theta0, device=dev), _x0(true_net, n_target),
                          keep_ckpt=False, tie_capacity=0)
-        self.target = tf.obs[: n_grid * 3 * n_target].view(n_grid, 3, n_target).mean(dim=2).clone()
+        self.target = tf.obs[: P_ * O_ * n_target].view(P_, O_, n_target).mean(dim=2).clone()
         del tf, ht
         # model state and schedules (device scalars)
-        self.h = ssa.Net([self.net], [n_traj], t_obs=[self.t_obs])
-        self.theta0 = torch.tensor(np.log(np.asarray(k_start, np.float64)).astype(np.float32), device=dev)
+        self.h = ssa.Net([true_net], [n_traj], t_obs=[self.t_obs])
+        self.theta0 = torch.tensor(np.asarray(theta_start, np.float32), device=dev)
         self.theta = self.theta0.clone()
         self.v = torch.zeros_like(self.theta)
-        self.x0 = _x0(self.net, n_traj)
+        self.x0 = _x0(true_net, n_traj)
         self.epoch = torch.zeros(1, dtype=torch.int32, device=dev)
         self.temp0, self.lr0 = t0, lr0
         self.temp = torch.full((1,), t0, dtype=torch.float32, device=dev)
         self.lr = torch.full((1,), lr0, dtype=torch.float32, device=dev)
         n1 = max(epochs - 1, 1)
         self.r_temp = (t1 / t0) ** (1.0 / n1)
-        self.r_lr = (lr1 / lr0) ** (1.0 / n1)
+        self.r_lr = self.r_temp if lr1 is None else (lr1 / lr0) ** (1.0 / n1)
         self.rho, self.eps = rho, eps
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.d_obs = torch.zeros(n_grid * 3 * n_traj, dtype=torch.float64, device=dev)
+        self.d_obs = torch.zeros(P_ * O_ * n_traj, dtype=torch.float64, device=dev)
         self.d_params = torch.zeros(self.h.param_total, dtype=torch.float32, device=dev)
         self.bufs = ssa.forward(self.h, self.cfg, self.theta, self.x0, tie_capacity=0, d_epoch=self.epoch,
                                 d_temperature=self.temp)
@@ -113,14 +119,14 @@ class Trainer:
 
     def step(self):
         """One optimisation step on the current stream (preallocated tensors only)."""
-        G, O, B = self.n_grid, self.n_obs, self.B
+        P_, O, B = self.n_pts, self.n_obs, self.B
         ssa.forward(self.h, self.cfg, self.theta, self.x0, buffers=self.bufs, tie_capacity=0,
                     d_epoch=self.epoch, d_temperature=self.temp)
-        o = self.bufs.obs[: G * O * B].view(G, O, B)
+        o = self.bufs.obs[: P_ * O * B].view(P_, O, B)
         e = o.mean(dim=2) - self.target
         self.loss.copy_(e.square().mean().reshape(1))
-        # dL/dobs = 2 (mean - target) / (G O B) for every trajectory
-        self.d_obs.view(G, O, B).copy_((e * (2.0 / (G * O * B))).unsqueeze(2).expand(G, O, B))
+        # dL/dobs = 2 (mean - target) / (points * species * B) for every trajectory
+        self.d_obs.view(P_, O, B).copy_((e * (2.0 / (P_ * O * B))).unsqueeze(2).expand(P_, O, B))
         ssa.backward(self.h, self.cfg, self.theta, self.x0, self.bufs, self.d_obs, d_params=self.d_params)
         g = self.d_params
         self.v.mul_(self.rho).addcmul_(g, g, value=1.0 - self.rho)
@@ -161,8 +167,41 @@ class Trainer:
                                int(self.bufs.steps_done.sum().item()), ls)
 
 
+def dimerization(k_true: Sequence[float] = TRUE_RATES, *, n_traj: int = 100_000, n_target: int = 100_000,
+                 n_steps: int = 250, n_grid: int = 64, epochs: int = 250, t0: float = 1.0, t1: float = 1e-3,
+                 lr0: float = 0.15, lr1: float = 1e-4, seed: int = 0, k_start: Sequence[float] = START_RATES,
+                 ckpt_every: int = 64) -> Trainer:
+    """A + B <-> C (Sec. 4.1): the grid observation of A, B and C on the
+    target's span, 250 steps, temperature 1.0 -> 0.001."""
+    true_net = W.dimerization_abc(*k_true, x0=X0)
+    cfg = W.RunConfig(seed=seed, n_steps=n_steps, obs_kind=W.OBS_GRID, n_bins=n_grid,
+                      t_obs=grid_end(true_net, n_target, n_steps, seed), ckpt_every=ckpt_every)
+    return Trainer(true_net, np.log(np.asarray(k_start, np.float64)), cfg, n_traj=n_traj, n_target=n_target,
+                   epochs=epochs, t0=t0, t1=t1, lr0=lr0, lr1=lr1)
+
+
+COI_RATES = (0.75, 0.103, 1.159)   # k_open, k_close, k_inact (1/ms) of the synthetic channel
+COI_START = (0.3, 0.3, 0.3)
+
+
+def ion_channel(k_true: Sequence[float] = COI_RATES, *, n_channels: int = 2, n_traj: int = 262_144,
+                n_target: int = 262_144, n_steps: int = 20, n_bins: int = 800, t_obs: float = 8.0,
+                epochs: int = 400, t0: float = 0.05, t1: float = 5e-4, lr0: float = 0.05, seed: int = 0,
+                k_start: Sequence[float] = COI_START, ckpt_every: int = 32) -> Trainer:
+    """Closed/open/inactivated channel (Sec. 4.4): N channels, 20 steps, exact
+    bin averages of the open count on the recording grid (800 bins of
+    0.01 ms), temperature 0.05 -> 0.0005 with the learning rate in
+    proportion; the recorded sweeps are replaced by a target ensemble at
+    known rates."""
+    true_net = W.ion_channel_coi(*k_true, n_channels=n_channels)
+    cfg = W.RunConfig(seed=seed, n_steps=n_steps, obs_kind=W.OBS_BINS, n_bins=n_bins, t_obs=t_obs,
+                      ckpt_every=ckpt_every)
+    return Trainer(true_net, np.log(np.asarray(k_start, np.float64)), cfg, n_traj=n_traj, n_target=n_target,
+                   epochs=epochs, t0=t0, t1=t1, lr0=lr0, lr1=None)
+
+
 def infer(k_true: Sequence[float] = TRUE_RATES, **kw) -> InferenceResult:
-    return Trainer(k_true, **kw).run()
+    return dimerization(k_true, **kw).run()
 
 
 def sweep(k2_values: Sequence[float] = K2_SWEEP, k1: float = TRUE_RATES[0], **kw) -> List[InferenceResult]:
