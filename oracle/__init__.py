@@ -53,7 +53,7 @@ class _Cfg(C.Structure):
                 ("n_steps", C.c_int64), ("t_end", C.c_double), ("obs_kind", C.c_int32),
                 ("n_bins", C.c_int32), ("t_obs", C.c_double), ("n_obs", C.c_int32),
                 ("obs_species", C.c_void_p), ("temperature", C.c_double),
-                ("tie_threshold", C.c_double), ("clock_tol", C.c_double)]
+                ("tie_threshold", C.c_double), ("clock_tol", C.c_double), ("selection", C.c_int32)]
 
 
 class _Grn(C.Structure):
@@ -167,7 +167,8 @@ def _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species=None):
                                        np.int32))
     c = _Cfg(cfg.seed, cfg.purpose, cfg.epoch, min(int(cfg.n_steps), 2 ** 62),
              float(cfg.t_end), cfg.obs_kind, cfg.n_bins, float(cfg.t_obs), len(obs_sp),
-             _p(obs_sp).value, float(cfg.temperature), tie_threshold, clock_tol)
+             _p(obs_sp).value, float(cfg.temperature), tie_threshold, clock_tol,
+             int(getattr(cfg, "selection", 0)))
     return n, c
 
 

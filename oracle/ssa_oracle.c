@@ -295,16 +295,38 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
             if (!fire) break;
         }
 
-        /* exponential race: argmin_j E_j / a_j == argmax_j ln a_j + G_j (Sec. 3.2) */
         int jbest = -1;
-        double r1 = INFINITY, r2 = INFINITY;
-        for (int j = 0; j < M; ++j) {
-            if (!(a[j] > 0.0)) continue;
-            double r = -log(u[1 + j]) / a[j];
-            if (r < r1) { r2 = r1; r1 = r; jbest = j; }
-            else if (r < r2) { r2 = r; }
+        double margin = INFINITY;
+        if (cfg->selection == ORC_SELECT_INVERSE_CDF) {
+            /* direct method (Sec. 2): the first j with a_1 + ... + a_j > u_1 a0;
+             * the margin is the relative distance of u_1 a0 from the nearest
+             * interior cumulative boundary */
+            const double target = u[1] * a0;
+            int last = -1;
+            for (int j = 0; j < M; ++j)
+                if (a[j] > 0.0) last = j;
+            double c = 0.0;
+            for (int j = 0; j < M; ++j) {
+                if (!(a[j] > 0.0)) continue;
+                c += a[j];
+                if (j != last) {
+                    const double d = fabs(c - target) / a0;
+                    if (d < margin) margin = d;
+                }
+                if (jbest < 0 && c > target) jbest = j;
+            }
+            if (jbest < 0) jbest = last;
+        } else {
+            /* exponential race: argmin_j E_j / a_j == argmax_j ln a_j + G_j (Sec. 3.2) */
+            double r1 = INFINITY, r2 = INFINITY;
+            for (int j = 0; j < M; ++j) {
+                if (!(a[j] > 0.0)) continue;
+                double r = -log(u[1 + j]) / a[j];
+                if (r < r1) { r2 = r1; r1 = r; jbest = j; }
+                else if (r < r2) { r2 = r; }
+            }
+            margin = isfinite(r2) ? (r2 - r1) / r1 : INFINITY;
         }
-        double margin = isfinite(r2) ? (r2 - r1) / r1 : INFINITY;
         if (margin < st->min_margin) st->min_margin = margin;
         if (margin <= cfg->tie_threshold) st->n_near++;
         if (ov_react >= 0 && ov_react != jbest) {
@@ -415,6 +437,7 @@ static int check_args(const orc_net *net, const orc_cfg *cfg)
     if (cfg->obs_kind == ORC_OBS_GRID && (cfg->n_bins < 2 || !(cfg->t_obs > 0.0)))
         return -1;
     if (cfg->obs_kind < ORC_OBS_FINAL || cfg->obs_kind > ORC_OBS_GRID) return -1;
+    if (cfg->selection != ORC_SELECT_GUMBEL_MAX && cfg->selection != ORC_SELECT_INVERSE_CDF) return -1;
     if (cfg->n_obs < 0 || (cfg->n_obs > 0 && !cfg->obs_species)) return -1;
     if (!(cfg->temperature > 0.0)) return -1;
     for (int j = 0; j < net->n_reactions; ++j)
@@ -624,6 +647,8 @@ int orc_adjoint(const orc_net *net, const orc_cfg *cfg, const double *theta,
                 double *grad, const orc_stats *stats, int n_threads)
 {
     if (check_args(net, cfg) || n_traj < 0) return -1;
+    /* the straight-through backward needs the Gumbel noise of the race */
+    if (cfg->selection != ORC_SELECT_GUMBEL_MAX) return -1;
     const int N = net->n_species, M = net->n_reactions, P = net->n_params, W = obs_width(cfg);
     double *k = malloc(sizeof(double) * M);
     if (!k) return -1;

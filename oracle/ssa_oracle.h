@@ -37,6 +37,12 @@ typedef struct orc_net {
  * last state after the last event (Sec. 4.1). */
 enum { ORC_OBS_FINAL = 0, ORC_OBS_BINS = 1, ORC_OBS_GRID = 2 };
 
+/* Channel selection of the forward: the Gumbel-max (exponential race) of
+ * Sec. 3.2, or the standard direct method's inverse CDF (Sec. 2: the first j
+ * whose cumulative propensity exceeds u a0), which has no straight-through
+ * backward. */
+enum { ORC_SELECT_GUMBEL_MAX = 0, ORC_SELECT_INVERSE_CDF = 1 };
+
 typedef struct orc_cfg {
     uint64_t seed;
     uint32_t purpose;
@@ -51,6 +57,7 @@ typedef struct orc_cfg {
     double temperature;     /* Gumbel-Softmax temperature T of Eq. (3) */
     double tie_threshold;   /* relative margin that counts as a near-tie (1e-6) */
     double clock_tol;       /* relative window |t + tau - t_end| <= clock_tol * t_end */
+    int32_t selection;      /* ORC_SELECT_* */
 } orc_cfg;
 
 /* Per-trajectory overrides taken from the GPU's near-tie log.  For trajectory

@@ -25,6 +25,12 @@ OBS_BINS = 1    # exact time average of the piecewise-constant path over uniform
 OBS_GRID = 2    # the path linearly interpolated between its event points at n_bins uniform
                 # times t_obs g / (n_bins - 1), held after the last event (Sec. 4.1)
 
+# Channel selection of the forward: the Gumbel-max (exponential race) of
+# Sec. 3.2, or the standard direct method's inverse CDF (Sec. 2), which has
+# no straight-through backward.
+SELECT_GUMBEL_MAX = 0
+SELECT_INVERSE_CDF = 1
+
 # Random-stream purposes (high byte of the fourth Philox counter word).
 PURPOSE_SIMULATE = 0
 PURPOSE_TARGET = 1
@@ -247,6 +253,7 @@ class RunConfig:
     t_obs: float = 0.0
     temperature: float = 0.5
     ckpt_every: int = 256
+    selection: int = 0                # SELECT_GUMBEL_MAX or SELECT_INVERSE_CDF (forward only)
 
     def replace(self, **kw) -> "RunConfig":
         d = dict(self.__dict__)

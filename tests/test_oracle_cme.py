@@ -232,3 +232,57 @@ def test_step_and_time_limits(orc):
     r = orc.run(net, W.RunConfig(n_steps=37, t_end=5.0), net.theta0, net.x0, traj_ids=np.arange(500))
     assert np.all(r.steps_done <= 37) and np.all(r.t_final <= 5.0)
     assert np.any(r.steps_done == 37) or np.all(r.t_final <= 5.0)
+
+
+def test_inverse_cdf_selects_categorically(orc):
+    """The standard direct method (Sec. 2): the first j whose cumulative
+    propensity exceeds u a0 is a draw from a_j/a0, from its own uniform."""
+    rates = np.array([0.5, 1.0, 2.0, 4.0, 0.25, 7.25])
+    net = _parallel_sources(rates)
+    n = 200000
+    cfg = W.RunConfig(n_steps=1, selection=W.SELECT_INVERSE_CDF)
+    r = orc.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n))
+    j = np.argmax(r.x_final, axis=1)
+    probs = np.exp(net.theta0.astype(np.float64))
+    probs /= probs.sum()
+    ok, pv = _chi2_ok(np.bincount(j, minlength=len(rates)), probs)
+    assert ok, pv
+
+
+def test_inverse_cdf_reads_the_cumulative_sum(orc):
+    """Along an oscillator path the chosen channel is the cumulative sum's
+    crossing of u_1 a0, and the margin is the nearest interior boundary."""
+    net = W.oscillator(0)
+    cfg = W.RunConfig(n_steps=2000, selection=W.SELECT_INVERSE_CDF)
+    tr = orc.trace(net, cfg, net.theta0, net.x0, traj_id=9, cap=2000)
+    c = np.cumsum(tr.a, axis=1)
+    a0 = c[:, -1]
+    target = tr.u[:, 1] * a0
+    j = np.argmax(c > target[:, None], axis=1)
+    assert np.array_equal(j, tr.j)
+    active = tr.a > 0
+    last = active.shape[1] - 1 - np.argmax(active[:, ::-1], axis=1)
+    d = np.abs(c - target[:, None]) / a0[:, None]
+    d[~active] = np.inf
+    d[np.arange(len(last)), last] = np.inf
+    assert np.allclose(d.min(axis=1), tr.margin, rtol=1e-9, atol=1e-15)
+
+
+def test_inverse_cdf_isomerization_binomial(orc):
+    kab, kba, nmol, T = 0.3, 0.7, 40, 2.0
+    net = W.isomerization(kab, kba, nmol)
+    n = 40000
+    r = orc.run(net, W.RunConfig(t_end=T, selection=W.SELECT_INVERSE_CDF), net.theta0, net.x0,
+                traj_ids=np.arange(n))
+    pi_a = kba / (kab + kba)
+    pa = pi_a + (1 - pi_a) * math.exp(-(kab + kba) * T)
+    probs = scipy.stats.binom.pmf(np.arange(nmol + 1), nmol, pa)
+    ok, pv = _chi2_ok(np.bincount(r.x_final[:, 0], minlength=nmol + 1), probs)
+    assert ok, pv
+
+
+def test_inverse_cdf_has_no_backward(orc):
+    net = W.dimerization_2a()
+    cfg = W.RunConfig(n_steps=10, selection=W.SELECT_INVERSE_CDF)
+    with pytest.raises(Exception):
+        orc.run(net, cfg, net.theta0, net.x0[None, :], traj_ids=[0], d_obs=np.zeros((1, 1)))
