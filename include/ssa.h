@@ -78,6 +78,16 @@ typedef enum ssa_status {
  *                  only: any other plan returns SSA_ENOTSUP. */
 enum { SSA_OBS_FINAL = 0, SSA_OBS_BINS = 1, SSA_OBS_GRID = 2 };
 
+/* Channel selection of the forward:
+ *   SSA_SELECT_GUMBEL_MAX   argmax_j ln a_j + G_j (Sec. 3.2), run as the exponential
+ *                           race argmin_j E_j / a_j over words 1..M of the step;
+ *   SSA_SELECT_INVERSE_CDF  the standard direct method (Sec. 2): the first j whose
+ *                           cumulative propensity exceeds u_1 a0, with u_1 from word 1.
+ *                           Forward only (ssa_backward returns SSA_ENOTSUP), final or bin
+ *                           observations, topology-specialised lane mode only.  It is the
+ *                           baseline of the selection-variant throughput comparison. */
+enum { SSA_SELECT_GUMBEL_MAX = 0, SSA_SELECT_INVERSE_CDF = 1 };
+
 /* How ssa_backward obtains the fired channel of each step.
  *   SSA_BWD_TAPE:      ssa_forward stores the fired channel index of every
  *                      step in a compact tape (1, 2, 4 or 8 bits a step);
@@ -162,6 +172,7 @@ typedef struct ssa_config {
     const float *d_temperature;    /* optional DEVICE scalar overriding temperature, read by the
                                       backward when it runs (annealing T under graph replay);
                                       it must then hold a finite value > 0.  NULL: temperature */
+    int32_t selection;             /* SSA_SELECT_*: how the forward picks the channel */
 } ssa_config;
 
 /* One logged step where the selection (kind 0) or the t_end stop decision

@@ -191,6 +191,15 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
     if (mode == SSA_BWD_RECOMPUTE && cfg->ckpt_every > kMaxRecomputeSegment)
         return fail(SSA_EINVAL, "recompute mode needs ckpt_every <= 64");
     if (cfg->tie_capacity < 0) return fail(SSA_EINVAL, "tie_capacity must be >= 0");
+    if (cfg->selection != SSA_SELECT_GUMBEL_MAX && cfg->selection != SSA_SELECT_INVERSE_CDF)
+        return fail(SSA_EINVAL, "unknown selection");
+    if (cfg->selection == SSA_SELECT_INVERSE_CDF) {
+        if (cfg->obs_kind == SSA_OBS_GRID)
+            return fail(SSA_ENOTSUP, "the inverse-CDF selection runs with the final or bin observation");
+        for (const auto &gr : net->groups)
+            if (gr.n_items && !gr.spec)
+                return fail(SSA_ENOTSUP, "the inverse-CDF selection runs in the topology-specialised lane mode only");
+    }
     return SSA_OK;
 }
 
@@ -219,6 +228,7 @@ RunParams base_params(const ssa_net *net, const ssa_config *cfg)
     p.traj_total = net->traj_total;
     p.temperature = cfg->temperature;
     p.d_temperature = cfg->d_temperature;
+    p.selection = cfg->selection;
     p.recompute = resolve_bwd_mode(cfg) == SSA_BWD_RECOMPUTE ? 1 : 0;
     p.inc_ptr = net->inc_ptr_d;
     p.chan_inc = net->chan_inc_d;
@@ -273,6 +283,7 @@ void ssa_config_default(ssa_config *cfg)
     cfg->n_bins = 0;
     cfg->temperature = 0.5f;
     cfg->d_temperature = nullptr;
+    cfg->selection = SSA_SELECT_GUMBEL_MAX;
     cfg->ckpt_every = 256;
     cfg->bwd_mode = SSA_BWD_AUTO;
     cfg->tie_capacity = 0;
@@ -669,6 +680,8 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
 {
     g_last_error.clear();
     ssa_status s = check_config(net, cfg);
+    if (s == SSA_OK && cfg->selection != SSA_SELECT_GUMBEL_MAX)
+        return fail(SSA_ENOTSUP, "the straight-through backward needs the Gumbel-max selection");
     if (s != SSA_OK) return s;
     if (!theta || !x0 || !x_final || !t_final || !steps_done || !d_params)
         return fail(SSA_EINVAL, "theta, x0, x_final, t_final, steps_done and d_params are required");
@@ -710,6 +723,7 @@ ssa_status ssa_step_batch(const ssa_net *net, const ssa_config *cfg, const float
     g_last_error.clear();
     ssa_status s = check_config(net, cfg);
     if (s != SSA_OK) return s;
+    if (cfg->selection != SSA_SELECT_GUMBEL_MAX) return fail(SSA_ENOTSUP, "ssa_step_batch runs the Gumbel-max selection");
     if (!theta || !x || !t || !chosen || !tau) return fail(SSA_EINVAL, "theta, x, t, chosen, tau are required");
     RunParams p = base_params(net, cfg);
     p.theta = theta;

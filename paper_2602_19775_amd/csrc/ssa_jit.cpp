@@ -76,6 +76,9 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
         s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_bwd" << sfx
           << "(ssa::RunParams p) { ssa::spec::backward<Net, " << g << ">(p); }\n";
     }
+    // the forward with the inverse-CDF selection (final and bin observations)
+    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_cdf"
+         "(ssa::RunParams p) { ssa::spec::forward<Net, false, true>(p); }\n";
     return s.str();
 }
 
@@ -125,7 +128,8 @@ bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
         hipModuleGetFunction(&k.fwd, k.module, "ssa_spec_fwd") != hipSuccess ||
         hipModuleGetFunction(&k.bwd, k.module, "ssa_spec_bwd") != hipSuccess ||
         hipModuleGetFunction(&k.fwd_grid, k.module, "ssa_spec_fwd_grid") != hipSuccess ||
-        hipModuleGetFunction(&k.bwd_grid, k.module, "ssa_spec_bwd_grid") != hipSuccess) {
+        hipModuleGetFunction(&k.bwd_grid, k.module, "ssa_spec_bwd_grid") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_cdf, k.module, "ssa_spec_fwd_cdf") != hipSuccess) {
         *log = "loading the compiled module failed";
         return false;
     }
@@ -141,7 +145,8 @@ hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, 
     RunParams copy = p;
     void *args[] = {&copy};
     const bool grid = p.obs_kind == 2;
-    hipFunction_t f = backward ? (grid ? k.bwd_grid : k.bwd) : (grid ? k.fwd_grid : k.fwd);
+    hipFunction_t f = backward ? (grid ? k.bwd_grid : k.bwd)
+                               : (p.selection == 1 ? k.fwd_cdf : grid ? k.fwd_grid : k.fwd);
     return hipModuleLaunchKernel(f, blocks, 1, 1, 64 * spec_waves_per_block, 1, 1, 0, stream, args, nullptr);
 }
 

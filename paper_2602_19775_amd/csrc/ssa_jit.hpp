@@ -17,6 +17,7 @@ struct SpecKernels {
     hipFunction_t bwd = nullptr;
     hipFunction_t fwd_grid = nullptr;   // grid observation
     hipFunction_t bwd_grid = nullptr;
+    hipFunction_t fwd_cdf = nullptr;    // inverse-CDF selection (forward only)
 };
 
 // Source of the specialised kernel pair for one network (host tables).

@@ -127,6 +127,7 @@ struct RunParams {
     int64_t traj_total;
     float temperature;
     const float *d_temperature;   // when set, the temperature is read here on the device
+    int32_t selection;            // 0 Gumbel-max race, 1 inverse CDF (forward only)
     int32_t recompute;      // backward: recover choices by re-running segments
 
     // wave mode: species -> range of incidence slots, and per channel the

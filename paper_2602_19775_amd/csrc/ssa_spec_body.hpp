@@ -72,12 +72,12 @@ struct Blocks {
 };
 
 // Philox words of step k (word 0: tau, word 1+j: channel j).
-template <class NET>
+template <class NET, int NW = Blocks<NET>::W>
 __device__ __forceinline__ void words(uint32_t k, uint32_t tid, uint32_t pe, uint32_t k0, uint32_t k1,
-                                      uint32_t (&wd)[Blocks<NET>::W])
+                                      uint32_t (&wd)[NW])
 {
 #pragma unroll
-    for (int b = 0; b < Blocks<NET>::NB; ++b) {
+    for (int b = 0; b < NW / 4; ++b) {
         const Philox::Out o = Philox::block((uint32_t)b, k, tid, pe, k0, k1);
         wd[4 * b] = o.x;
         wd[4 * b + 1] = o.y;
@@ -133,8 +133,10 @@ __device__ __forceinline__ void rates(const RunParams &p, const NetDev &nd, floa
 constexpr int obs_cap(int n) { return n > 0 ? n : 1; }
 
 // --------------------------------------------------------------------------
-// GRID: the grid observation (the other kinds are runtime cases of GRID = false)
-template <class NET, bool HAS_T_END, bool GRID>
+// GRID: the grid observation (the other kinds are runtime cases of GRID = false).
+// CDF: the channel is the standard direct method's inverse-CDF draw from word 1
+// (Sec. 2) instead of the Gumbel-max race; such a run has no backward.
+template <class NET, bool HAS_T_END, bool GRID, bool CDF = false>
 __device__ void forward_run(const RunParams &p)
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
@@ -194,8 +196,9 @@ __device__ void forward_run(const RunParams &p)
     // Per-step bookkeeping stays out of the body: checkpoints are written
     // per segment, the tape word is stored per word, and lanes that stop
     // (absorbing state, t_end) go through the rare path.
-    uint32_t wd[Blocks<NET>::W];
-    words<NET>(0u, tid, pe, p.seed_lo, p.seed_hi, wd);
+    constexpr int NW = CDF ? 4 : Blocks<NET>::W;   // the inverse CDF draws from block 0 only
+    uint32_t wd[NW];
+    words<NET, NW>(0u, tid, pe, p.seed_lo, p.seed_hi, wd);
     int k = 0;
     bool any = ballot(active) != 0ull;
     while (any && k < p.n_steps) {
@@ -216,20 +219,43 @@ __device__ void forward_run(const RunParams &p)
         const float a0 = propensities<NET, false>(c, X, a, A1, A2);
         const float tau = neglog_u(wd[0]) * fast_rcp(a0);
         const double tn = t + (double)tau;
-        // exponential race: smallest and second smallest E_j / a_j
         float r[M];
         float r1 = INFINITY, r2 = INFINITY;
         int j1 = 0;
+        float cdf_gap = INFINITY;     // inverse CDF: distance of u a0 from the nearest interior boundary
+        int cdf_side = 0;             // ... and the channel across it
+        if (!CDF) {
+            // exponential race: smallest and second smallest E_j / a_j
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            r[j] = neglog_u(wd[1 + j]) * fast_rcp(a[j]);    // a_j = 0 gives +inf: never fires
-            const bool lt = r[j] < r1;
-            r2 = lt ? r1 : fminf(r2, r[j]);
-            j1 = lt ? j : j1;
-            r1 = fminf(r1, r[j]);
+            for (int j = 0; j < M; ++j) {
+                r[j] = neglog_u(wd[1 + j]) * fast_rcp(a[j]);    // a_j = 0 gives +inf: never fires
+                const bool lt = r[j] < r1;
+                r2 = lt ? r1 : fminf(r2, r[j]);
+                j1 = lt ? j : j1;
+                r1 = fminf(r1, r[j]);
+            }
+        } else {
+            // first j whose cumulative propensity (summed in a0's order) exceeds u a0
+            const float target = lattice_u(wd[1]) * a0;
+            float cs = 0.f;
+            bool found = false;
+            int last = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                cs += a[j];
+                const bool cross = !found && cs > target;
+                j1 = cross ? j : j1;
+                found = found || cross;
+                last = a[j] > 0.f ? j : last;
+                const float d = fabsf(cs - target);
+                const bool closer = a[j] > 0.f && cs < a0 && d < cdf_gap;
+                cdf_side = closer ? (cs > target ? j + 1 : j) : cdf_side;
+                cdf_gap = closer ? d : cdf_gap;
+            }
+            j1 = found ? j1 : last;
         }
-        uint32_t wn[Blocks<NET>::W];
-        words<NET>((uint32_t)(k + 1), tid, pe, p.seed_lo, p.seed_hi, wn);
+        uint32_t wn[NW];
+        words<NET, NW>((uint32_t)(k + 1), tid, pe, p.seed_lo, p.seed_hi, wn);
 
         const bool live = active && a0 > 0.f;           // a0 = 0: absorbing state
         const bool fire = live && (!HAS_T_END || tn <= p.t_end);
@@ -238,7 +264,7 @@ __device__ void forward_run(const RunParams &p)
 #pragma unroll
         for (int o = 0; o < NO; ++o) acc[o] += (double)X[NET::OBS[o]] * w_obs;
         const bool clock_tie = HAS_T_END && live && fabs(tn - p.t_end) <= kClockTieLog * p.t_end;
-        const bool near_tie = fire && r2 <= r1 * (1.f + kTieLog);
+        const bool near_tie = fire && (CDF ? cdf_gap <= kTieLog * a0 : r2 <= r1 * (1.f + kTieLog));
         const bool crossing = fire && !in_bin && bin < n_bins;
         const bool gcross = grid && fire && grid_t < tn;    // grid points in [t, t + tau)
         const bool odd = active && !(a0 >= 0.f);
@@ -249,12 +275,16 @@ __device__ void forward_run(const RunParams &p)
             if (clock_tie)
                 log_tie(p, (uint32_t)g, k, fire ? 1 : 0, 0, (float)((tn - p.t_end) / p.t_end), 1);
             if (near_tie) {
-                int j2 = -1;
-                float best = INFINITY;
+                if (CDF) {
+                    log_tie(p, (uint32_t)g, k, j1, cdf_side == j1 ? cdf_side - 1 : cdf_side, cdf_gap / a0, 0);
+                } else {
+                    int j2 = -1;
+                    float best = INFINITY;
 #pragma unroll
-                for (int j = 0; j < M; ++j)
-                    if (j != j1 && r[j] < best) { best = r[j]; j2 = j; }
-                log_tie(p, (uint32_t)g, k, j1, j2, (r2 - r1) / r1, 0);
+                    for (int j = 0; j < M; ++j)
+                        if (j != j1 && r[j] < best) { best = r[j]; j2 = j; }
+                    log_tie(p, (uint32_t)g, k, j1, j2, (r2 - r1) / r1, 0);
+                }
             }
             if (crossing) {
                 double t0 = t;
@@ -297,7 +327,7 @@ __device__ void forward_run(const RunParams &p)
         n_done += fire ? 1 : 0;
         active = fire;
 #pragma unroll
-        for (int q = 0; q < Blocks<NET>::W; ++q) wd[q] = wn[q];
+        for (int q = 0; q < NW; ++q) wd[q] = wn[q];
         if (!any) {
             ++k;
             break;
@@ -347,11 +377,11 @@ __device__ void forward_run(const RunParams &p)
     if (flags) atomicOr(p.flags, flags);
 }
 
-template <class NET, bool GRID>
+template <class NET, bool GRID, bool CDF = false>
 __device__ void forward(const RunParams &p)
 {
-    if (p.t_end < INFINITY) forward_run<NET, true, GRID>(p);
-    else forward_run<NET, false, GRID>(p);
+    if (p.t_end < INFINITY) forward_run<NET, true, GRID, CDF>(p);
+    else forward_run<NET, false, GRID, CDF>(p);
 }
 
 // --------------------------------------------------------------------------

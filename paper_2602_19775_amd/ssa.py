@@ -49,7 +49,7 @@ class _Cfg(C.Structure):
                 ("d_epoch", C.c_void_p), ("traj_ids", C.c_void_p), ("n_steps", C.c_int32),
                 ("t_end", C.c_double), ("obs_kind", C.c_int32), ("n_bins", C.c_int32),
                 ("temperature", C.c_float), ("ckpt_every", C.c_int32), ("bwd_mode", C.c_int32),
-                ("tie_capacity", C.c_int32), ("d_temperature", C.c_void_p)]
+                ("tie_capacity", C.c_int32), ("d_temperature", C.c_void_p), ("selection", C.c_int32)]
 
 
 TIE_DTYPE = np.dtype([("traj", np.uint32), ("step", np.uint32), ("chosen", np.int32),
@@ -183,7 +183,8 @@ def make_cfg(cfg: W.RunConfig, tie_capacity: int = 0, bwd_mode: str = "auto",
     return _Cfg(int(cfg.seed) & (2 ** 64 - 1), int(cfg.purpose), int(cfg.epoch), _ptr(d_epoch),
                 _ptr(traj_ids), n_steps, float(cfg.t_end), int(cfg.obs_kind),
                 int(cfg.n_bins if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID) else 0), float(cfg.temperature),
-                int(cfg.ckpt_every), _BWD[bwd_mode], int(tie_capacity), _ptr(d_temperature))
+                int(cfg.ckpt_every), _BWD[bwd_mode], int(tie_capacity), _ptr(d_temperature),
+                int(getattr(cfg, "selection", W.SELECT_GUMBEL_MAX)))
 
 
 @dataclass

@@ -1,0 +1,87 @@
+"""The inverse-CDF selection of the standard direct method (Sec. 2) on the
+topology-specialised forward, against the FP64 oracle through the C ABI:
+counts and step counts bit-exact except at logged near-ties (a cumulative
+boundary within 2e-6 a0 of u a0, where the oracle takes the GPU's choice if
+its own gap is within 1e-6), clocks and bin averages within 1e-5.  It has no
+backward, and runs in the specialised lane mode only."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_19775_amd import workloads as W
+
+from test_gpu_parity import assert_forward_parity, run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_19775_amd import ssa as m
+    m.lib()
+    return m
+
+
+def test_inverse_cdf_dimer_to_t_end(ssa):
+    wl = W.dimer_forward_1k()
+    cfg = wl.cfg.replace(selection=W.SELECT_INVERSE_CDF)
+    gpu, r, ids, _ = run_pair(ssa, wl.net, cfg, wl.n_traj)
+    assert_forward_parity(gpu, r, ids, cfg)
+
+
+def test_inverse_cdf_oscillator_bins(ssa):
+    net = W.oscillator(0)
+    cfg = W.RunConfig(seed=5, n_steps=20000, obs_kind=W.OBS_BINS, n_bins=16, t_obs=0.0,
+                      selection=W.SELECT_INVERSE_CDF)
+    import oracle
+    pilot = oracle.run(net, cfg.replace(obs_kind=W.OBS_FINAL), net.theta0, net.x0, traj_ids=np.arange(8))
+    cfg = cfg.replace(t_obs=0.8 * float(pilot.t_final.min()))
+    B = 4096
+    sample = np.unique(np.concatenate([[0, B - 1], np.random.default_rng(2).choice(B, 40, replace=False)]))
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, sample=sample)
+    assert_forward_parity(gpu, r, ids, cfg)
+
+
+def test_inverse_cdf_differs_from_the_race_but_not_in_law(ssa):
+    """Same network and stream, other selection: other paths, same law (the
+    isomerisation's binomial count at t_end)."""
+    import math
+    import scipy.stats
+    kab, kba, nmol, T = 0.3, 0.7, 40, 2.0
+    net = W.isomerization(kab, kba, nmol)
+    B = 65536
+    h = ssa.Net([net], [B])
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = torch.tensor(np.repeat(net.x0[:, None], B, axis=1).reshape(-1), dtype=torch.int32, device="cuda")
+    counts = {}
+    for sel in (W.SELECT_GUMBEL_MAX, W.SELECT_INVERSE_CDF):
+        f = ssa.forward(h, W.RunConfig(t_end=T, selection=sel), th, x0, keep_ckpt=False, tie_capacity=0)
+        counts[sel] = f.x_final.cpu().numpy().reshape(2, B)[0]
+    assert not np.array_equal(counts[0], counts[1])
+    pi_a = kba / (kab + kba)
+    pa = pi_a + (1 - pi_a) * math.exp(-(kab + kba) * T)
+    probs = scipy.stats.binom.pmf(np.arange(nmol + 1), nmol, pa)
+    for sel, c in counts.items():
+        obs = np.bincount(c, minlength=nmol + 1)
+        keep = probs * B >= 5
+        exp = probs[keep] * B
+        chi2 = (((obs[keep] - exp) ** 2) / exp).sum() + 0.0
+        assert scipy.stats.chi2.sf(chi2, keep.sum() - 1) > 1e-4, sel
+
+
+def test_inverse_cdf_is_forward_only(ssa):
+    net = W.dimerization_2a()
+    B = 256
+    cfg = W.RunConfig(n_steps=50, selection=W.SELECT_INVERSE_CDF)
+    h = ssa.Net([net], [B])
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = torch.tensor(np.repeat(net.x0[:, None], B, axis=1).reshape(-1), dtype=torch.int32, device="cuda")
+    f = ssa.forward(h, cfg, th, x0)
+    with pytest.raises(ssa.SSAError, match="Gumbel-max"):
+        ssa.backward(h, cfg, th, x0, f, torch.zeros(B, dtype=torch.float64, device="cuda"))
+    for mode in ("lane", "wave"):
+        hm = ssa.Net([net], [B], exec_mode=mode)
+        with pytest.raises(ssa.SSAError, match="inverse-CDF"):
+            ssa.forward(hm, cfg, th, x0)
