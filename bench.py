@@ -471,19 +471,80 @@ def bench_infer(args, torch, dev):
     print(json.dumps(out))
 
 
+def bench_selection(args, torch, dev):
+    """Selection-variant study (the paper's standard Gillespie / Gumbel-Max /
+    Gumbel-Softmax comparison): on the dimer and oscillator workloads, the
+    plain forward with the inverse-CDF draw (one uniform for the channel), the
+    plain forward with the Gumbel-max race (M uniforms), and one
+    straight-through training step (Gumbel-max forward keeping its tape and
+    checkpoints, then the Gumbel-Softmax backward).  Forward parity of the
+    inverse-CDF runs is checked on a sample against the oracle."""
+    from paper_2602_19775_amd import ssa
+    from paper_2602_19775_amd import workloads as W
+    import oracle
+
+    rows = []
+    for name, wl in (("dimer", W.dimer_fwdbwd_64k()), ("oscillator", W.oscillator_fwdbwd_64k(n_steps=args.n_steps or 200000))):
+        net, B, cfg = wl.net, wl.n_traj, wl.cfg
+        h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
+        th = torch.tensor(net.theta0, device=dev)
+        x0 = torch.tensor(wl.x0_soa().reshape(-1), device=dev)
+        row = {"workload": wl.name}
+
+        def timed(fn, n):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / n
+
+        n_rep = args.steps if name == "dimer" else max(1, args.steps // 5)
+        for label, sel in (("inverse_cdf", W.SELECT_INVERSE_CDF), ("gumbel_max", W.SELECT_GUMBEL_MAX)):
+            c = cfg.replace(selection=sel)
+            b = ssa.forward(h, c, th, x0, keep_ckpt=False, tie_capacity=1 << 20)
+            dt = timed(lambda: ssa.forward(h, c, th, x0, keep_ckpt=False, tie_capacity=1 << 20, buffers=b), n_rep)
+            fired = int(b.steps_done.sum().item())
+            row[label + "_forward_steps_per_s"] = fired / dt
+            if sel == W.SELECT_INVERSE_CDF:
+                sample = np.arange(0, B, B // 16)[:16]
+                idx = {int(q): k for k, q in enumerate(sample)}
+                ov = [(idx[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
+                      for t in b.tie_records() if int(t["traj"]) in idx]
+                r = oracle.run(net, c, net.theta0, net.x0, traj_ids=sample, ties=ov)
+                xf = b.x_final.cpu().numpy().reshape(net.n_species, B).T[sample]
+                row["inverse_cdf_counts_bit_exact_sample"] = bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
+        bufs = ssa.forward(h, cfg, th, x0, tie_capacity=0)
+        d_obs = torch.randn(bufs.obs.numel(), dtype=torch.float64, device=dev)
+        d_params = torch.empty(h.param_total, dtype=torch.float32, device=dev)
+
+        def st_step():
+            ssa.forward(h, cfg, th, x0, buffers=bufs, tie_capacity=0)
+            ssa.backward(h, cfg, th, x0, bufs, d_obs, d_params=d_params)
+        dt = timed(st_step, n_rep)
+        row["gumbel_softmax_st_fwdbwd_steps_per_s"] = int(bufs.steps_done.sum().item()) / dt
+        rows.append(row)
+    out = {"metric": METRIC, "study": "selection variants", "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+           "rows": rows}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="dimer",
-                    choices=["dimer", "oscillator", "uneven", "grn", "abc_infer", "coi_infer"],
+                    choices=["dimer", "oscillator", "uneven", "grn", "abc_infer", "coi_infer", "selection"],
                     help="dimer: 2A<->A2, 65,536 x 10,000 steps (default); "
                          "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps; "
                          "uneven: 4,096 random networks x 256 trajectories x 5,000 steps; "
                          "grn: 784->256->10 gene-network classifier, 512 images x 32 trajectories x 2,000 steps; "
                          "abc_infer: rate inference for A+B<->C, 100,000 x 250 steps, 250 captured epochs; "
-                         "coi_infer: ion-channel rate inference, 262,144 x 20 steps, 800 bins, 400 captured epochs")
+                         "coi_infer: ion-channel rate inference, 262,144 x 20 steps, 800 bins, 400 captured epochs; "
+                         "selection: inverse-CDF vs Gumbel-max forward vs Gumbel-Softmax training step (dimer, oscillator)")
     ap.add_argument("--sweep", action="store_true", help="abc_infer: also run the k2 sweep (8 targets)")
     ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
     ap.add_argument("--n-traj", type=int, default=65536)
@@ -515,6 +576,8 @@ def main():
         return bench_grn(args, torch, dev)
     if args.workload in ("abc_infer", "coi_infer"):
         return bench_infer(args, torch, dev)
+    if args.workload == "selection":
+        return bench_selection(args, torch, dev)
 
     if args.copy_bytes:
         n = args.copy_bytes // 4
