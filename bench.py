@@ -100,17 +100,30 @@ def measure_issue_costs():
             "cvt": t[6] - i32, "f64": t[5]}
 
 
-def sources_sha1() -> str:
-    """Digest of the library sources (the profile summaries record the one
-    their counters were taken with)."""
+# Library sources each workload's kernels are built from.
+_SPEC_SOURCES = ["ssa_spec_body.hpp", "ssa_device.hpp", "ssa_plan.hpp", "ssa_jit.cpp", "ssa_jit.hpp",
+                 "ssa_misc.hip", "ssa_misc.hpp", "ssa_api.cpp"]
+WORKLOAD_SOURCES = {
+    "dimer": _SPEC_SOURCES, "oscillator": _SPEC_SOURCES, "abc_infer": _SPEC_SOURCES, "coi_infer": _SPEC_SOURCES,
+    "uneven": ["ssa_wave.hip", "ssa_wave.hpp", "ssa_device.hpp", "ssa_plan.hpp", "ssa_misc.hip", "ssa_misc.hpp",
+               "ssa_api.cpp"],
+    "grn": ["ssa_grn.hip", "ssa_grn.hpp", "ssa_grn_api.cpp", "ssa_device.hpp", "ssa_plan.hpp"],
+}
+
+
+def sources_sha1(workload: str = None) -> str:
+    """Digest of the library sources a workload's kernels are built from (all
+    of them when no workload is named); the profile summaries record the one
+    their counters were taken with."""
     import hashlib
     h = hashlib.sha1()
     d = os.path.join(ROOT, "paper_2602_19775_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    files = WORKLOAD_SOURCES[workload] if workload else [
+        f for f in os.listdir(d) if f.endswith((".hip", ".hpp", ".cpp", ".h"))]
+    for f in sorted(files):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -122,7 +135,7 @@ def profiled_traffic(workload: str, kernel: str):
     d = os.path.join(ROOT, "profiles")
     if not os.path.isdir(d):
         return None
-    sha = sources_sha1()
+    sha = sources_sha1(workload)
     for f in sorted(os.listdir(d)):
         if not f.endswith(".md"):
             continue
