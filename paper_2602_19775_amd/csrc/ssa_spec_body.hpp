@@ -343,20 +343,16 @@ __device__ void forward_run(const RunParams &p)
     if (!valid) return;
     if (spw && (k & (spw - 1)) != 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
     if (bin < n_bins) {
-        // hold the last state up to t_obs
-        double t0 = t;
-        while (bin < n_bins) {
-            const double hi = bin_hi;
+        // hold the last state up to t_obs: the rest of the current bin, then
+        // every later bin, whose average is the last state itself
 #pragma unroll
-            for (int o = 0; o < NO; ++o) {
-                acc[o] += (double)X[NET::OBS[o]] * fmax(fmin(hi, t_obs) - t0, 0.0);
-                if (o < NOBS) obs_lane[((int64_t)bin * NOBS + o) * B] = acc[o] * inv_dt;
-                acc[o] = 0.0;
-            }
-            t0 = fmax(t0, hi);
-            bin += 1;
-            bin_hi = bin < n_bins ? bin_edge(t_obs, bin + 1, n_bins) : INFINITY;
+        for (int o = 0; o < NO; ++o) {
+            acc[o] += (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0);
+            if (o < NOBS) obs_lane[((int64_t)bin * NOBS + o) * B] = acc[o] * inv_dt;
         }
+        for (bin += 1; bin < n_bins; ++bin)
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)bin * NOBS + o) * B] = (double)X[NET::OBS[o]];
     }
     if (p.obs_kind == 0) {
 #pragma unroll
@@ -457,21 +453,28 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
 #pragma unroll
     for (int o = 0; o < NO; ++o) { doi[o] = 0.0; doi32[o] = 0.f; }
     if (valid) {
-        if (bins) {
-            double hi = t_obs;
-            while (rbin > 0 && t < rlo) {
-                rbin -= 1;
-                rlo = rbin > 0 ? bin_edge(t_obs, rbin, n_bins) : -INFINITY;
+        if (bins && t < t_obs) {
+            // the bin holding the last event's time: an estimate, then exact
+            // comparisons with the bin edges themselves
+            const double est = floor(t * (double)n_bins / t_obs);
+            int b = !(est > 0.0) ? 0 : est >= (double)n_bins ? n_bins - 1 : (int)est;
+            while (b > 0 && t < bin_edge(t_obs, b, n_bins)) --b;
+            while (b + 1 < n_bins && t >= bin_edge(t_obs, b + 1, n_bins)) ++b;
+            // later bins average the held final state: their dL/dobs go to it whole
+            for (int bb = n_bins - 1; bb > b; --bb)
 #pragma unroll
-                for (int o = 0; o < NO; ++o) {
-                    doi[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] * inv_dt : 0.0;
-                    doi32[o] = (float)doi[o];
-                }
-                const double seg = hi - fmax(t, rlo);
+                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[((int64_t)bb * NOBS + o) * B];
+            // and the part of bin b after the last event
+            rbin = b;
+            rlo = b > 0 ? bin_edge(t_obs, b, n_bins) : -INFINITY;
+            const double hi = b + 1 < n_bins ? bin_edge(t_obs, b + 1, n_bins) : t_obs;
 #pragma unroll
-                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += doi[o] * seg;
-                hi = rlo;
+            for (int o = 0; o < NO; ++o) {
+                doi[o] = o < NOBS ? dobs_lane[((int64_t)b * NOBS + o) * B] * inv_dt : 0.0;
+                doi32[o] = (float)doi[o];
             }
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += doi[o] * (hi - t);
         } else if (p.obs_kind == 0) {
 #pragma unroll
             for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[(int64_t)o * B];
