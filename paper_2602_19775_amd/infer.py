@@ -94,7 +94,7 @@ class Trainer:
         tf = ssa.forward(ht, self.cfg.replace(purpose=W.PURPOSE_TARGET),
                          torch.tensor(true_net.theta0, device=dev), _x0(true_net, n_target),
                          keep_ckpt=False, tie_capacity=0)
-        self.target = tf.obs[: P_ * O_ * n_target].view(P_, O_, n_target).mean(dim=2).clone()
+        self.target = self.means(tf.obs, n_target).clone()
         del tf, ht
         # model state and schedules (device scalars)
         self.h = ssa.Net([true_net], [n_traj], t_obs=[self.t_obs])
@@ -117,16 +117,24 @@ class Trainer:
                                 d_temperature=self.temp)
         self.graph: Optional[CapturedStep] = None
 
+    def means(self, obs: torch.Tensor, n: int) -> torch.Tensor:
+        """Ensemble means [points][species] of an observation buffer of n
+        trajectories (laid out [point][species][trajectory])."""
+        P_, O = self.n_pts, self.n_obs
+        return obs[: P_ * O * n].view(P_, O, n).mean(dim=2)
+
+    def d_obs_of(self, e: torch.Tensor, out: torch.Tensor):
+        """dL/dobs = 2 (mean - target) / (points * species * B) for every trajectory."""
+        P_, O, B = self.n_pts, self.n_obs, self.B
+        out.view(P_, O, B).copy_((e * (2.0 / (P_ * O * B))).unsqueeze(2).expand(P_, O, B))
+
     def step(self):
         """One optimisation step on the current stream (preallocated tensors only)."""
-        P_, O, B = self.n_pts, self.n_obs, self.B
         ssa.forward(self.h, self.cfg, self.theta, self.x0, buffers=self.bufs, tie_capacity=0,
                     d_epoch=self.epoch, d_temperature=self.temp)
-        o = self.bufs.obs[: P_ * O * B].view(P_, O, B)
-        e = o.mean(dim=2) - self.target
+        e = self.means(self.bufs.obs, self.B) - self.target
         self.loss.copy_(e.square().mean().reshape(1))
-        # dL/dobs = 2 (mean - target) / (points * species * B) for every trajectory
-        self.d_obs.view(P_, O, B).copy_((e * (2.0 / (P_ * O * B))).unsqueeze(2).expand(P_, O, B))
+        self.d_obs_of(e, self.d_obs)
         ssa.backward(self.h, self.cfg, self.theta, self.x0, self.bufs, self.d_obs, d_params=self.d_params)
         g = self.d_params
         self.v.mul_(self.rho).addcmul_(g, g, value=1.0 - self.rho)

@@ -18,8 +18,14 @@ def infer():
     return m
 
 
-def test_captured_step_replays_the_eager_step(infer):
-    tr = infer.dimerization(infer.TRUE_RATES, n_traj=8192, n_target=8192, n_grid=24, epochs=20)
+@pytest.mark.parametrize("system", ["dimerization", "dimerization_benchmarked", "ion_channel"])
+def test_captured_step_replays_the_eager_step(infer, system):
+    if system == "dimerization":
+        tr = infer.dimerization(infer.TRUE_RATES, n_traj=8192, n_target=8192, n_grid=24, epochs=20)
+    elif system == "dimerization_benchmarked":      # the benchmark's batch and grid
+        tr = infer.dimerization(infer.TRUE_RATES, epochs=20)
+    else:
+        tr = infer.ion_channel(n_traj=16384, n_target=16384, n_bins=200, epochs=20)
     ref = []
     for _ in range(4):
         tr.step()
