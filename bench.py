@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SSA steps/sec fwd and fwd+bwd on 1 MI355X; grad rel-err vs FP64 oracle"
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per clock x clock
+HBM_PEAK = 8.0e12                        # MI355X HBM3E, bytes/s
 
 
 def alu_ops_per_step(net, backward: bool, inv_t_is_2=True) -> dict:
@@ -443,11 +444,23 @@ def bench_infer(args, torch, dev):
     inv2 = abs(1.0 / T_end - 2.0) < 1e-12
     ops_f, ops_b = alu_ops_per_step(tr.net, False, inv2), alu_ops_per_step(tr.net, True, inv2)
     dom, dom_ms, ops = ("backward", bwd_ms, ops_b) if bwd_ms >= fwd_ms else ("forward", fwd_ms, ops_f)
-    achieved = fired * slots(ops, cost) / (dom_ms * 1e-3)
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS,
-                "traffic": profiled_traffic(args.workload, dom), "kernel_ms": dom_ms,
-                "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
+    # algorithmic HBM bytes of one launch: the observation buffer (written by
+    # the forward, read back as dL/dobs by the backward), the checkpoints and
+    # tape (written, then read), the per-trajectory state and clock
+    io = bufs.x_final.numel() * 4 * 2 + B * (8 + 4)
+    ck = bufs.ckpt.numel() if bufs.ckpt is not None else 0
+    alg_bytes = G * O * B * 8 + ck + io
+    alu_s = fired * slots(ops, cost) / PEAK_LANE_SLOTS
+    if alg_bytes / HBM_PEAK > alu_s:
+        achieved = alg_bytes / (dom_ms * 1e-3)
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK, "algorithmic_bytes": alg_bytes}
+    else:
+        achieved = fired * slots(ops, cost) / (dom_ms * 1e-3)
+        roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
+                    "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "algorithmic_bytes": alg_bytes}
+    roofline.update({"traffic": profiled_traffic(args.workload, dom), "kernel_ms": dom_ms,
+                     "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS})
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

@@ -350,9 +350,11 @@ __device__ void forward_run(const RunParams &p)
             acc[o] += (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0);
             if (o < NOBS) obs_lane[((int64_t)bin * NOBS + o) * B] = acc[o] * inv_dt;
         }
-        for (bin += 1; bin < n_bins; ++bin)
+        // rows from the top down, so the wave's lanes store the same row
+        // together whatever bin each of them stopped in
+        for (int bb = n_bins - 1; bb > bin; --bb)
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)bin * NOBS + o) * B] = (double)X[NET::OBS[o]];
+            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)bb * NOBS + o) * B] = (double)X[NET::OBS[o]];
     }
     if (p.obs_kind == 0) {
 #pragma unroll
@@ -360,9 +362,9 @@ __device__ void forward_run(const RunParams &p)
     }
     // grid points after the last event hold the last state
     if (grid)
-        for (; gi < n_bins; ++gi)
+        for (int gg = n_bins - 1; gg >= gi; --gg)
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)gi * NOBS + o) * B] = (double)X[NET::OBS[o]];
+            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)gg * NOBS + o) * B] = (double)X[NET::OBS[o]];
 #pragma unroll
     for (int s = 0; s < N; ++s) {
         p.x_final[nd.state_off + s * B + i] = X[s];
