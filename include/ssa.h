@@ -37,8 +37,10 @@
  *   x0 / x_final       int32  [sum N_n*B_n]        (block [N_n][B_n], species-major)
  *   t_final            double [sum B_n]
  *   steps_done         int32  [sum B_n]
- *   obs / d_obs        double [sum W_n*B_n]        (block [W_n][B_n];
- *                       W_n = n_bins*n_obs_n as [bin][obs] for bins, n_obs_n for final counts)
+ *   obs / d_obs        double [sum W_n*B_n]        (block [W_n][B_n], or [B_n][W_n] with
+ *                       SSA_OBS_TRAJ_MAJOR; W_n = n_bins*n_obs_n as [point][obs] for bins
+ *                       and grids, n_obs_n for final counts)
+ *   ensemble means     double [sum W_n]            (ssa_obs_mean; a shared d_obs)
  *   d_params_per_traj  float  [sum P_n*B_n]        (block [P_n][B_n])
  * ssa_net_layout() returns every offset.
  */
@@ -87,6 +89,20 @@ enum { SSA_OBS_FINAL = 0, SSA_OBS_BINS = 1, SSA_OBS_GRID = 2 };
  *                           observations, topology-specialised lane mode only.  It is the
  *                           baseline of the selection-variant throughput comparison. */
 enum { SSA_SELECT_GUMBEL_MAX = 0, SSA_SELECT_INVERSE_CDF = 1 };
+
+/* Memory order of a network's observation block (obs of ssa_forward, d_obs of
+ * ssa_backward):
+ *   SSA_OBS_POINT_MAJOR  [W_n][B_n]: value w of every trajectory is contiguous;
+ *   SSA_OBS_TRAJ_MAJOR   [B_n][W_n]: the W_n values of one trajectory are
+ *                        contiguous.  Every trajectory then writes (and the
+ *                        backward reads) whole cache lines of its own as it
+ *                        crosses bins or grid points at its own pace.
+ *                        Topology-specialised lane mode only (else SSA_ENOTSUP).
+ * A loss of ensemble means (Sec. 4.1, Sec. 4.4) gives every trajectory of a
+ * network the same dL/dobs; with dobs_shared set, ssa_backward reads d_obs as
+ * that one block of W_n values per network (the ssa_obs_mean layout), whatever
+ * obs_layout is.  Topology-specialised lane mode only. */
+enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1 };
 
 /* How ssa_backward obtains the fired channel of each step.
  *   SSA_BWD_TAPE:      ssa_forward stores the fired channel index of every
@@ -151,6 +167,7 @@ typedef struct ssa_net_layout_t {
     int64_t param_offset;
     int64_t obs_offset;            /* for the observation kind and n_bins of the query */
     int64_t ppt_offset;            /* d_params_per_traj */
+    int64_t mean_offset;           /* ensemble means / shared d_obs, same kind and n_bins */
 } ssa_net_layout_t;
 
 /* Run settings shared by forward, backward and step calls.
@@ -173,6 +190,8 @@ typedef struct ssa_config {
                                       backward when it runs (annealing T under graph replay);
                                       it must then hold a finite value > 0.  NULL: temperature */
     int32_t selection;             /* SSA_SELECT_*: how the forward picks the channel */
+    int32_t obs_layout;            /* SSA_OBS_POINT_MAJOR or SSA_OBS_TRAJ_MAJOR */
+    int32_t dobs_shared;           /* nonzero: d_obs holds one dL/dobs block [W_n] per network */
 } ssa_config;
 
 /* One logged step where the selection (kind 0) or the t_end stop decision
@@ -243,6 +262,19 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
 ssa_status ssa_step_batch(const ssa_net *net, const ssa_config *cfg, const float *theta,
                           int32_t *x, double *t, uint32_t step, int32_t *chosen, float *tau,
                           float *a, hipStream_t stream);
+
+/* Ensemble mean of an observation buffer (the statistic the losses of
+ * Sec. 4.1 and Sec. 4.4 compare): mean[mean_offset_n + w] = the average over
+ * the B_n trajectories of network n of value w < W_n, for the obs_kind,
+ * n_bins and obs_layout of cfg.  Each network is summed in FP64 in a fixed
+ * order (chunks of trajectories, then the chunks in index order), so the
+ * result is the same on every call; a network without trajectories gets 0.
+ *   obs: DEVICE, the forward's layout; mean: DEVICE double [sum W_n];
+ *   work: the work buffer of ssa_buffer_sizes for the same cfg (its contents
+ *   are overwritten; do not share it with a concurrent forward or backward).
+ * Enqueues on `stream` only (graph-capturable), any execution mode. */
+ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double *obs, double *mean,
+                        void *work, size_t work_bytes, hipStream_t stream);
 
 /* Sticky device flags raised since the handle was created (bit 0: overflow,
  * bit 1: non-finite propensity or clock).  Synchronises `stream`. */

@@ -88,7 +88,7 @@ struct ssa_net {
     std::vector<Group> groups;
     uint32_t *flags_d = nullptr;
     int64_t traj_total = 0, state_total = 0, param_total = 0, obsb_total = 0, part_total = 0,
-            ppt_total = 0;
+            ppt_total = 0, obsw_total = 0;
     int max_M = 0;
     int64_t max_B = 0;
     int device = 0;
@@ -154,10 +154,30 @@ size_t partials_bytes(const ssa_net *net)
     return align_up(sizeof(double) * (size_t)net->part_total, 256);
 }
 
-size_t work_bytes_for(const ssa_net *net)
+size_t grad_work_bytes(const ssa_net *net)
 {
     return kWorkHeader + partials_bytes(net) +
            align_up(sizeof(double) * (size_t)net->param_total * reduce_chunks(net->max_B), 256);
+}
+
+// values per trajectory of network nd for the observation of cfg
+int64_t obs_width(const NetDev &nd, const ssa_config *cfg)
+{
+    return (int64_t)nd.n_obs * (cfg->obs_kind != SSA_OBS_FINAL ? cfg->n_bins : 1);
+}
+
+// The ensemble-mean chunk sums follow the gradient region of the work buffer.
+size_t mean_work_bytes(const ssa_net *net, const ssa_config *cfg)
+{
+    size_t m = 0;
+    for (const NetDev &nd : net->nets_h)
+        m = std::max(m, sizeof(double) * (size_t)obs_mean_chunks(nd.B) * (size_t)obs_width(nd, cfg));
+    return align_up(m, 256);
+}
+
+size_t work_bytes_for(const ssa_net *net, const ssa_config *cfg)
+{
+    return grad_work_bytes(net) + mean_work_bytes(net, cfg);
 }
 
 ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
@@ -191,6 +211,13 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
     if (mode == SSA_BWD_RECOMPUTE && cfg->ckpt_every > kMaxRecomputeSegment)
         return fail(SSA_EINVAL, "recompute mode needs ckpt_every <= 64");
     if (cfg->tie_capacity < 0) return fail(SSA_EINVAL, "tie_capacity must be >= 0");
+    if (cfg->obs_layout != SSA_OBS_POINT_MAJOR && cfg->obs_layout != SSA_OBS_TRAJ_MAJOR)
+        return fail(SSA_EINVAL, "obs_layout must be SSA_OBS_POINT_MAJOR or SSA_OBS_TRAJ_MAJOR");
+    if (cfg->obs_layout == SSA_OBS_TRAJ_MAJOR || cfg->dobs_shared)
+        for (const auto &gr : net->groups)
+            if (gr.n_items && !gr.spec)
+                return fail(SSA_ENOTSUP, "the trajectory-major layout and a shared d_obs run in the "
+                                         "topology-specialised lane mode only");
     if (cfg->selection != SSA_SELECT_GUMBEL_MAX && cfg->selection != SSA_SELECT_INVERSE_CDF)
         return fail(SSA_EINVAL, "unknown selection");
     if (cfg->selection == SSA_SELECT_INVERSE_CDF) {
@@ -229,6 +256,8 @@ RunParams base_params(const ssa_net *net, const ssa_config *cfg)
     p.temperature = cfg->temperature;
     p.d_temperature = cfg->d_temperature;
     p.selection = cfg->selection;
+    p.obs_tm = cfg->obs_layout == SSA_OBS_TRAJ_MAJOR ? 1 : 0;
+    p.dobs_shared = cfg->dobs_shared ? 1 : 0;
     p.recompute = resolve_bwd_mode(cfg) == SSA_BWD_RECOMPUTE ? 1 : 0;
     p.inc_ptr = net->inc_ptr_d;
     p.chan_inc = net->chan_inc_d;
@@ -428,6 +457,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         nd.state_off = net->state_total;
         nd.param_off = net->param_total;
         nd.obsb_off = net->obsb_total;
+        nd.obsw_off = net->obsw_total;
         nd.part_off = net->part_total;
         nd.ppt_off = net->ppt_total;
         nd.t_obs = d->t_obs ? d->t_obs[n] : 0.0;
@@ -497,6 +527,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         net->state_total += (int64_t)N * B;
         net->param_total += P;
         net->obsb_total += (int64_t)nob * B;
+        net->obsw_total += nob;
         net->part_total += (int64_t)M * B;
         net->ppt_total += (int64_t)P * B;
         net->max_M = std::max(net->max_M, M);
@@ -616,6 +647,7 @@ ssa_status ssa_net_layout(const ssa_net *net, int32_t obs_kind, int32_t n_bins, 
     out->param_offset = nd.param_off;
     out->obs_offset = nd.obsb_off * (obs_kind != SSA_OBS_FINAL ? n_bins : 1);
     out->ppt_offset = nd.ppt_off;
+    out->mean_offset = nd.obsw_off * (obs_kind != SSA_OBS_FINAL ? n_bins : 1);
     return SSA_OK;
 }
 
@@ -625,7 +657,7 @@ ssa_status ssa_buffer_sizes(const ssa_net *net, const ssa_config *cfg, size_t *c
     ssa_status s = check_config(net, cfg);
     if (s != SSA_OK) return s;
     if (ckpt_bytes) *ckpt_bytes = ckpt_layout(net, cfg).bytes;
-    if (work_bytes) *work_bytes = work_bytes_for(net);
+    if (work_bytes) *work_bytes = work_bytes_for(net, cfg);
     return SSA_OK;
 }
 
@@ -640,7 +672,7 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
     if (!theta || !x0 || !x_final || !t_final || !steps_done)
         return fail(SSA_EINVAL, "theta, x0, x_final, t_final and steps_done are required");
     if (net->obsb_total > 0 && !obs) return fail(SSA_EINVAL, "obs is NULL but species are observed");
-    if (!work || work_bytes < work_bytes_for(net)) return fail(SSA_EWORKSPACE, "work buffer too small");
+    if (!work || work_bytes < work_bytes_for(net, cfg)) return fail(SSA_EWORKSPACE, "work buffer too small");
     if ((ties == nullptr) != (n_ties == nullptr)) return fail(SSA_EINVAL, "ties and n_ties go together");
     const CkptLayout L = ckpt_layout(net, cfg);
     if (ckpt && ckpt_bytes < L.bytes) return fail(SSA_EWORKSPACE, "checkpoint buffer too small");
@@ -689,7 +721,7 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
     const CkptLayout L = ckpt_layout(net, cfg);
     if (L.bytes == 0) return fail(SSA_EINVAL, "the backward needs a bounded n_steps");
     if (!ckpt || ckpt_bytes < L.bytes) return fail(SSA_EWORKSPACE, "checkpoint buffer too small");
-    if (!work || work_bytes < work_bytes_for(net)) return fail(SSA_EWORKSPACE, "work buffer too small");
+    if (!work || work_bytes < work_bytes_for(net, cfg)) return fail(SSA_EWORKSPACE, "work buffer too small");
 
     RunParams p = base_params(net, cfg);
     p.theta = theta;
@@ -714,6 +746,27 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
                                         net->param_total, net->max_B, p.partials, chunk_sums, d_params,
                                         d_params_per_traj, stream);
     if (e != hipSuccess) return hip_fail(e, "gradient reduction");
+    return SSA_OK;
+}
+
+ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double *obs, double *mean,
+                        void *work, size_t work_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    ssa_status s = check_config(net, cfg);
+    if (s != SSA_OK) return s;
+    if (net->obsw_total > 0 && (!obs || !mean)) return fail(SSA_EINVAL, "obs and mean are required");
+    if (!work || work_bytes < work_bytes_for(net, cfg)) return fail(SSA_EWORKSPACE, "work buffer too small");
+    double *sums = (double *)((char *)work + grad_work_bytes(net));
+    const int64_t npts = cfg->obs_kind != SSA_OBS_FINAL ? cfg->n_bins : 1;
+    for (const NetDev &nd : net->nets_h) {
+        const int64_t W = obs_width(nd, cfg);
+        if (W == 0) continue;
+        hipError_t e = launch_obs_mean(obs + nd.obsb_off * npts, nd.B, W,
+                                       cfg->obs_layout == SSA_OBS_TRAJ_MAJOR, sums,
+                                       mean + nd.obsw_off * npts, stream);
+        if (e != hipSuccess) return hip_fail(e, "ensemble mean");
+    }
     return SSA_OK;
 }
 

@@ -38,6 +38,8 @@ ssa_status check_cfg(const ssa_grn *g, const ssa_config *cfg)
     if (!(cfg->t_end > 0.0)) return fail(SSA_EINVAL, "t_end must be > 0");
     if (cfg->t_end != INFINITY) return fail(SSA_ENOTSUP, "GRN runs stop after n_steps only (t_end must be INFINITY)");
     if (cfg->obs_kind != SSA_OBS_FINAL) return fail(SSA_ENOTSUP, "GRN runs observe the final output counts only");
+    if (cfg->obs_layout != SSA_OBS_POINT_MAJOR || cfg->dobs_shared)
+        return fail(SSA_ENOTSUP, "GRN runs use the point-major observation layout");
     if (!(cfg->temperature > 0.f) || !std::isfinite(cfg->temperature))
         return fail(SSA_EINVAL, "temperature must be finite and > 0");
     if (cfg->tie_capacity < 0) return fail(SSA_EINVAL, "tie_capacity must be >= 0");

@@ -137,6 +137,60 @@ __global__ __launch_bounds__(256) void reduce_total_kernel(const NetDev *nets, c
     d_params[pg] = (float)acc;
 }
 
+// Ensemble means.  Pass 1, trajectory-major blocks [B][W]: thread w of a
+// block walks the trajectories of one chunk in order (eight interleaved
+// accumulators, combined in a fixed tree), so a wave reads contiguous values.
+__global__ __launch_bounds__(64) void mean_sums_tm_kernel(const double *obs, int64_t B, int64_t W, int64_t len,
+                                                          double *sums)
+{
+    const int64_t c = blockIdx.x;
+    const int64_t lo = c * len, hi = min(B, lo + len);
+    for (int64_t w = (int64_t)blockIdx.y * 64 + threadIdx.x; w < W; w += (int64_t)gridDim.y * 64) {
+        const double *q = obs + lo * W + w;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int64_t i = lo;
+        for (; i + 8 <= hi; i += 8, q += 8 * W)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) a[r] += q[r * W];
+        for (int r = 0; i < hi; ++i, ++r, q += W) a[r] += q[0];
+        sums[c * W + w] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+}
+
+// Pass 1, point-major blocks [W][B]: one row w per block iteration, the
+// threads stride over the chunk's trajectories, then a fixed LDS tree.
+__global__ __launch_bounds__(256) void mean_sums_pm_kernel(const double *obs, int64_t B, int64_t W, int64_t len,
+                                                           double *sums)
+{
+    __shared__ double red[256];
+    const int64_t c = blockIdx.x;
+    const int64_t lo = c * len, hi = min(B, lo + len);
+    for (int64_t w = blockIdx.y; w < W; w += gridDim.y) {
+        const double *q = obs + w * B;
+        double a = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) a += q[i];
+        red[threadIdx.x] = a;
+        __syncthreads();
+        for (int k = 128; k > 0; k >>= 1) {
+            if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) sums[c * W + w] = red[0];
+        __syncthreads();
+    }
+}
+
+// Pass 2: the chunk sums of each value in chunk order, divided by B.
+__global__ __launch_bounds__(256) void mean_total_kernel(const double *sums, int nc, int64_t W, int64_t B,
+                                                         double *mean)
+{
+    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (w >= W) return;
+    double a = 0.0;
+    for (int c = 0; c < nc; ++c) a += sums[(int64_t)c * W + w];
+    mean[w] = B > 0 ? a / (double)B : 0.0;
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,6 +251,44 @@ hipError_t launch_reduce_params(const NetDev *nets, const int32_t *pmap_off, con
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_total_kernel, dim3((unsigned)((param_total + 255) / 256)), dim3(256), 0, stream,
                        nets, param_net, param_total, nc, chunk_sums, d_params);
+    return hipGetLastError();
+}
+
+// Trajectories per chunk: a multiple of 64, about 256 chunks for large B.
+static int64_t obs_mean_chunk_len(int64_t B)
+{
+    constexpr int64_t kMeanSplit = 256;
+    const int64_t c = (B + kMeanSplit - 1) / kMeanSplit;
+    return std::max<int64_t>(64, (c + 63) / 64 * 64);
+}
+
+int obs_mean_chunks(int64_t B)
+{
+    if (B <= 0) return 0;
+    const int64_t len = obs_mean_chunk_len(B);
+    return (int)((B + len - 1) / len);
+}
+
+hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_major, double *sums,
+                           double *mean, hipStream_t stream)
+{
+    if (W <= 0) return hipSuccess;
+    const int nc = obs_mean_chunks(B);
+    const int64_t len = obs_mean_chunk_len(B);
+    if (nc > 0) {
+        if (traj_major) {
+            const unsigned gy = (unsigned)std::min<int64_t>((W + 63) / 64, 65535);
+            hipLaunchKernelGGL(mean_sums_tm_kernel, dim3((unsigned)nc, gy), dim3(64), 0, stream, obs, B, W, len,
+                               sums);
+        } else {
+            const unsigned gy = (unsigned)std::min<int64_t>(W, 65535);
+            hipLaunchKernelGGL(mean_sums_pm_kernel, dim3((unsigned)nc, gy), dim3(256), 0, stream, obs, B, W, len,
+                               sums);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(mean_total_kernel, dim3(grid_for(W, 256)), dim3(256), 0, stream, sums, nc, W, B, mean);
     return hipGetLastError();
 }
 

@@ -17,6 +17,13 @@ hipError_t launch_reduce_params(const NetDev *nets, const int32_t *pmap_off, con
                                 const int32_t *param_net, int64_t param_total, int64_t max_traj,
                                 const double *partials, double *chunk_sums, float *d_params, float *d_ppt,
                                 hipStream_t stream);
+// Ensemble mean of one network's observation block (B trajectories, W values
+// each; traj_major: [B][W], else [W][B]): FP64 sums over chunks of
+// obs_mean_chunks(B) trajectories, then over the chunks in index order, into
+// mean[W].  sums holds obs_mean_chunks(B) * W doubles.
+int obs_mean_chunks(int64_t B);
+hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_major, double *sums,
+                           double *mean, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_selftest_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t stream);
 hipError_t launch_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream);

@@ -52,6 +52,8 @@ struct NetDev {
     int64_t obsb_off;    // sum of n_obs*B (times n_bins for bin observations)
     int64_t part_off;    // sum of M*B (per-channel gradient partials)
     int64_t ppt_off;     // sum of P*B (per-trajectory parameter gradients)
+    int64_t obsw_off;    // sum of n_obs (times n_bins for bin and grid observations):
+                         // ensemble means and a shared dL/dobs
     double t_obs;
 };
 
@@ -129,6 +131,8 @@ struct RunParams {
     const float *d_temperature;   // when set, the temperature is read here on the device
     int32_t selection;            // 0 Gumbel-max race, 1 inverse CDF (forward only)
     int32_t recompute;      // backward: recover choices by re-running segments
+    int32_t obs_tm;         // obs / d_obs blocks are [trajectory][point][obs]
+    int32_t dobs_shared;    // d_obs is one [point][obs] block per network
 
     // wave mode: species -> range of incidence slots, and per channel the
     // slots of its (role 1, role 2) contributions: pos1 | pos2 << 16 with

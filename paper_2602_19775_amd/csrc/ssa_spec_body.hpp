@@ -172,7 +172,10 @@ __device__ void forward_run(const RunParams &p)
     double acc[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) acc[o] = 0.0;
-    double *obs_lane = p.obs + nd.obsb_off * (p.obs_kind != 0 ? n_bins : 1) + i;
+    // observation block [point][obs][B], or [B][point][obs] trajectory-major
+    const int64_t npts = p.obs_kind != 0 ? n_bins : 1;
+    const int64_t orow = p.obs_tm ? (int64_t)NOBS : (int64_t)NOBS * B, ocol = p.obs_tm ? 1 : B;
+    double *obs_lane = p.obs + nd.obsb_off * npts + (p.obs_tm ? i * npts * NOBS : i);
     // grid observation: next grid point gi, at time grid_t >= t
     int gi = 0;
     double grid_t = grid ? 0.0 : INFINITY;
@@ -298,7 +301,7 @@ __device__ void forward_run(const RunParams &p)
 #pragma unroll
                     for (int o = 0; o < NO; ++o) {
                         acc[o] += (double)X[NET::OBS[o]] * fmax(hi - t0, 0.0);
-                        if (o < NOBS) obs_lane[((int64_t)bin * NOBS + o) * B] = acc[o] * inv_dt;
+                        if (o < NOBS) obs_lane[bin * orow + o * ocol] = acc[o] * inv_dt;
                         acc[o] = 0.0;
                     }
                     t0 = fmax(t0, hi);
@@ -313,7 +316,7 @@ __device__ void forward_run(const RunParams &p)
                     const double f = (grid_t - t) * inv_tau;
 #pragma unroll
                     for (int o = 0; o < NOBS; ++o)
-                        obs_lane[((int64_t)gi * NOBS + o) * B] =
+                        obs_lane[gi * orow + o * ocol] =
                             (double)X[NET::OBS[o]] + f * (double)delta_of<NET>(j1, NET::OBS[o]);
                     gi += 1;
                     grid_t = gi < n_bins ? grid_time(t_obs, gi, n_bins) : INFINITY;
@@ -348,23 +351,23 @@ __device__ void forward_run(const RunParams &p)
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
             acc[o] += (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0);
-            if (o < NOBS) obs_lane[((int64_t)bin * NOBS + o) * B] = acc[o] * inv_dt;
+            if (o < NOBS) obs_lane[bin * orow + o * ocol] = acc[o] * inv_dt;
         }
         // rows from the top down, so the wave's lanes store the same row
         // together whatever bin each of them stopped in
         for (int bb = n_bins - 1; bb > bin; --bb)
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)bb * NOBS + o) * B] = (double)X[NET::OBS[o]];
+            for (int o = 0; o < NOBS; ++o) obs_lane[bb * orow + o * ocol] = (double)X[NET::OBS[o]];
     }
     if (p.obs_kind == 0) {
 #pragma unroll
-        for (int o = 0; o < NOBS; ++o) obs_lane[(int64_t)o * B] = (double)X[NET::OBS[o]];
+        for (int o = 0; o < NOBS; ++o) obs_lane[o * ocol] = (double)X[NET::OBS[o]];
     }
     // grid points after the last event hold the last state
     if (grid)
         for (int gg = n_bins - 1; gg >= gi; --gg)
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) obs_lane[((int64_t)gg * NOBS + o) * B] = (double)X[NET::OBS[o]];
+            for (int o = 0; o < NOBS; ++o) obs_lane[gg * orow + o * ocol] = (double)X[NET::OBS[o]];
 #pragma unroll
     for (int s = 0; s < N; ++s) {
         p.x_final[nd.state_off + s * B + i] = X[s];
@@ -434,7 +437,13 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     const int n_bins = p.n_bins;
     const double t_obs = nd.t_obs;
     const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
-    const double *dobs_lane = p.d_obs + nd.obsb_off * (p.obs_kind != 0 ? n_bins : 1) + i;
+    // dL/dobs in the observation layout, or one block per network shared by
+    // its trajectories
+    const int64_t npts = p.obs_kind != 0 ? n_bins : 1;
+    const bool dtm = p.obs_tm || p.dobs_shared;
+    const int64_t drow = dtm ? (int64_t)NOBS : (int64_t)NOBS * B, dcol = dtm ? 1 : B;
+    const double *dobs_lane = p.d_obs + (p.dobs_shared ? nd.obsw_off * npts
+                                                      : nd.obsb_off * npts + (p.obs_tm ? i * npts * NOBS : i));
 
     // adjoint of the state: FP64 accumulator, FP32 increments folded every kFold steps
     double lam[N];
@@ -465,21 +474,21 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
             // later bins average the held final state: their dL/dobs go to it whole
             for (int bb = n_bins - 1; bb > b; --bb)
 #pragma unroll
-                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[((int64_t)bb * NOBS + o) * B];
+                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[bb * drow + o * dcol];
             // and the part of bin b after the last event
             rbin = b;
             rlo = b > 0 ? bin_edge(t_obs, b, n_bins) : -INFINITY;
             const double hi = b + 1 < n_bins ? bin_edge(t_obs, b + 1, n_bins) : t_obs;
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
-                doi[o] = o < NOBS ? dobs_lane[((int64_t)b * NOBS + o) * B] * inv_dt : 0.0;
+                doi[o] = o < NOBS ? dobs_lane[b * drow + o * dcol] * inv_dt : 0.0;
                 doi32[o] = (float)doi[o];
             }
 #pragma unroll
             for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += doi[o] * (hi - t);
         } else if (p.obs_kind == 0) {
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[(int64_t)o * B];
+            for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[o * dcol];
         }
     }
     // grid observation: the points at or after the last event see the final
@@ -500,12 +509,12 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
             while (gh < n_bins && grid_time(t_obs, gh, n_bins) < t) ++gh;
             for (int g = gh; g < n_bins; ++g)
 #pragma unroll
-                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[((int64_t)g * NOBS + o) * B];
+                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[g * drow + o * dcol];
         }
         glo = gh > 0 ? grid_time(t_obs, gh - 1, n_bins) : -INFINITY;
         if (gh > 0)
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) gd[o] = dobs_lane[((int64_t)(gh - 1) * NOBS + o) * B];
+            for (int o = 0; o < NOBS; ++o) gd[o] = dobs_lane[(gh - 1) * drow + o * dcol];
     }
 #pragma unroll
     for (int s = 0; s < N; ++s) lam32[s] = (float)lam[s];
@@ -602,7 +611,7 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                         glo = gh > 0 ? grid_time(t_obs, gh - 1, n_bins) : -INFINITY;
                         if (gh > 0)
     #pragma unroll
-                            for (int o = 0; o < NOBS; ++o) gd[o] = dobs_lane[((int64_t)(gh - 1) * NOBS + o) * B];
+                            for (int o = 0; o < NOBS; ++o) gd[o] = dobs_lane[(gh - 1) * drow + o * dcol];
                     }
                 }
                 // soft sample y~ in ratio form: y~_q ~ (r_j / r_q)^(1/T) with j
@@ -676,7 +685,7 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                         rlo = rbin > 0 ? bin_edge(t_obs, rbin, n_bins) : -INFINITY;
     #pragma unroll
                         for (int o = 0; o < NO; ++o) {
-                            doi[o] = o < NOBS ? dobs_lane[((int64_t)rbin * NOBS + o) * B] * inv_dt : 0.0;
+                            doi[o] = o < NOBS ? dobs_lane[rbin * drow + o * dcol] * inv_dt : 0.0;
                             doi32[o] = (float)doi[o];
                         }
                     }

@@ -14,6 +14,10 @@
   0.001 for the dimerisation, 0.05 to 0.0005 for the channel), the learning
   rate geometrically as well (the channel's in proportion to the
   temperature, Sec. 4.4).
+- **Layout.** The runs write each trajectory's observation contiguously
+  (trajectory-major), the library reduces it to the ensemble means, and the
+  backward reads the loss gradient as one block shared by all trajectories
+  (every trajectory's dL/dobs is the same for a loss of ensemble means).
 - **Graph.** One optimisation step is captured once into a HIP graph and
   replayed per epoch. The step is: forward, loss gradient, backward, RMSprop
   update, schedule update and epoch count. The epoch, the temperature and the
@@ -87,14 +91,14 @@ class Trainer:
         self.epochs = epochs
         self.n_pts = cfg.n_bins if cfg.obs_kind != W.OBS_FINAL else 1
         self.n_obs, self.B = len(true_net.obs_species), n_traj
-        self.cfg = cfg.replace(temperature=t0)
+        self.cfg = cfg.replace(temperature=t0, obs_layout=W.OBS_TRAJ_MAJOR, dobs_shared=True)
         P_, O_ = self.n_pts, self.n_obs
         # target ensemble means
         ht = ssa.Net([true_net], [n_target], t_obs=[self.t_obs])
         tf = ssa.forward(ht, self.cfg.replace(purpose=W.PURPOSE_TARGET),
                          torch.tensor(true_net.theta0, device=dev), _x0(true_net, n_target),
                          keep_ckpt=False, tie_capacity=0)
-        self.target = self.means(tf.obs, n_target).clone()
+        self.target = ssa.obs_mean(ht, tf).view(P_, O_).clone()
         del tf, ht
         # model state and schedules (device scalars)
         self.h = ssa.Net([true_net], [n_traj], t_obs=[self.t_obs])
@@ -111,28 +115,28 @@ class Trainer:
         self.r_lr = self.r_temp if lr1 is None else (lr1 / lr0) ** (1.0 / n1)
         self.rho, self.eps = rho, eps
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.d_obs = torch.zeros(P_ * O_ * n_traj, dtype=torch.float64, device=dev)
+        self.d_obs = torch.zeros(P_ * O_, dtype=torch.float64, device=dev)      # shared by the trajectories
+        self.mean = torch.zeros(P_ * O_, dtype=torch.float64, device=dev)
         self.d_params = torch.zeros(self.h.param_total, dtype=torch.float32, device=dev)
         self.bufs = ssa.forward(self.h, self.cfg, self.theta, self.x0, tie_capacity=0, d_epoch=self.epoch,
                                 d_temperature=self.temp)
         self.graph: Optional[CapturedStep] = None
 
-    def means(self, obs: torch.Tensor, n: int) -> torch.Tensor:
-        """Ensemble means [points][species] of an observation buffer of n
-        trajectories (laid out [point][species][trajectory])."""
-        P_, O = self.n_pts, self.n_obs
-        return obs[: P_ * O * n].view(P_, O, n).mean(dim=2)
+    def means(self, fwd=None) -> torch.Tensor:
+        """Ensemble means [points][species] of the model forward's observation."""
+        ssa.obs_mean(self.h, self.bufs if fwd is None else fwd, out=self.mean)
+        return self.mean.view(self.n_pts, self.n_obs)
 
     def d_obs_of(self, e: torch.Tensor, out: torch.Tensor):
-        """dL/dobs = 2 (mean - target) / (points * species * B) for every trajectory."""
-        P_, O, B = self.n_pts, self.n_obs, self.B
-        out.view(P_, O, B).copy_((e * (2.0 / (P_ * O * B))).unsqueeze(2).expand(P_, O, B))
+        """dL/dobs = 2 (mean - target) / (points * species * B), the same for
+        every trajectory: one shared block [points][species]."""
+        torch.mul(e.reshape(-1), 2.0 / (self.n_pts * self.n_obs * self.B), out=out)
 
     def step(self):
         """One optimisation step on the current stream (preallocated tensors only)."""
         ssa.forward(self.h, self.cfg, self.theta, self.x0, buffers=self.bufs, tie_capacity=0,
                     d_epoch=self.epoch, d_temperature=self.temp)
-        e = self.means(self.bufs.obs, self.B) - self.target
+        e = self.means() - self.target
         self.loss.copy_(e.square().mean().reshape(1))
         self.d_obs_of(e, self.d_obs)
         ssa.backward(self.h, self.cfg, self.theta, self.x0, self.bufs, self.d_obs, d_params=self.d_params)

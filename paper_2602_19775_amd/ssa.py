@@ -41,7 +41,7 @@ class _Desc(C.Structure):
 
 class _Layout(C.Structure):
     _fields_ = [("traj_offset", C.c_int64), ("state_offset", C.c_int64), ("param_offset", C.c_int64),
-                ("obs_offset", C.c_int64), ("ppt_offset", C.c_int64)]
+                ("obs_offset", C.c_int64), ("ppt_offset", C.c_int64), ("mean_offset", C.c_int64)]
 
 
 class _Cfg(C.Structure):
@@ -49,7 +49,8 @@ class _Cfg(C.Structure):
                 ("d_epoch", C.c_void_p), ("traj_ids", C.c_void_p), ("n_steps", C.c_int32),
                 ("t_end", C.c_double), ("obs_kind", C.c_int32), ("n_bins", C.c_int32),
                 ("temperature", C.c_float), ("ckpt_every", C.c_int32), ("bwd_mode", C.c_int32),
-                ("tie_capacity", C.c_int32), ("d_temperature", C.c_void_p), ("selection", C.c_int32)]
+                ("tie_capacity", C.c_int32), ("d_temperature", C.c_void_p), ("selection", C.c_int32),
+                ("obs_layout", C.c_int32), ("dobs_shared", C.c_int32)]
 
 
 TIE_DTYPE = np.dtype([("traj", np.uint32), ("step", np.uint32), ("chosen", np.int32),
@@ -64,7 +65,7 @@ EXPORTS = ["ssa_config_default", "ssa_net_create", "ssa_net_destroy", "ssa_net_s
            "ssa_buffer_sizes", "ssa_forward", "ssa_backward", "ssa_step_batch", "ssa_device_status",
            "ssa_status_string", "ssa_last_error", "ssa_selftest_philox", "ssa_selftest_neglog",
            "ssa_grn_create", "ssa_grn_destroy", "ssa_grn_buffer_sizes", "ssa_grn_forward",
-           "ssa_grn_backward", "ssa_grn_device_status"]
+           "ssa_grn_backward", "ssa_grn_device_status", "ssa_obs_mean"]
 
 
 def lib():
@@ -86,6 +87,7 @@ def lib():
         L.ssa_backward.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, C.c_size_t, V, V, V, V,
                                    C.c_size_t, V]
         L.ssa_step_batch.argtypes = [V, C.POINTER(_Cfg), V, V, V, C.c_uint32, V, V, V, V]
+        L.ssa_obs_mean.argtypes = [V, C.POINTER(_Cfg), V, V, V, C.c_size_t, V]
         L.ssa_device_status.argtypes = [V, V, C.POINTER(C.c_uint32)]
         L.ssa_status_string.argtypes = [C.c_int]
         L.ssa_status_string.restype = C.c_char_p
@@ -169,6 +171,11 @@ class Net:
         per = sum(len(o) * b for o, b in zip(self.obs_species, self.n_traj))
         return per * (n_bins if obs_kind in (W.OBS_BINS, W.OBS_GRID) else 1)
 
+    def mean_total(self, obs_kind: int, n_bins: int) -> int:
+        """Length of the ensemble-mean buffer (and of a shared d_obs)."""
+        per = sum(len(o) for o in self.obs_species)
+        return per * (n_bins if obs_kind in (W.OBS_BINS, W.OBS_GRID) else 1)
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and _lib is not None:
@@ -184,7 +191,7 @@ def make_cfg(cfg: W.RunConfig, tie_capacity: int = 0, bwd_mode: str = "auto",
                 _ptr(traj_ids), n_steps, float(cfg.t_end), int(cfg.obs_kind),
                 int(cfg.n_bins if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID) else 0), float(cfg.temperature),
                 int(cfg.ckpt_every), _BWD[bwd_mode], int(tie_capacity), _ptr(d_temperature),
-                int(getattr(cfg, "selection", W.SELECT_GUMBEL_MAX)))
+                int(cfg.selection), int(cfg.obs_layout), int(bool(cfg.dobs_shared)))
 
 
 @dataclass
@@ -274,6 +281,24 @@ def backward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, 
                             fwd.work.numel(), _stream(stream))
     _check(rc, "ssa_backward")
     return (d_params, ppt) if per_traj else d_params
+
+
+def obs_mean(net: Net, fwd: Forward, out: Optional[torch.Tensor] = None, obs: Optional[torch.Tensor] = None,
+             stream=None) -> torch.Tensor:
+    """Runs ssa_obs_mean on the observation of a forward (or on `obs`, laid
+    out as that forward's observation): the ensemble means of every network,
+    float64 [mean_total].  Uses the forward's work buffer."""
+    c = fwd.ccfg
+    obs = fwd.obs if obs is None else obs
+    assert obs.dtype == torch.float64 and obs.is_cuda and obs.is_contiguous()
+    n = max(net.mean_total(c.obs_kind, c.n_bins), 1)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=obs.device)
+    assert out.dtype == torch.float64 and out.numel() >= n and out.is_contiguous()
+    rc = lib().ssa_obs_mean(net.handle, C.byref(c), _ptr(obs), _ptr(out), _ptr(fwd.work), fwd.work.numel(),
+                            _stream(stream))
+    _check(rc, "ssa_obs_mean")
+    return out
 
 
 def step_batch(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x: torch.Tensor, t: torch.Tensor,

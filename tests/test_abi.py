@@ -47,6 +47,7 @@ def test_status_strings_and_defaults(L):
     assert cfg.n_steps == 2 ** 31 - 1 and math.isinf(cfg.t_end) and cfg.ckpt_every == 256
     assert abs(cfg.temperature - 0.5) < 1e-7
     assert cfg.d_temperature is None and cfg.d_epoch is None and cfg.selection == 0
+    assert cfg.obs_layout == 0 and cfg.dobs_shared == 0
 
 
 def test_host_side_argument_errors(L):

@@ -1,0 +1,154 @@
+"""The trajectory-major observation layout, the shared dL/dobs of a loss of
+ensemble means (Sec. 4.1, Sec. 4.4) and the library's ensemble mean, through
+the C ABI.
+
+- Forward and backward in the trajectory-major layout against the FP64 oracle
+  with the same bars as the point-major parity tests, and bit for bit against
+  the point-major run of the same seeds (the layout moves values, it changes
+  no arithmetic).
+- A shared dL/dobs block against the oracle fed that block for every
+  trajectory, and bit for bit against the point-major backward given the
+  block broadcast over the trajectories.
+- ssa_obs_mean on observation values the oracle produced, in both layouts,
+  against numpy's FP64 mean; fixed summation order (repeat calls agree bit for
+  bit); ragged trajectory counts, several networks, a network without
+  trajectories."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_19775_amd import workloads as W
+
+from test_gpu_parity import _x0, assert_forward_parity, assert_grad_parity, edge_safe, run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_19775_amd import ssa as m
+    m.lib()
+    return m
+
+
+CASES = {
+    # A + B <-> C on a 24-point grid (the inference's observation), ragged batch
+    "abc_grid": (lambda: W.dimerization_abc(),
+                 W.RunConfig(seed=5, n_steps=250, obs_kind=W.OBS_GRID, n_bins=24, t_obs=4.5, temperature=0.5,
+                             ckpt_every=64), 3000),
+    # the ion channel's bin averages: most bins follow the absorbing state
+    "channel_bins": (lambda: W.ion_channel_coi(n_channels=3),
+                     W.RunConfig(seed=6, n_steps=20, obs_kind=W.OBS_BINS, n_bins=60, t_obs=8.0, temperature=0.2,
+                                 ckpt_every=8), 2500),
+    # final counts of the dimerisation
+    "dimer_final": (lambda: W.dimerization_2a(),
+                    W.RunConfig(seed=7, n_steps=300, obs_kind=W.OBS_FINAL, temperature=0.5, ckpt_every=64), 1000),
+}
+
+
+def _d_obs(cfg, nob, B, seed, shared):
+    g = np.random.default_rng(seed)
+    npts = cfg.n_bins if cfg.obs_kind != W.OBS_FINAL else 1
+    if shared:
+        v = g.normal(size=(npts, nob, 1))
+        d = np.repeat(v, B, axis=2)
+    else:
+        d = g.normal(size=(npts, nob, B))
+    return d if cfg.obs_kind != W.OBS_FINAL else d[0]
+
+
+def _parity(gpu, r, ids, cfg):
+    assert_forward_parity(gpu, r, ids, cfg)
+    keep = edge_safe(gpu, r, ids)
+    assert keep.mean() > 0.5
+    for k in np.flatnonzero(keep):
+        assert_grad_parity(gpu["ppt"][ids[k]], r.grad[k], rtol=1e-5)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("shared", [False, True], ids=["per_traj_dobs", "shared_dobs"])
+def test_traj_major_parity(ssa, case, shared):
+    mk, cfg, B = CASES[case]
+    net = mk()
+    nob = len(net.obs_species)
+    d_obs = _d_obs(cfg, nob, B, 11, shared)
+    g = np.random.default_rng(3)
+    sample = np.unique(np.concatenate([[0, 63, 64, B - 1], g.choice(B, 36, replace=False)]))
+    tm_cfg = cfg.replace(obs_layout=W.OBS_TRAJ_MAJOR, dobs_shared=shared)
+    gpu, r, ids, _ = run_pair(ssa, net, tm_cfg, B, d_obs=d_obs, bwd_mode="tape", sample=sample)
+    _parity(gpu, r, ids, tm_cfg)
+    # the point-major run of the same seeds with the per-trajectory d_obs
+    ref, _, _, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode="tape", sample=sample[:2])
+    assert np.array_equal(gpu["obs"], ref["obs"])
+    assert np.array_equal(gpu["x_final"], ref["x_final"])
+    assert np.array_equal(gpu["ppt"], ref["ppt"])
+    assert np.array_equal(gpu["d_params"], ref["d_params"])
+
+
+def test_layout_needs_the_specialised_mode(ssa):
+    net = W.dimerization_abc()
+    B = 64
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = _x0([net], [B])
+    for mode in ("lane", "wave"):
+        h = ssa.Net([net], [B], t_obs=[4.0], exec_mode=mode)
+        for kw in ({"obs_layout": W.OBS_TRAJ_MAJOR}, {"dobs_shared": True}):
+            cfg = W.RunConfig(seed=1, n_steps=10, obs_kind=W.OBS_BINS, n_bins=4, t_obs=4.0, **kw)
+            with pytest.raises(ssa.SSAError, match="specialised"):
+                ssa.forward(h, cfg, th, x0)
+
+
+def _oracle_obs(net, cfg, B, seed):
+    """Per-trajectory observations of B trajectories from the oracle: [B][W]."""
+    r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(B))
+    o = np.asarray(r.obs, np.float64)
+    return o.reshape(B, -1)
+
+
+@pytest.mark.parametrize("layout", [W.OBS_POINT_MAJOR, W.OBS_TRAJ_MAJOR], ids=["point_major", "traj_major"])
+def test_obs_mean_of_oracle_values(ssa, layout):
+    """Three networks (ragged trajectory counts, the last with none), the
+    oracle's bin averages uploaded in the layout under test; the means match
+    numpy's to 1e-13, and the empty network's are 0."""
+    nets = [W.ion_channel_coi(n_channels=3), W.dimerization_abc(), W.dimerization_2a()]
+    Bs = [1000, 333, 0]
+    cfg = W.RunConfig(seed=2, n_steps=30, obs_kind=W.OBS_BINS, n_bins=17, t_obs=6.0, obs_layout=layout)
+    h = ssa.Net(nets, Bs, t_obs=[6.0, 6.0, 6.0])
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    x0 = _x0(nets, Bs)
+    fwd = ssa.forward(h, cfg, th, x0, keep_ckpt=False, tie_capacity=0)
+    blocks, expect = [], []
+    for k, (net, B) in enumerate(zip(nets[:2], Bs[:2])):
+        v = _oracle_obs(net, cfg.replace(obs_layout=0), B, k)        # [B][W]
+        expect.append(v.mean(axis=0))
+        blocks.append(v if layout == W.OBS_TRAJ_MAJOR else v.T)
+    obs = torch.tensor(np.concatenate([b.reshape(-1) for b in blocks]), device="cuda")
+    m1 = ssa.obs_mean(h, fwd, obs=obs).cpu().numpy()
+    m2 = ssa.obs_mean(h, fwd, obs=obs).cpu().numpy()
+    assert np.array_equal(m1, m2)
+    for k in range(len(expect)):
+        off = h.layout(k, cfg.obs_kind, cfg.n_bins).mean_offset
+        got = m1[off: off + expect[k].size]
+        assert np.allclose(got, expect[k], rtol=1e-13, atol=1e-13 * np.abs(expect[k]).max())
+    off = h.layout(2, cfg.obs_kind, cfg.n_bins).mean_offset
+    assert off + cfg.n_bins == m1.size and np.all(m1[off:] == 0.0)
+
+
+@pytest.mark.parametrize("layout", [W.OBS_POINT_MAJOR, W.OBS_TRAJ_MAJOR], ids=["point_major", "traj_major"])
+def test_obs_mean_large_ragged(ssa, layout):
+    """Many chunks and a ragged tail: 100,003 trajectories x 37 values of
+    seeded data, against numpy's FP64 mean."""
+    net = W.dimerization_abc()
+    B, nb = 100_003, 37
+    cfg = W.RunConfig(seed=0, n_steps=1, obs_kind=W.OBS_BINS, n_bins=nb, t_obs=1.0, obs_layout=layout)
+    h = ssa.Net([net], [B], t_obs=[1.0], obs_species=[[0]])
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = _x0([net], [B])
+    fwd = ssa.forward(h, cfg, th, x0, keep_ckpt=False, tie_capacity=0)
+    v = np.random.default_rng(8).normal(loc=3.0, size=(B, nb))
+    host = v if layout == W.OBS_TRAJ_MAJOR else v.T
+    m = ssa.obs_mean(h, fwd, obs=torch.tensor(np.ascontiguousarray(host).reshape(-1), device="cuda"))
+    assert np.allclose(m.cpu().numpy(), v.mean(axis=0), rtol=1e-13, atol=1e-13)

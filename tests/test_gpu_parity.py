@@ -53,7 +53,9 @@ def _ties_for_oracle(recs, traj_offset=0, traj_index=None):
 def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=None, per_traj=True,
              exec_mode="auto"):
     """GPU forward (+backward) over B trajectories and the oracle on `sample`
-    trajectory ids (default: all)."""
+    trajectory ids (default: all).  d_obs is [n_bins][n_obs][B] (bins, grid)
+    or [n_obs][B] (final counts) whatever cfg.obs_layout is; with
+    cfg.dobs_shared every trajectory's column must be the same."""
     theta = net.theta0 if theta is None else theta
     h = ssa.Net([net], [B], t_obs=[cfg.t_obs], exec_mode=exec_mode)
     th = torch.tensor(theta, dtype=torch.float32, device="cuda")
@@ -63,8 +65,17 @@ def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=N
     bins = cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID)     # [n_bins][n_obs][B] layouts
     nob = len(net.obs_species)
     gpu = {}
+    tm = cfg.obs_layout == W.OBS_TRAJ_MAJOR
     if d_obs is not None:
-        dd = torch.tensor(np.ascontiguousarray(d_obs).reshape(-1), device="cuda")
+        dl = np.asarray(d_obs, np.float64)
+        if not bins:
+            dl = dl[None]
+        if cfg.dobs_shared:
+            assert np.array_equal(dl, np.broadcast_to(dl[:, :, :1], dl.shape))
+            dl = dl[:, :, 0]
+        elif tm:
+            dl = dl.transpose(2, 0, 1)
+        dd = torch.tensor(np.ascontiguousarray(dl).reshape(-1), device="cuda")
         dp, ppt = ssa.backward(h, cfg, th, x0, fwd, dd, per_traj=True)
         gpu["d_params"] = dp.cpu().numpy()
         gpu["ppt"] = ppt.cpu().numpy().reshape(net.n_params, B).T
@@ -76,8 +87,13 @@ def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=N
     gpu["t_final"] = fwd.t_final.cpu().numpy()
     gpu["steps_done"] = fwd.steps_done.cpu().numpy()
     obs = fwd.obs.cpu().numpy()
-    gpu["obs"] = (obs[: cfg.n_bins * nob * B].reshape(cfg.n_bins, nob, B).transpose(2, 0, 1) if bins
-                  else obs[: nob * B].reshape(nob, B).T)
+    npts = cfg.n_bins if bins else 1
+    if tm:
+        o = obs[: npts * nob * B].reshape(B, npts, nob)
+        gpu["obs"] = o if bins else o[:, 0, :]
+    else:
+        gpu["obs"] = (obs[: cfg.n_bins * nob * B].reshape(cfg.n_bins, nob, B).transpose(2, 0, 1) if bins
+                      else obs[: nob * B].reshape(nob, B).T)
     gpu["ties"] = ties
     ids = np.arange(B) if sample is None else np.asarray(sample)
     index = {int(q): k for k, q in enumerate(ids)}
