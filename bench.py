@@ -371,15 +371,16 @@ def bench_infer(args, torch, dev):
     import oracle
 
     coi = args.workload == "coi_infer"
+    ep = {"epochs": args.epochs} if args.epochs else {}
     if coi:
         n_traj = args.n_traj if args.n_traj != 65536 else 262_144
         n_steps = args.n_steps or 20
-        tr = infer.ion_channel(n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
+        tr = infer.ion_channel(n_traj=n_traj, n_target=n_traj, n_steps=n_steps, **ep)
         k_start = infer.COI_START
     else:
         n_traj = args.n_traj if args.n_traj != 65536 else 100_000
         n_steps = args.n_steps or 250
-        tr = infer.dimerization(infer.TRUE_RATES, n_traj=n_traj, n_target=n_traj, n_steps=n_steps)
+        tr = infer.dimerization(infer.TRUE_RATES, n_traj=n_traj, n_target=n_traj, n_steps=n_steps, **ep)
         k_start = infer.START_RATES
     tr.capture()
     res = tr.run()
@@ -575,6 +576,8 @@ def main():
                          "coi_infer: ion-channel rate inference, 262,144 x 20 steps, 800 bins, 400 captured epochs; "
                          "selection: inverse-CDF vs Gumbel-max forward vs Gumbel-Softmax training step (dimer, oscillator)")
     ap.add_argument("--sweep", action="store_true", help="abc_infer: also run the k2 sweep (8 targets)")
+    ap.add_argument("--epochs", type=int, default=0,
+                    help="abc_infer / coi_infer: replayed epochs (0: the protocol's; fewer for profiling)")
     ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
     ap.add_argument("--n-traj", type=int, default=65536)
     ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")

@@ -175,9 +175,16 @@ size_t mean_work_bytes(const ssa_net *net, const ssa_config *cfg)
     return align_up(m, 256);
 }
 
+// Prefix sums of a shared bin dL/dobs block follow the ensemble-mean region.
+size_t prefix_work_bytes(const ssa_net *net, const ssa_config *cfg)
+{
+    if (!cfg->dobs_shared || cfg->obs_kind != SSA_OBS_BINS) return 0;
+    return align_up(sizeof(double) * (size_t)net->obsw_total * (size_t)(cfg->n_bins + 1), 256);
+}
+
 size_t work_bytes_for(const ssa_net *net, const ssa_config *cfg)
 {
-    return grad_work_bytes(net) + mean_work_bytes(net, cfg);
+    return grad_work_bytes(net) + mean_work_bytes(net, cfg) + prefix_work_bytes(net, cfg);
 }
 
 ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
@@ -739,6 +746,12 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
     p.tape_words = L.tape_words;
     p.partials = (double *)((char *)work + kWorkHeader);
     p.work_counter = (uint32_t *)((char *)work + 64);
+    if (prefix_work_bytes(net, cfg) > 0) {
+        double *pre = (double *)((char *)work + grad_work_bytes(net) + mean_work_bytes(net, cfg));
+        hipError_t e = launch_dobs_prefix(net->nets_d, net->n_networks, cfg->n_bins, d_obs, pre, stream);
+        if (e != hipSuccess) return hip_fail(e, "dL/dobs prefix sums");
+        p.dobs_prefix = pre;
+    }
     s = launch_all_classes(net, p, true, stream);
     if (s != SSA_OK) return s;
     double *chunk_sums = (double *)((char *)work + kWorkHeader + partials_bytes(net));

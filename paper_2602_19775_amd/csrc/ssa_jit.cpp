@@ -77,6 +77,12 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
           << "(ssa::RunParams p) { ssa::spec::backward<Net, " << g << ">(p); }\n";
     }
     // the forward with the inverse-CDF selection (final and bin observations)
+    // the backward of bin observations with a shared dL/dobs block
+    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_bwd_sh"
+         "(ssa::RunParams p) { ssa::spec::backward<Net, false, true>(p); }\n";
+    // the forward of bin observations in the trajectory-major layout
+    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_tm"
+         "(ssa::RunParams p) { ssa::spec::forward<Net, false, false, true>(p); }\n";
     s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_cdf"
          "(ssa::RunParams p) { ssa::spec::forward<Net, false, true>(p); }\n";
     return s.str();
@@ -129,7 +135,9 @@ bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
         hipModuleGetFunction(&k.bwd, k.module, "ssa_spec_bwd") != hipSuccess ||
         hipModuleGetFunction(&k.fwd_grid, k.module, "ssa_spec_fwd_grid") != hipSuccess ||
         hipModuleGetFunction(&k.bwd_grid, k.module, "ssa_spec_bwd_grid") != hipSuccess ||
-        hipModuleGetFunction(&k.fwd_cdf, k.module, "ssa_spec_fwd_cdf") != hipSuccess) {
+        hipModuleGetFunction(&k.fwd_cdf, k.module, "ssa_spec_fwd_cdf") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_tm, k.module, "ssa_spec_fwd_tm") != hipSuccess ||
+        hipModuleGetFunction(&k.bwd_sh, k.module, "ssa_spec_bwd_sh") != hipSuccess) {
         *log = "loading the compiled module failed";
         return false;
     }
@@ -145,8 +153,9 @@ hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, 
     RunParams copy = p;
     void *args[] = {&copy};
     const bool grid = p.obs_kind == 2;
-    hipFunction_t f = backward ? (grid ? k.bwd_grid : k.bwd)
-                               : (p.selection == 1 ? k.fwd_cdf : grid ? k.fwd_grid : k.fwd);
+    hipFunction_t f = backward ? (grid ? k.bwd_grid : p.dobs_prefix ? k.bwd_sh : k.bwd)
+                               : (p.selection == 1 ? k.fwd_cdf : grid ? k.fwd_grid
+                                                                     : p.obs_tm && p.obs_kind == 1 ? k.fwd_tm : k.fwd);
     return hipModuleLaunchKernel(f, blocks, 1, 1, 64 * spec_waves_per_block, 1, 1, 0, stream, args, nullptr);
 }
 

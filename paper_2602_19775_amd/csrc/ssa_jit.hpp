@@ -18,6 +18,8 @@ struct SpecKernels {
     hipFunction_t fwd_grid = nullptr;   // grid observation
     hipFunction_t bwd_grid = nullptr;
     hipFunction_t fwd_cdf = nullptr;    // inverse-CDF selection (forward only)
+    hipFunction_t fwd_tm = nullptr;     // bin observation, trajectory-major layout
+    hipFunction_t bwd_sh = nullptr;     // bin observation, shared dL/dobs (prefix sums)
 };
 
 // Source of the specialised kernel pair for one network (host tables).

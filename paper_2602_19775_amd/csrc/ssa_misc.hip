@@ -180,15 +180,61 @@ __global__ __launch_bounds__(256) void mean_sums_pm_kernel(const double *obs, in
     }
 }
 
-// Pass 2: the chunk sums of each value in chunk order, divided by B.
+// Pass 2: the chunk sums of each value, divided by B.  Thread (part, w) of a
+// block of 64 values sums the chunks c = part (mod 4) with eight interleaved
+// accumulators; the four parts are then added in order in LDS.  The loads of
+// a thread are independent, so the pass is not a chain of memory latencies.
 __global__ __launch_bounds__(256) void mean_total_kernel(const double *sums, int nc, int64_t W, int64_t B,
                                                          double *mean)
 {
-    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (w >= W) return;
-    double a = 0.0;
-    for (int c = 0; c < nc; ++c) a += sums[(int64_t)c * W + w];
-    mean[w] = B > 0 ? a / (double)B : 0.0;
+    __shared__ double part_sum[4][64];
+    const int wl = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * 64 + wl;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (w < W) {
+        int c = part;
+        for (; c + 28 < nc; c += 32)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) a[r] += sums[(int64_t)(c + 4 * r) * W + w];
+        for (int r = 0; c < nc; c += 4, ++r) a[r] += sums[(int64_t)c * W + w];
+    }
+    part_sum[part][wl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    __syncthreads();
+    if (part == 0 && w < W) {
+        const double s = ((part_sum[0][wl] + part_sum[1][wl]) + part_sum[2][wl]) + part_sum[3][wl];
+        mean[w] = B > 0 ? s / (double)B : 0.0;
+    }
+}
+
+// Prefix sums over the bins of a shared dL/dobs block, one block per network:
+// pre[o][b] = the sum of d_obs[b'][o] over b' < b, for b <= n_bins.  Each
+// chunk of 256 bins is scanned in LDS (a fixed sequence of additions, so the
+// result is the same on every call) and carried into the next.
+__global__ __launch_bounds__(256) void dobs_prefix_kernel(const NetDev *nets, int n_bins, const double *d_obs,
+                                                          double *pre)
+{
+    __shared__ double buf[256];
+    const NetDev nd = nets[blockIdx.x];
+    for (int o = 0; o < nd.n_obs; ++o) {
+        const double *d = d_obs + nd.obsw_off * n_bins + o;
+        double *q = pre + nd.obsw_off * (int64_t)(n_bins + 1) + (int64_t)o * (n_bins + 1);
+        double carry = 0.0;
+        for (int b0 = 0; b0 < n_bins; b0 += 256) {
+            const int b = b0 + (int)threadIdx.x;
+            buf[threadIdx.x] = b < n_bins ? d[(int64_t)b * nd.n_obs] : 0.0;
+            __syncthreads();
+            for (int off = 1; off < 256; off <<= 1) {
+                const double a = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0.0;
+                __syncthreads();
+                buf[threadIdx.x] += a;
+                __syncthreads();
+            }
+            if (b < n_bins) q[b + 1] = carry + buf[threadIdx.x];
+            carry += buf[255];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) q[0] = 0.0;
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v)
@@ -288,7 +334,16 @@ hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_ma
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(mean_total_kernel, dim3(grid_for(W, 256)), dim3(256), 0, stream, sums, nc, W, B, mean);
+    hipLaunchKernelGGL(mean_total_kernel, dim3(grid_for(W, 64)), dim3(256), 0, stream, sums, nc, W, B, mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_dobs_prefix(const NetDev *nets, int n_networks, int n_bins, const double *d_obs, double *pre,
+                              hipStream_t stream)
+{
+    if (n_networks <= 0 || n_bins <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dobs_prefix_kernel, dim3((unsigned)n_networks), dim3(256), 0, stream, nets, n_bins, d_obs,
+                       pre);
     return hipGetLastError();
 }
 

@@ -24,6 +24,10 @@ hipError_t launch_reduce_params(const NetDev *nets, const int32_t *pmap_off, con
 int obs_mean_chunks(int64_t B);
 hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_major, double *sums,
                            double *mean, hipStream_t stream);
+// Prefix sums [obs][n_bins + 1] per network of a shared bin dL/dobs block
+// (networks at obsw_off * n_bins in d_obs, at obsw_off * (n_bins + 1) in pre).
+hipError_t launch_dobs_prefix(const NetDev *nets, int n_networks, int n_bins, const double *d_obs, double *pre,
+                              hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_selftest_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t stream);
 hipError_t launch_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream);

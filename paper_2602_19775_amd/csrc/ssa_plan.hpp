@@ -133,6 +133,7 @@ struct RunParams {
     int32_t recompute;      // backward: recover choices by re-running segments
     int32_t obs_tm;         // obs / d_obs blocks are [trajectory][point][obs]
     int32_t dobs_shared;    // d_obs is one [point][obs] block per network
+    const double *dobs_prefix;   // bins, shared d_obs: [obs][n_bins + 1] prefix sums per network
 
     // wave mode: species -> range of incidence slots, and per channel the
     // slots of its (role 1, role 2) contributions: pos1 | pos2 << 16 with

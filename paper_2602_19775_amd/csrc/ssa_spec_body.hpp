@@ -52,6 +52,43 @@ __device__ __forceinline__ int delta_of(int j, int s)
     return d;
 }
 
+// Runs of bins of a trajectory-major observation block, filled by the whole
+// wave: lane l holds the bins [lo_l, hi_l) of its own row, all with its held
+// counts x (scaled: the bin integral of the held state divided by the bin
+// width, computed as the per-bin accumulation computes it; otherwise the
+// count itself).  One lane's run at a time, 64 consecutive values a store, so
+// a row's cache lines are written whole instead of one value per lane and
+// store.  Every lane of the wave must be active.
+template <class NET>
+__device__ __forceinline__ void fill_runs(double *blk, int64_t first, int64_t npts, int lo, int hi,
+                                          const int (&X)[NET::N + 1], bool scaled, double t_obs, int n_bins,
+                                          double inv_dt)
+{
+    constexpr int NOBS = NET::NOBS;
+    if constexpr (NOBS > 0) {
+        const int lane = threadIdx.x & 63;
+        uint64_t m = ballot(hi > lo);
+        while (m != 0ull) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            const int rlo = __builtin_amdgcn_readlane(lo, l), rhi = __builtin_amdgcn_readlane(hi, l);
+            int xv[NOBS];
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) xv[o] = __builtin_amdgcn_readlane(X[NET::OBS[o]], l);
+            double *row = blk + (first + l) * npts * NOBS;
+            for (int64_t q = (int64_t)rlo * NOBS + lane; q < (int64_t)rhi * NOBS; q += 64) {
+                const int b = (int)(q / NOBS), o = (int)(q - (int64_t)b * NOBS);
+                int x = xv[0];
+#pragma unroll
+                for (int u = 1; u < NOBS; ++u) x = o == u ? xv[u] : x;
+                row[q] = scaled ? ((double)x * fmax(bin_edge(t_obs, b + 1, n_bins) - bin_edge(t_obs, b, n_bins),
+                                                    0.0)) * inv_dt
+                                : (double)x;
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void log_tie(const RunParams &p, uint32_t g, int k, int chosen, int second,
                                      float margin, int kind)
 {
@@ -136,7 +173,9 @@ constexpr int obs_cap(int n) { return n > 0 ? n : 1; }
 // GRID: the grid observation (the other kinds are runtime cases of GRID = false).
 // CDF: the channel is the standard direct method's inverse-CDF draw from word 1
 // (Sec. 2) instead of the Gumbel-max race; such a run has no backward.
-template <class NET, bool HAS_T_END, bool GRID, bool CDF = false>
+// TMB: bin observations in the trajectory-major layout, whose whole bins are
+// filled by the wave (the other kernels take either layout through strides).
+template <class NET, bool HAS_T_END, bool GRID, bool CDF = false, bool TMB = false>
 __device__ void forward_run(const RunParams &p)
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
@@ -175,7 +214,8 @@ __device__ void forward_run(const RunParams &p)
     // observation block [point][obs][B], or [B][point][obs] trajectory-major
     const int64_t npts = p.obs_kind != 0 ? n_bins : 1;
     const int64_t orow = p.obs_tm ? (int64_t)NOBS : (int64_t)NOBS * B, ocol = p.obs_tm ? 1 : B;
-    double *obs_lane = p.obs + nd.obsb_off * npts + (p.obs_tm ? i * npts * NOBS : i);
+    double *obs_base = p.obs + nd.obsb_off * npts;
+    double *obs_lane = obs_base + (p.obs_tm ? i * npts * NOBS : i);
     // grid observation: next grid point gi, at time grid_t >= t
     int gi = 0;
     double grid_t = grid ? 0.0 : INFINITY;
@@ -289,7 +329,37 @@ __device__ void forward_run(const RunParams &p)
                     log_tie(p, (uint32_t)g, k, j1, j2, (r2 - r1) / r1, 0);
                 }
             }
-            if (crossing) {
+            // bins the interval completes
+            int run_lo = 0, run_hi = 0;
+            if (TMB && crossing) {
+                // the first one carries the accumulated integral; the whole
+                // bins after it go to the wave-wide fill; the last bin the
+                // interval reaches into is found from an estimate and exact
+                // comparisons with the edges themselves
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    acc[o] += (double)X[NET::OBS[o]] * fmax(bin_hi - t, 0.0);
+                    if (o < NOBS) obs_lane[bin * orow + o * ocol] = acc[o] * inv_dt;
+                    acc[o] = 0.0;
+                }
+                int b = bin + 1;
+                if (b < n_bins) {
+                    const double est = ceil(tn * (double)n_bins / t_obs) - 1.0;
+                    b = !(est > (double)b) ? b : est >= (double)n_bins ? n_bins : (int)est;
+                    while (b > bin + 1 && tn <= bin_edge(t_obs, b, n_bins)) --b;
+                    while (b < n_bins && tn > bin_edge(t_obs, b + 1, n_bins)) ++b;
+                }
+                run_lo = bin + 1;
+                run_hi = b;
+                if (b < n_bins) {
+#pragma unroll
+                    for (int o = 0; o < NO; ++o) acc[o] += (double)X[NET::OBS[o]] * (tn - bin_edge(t_obs, b, n_bins));
+                }
+                bin = b;
+                bin_hi = b < n_bins ? bin_edge(t_obs, b + 1, n_bins) : INFINITY;
+            }
+            if (TMB) fill_runs<NET>(obs_base, it.first, npts, run_lo, run_hi, X, true, t_obs, n_bins, inv_dt);
+            if (!TMB && crossing) {
                 double t0 = t;
                 while (bin < n_bins) {
                     const double hi = bin_hi;
@@ -343,11 +413,14 @@ __device__ void forward_run(const RunParams &p)
         }
       }
     }
+    // hold the last state up to t_obs: the rest of the current bin, then every
+    // later bin, whose average is the last state itself
+    if (TMB)
+        fill_runs<NET>(obs_base, it.first, npts, valid && bin < n_bins ? bin + 1 : 0,
+                       valid && bin < n_bins ? n_bins : 0, X, false, t_obs, n_bins, inv_dt);
     if (!valid) return;
     if (spw && (k & (spw - 1)) != 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
     if (bin < n_bins) {
-        // hold the last state up to t_obs: the rest of the current bin, then
-        // every later bin, whose average is the last state itself
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
             acc[o] += (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0);
@@ -355,9 +428,10 @@ __device__ void forward_run(const RunParams &p)
         }
         // rows from the top down, so the wave's lanes store the same row
         // together whatever bin each of them stopped in
-        for (int bb = n_bins - 1; bb > bin; --bb)
+        if (!TMB)
+            for (int bb = n_bins - 1; bb > bin; --bb)
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) obs_lane[bb * orow + o * ocol] = (double)X[NET::OBS[o]];
+                for (int o = 0; o < NOBS; ++o) obs_lane[bb * orow + o * ocol] = (double)X[NET::OBS[o]];
     }
     if (p.obs_kind == 0) {
 #pragma unroll
@@ -378,11 +452,11 @@ __device__ void forward_run(const RunParams &p)
     if (flags) atomicOr(p.flags, flags);
 }
 
-template <class NET, bool GRID, bool CDF = false>
+template <class NET, bool GRID, bool CDF = false, bool TMB = false>
 __device__ void forward(const RunParams &p)
 {
-    if (p.t_end < INFINITY) forward_run<NET, true, GRID, CDF>(p);
-    else forward_run<NET, false, GRID, CDF>(p);
+    if (p.t_end < INFINITY) forward_run<NET, true, GRID, CDF, TMB>(p);
+    else forward_run<NET, false, GRID, CDF, TMB>(p);
 }
 
 // --------------------------------------------------------------------------
@@ -391,7 +465,10 @@ __device__ void forward(const RunParams &p)
 // instead of the tape.
 constexpr int kRecSteps = 64;   // recompute mode: steps of a segment kept in LDS
 
-template <class NET, int TMODE, bool RECOMPUTE, bool GRID>
+// SH: bin observations with one dL/dobs block shared by the trajectories,
+// whose per-species prefix sums over the bins (p.dobs_prefix) give the
+// contribution of every whole bin an interval spans in one difference.
+template <class NET, int TMODE, bool RECOMPUTE, bool GRID, bool SH = false>
 __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64])
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
@@ -444,6 +521,8 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     const int64_t drow = dtm ? (int64_t)NOBS : (int64_t)NOBS * B, dcol = dtm ? 1 : B;
     const double *dobs_lane = p.d_obs + (p.dobs_shared ? nd.obsw_off * npts
                                                       : nd.obsb_off * npts + (p.obs_tm ? i * npts * NOBS : i));
+    // prefix sums [obs][n_bins + 1] of the shared block (SH)
+    const double *pre = SH ? p.dobs_prefix + nd.obsw_off * (int64_t)(n_bins + 1) : nullptr;
 
     // adjoint of the state: FP64 accumulator, FP32 increments folded every kFold steps
     double lam[N];
@@ -472,9 +551,15 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
             while (b > 0 && t < bin_edge(t_obs, b, n_bins)) --b;
             while (b + 1 < n_bins && t >= bin_edge(t_obs, b + 1, n_bins)) ++b;
             // later bins average the held final state: their dL/dobs go to it whole
-            for (int bb = n_bins - 1; bb > b; --bb)
+            if (SH) {
 #pragma unroll
-                for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[bb * drow + o * dcol];
+                for (int o = 0; o < NOBS; ++o)
+                    lam[NET::OBS[o]] += pre[o * (n_bins + 1) + n_bins] - pre[o * (n_bins + 1) + b + 1];
+            } else {
+                for (int bb = n_bins - 1; bb > b; --bb)
+#pragma unroll
+                    for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[bb * drow + o * dcol];
+            }
             // and the part of bin b after the last event
             rbin = b;
             rlo = b > 0 ? bin_edge(t_obs, b, n_bins) : -INFINITY;
@@ -673,7 +758,37 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
                 if (bins) {
                     double hi = t < t_obs ? t : t_obs;
                     // below the first bin's edge rlo is -inf: nothing left to cross
-                    if (ballot(t_k < rlo) != 0ull)
+                    if (SH && ballot(t_k < rlo) != 0ull) {
+                        if (t_k < rlo) {
+                            // the rest of the current bin, then the bin b that
+                            // holds t_k (an estimate, then exact comparisons
+                            // with the edges), and the whole bins between from
+                            // the prefix sums (width / bin width = 1)
+                            if (rbin < n_bins) {
+                                const double seg = fmax(hi - rlo, 0.0);
+    #pragma unroll
+                                for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += (float)(doi[o] * seg);
+                            }
+                            const double est = floor(t_k * (double)n_bins / t_obs);
+                            int b = !(est > 0.0) ? 0 : est >= (double)(rbin - 1) ? rbin - 1 : (int)est;
+                            while (b > 0 && t_k < bin_edge(t_obs, b, n_bins)) --b;
+                            while (b + 1 < rbin && t_k >= bin_edge(t_obs, b + 1, n_bins)) ++b;
+                            if (rbin > b + 1) {
+    #pragma unroll
+                                for (int o = 0; o < NOBS; ++o)
+                                    dlam[NET::OBS[o]] += (float)(pre[o * (n_bins + 1) + rbin] -
+                                                                 pre[o * (n_bins + 1) + b + 1]);
+                            }
+                            hi = b + 1 == rbin ? fmin(hi, rlo) : bin_edge(t_obs, b + 1, n_bins);
+                            rbin = b;
+                            rlo = b > 0 ? bin_edge(t_obs, b, n_bins) : -INFINITY;
+    #pragma unroll
+                            for (int o = 0; o < NO; ++o) {
+                                doi[o] = o < NOBS ? dobs_lane[rbin * drow + o * dcol] * inv_dt : 0.0;
+                                doi32[o] = (float)doi[o];
+                            }
+                        }
+                    } else if (!SH && ballot(t_k < rlo) != 0ull)
                     while (t_k < rlo) {
                         if (rbin < n_bins) {
                             const double seg = fmax(hi - rlo, 0.0);
@@ -784,19 +899,19 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     for (int q = 0; q < M; ++q) p.partials[nd.part_off + q * B + i] = dth[q];
 }
 
-template <class NET, bool GRID>
+template <class NET, bool GRID, bool SH = false>
 __device__ void backward(const RunParams &p)
 {
     __shared__ uint8_t s_tape[kWaves][kRecSteps][64];
     const float invT = 1.0f / run_temperature(p);
     if (p.recompute) {
-        if (invT == 2.0f) backward_run<NET, 2, true, GRID>(p, s_tape);
-        else if (invT == 1.0f) backward_run<NET, 1, true, GRID>(p, s_tape);
-        else backward_run<NET, 0, true, GRID>(p, s_tape);
+        if (invT == 2.0f) backward_run<NET, 2, true, GRID, SH>(p, s_tape);
+        else if (invT == 1.0f) backward_run<NET, 1, true, GRID, SH>(p, s_tape);
+        else backward_run<NET, 0, true, GRID, SH>(p, s_tape);
     } else {
-        if (invT == 2.0f) backward_run<NET, 2, false, GRID>(p, s_tape);
-        else if (invT == 1.0f) backward_run<NET, 1, false, GRID>(p, s_tape);
-        else backward_run<NET, 0, false, GRID>(p, s_tape);
+        if (invT == 2.0f) backward_run<NET, 2, false, GRID, SH>(p, s_tape);
+        else if (invT == 1.0f) backward_run<NET, 1, false, GRID, SH>(p, s_tape);
+        else backward_run<NET, 0, false, GRID, SH>(p, s_tape);
     }
 }
 

@@ -20,7 +20,8 @@ import torch
 import oracle
 from paper_2602_19775_amd import workloads as W
 
-from test_gpu_parity import _x0, assert_forward_parity, assert_grad_parity, edge_safe, run_pair
+from test_gpu_parity import (_ties_for_oracle, _x0, assert_forward_parity, assert_grad_parity, edge_safe,
+                              run_pair)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +44,10 @@ CASES = {
     "channel_bins": (lambda: W.ion_channel_coi(n_channels=3),
                      W.RunConfig(seed=6, n_steps=20, obs_kind=W.OBS_BINS, n_bins=60, t_obs=8.0, temperature=0.2,
                                  ckpt_every=8), 2500),
+    # bin averages of three observed species (paths run past t_obs)
+    "abc_bins": (lambda: W.dimerization_abc(),
+                 W.RunConfig(seed=8, n_steps=200, obs_kind=W.OBS_BINS, n_bins=40, t_obs=3.0, temperature=0.5,
+                             ckpt_every=32), 2200),
     # final counts of the dimerisation
     "dimer_final": (lambda: W.dimerization_2a(),
                     W.RunConfig(seed=7, n_steps=300, obs_kind=W.OBS_FINAL, temperature=0.5, ckpt_every=64), 1000),
@@ -84,8 +89,56 @@ def test_traj_major_parity(ssa, case, shared):
     ref, _, _, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode="tape", sample=sample[:2])
     assert np.array_equal(gpu["obs"], ref["obs"])
     assert np.array_equal(gpu["x_final"], ref["x_final"])
-    assert np.array_equal(gpu["ppt"], ref["ppt"])
-    assert np.array_equal(gpu["d_params"], ref["d_params"])
+    if shared and cfg.obs_kind == W.OBS_BINS:
+        # whole bins enter through prefix sums of the shared block: the same
+        # terms in another order and in FP64
+        for q in range(B):
+            assert_grad_parity(gpu["ppt"][q], ref["ppt"][q], rtol=1e-5)
+        tot = ref["ppt"].astype(np.float64).sum(0)
+        assert np.allclose(gpu["d_params"], ref["d_params"], rtol=1e-5,
+                           atol=1e-6 * np.abs(ref["ppt"].astype(np.float64)).sum(0).max())
+    else:
+        assert np.array_equal(gpu["ppt"], ref["ppt"])
+        assert np.array_equal(gpu["d_params"], ref["d_params"])
+
+
+def test_shared_dobs_two_networks(ssa):
+    """Two topologies in one handle, each with its own shared bin dL/dobs
+    block (the prefix sums are laid out per network): per-trajectory
+    gradients against the oracle fed each network's block."""
+    nets = [W.ion_channel_coi(n_channels=3), W.dimerization_abc()]
+    Bs = [700, 450]
+    cfg = W.RunConfig(seed=12, n_steps=60, obs_kind=W.OBS_BINS, n_bins=30, t_obs=5.0, temperature=0.4,
+                      ckpt_every=16, obs_layout=W.OBS_TRAJ_MAJOR, dobs_shared=True)
+    h = ssa.Net(nets, Bs, t_obs=[5.0, 5.0])
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    x0 = _x0(nets, Bs)
+    g = np.random.default_rng(5)
+    blocks = [g.normal(size=(cfg.n_bins, len(n.obs_species))) for n in nets]
+    d = torch.tensor(np.concatenate([b.reshape(-1) for b in blocks]), device="cuda")
+    fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 16, bwd_mode="tape")
+    dp, ppt = ssa.backward(h, cfg, th, x0, fwd, d, per_traj=True)
+    torch.cuda.synchronize()
+    ties = fwd.tie_records()
+    ppt = ppt.cpu().numpy()
+    tf = fwd.t_final.cpu().numpy()
+    for k, (net, B) in enumerate(zip(nets, Bs)):
+        L = h.layout(k, cfg.obs_kind, cfg.n_bins)
+        assert L.mean_offset == sum(cfg.n_bins * len(n.obs_species) for n in nets[:k])
+        ids = np.arange(0, B, 7)
+        index = {int(q): j for j, q in enumerate(ids)}
+        ov = _ties_for_oracle([t for t in ties if L.traj_offset <= t["traj"] < L.traj_offset + B], L.traj_offset,
+                              index)
+        dn = np.broadcast_to(blocks[k][None], (len(ids),) + blocks[k].shape).copy()
+        r = oracle.run(net, cfg.replace(obs_layout=0, dobs_shared=False), net.theta0, net.x0,
+                       traj_ids=L.traj_offset + ids, ties=ov, d_obs=dn)
+        assert r.n_bad.sum() == 0
+        drift = float(np.max(np.abs(tf[L.traj_offset + ids] - r.t_final)))
+        keep = r.bin_edge_dist > 50 * max(drift, 1e-12)
+        assert keep.mean() > 0.5
+        gk = ppt[L.ppt_offset: L.ppt_offset + net.n_params * B].reshape(net.n_params, B).T[ids]
+        for j in np.flatnonzero(keep):
+            assert_grad_parity(gk[j], r.grad[j], rtol=1e-5)
 
 
 def test_layout_needs_the_specialised_mode(ssa):
