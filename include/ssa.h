@@ -244,7 +244,9 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
                        hipStream_t stream);
 
 /* Straight-through backward.  Inputs are the forward's inputs and outputs
- * (same cfg, theta, x0) and d_obs = dL/dobs (double, obs layout).
+ * (same cfg, theta, x0) and d_obs = dL/dobs (double, obs layout; with
+ * cfg->dobs_shared, one block of W_n values per network at its mean_offset,
+ * used for every trajectory of the network).
  *   d_params [sum P_n] float: overwritten with dL/dtheta (deterministic:
  *     per-trajectory FP64 partials reduced in a fixed order);
  *   d_params_per_traj: optional [sum P_n*B_n] per-trajectory gradients. */
