@@ -205,3 +205,18 @@ def test_obs_mean_large_ragged(ssa, layout):
     host = v if layout == W.OBS_TRAJ_MAJOR else v.T
     m = ssa.obs_mean(h, fwd, obs=torch.tensor(np.ascontiguousarray(host).reshape(-1), device="cuda"))
     assert np.allclose(m.cpu().numpy(), v.mean(axis=0), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("bwd_mode,T", [("recompute", 0.5), ("tape", 1.0), ("recompute", 1.0), ("recompute", 0.2)])
+def test_shared_bins_backward_variants(ssa, bwd_mode, T):
+    """The shared-block bin backward in each choice source (tape, segment
+    re-run) and temperature class (1/T = 2, 1, other), against the oracle."""
+    net = W.ion_channel_coi(n_channels=4)
+    B = 1500
+    cfg = W.RunConfig(seed=21, n_steps=24, obs_kind=W.OBS_BINS, n_bins=50, t_obs=6.0, temperature=T,
+                      ckpt_every=8, obs_layout=W.OBS_TRAJ_MAJOR, dobs_shared=True)
+    d_obs = _d_obs(cfg, len(net.obs_species), B, 4, True)
+    g = np.random.default_rng(6)
+    sample = np.unique(np.concatenate([[0, B - 1], g.choice(B, 40, replace=False)]))
+    gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode=bwd_mode, sample=sample)
+    _parity(gpu, r, ids, cfg)
