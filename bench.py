@@ -448,11 +448,14 @@ def bench_infer(args, torch, dev):
     ops_f, ops_b = alu_ops_per_step(tr.net, False, inv2), alu_ops_per_step(tr.net, True, inv2)
     dom, dom_ms, ops = ("backward", bwd_ms, ops_b) if bwd_ms >= fwd_ms else ("forward", fwd_ms, ops_f)
     # algorithmic HBM bytes of one launch: the observation buffer (written by
-    # the forward; the backward reads the shared dL/dobs block only), the
-    # checkpoints and tape (written, then read), the per-trajectory state and clock
+    # the forward, or its tiles' sums; the backward reads the shared dL/dobs
+    # block only), the checkpoints and tape (written, then read), the
+    # per-trajectory state and clock
     io = bufs.x_final.numel() * 4 * 2 + B * (8 + 4)
     ck = bufs.ckpt.numel() if bufs.ckpt is not None else 0
-    alg_bytes = (G * O * B * 8 if dom == "forward" else 0) + ck + io
+    ens = tr.cfg.obs_layout == W.OBS_ENSEMBLE_MEAN       # the forward stores one row of sums a 64-trajectory tile
+    obs_bytes = -(-B // 64) * G * O * 8 if ens else G * O * B * 8
+    alg_bytes = (obs_bytes if dom == "forward" else 0) + ck + io
     alu_s = fired * slots(ops, cost) / PEAK_LANE_SLOTS
     if alg_bytes / HBM_PEAK > alu_s:
         achieved = alg_bytes / (dom_ms * 1e-3)

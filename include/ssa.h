@@ -39,7 +39,8 @@
  *   steps_done         int32  [sum B_n]
  *   obs / d_obs        double [sum W_n*B_n]        (block [W_n][B_n], or [B_n][W_n] with
  *                       SSA_OBS_TRAJ_MAJOR; W_n = n_bins*n_obs_n as [point][obs] for bins
- *                       and grids, n_obs_n for final counts)
+ *                       and grids, n_obs_n for final counts; [sum W_n] with
+ *                       SSA_OBS_ENSEMBLE_MEAN)
  *   ensemble means     double [sum W_n]            (ssa_obs_mean; a shared d_obs)
  *   d_params_per_traj  float  [sum P_n*B_n]        (block [P_n][B_n])
  * ssa_net_layout() returns every offset.
@@ -102,7 +103,16 @@ enum { SSA_SELECT_GUMBEL_MAX = 0, SSA_SELECT_INVERSE_CDF = 1 };
  * network the same dL/dobs; with dobs_shared set, ssa_backward reads d_obs as
  * that one block of W_n values per network (the ssa_obs_mean layout), whatever
  * obs_layout is.  Topology-specialised lane mode only. */
-enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1 };
+enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1, SSA_OBS_ENSEMBLE_MEAN = 2 };
+/* SSA_OBS_ENSEMBLE_MEAN: ssa_forward writes the ensemble means themselves
+ * (the ssa_obs_mean layout, double [sum W_n]) and never stores the values of
+ * single trajectories.  Each wave sums its trajectories' values in LDS in a
+ * fixed lane order, each 64-trajectory tile leaves one row of sums, and the
+ * rows of a network are reduced in a fixed order, so the result is the same
+ * on every call.  Bin observations, topology-specialised lane mode,
+ * n_bins * (n_obs + 1) <= 2048 (a wave holds its sums and the bin widths in
+ * LDS); ssa_backward then needs dobs_shared.  Anything else returns
+ * SSA_ENOTSUP. */
 
 /* How ssa_backward obtains the fired channel of each step.
  *   SSA_BWD_TAPE:      ssa_forward stores the fired channel index of every
@@ -190,7 +200,7 @@ typedef struct ssa_config {
                                       backward when it runs (annealing T under graph replay);
                                       it must then hold a finite value > 0.  NULL: temperature */
     int32_t selection;             /* SSA_SELECT_*: how the forward picks the channel */
-    int32_t obs_layout;            /* SSA_OBS_POINT_MAJOR or SSA_OBS_TRAJ_MAJOR */
+    int32_t obs_layout;            /* SSA_OBS_POINT_MAJOR, SSA_OBS_TRAJ_MAJOR or SSA_OBS_ENSEMBLE_MEAN */
     int32_t dobs_shared;           /* nonzero: d_obs holds one dL/dobs block [W_n] per network */
 } ssa_config;
 
@@ -275,6 +285,7 @@ ssa_status ssa_step_batch(const ssa_net *net, const ssa_config *cfg, const float
  *   work: the work buffer of ssa_buffer_sizes for the same cfg (its contents
  *   are overwritten; do not share it with a concurrent forward or backward).
  * Enqueues on `stream` only (graph-capturable), any execution mode. */
+/* (SSA_OBS_ENSEMBLE_MEAN observations are means already: SSA_EINVAL.) */
 ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double *obs, double *mean,
                         void *work, size_t work_bytes, hipStream_t stream);
 

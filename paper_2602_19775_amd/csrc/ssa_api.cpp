@@ -82,13 +82,14 @@ struct ssa_net {
         int tab_m = 0, tab_nnz = 0;   // per-group LDS table capacities
         int wide_ve = 0;              // a channel changes more than kVecSlots species
         SpecKernels kernels;
+        int spec_nobs = 0;            // observed species of the group's topology
         LaneItem *items_d = nullptr;
         int n_items = 0;
     };
     std::vector<Group> groups;
     uint32_t *flags_d = nullptr;
     int64_t traj_total = 0, state_total = 0, param_total = 0, obsb_total = 0, part_total = 0,
-            ppt_total = 0, obsw_total = 0;
+            ppt_total = 0, obsw_total = 0, tobs_total = 0;
     int max_M = 0;
     int64_t max_B = 0;
     int device = 0;
@@ -118,6 +119,9 @@ int resolve_bwd_mode(const ssa_config *cfg)
 }
 
 constexpr int kMaxRecomputeSegment = 64;
+// LDS doubles a wave of the ensemble-mean forward holds: n_bins * n_obs sums
+// and n_bins bin widths (4 waves x 16 KiB a block)
+constexpr int64_t kMeanMaxValues = 2048;
 
 bool bounded_steps(const ssa_config *cfg)
 {
@@ -182,9 +186,23 @@ size_t prefix_work_bytes(const ssa_net *net, const ssa_config *cfg)
     return align_up(sizeof(double) * (size_t)net->obsw_total * (size_t)(cfg->n_bins + 1), 256);
 }
 
+// Per-tile sums of the ensemble-mean forward follow the prefix sums.
+size_t tile_work_bytes(const ssa_net *net, const ssa_config *cfg)
+{
+    if (cfg->obs_layout != SSA_OBS_ENSEMBLE_MEAN) return 0;
+    return align_up(sizeof(double) * (size_t)net->tobs_total * (size_t)cfg->n_bins, 256);
+}
+
 size_t work_bytes_for(const ssa_net *net, const ssa_config *cfg)
 {
-    return grad_work_bytes(net) + mean_work_bytes(net, cfg) + prefix_work_bytes(net, cfg);
+    return grad_work_bytes(net) + mean_work_bytes(net, cfg) + prefix_work_bytes(net, cfg) +
+           tile_work_bytes(net, cfg);
+}
+
+double *tile_sums_of(const ssa_net *net, const ssa_config *cfg, void *work)
+{
+    return (double *)((char *)work + grad_work_bytes(net) + mean_work_bytes(net, cfg) +
+                      prefix_work_bytes(net, cfg));
 }
 
 ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
@@ -218,16 +236,26 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
     if (mode == SSA_BWD_RECOMPUTE && cfg->ckpt_every > kMaxRecomputeSegment)
         return fail(SSA_EINVAL, "recompute mode needs ckpt_every <= 64");
     if (cfg->tie_capacity < 0) return fail(SSA_EINVAL, "tie_capacity must be >= 0");
-    if (cfg->obs_layout != SSA_OBS_POINT_MAJOR && cfg->obs_layout != SSA_OBS_TRAJ_MAJOR)
-        return fail(SSA_EINVAL, "obs_layout must be SSA_OBS_POINT_MAJOR or SSA_OBS_TRAJ_MAJOR");
-    if (cfg->obs_layout == SSA_OBS_TRAJ_MAJOR || cfg->dobs_shared)
+    if (cfg->obs_layout != SSA_OBS_POINT_MAJOR && cfg->obs_layout != SSA_OBS_TRAJ_MAJOR &&
+        cfg->obs_layout != SSA_OBS_ENSEMBLE_MEAN)
+        return fail(SSA_EINVAL, "obs_layout must be SSA_OBS_POINT_MAJOR, SSA_OBS_TRAJ_MAJOR or SSA_OBS_ENSEMBLE_MEAN");
+    if (cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN) {
+        if (cfg->obs_kind != SSA_OBS_BINS)
+            return fail(SSA_ENOTSUP, "the ensemble-mean forward observes bins only");
+        for (const NetDev &nd : net->nets_h)
+            if ((int64_t)(nd.n_obs + 1) * cfg->n_bins > kMeanMaxValues)
+                return fail(SSA_ENOTSUP, "the ensemble-mean forward needs n_bins * (n_obs + 1) <= 2048");
+    }
+    if (cfg->obs_layout != SSA_OBS_POINT_MAJOR || cfg->dobs_shared)
         for (const auto &gr : net->groups)
             if (gr.n_items && !gr.spec)
-                return fail(SSA_ENOTSUP, "the trajectory-major layout and a shared d_obs run in the "
-                                         "topology-specialised lane mode only");
+                return fail(SSA_ENOTSUP, "the trajectory-major and ensemble-mean layouts and a shared d_obs "
+                                         "run in the topology-specialised lane mode only");
     if (cfg->selection != SSA_SELECT_GUMBEL_MAX && cfg->selection != SSA_SELECT_INVERSE_CDF)
         return fail(SSA_EINVAL, "unknown selection");
     if (cfg->selection == SSA_SELECT_INVERSE_CDF) {
+        if (cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN)
+            return fail(SSA_ENOTSUP, "the inverse-CDF selection writes per-trajectory observations");
         if (cfg->obs_kind == SSA_OBS_GRID)
             return fail(SSA_ENOTSUP, "the inverse-CDF selection runs with the final or bin observation");
         for (const auto &gr : net->groups)
@@ -263,7 +291,8 @@ RunParams base_params(const ssa_net *net, const ssa_config *cfg)
     p.temperature = cfg->temperature;
     p.d_temperature = cfg->d_temperature;
     p.selection = cfg->selection;
-    p.obs_tm = cfg->obs_layout == SSA_OBS_TRAJ_MAJOR ? 1 : 0;
+    p.obs_tm = cfg->obs_layout != SSA_OBS_POINT_MAJOR ? 1 : 0;
+    p.obs_ens = cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN ? 1 : 0;
     p.dobs_shared = cfg->dobs_shared ? 1 : 0;
     p.recompute = resolve_bwd_mode(cfg) == SSA_BWD_RECOMPUTE ? 1 : 0;
     p.inc_ptr = net->inc_ptr_d;
@@ -287,7 +316,11 @@ ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hi
             e = launch_fill_u32(p.work_counter, 1, 0u, stream);
             if (e == hipSuccess) e = wave_launch(gr.wave_class, p, backward, gr.wave_blocks, stream);
         } else {
-            e = gr.spec ? spec_launch(gr.kernels, p, backward, stream) : lane_launch(gr.lane_class, p, backward, stream);
+            const size_t mean_lds = !backward && p.obs_ens ? sizeof(double) * spec_waves_per_block *
+                                                                 (size_t)p.n_bins * (gr.spec_nobs + 1)
+                                                           : 0;
+            e = gr.spec ? spec_launch(gr.kernels, p, backward, mean_lds, stream)
+                        : lane_launch(gr.lane_class, p, backward, stream);
         }
         if (e != hipSuccess) return hip_fail(e, backward ? "backward launch" : "forward launch");
     }
@@ -465,6 +498,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         nd.param_off = net->param_total;
         nd.obsb_off = net->obsb_total;
         nd.obsw_off = net->obsw_total;
+        nd.tobs_off = net->tobs_total;
         nd.part_off = net->part_total;
         nd.ppt_off = net->ppt_total;
         nd.t_obs = d->t_obs ? d->t_obs[n] : 0.0;
@@ -535,6 +569,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         net->param_total += P;
         net->obsb_total += (int64_t)nob * B;
         net->obsw_total += nob;
+        net->tobs_total += (int64_t)((B + 63) / 64) * nob;
         net->part_total += (int64_t)M * B;
         net->ppt_total += (int64_t)P * B;
         net->max_M = std::max(net->max_M, M);
@@ -568,6 +603,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         ssa_net::Group gr;
         gr.spec = true;
         gr.kernels = spec_kernels[kv.first];
+        gr.spec_nobs = kv.second.empty() ? 0 : d->n_obs[kv.second.front().net];
         gr.n_items = (int)kv.second.size();
         e = upload(&gr.items_d, kv.second);
         net->groups.push_back(gr);
@@ -709,7 +745,20 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
         hipError_t e = launch_fill_u32(n_ties, 1, 0u, stream);
         if (e != hipSuccess) return hip_fail(e, "clearing the tie counter");
     }
-    return launch_all_classes(net, p, false, stream);
+    if (cfg->obs_layout != SSA_OBS_ENSEMBLE_MEAN) return launch_all_classes(net, p, false, stream);
+    // ensemble means: the tiles' rows of sums, then each network's rows in order
+    p.tile_sums = tile_sums_of(net, cfg, work);
+    s = launch_all_classes(net, p, false, stream);
+    if (s != SSA_OK) return s;
+    double *sums = (double *)((char *)work + grad_work_bytes(net));
+    for (const NetDev &nd : net->nets_h) {
+        const int64_t W = obs_width(nd, cfg);
+        if (W == 0) continue;
+        hipError_t e = launch_obs_mean(p.tile_sums + nd.tobs_off * cfg->n_bins, (nd.B + 63) / 64, W, true, sums,
+                                       obs + nd.obsw_off * cfg->n_bins, nd.B, stream);
+        if (e != hipSuccess) return hip_fail(e, "ensemble mean of the tiles");
+    }
+    return SSA_OK;
 }
 
 ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *theta, const int32_t *x0,
@@ -722,6 +771,8 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
     if (s == SSA_OK && cfg->selection != SSA_SELECT_GUMBEL_MAX)
         return fail(SSA_ENOTSUP, "the straight-through backward needs the Gumbel-max selection");
     if (s != SSA_OK) return s;
+    if (cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN && !cfg->dobs_shared)
+        return fail(SSA_ENOTSUP, "after an ensemble-mean forward the backward needs a shared d_obs");
     if (!theta || !x0 || !x_final || !t_final || !steps_done || !d_params)
         return fail(SSA_EINVAL, "theta, x0, x_final, t_final, steps_done and d_params are required");
     if (net->obsb_total > 0 && !d_obs) return fail(SSA_EINVAL, "d_obs is NULL but species are observed");
@@ -768,6 +819,8 @@ ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double 
     g_last_error.clear();
     ssa_status s = check_config(net, cfg);
     if (s != SSA_OK) return s;
+    if (cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN)
+        return fail(SSA_EINVAL, "ensemble-mean observations are means already");
     if (net->obsw_total > 0 && (!obs || !mean)) return fail(SSA_EINVAL, "obs and mean are required");
     if (!work || work_bytes < work_bytes_for(net, cfg)) return fail(SSA_EWORKSPACE, "work buffer too small");
     double *sums = (double *)((char *)work + grad_work_bytes(net));
@@ -777,7 +830,7 @@ ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double 
         if (W == 0) continue;
         hipError_t e = launch_obs_mean(obs + nd.obsb_off * npts, nd.B, W,
                                        cfg->obs_layout == SSA_OBS_TRAJ_MAJOR, sums,
-                                       mean + nd.obsw_off * npts, stream);
+                                       mean + nd.obsw_off * npts, nd.B, stream);
         if (e != hipSuccess) return hip_fail(e, "ensemble mean");
     }
     return SSA_OK;

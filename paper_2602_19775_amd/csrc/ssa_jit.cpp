@@ -80,6 +80,9 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
     // the backward of bin observations with a shared dL/dobs block
     s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_bwd_sh"
          "(ssa::RunParams p) { ssa::spec::backward<Net, false, true>(p); }\n";
+    // the forward of bin observations that keeps only the ensemble means
+    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_ens"
+         "(ssa::RunParams p) { ssa::spec::forward<Net, false, false, true, true>(p); }\n";
     // the forward of bin observations in the trajectory-major layout
     s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_tm"
          "(ssa::RunParams p) { ssa::spec::forward<Net, false, false, true>(p); }\n";
@@ -137,7 +140,8 @@ bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
         hipModuleGetFunction(&k.bwd_grid, k.module, "ssa_spec_bwd_grid") != hipSuccess ||
         hipModuleGetFunction(&k.fwd_cdf, k.module, "ssa_spec_fwd_cdf") != hipSuccess ||
         hipModuleGetFunction(&k.fwd_tm, k.module, "ssa_spec_fwd_tm") != hipSuccess ||
-        hipModuleGetFunction(&k.bwd_sh, k.module, "ssa_spec_bwd_sh") != hipSuccess) {
+        hipModuleGetFunction(&k.bwd_sh, k.module, "ssa_spec_bwd_sh") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_ens, k.module, "ssa_spec_fwd_ens") != hipSuccess) {
         *log = "loading the compiled module failed";
         return false;
     }
@@ -146,7 +150,8 @@ bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
     return true;
 }
 
-hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, hipStream_t stream)
+hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, size_t dyn_lds,
+                       hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((p.n_items + spec_waves_per_block - 1) / spec_waves_per_block);
     if (blocks == 0) return hipSuccess;
@@ -154,9 +159,13 @@ hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, 
     void *args[] = {&copy};
     const bool grid = p.obs_kind == 2;
     hipFunction_t f = backward ? (grid ? k.bwd_grid : p.dobs_prefix ? k.bwd_sh : k.bwd)
-                               : (p.selection == 1 ? k.fwd_cdf : grid ? k.fwd_grid
-                                                                     : p.obs_tm && p.obs_kind == 1 ? k.fwd_tm : k.fwd);
-    return hipModuleLaunchKernel(f, blocks, 1, 1, 64 * spec_waves_per_block, 1, 1, 0, stream, args, nullptr);
+                               : (p.selection == 1 ? k.fwd_cdf
+                                  : grid           ? k.fwd_grid
+                                  : p.obs_ens      ? k.fwd_ens
+                                  : p.obs_tm && p.obs_kind == 1 ? k.fwd_tm
+                                                   : k.fwd);
+    return hipModuleLaunchKernel(f, blocks, 1, 1, 64 * spec_waves_per_block, 1, 1, (unsigned)dyn_lds, stream, args,
+                                 nullptr);
 }
 
 }  // namespace ssa

@@ -20,6 +20,7 @@ struct SpecKernels {
     hipFunction_t fwd_cdf = nullptr;    // inverse-CDF selection (forward only)
     hipFunction_t fwd_tm = nullptr;     // bin observation, trajectory-major layout
     hipFunction_t bwd_sh = nullptr;     // bin observation, shared dL/dobs (prefix sums)
+    hipFunction_t fwd_ens = nullptr;    // bin observation, ensemble means only (LDS tile sums)
 };
 
 // Source of the specialised kernel pair for one network (host tables).
@@ -27,6 +28,7 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
                         const int8_t *stoich, int n_obs, const int32_t *obs_species);
 // Compiles (or fetches from the in-process cache) the module for `src`.
 bool spec_compile(const std::string &src, SpecKernels *out, std::string *log);
-hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, hipStream_t stream);
+hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, size_t dyn_lds,
+                       hipStream_t stream);
 
 }  // namespace ssa

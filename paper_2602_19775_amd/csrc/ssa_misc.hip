@@ -316,7 +316,7 @@ int obs_mean_chunks(int64_t B)
 }
 
 hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_major, double *sums,
-                           double *mean, hipStream_t stream)
+                           double *mean, int64_t divisor, hipStream_t stream)
 {
     if (W <= 0) return hipSuccess;
     const int nc = obs_mean_chunks(B);
@@ -334,7 +334,7 @@ hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_ma
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(mean_total_kernel, dim3(grid_for(W, 64)), dim3(256), 0, stream, sums, nc, W, B, mean);
+    hipLaunchKernelGGL(mean_total_kernel, dim3(grid_for(W, 64)), dim3(256), 0, stream, sums, nc, W, divisor, mean);
     return hipGetLastError();
 }
 

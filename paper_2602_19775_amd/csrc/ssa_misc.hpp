@@ -17,13 +17,13 @@ hipError_t launch_reduce_params(const NetDev *nets, const int32_t *pmap_off, con
                                 const int32_t *param_net, int64_t param_total, int64_t max_traj,
                                 const double *partials, double *chunk_sums, float *d_params, float *d_ppt,
                                 hipStream_t stream);
-// Ensemble mean of one network's observation block (B trajectories, W values
-// each; traj_major: [B][W], else [W][B]): FP64 sums over chunks of
-// obs_mean_chunks(B) trajectories, then over the chunks in index order, into
-// mean[W].  sums holds obs_mean_chunks(B) * W doubles.
+// Ensemble mean of one network's observation block (B rows, W values each;
+// traj_major: [B][W], else [W][B]): FP64 sums over chunks of rows, then over
+// the chunks in index order, divided by `divisor` into mean[W].  sums holds
+// obs_mean_chunks(B) * W doubles.
 int obs_mean_chunks(int64_t B);
 hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_major, double *sums,
-                           double *mean, hipStream_t stream);
+                           double *mean, int64_t divisor, hipStream_t stream);
 // Prefix sums [obs][n_bins + 1] per network of a shared bin dL/dobs block
 // (networks at obsw_off * n_bins in d_obs, at obsw_off * (n_bins + 1) in pre).
 hipError_t launch_dobs_prefix(const NetDev *nets, int n_networks, int n_bins, const double *d_obs, double *pre,

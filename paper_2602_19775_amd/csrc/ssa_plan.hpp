@@ -54,6 +54,8 @@ struct NetDev {
     int64_t ppt_off;     // sum of P*B (per-trajectory parameter gradients)
     int64_t obsw_off;    // sum of n_obs (times n_bins for bin and grid observations):
                          // ensemble means and a shared dL/dobs
+    int64_t tobs_off;    // sum of ceil(B / 64) * n_obs (times n_bins): per-tile sums of the
+                         // ensemble-mean forward, [tile][n_bins][n_obs] per network
     double t_obs;
 };
 
@@ -134,6 +136,8 @@ struct RunParams {
     int32_t obs_tm;         // obs / d_obs blocks are [trajectory][point][obs]
     int32_t dobs_shared;    // d_obs is one [point][obs] block per network
     const double *dobs_prefix;   // bins, shared d_obs: [obs][n_bins + 1] prefix sums per network
+    double *tile_sums;           // ensemble-mean forward: per-tile sums (NetDev::tobs_off)
+    int32_t obs_ens;             // the forward writes ensemble means (tile sums) only
 
     // wave mode: species -> range of incidence slots, and per channel the
     // slots of its (role 1, role 2) contributions: pos1 | pos2 << 16 with

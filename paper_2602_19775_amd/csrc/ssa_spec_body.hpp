@@ -29,6 +29,8 @@ namespace spec {
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 constexpr int kFold = 32;   // FP32 adjoint increments are folded into FP64 this often
+// register arrays of the observed species need at least one slot
+constexpr int obs_cap(int n) { return n > 0 ? n : 1; }
 
 __device__ __forceinline__ double bin_edge(double t_obs, int b, int n_bins)
 {
@@ -84,6 +86,57 @@ __device__ __forceinline__ void fill_runs(double *blk, int64_t first, int64_t np
                 row[q] = scaled ? ((double)x * fmax(bin_edge(t_obs, b + 1, n_bins) - bin_edge(t_obs, b, n_bins),
                                                     0.0)) * inv_dt
                                 : (double)x;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The ensemble-mean forward's counterpart of fill_runs: lane l's single bin
+// fb_l (values fv_l, the bin an interval completes or the one the path stops
+// in; -1 for none) and its run [lo_l, hi_l) are added to the wave's LDS sums
+// ens [bin][obs], one lane at a time in lane order, so every sum takes its
+// terms in the same order on every run.  wtab[b] holds bin b's width as the
+// per-bin accumulation computes it.  Every lane of the wave must be active.
+template <class NET>
+__device__ __forceinline__ void add_runs(double *ens, const double *wtab, int fb,
+                                         const double (&fv)[obs_cap(NET::NOBS)], int lo, int hi,
+                                         const int (&X)[NET::N + 1], bool scaled, double inv_dt)
+{
+    constexpr int NOBS = NET::NOBS;
+    if constexpr (NOBS > 0) {
+        const int lane = threadIdx.x & 63;
+        uint64_t m = ballot(fb >= 0 || hi > lo);
+        while (m != 0ull) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            const int rfb = __builtin_amdgcn_readlane(fb, l);
+            if (rfb >= 0) {
+                double v = 0.0;
+#pragma unroll
+                for (int u = 0; u < NOBS; ++u) {
+                    const double fu = readlane_f64(fv[u], l);
+                    v = lane == u ? fu : v;
+                }
+                if (lane < NOBS) ens[rfb * NOBS + lane] += v;
+            }
+            const int rlo = __builtin_amdgcn_readlane(lo, l), rhi = __builtin_amdgcn_readlane(hi, l);
+            int xv[NOBS];
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) xv[o] = __builtin_amdgcn_readlane(X[NET::OBS[o]], l);
+            for (int q = rlo * NOBS + lane; q < rhi * NOBS; q += 64) {
+                const int b = q / NOBS, o = q - b * NOBS;
+                int x = xv[0];
+#pragma unroll
+                for (int u = 1; u < NOBS; ++u) x = o == u ? xv[u] : x;
+                ens[q] += scaled ? ((double)x * wtab[b]) * inv_dt : (double)x;
             }
         }
     }
@@ -167,15 +220,15 @@ __device__ __forceinline__ void rates(const RunParams &p, const NetDev &nd, floa
     for (int j = 0; j < NET::M; ++j) c[j] = expf(p.theta[nd.param_off + NET::RATE[j]]) * NET::MULT[j];
 }
 
-constexpr int obs_cap(int n) { return n > 0 ? n : 1; }
-
 // --------------------------------------------------------------------------
 // GRID: the grid observation (the other kinds are runtime cases of GRID = false).
 // CDF: the channel is the standard direct method's inverse-CDF draw from word 1
 // (Sec. 2) instead of the Gumbel-max race; such a run has no backward.
 // TMB: bin observations in the trajectory-major layout, whose whole bins are
 // filled by the wave (the other kernels take either layout through strides).
-template <class NET, bool HAS_T_END, bool GRID, bool CDF = false, bool TMB = false>
+// ENS (with TMB): only the ensemble means are kept; each wave sums its
+// trajectories' bins in LDS and stores one row of sums for its tile.
+template <class NET, bool HAS_T_END, bool GRID, bool CDF = false, bool TMB = false, bool ENS = false>
 __device__ void forward_run(const RunParams &p)
 {
     constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
@@ -216,6 +269,16 @@ __device__ void forward_run(const RunParams &p)
     const int64_t orow = p.obs_tm ? (int64_t)NOBS : (int64_t)NOBS * B, ocol = p.obs_tm ? 1 : B;
     double *obs_base = p.obs + nd.obsb_off * npts;
     double *obs_lane = obs_base + (p.obs_tm ? i * npts * NOBS : i);
+    // ensemble-mean forward: the wave's sums [bin][obs] in LDS, cleared here,
+    // followed by its table of bin widths
+    extern __shared__ double s_ens[];
+    double *ens = ENS ? s_ens + (int64_t)wid * n_bins * (NOBS + 1) : nullptr;
+    double *wtab = ENS ? ens + n_bins * NOBS : nullptr;
+    if (ENS) {
+        for (int q = lane; q < n_bins * NOBS; q += 64) ens[q] = 0.0;
+        for (int b = lane; b < n_bins; b += 64)
+            wtab[b] = fmax(bin_edge(t_obs, b + 1, n_bins) - bin_edge(t_obs, b, n_bins), 0.0);
+    }
     // grid observation: next grid point gi, at time grid_t >= t
     int gi = 0;
     double grid_t = grid ? 0.0 : INFINITY;
@@ -330,7 +393,8 @@ __device__ void forward_run(const RunParams &p)
                 }
             }
             // bins the interval completes
-            int run_lo = 0, run_hi = 0;
+            int run_lo = 0, run_hi = 0, fb = -1;
+            double fv[NO];
             if (TMB && crossing) {
                 // the first one carries the accumulated integral; the whole
                 // bins after it go to the wave-wide fill; the last bin the
@@ -339,9 +403,11 @@ __device__ void forward_run(const RunParams &p)
 #pragma unroll
                 for (int o = 0; o < NO; ++o) {
                     acc[o] += (double)X[NET::OBS[o]] * fmax(bin_hi - t, 0.0);
-                    if (o < NOBS) obs_lane[bin * orow + o * ocol] = acc[o] * inv_dt;
+                    fv[o] = acc[o] * inv_dt;
+                    if (!ENS && o < NOBS) obs_lane[bin * orow + o * ocol] = fv[o];
                     acc[o] = 0.0;
                 }
+                fb = bin;
                 int b = bin + 1;
                 if (b < n_bins) {
                     const double est = ceil(tn * (double)n_bins / t_obs) - 1.0;
@@ -358,7 +424,8 @@ __device__ void forward_run(const RunParams &p)
                 bin = b;
                 bin_hi = b < n_bins ? bin_edge(t_obs, b + 1, n_bins) : INFINITY;
             }
-            if (TMB) fill_runs<NET>(obs_base, it.first, npts, run_lo, run_hi, X, true, t_obs, n_bins, inv_dt);
+            if (ENS) add_runs<NET>(ens, wtab, fb, fv, run_lo, run_hi, X, true, inv_dt);
+            else if (TMB) fill_runs<NET>(obs_base, it.first, npts, run_lo, run_hi, X, true, t_obs, n_bins, inv_dt);
             if (!TMB && crossing) {
                 double t0 = t;
                 while (bin < n_bins) {
@@ -415,12 +482,23 @@ __device__ void forward_run(const RunParams &p)
     }
     // hold the last state up to t_obs: the rest of the current bin, then every
     // later bin, whose average is the last state itself
-    if (TMB)
+    if (ENS) {
+        const bool tail = valid && bin < n_bins;
+        double fv[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+            fv[o] = (acc[o] + (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0)) * inv_dt;
+        add_runs<NET>(ens, wtab, tail ? bin : -1, fv, tail ? bin + 1 : 0, tail ? n_bins : 0, X, false, inv_dt);
+        // the tile's row of sums
+        double *row = p.tile_sums + nd.tobs_off * n_bins + (int64_t)(it.first >> 6) * n_bins * NOBS;
+        for (int q = lane; q < n_bins * NOBS; q += 64) row[q] = ens[q];
+    } else if (TMB) {
         fill_runs<NET>(obs_base, it.first, npts, valid && bin < n_bins ? bin + 1 : 0,
                        valid && bin < n_bins ? n_bins : 0, X, false, t_obs, n_bins, inv_dt);
+    }
     if (!valid) return;
     if (spw && (k & (spw - 1)) != 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
-    if (bin < n_bins) {
+    if (!ENS && bin < n_bins) {
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
             acc[o] += (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0);
@@ -452,11 +530,11 @@ __device__ void forward_run(const RunParams &p)
     if (flags) atomicOr(p.flags, flags);
 }
 
-template <class NET, bool GRID, bool CDF = false, bool TMB = false>
+template <class NET, bool GRID, bool CDF = false, bool TMB = false, bool ENS = false>
 __device__ void forward(const RunParams &p)
 {
-    if (p.t_end < INFINITY) forward_run<NET, true, GRID, CDF, TMB>(p);
-    else forward_run<NET, false, GRID, CDF, TMB>(p);
+    if (p.t_end < INFINITY) forward_run<NET, true, GRID, CDF, TMB, ENS>(p);
+    else forward_run<NET, false, GRID, CDF, TMB, ENS>(p);
 }
 
 // --------------------------------------------------------------------------

@@ -14,10 +14,12 @@
   0.001 for the dimerisation, 0.05 to 0.0005 for the channel), the learning
   rate geometrically as well (the channel's in proportion to the
   temperature, Sec. 4.4).
-- **Layout.** The runs write each trajectory's observation contiguously
-  (trajectory-major), the library reduces it to the ensemble means, and the
-  backward reads the loss gradient as one block shared by all trajectories
-  (every trajectory's dL/dobs is the same for a loss of ensemble means).
+- **Layout.** Bin observations are summed over the ensemble inside the
+  forward, which stores only the means; grid observations are written
+  trajectory by trajectory (trajectory-major) and reduced to the means by the
+  library.  The backward reads the loss gradient as one block shared by all
+  trajectories (every trajectory's dL/dobs is the same for a loss of
+  ensemble means).
 - **Graph.** One optimisation step is captured once into a HIP graph and
   replayed per epoch. The step is: forward, loss gradient, backward, RMSprop
   update, schedule update and epoch count. The epoch, the temperature and the
@@ -91,14 +93,15 @@ class Trainer:
         self.epochs = epochs
         self.n_pts = cfg.n_bins if cfg.obs_kind != W.OBS_FINAL else 1
         self.n_obs, self.B = len(true_net.obs_species), n_traj
-        self.cfg = cfg.replace(temperature=t0, obs_layout=W.OBS_TRAJ_MAJOR, dobs_shared=True)
+        layout = W.OBS_ENSEMBLE_MEAN if cfg.obs_kind == W.OBS_BINS else W.OBS_TRAJ_MAJOR
+        self.cfg = cfg.replace(temperature=t0, obs_layout=layout, dobs_shared=True)
         P_, O_ = self.n_pts, self.n_obs
         # target ensemble means
         ht = ssa.Net([true_net], [n_target], t_obs=[self.t_obs])
         tf = ssa.forward(ht, self.cfg.replace(purpose=W.PURPOSE_TARGET),
                          torch.tensor(true_net.theta0, device=dev), _x0(true_net, n_target),
                          keep_ckpt=False, tie_capacity=0)
-        self.target = ssa.obs_mean(ht, tf).view(P_, O_).clone()
+        self.target = self._means_of(ht, tf).view(P_, O_).clone()
         del tf, ht
         # model state and schedules (device scalars)
         self.h = ssa.Net([true_net], [n_traj], t_obs=[self.t_obs])
@@ -122,10 +125,15 @@ class Trainer:
                                 d_temperature=self.temp)
         self.graph: Optional[CapturedStep] = None
 
+    def _means_of(self, h, fwd, out=None) -> torch.Tensor:
+        if self.cfg.obs_layout == W.OBS_ENSEMBLE_MEAN:
+            return fwd.obs[: self.n_pts * self.n_obs]
+        return ssa.obs_mean(h, fwd, out=out)
+
     def means(self, fwd=None) -> torch.Tensor:
         """Ensemble means [points][species] of the model forward's observation."""
-        ssa.obs_mean(self.h, self.bufs if fwd is None else fwd, out=self.mean)
-        return self.mean.view(self.n_pts, self.n_obs)
+        m = self._means_of(self.h, self.bufs if fwd is None else fwd, out=self.mean)
+        return m.view(self.n_pts, self.n_obs)
 
     def d_obs_of(self, e: torch.Tensor, out: torch.Tensor):
         """dL/dobs = 2 (mean - target) / (points * species * B), the same for

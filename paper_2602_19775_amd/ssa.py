@@ -239,7 +239,8 @@ def forward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, *
     ccfg = make_cfg(cfg, tie_capacity, bwd_mode, traj_ids, d_epoch, d_temperature)
     ck_bytes, wk_bytes = buffer_sizes(net, ccfg)
     if buffers is None:
-        obs_n = max(net.obs_total(cfg.obs_kind, cfg.n_bins), 1)
+        obs_n = max(net.mean_total(cfg.obs_kind, cfg.n_bins) if cfg.obs_layout == W.OBS_ENSEMBLE_MEAN
+                    else net.obs_total(cfg.obs_kind, cfg.n_bins), 1)
         buffers = Forward(
             torch.empty(net.state_total, dtype=torch.int32, device=dev),
             torch.empty(net.traj_total, dtype=torch.float64, device=dev),

@@ -30,9 +30,11 @@ OBS_GRID = 2    # the path linearly interpolated between its event points at n_b
 # no straight-through backward.
 SELECT_GUMBEL_MAX = 0
 SELECT_INVERSE_CDF = 1
-# memory order of an observation block: [point][obs][trajectory] or [trajectory][point][obs]
+# memory order of an observation block: [point][obs][trajectory] or [trajectory][point][obs];
+# or only the ensemble means [point][obs] of each network
 OBS_POINT_MAJOR = 0
 OBS_TRAJ_MAJOR = 1
+OBS_ENSEMBLE_MEAN = 2
 
 # Random-stream purposes (high byte of the fourth Philox counter word).
 PURPOSE_SIMULATE = 0
@@ -257,7 +259,7 @@ class RunConfig:
     temperature: float = 0.5
     ckpt_every: int = 256
     selection: int = 0                # SELECT_GUMBEL_MAX or SELECT_INVERSE_CDF (forward only)
-    obs_layout: int = 0               # OBS_POINT_MAJOR or OBS_TRAJ_MAJOR (memory order of obs / d_obs)
+    obs_layout: int = 0               # OBS_POINT_MAJOR, OBS_TRAJ_MAJOR or OBS_ENSEMBLE_MEAN
     dobs_shared: bool = False         # d_obs is one block per network (a loss of ensemble means)
 
     def replace(self, **kw) -> "RunConfig":

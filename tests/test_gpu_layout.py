@@ -220,3 +220,77 @@ def test_shared_bins_backward_variants(ssa, bwd_mode, T):
     sample = np.unique(np.concatenate([[0, B - 1], g.choice(B, 40, replace=False)]))
     gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, bwd_mode=bwd_mode, sample=sample)
     _parity(gpu, r, ids, cfg)
+
+
+@pytest.mark.parametrize("case", ["channel_bins", "abc_bins"])
+def test_ensemble_mean_forward(ssa, case):
+    """The forward that keeps only the ensemble means of the bins: against
+    the mean of the oracle's bin averages over every trajectory (the same
+    near-tie choices), against the trajectory-major forward of the same seeds
+    reduced by ssa_obs_mean, repeatable bit for bit, and followed by the same
+    backward as that forward."""
+    mk, cfg, B = CASES[case]
+    net = mk()
+    nob = len(net.obs_species)
+    h = ssa.Net([net], [B], t_obs=[cfg.t_obs])
+    th = torch.tensor(net.theta0, device="cuda")
+    x0 = _x0([net], [B])
+    ens = cfg.replace(obs_layout=W.OBS_ENSEMBLE_MEAN, dobs_shared=True)
+    f1 = ssa.forward(h, ens, th, x0, tie_capacity=1 << 16, bwd_mode="tape")
+    m1 = f1.obs.cpu().numpy()[: cfg.n_bins * nob].reshape(cfg.n_bins, nob)
+    f2 = ssa.forward(h, ens, th, x0, tie_capacity=1 << 16, bwd_mode="tape")
+    assert np.array_equal(f2.obs.cpu().numpy(), f1.obs.cpu().numpy())
+    # the oracle, every trajectory
+    ties = f1.tie_records()
+    r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(B), ties=_ties_for_oracle(ties))
+    assert r.n_bad.sum() == 0
+    assert np.array_equal(f1.x_final.cpu().numpy().reshape(net.n_species, B).T, r.x_final)
+    drift = float(np.max(np.abs(f1.t_final.cpu().numpy() - r.t_final)))
+    ref = np.asarray(r.obs, np.float64).reshape(B, cfg.n_bins, nob).mean(axis=0)
+    big = float(np.abs(r.obs).max())
+    atol = 4.0 * big * drift * cfg.n_bins / cfg.t_obs + 1e-12
+    assert np.all(np.abs(m1 - ref) <= 1e-5 * np.abs(ref) + atol)
+    # the trajectory-major forward of the same seeds, reduced by the library
+    tm = cfg.replace(obs_layout=W.OBS_TRAJ_MAJOR, dobs_shared=True)
+    f3 = ssa.forward(h, tm, th, x0, tie_capacity=1 << 16, bwd_mode="tape")
+    m3 = ssa.obs_mean(h, f3).cpu().numpy().reshape(cfg.n_bins, nob)
+    assert np.allclose(m1, m3, rtol=1e-12, atol=1e-12 * np.abs(m3).max())
+    # the backward reads checkpoints and tape only: the same after both forwards
+    d = torch.tensor(np.random.default_rng(2).normal(size=cfg.n_bins * nob), device="cuda")
+    g1 = ssa.backward(h, ens, th, x0, f1, d, per_traj=True)[1]
+    g3 = ssa.backward(h, tm, th, x0, f3, d, per_traj=True)[1]
+    assert torch.equal(g1, g3)
+
+
+def test_ensemble_mean_forward_networks_and_limits(ssa):
+    """Two topologies and an empty network in one handle; the combinations
+    the ensemble-mean forward does not run are refused before any launch."""
+    nets = [W.ion_channel_coi(n_channels=2), W.dimerization_abc(), W.dimerization_2a()]
+    Bs = [777, 130, 0]
+    cfg = W.RunConfig(seed=13, n_steps=40, obs_kind=W.OBS_BINS, n_bins=25, t_obs=5.0, temperature=0.5,
+                      ckpt_every=16, obs_layout=W.OBS_ENSEMBLE_MEAN, dobs_shared=True)
+    h = ssa.Net(nets, Bs, t_obs=[5.0, 5.0, 5.0])
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    x0 = _x0(nets, Bs)
+    f = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 16)
+    m = f.obs.cpu().numpy()
+    ft = ssa.forward(h, cfg.replace(obs_layout=W.OBS_TRAJ_MAJOR), th, x0, tie_capacity=1 << 16)
+    mt = ssa.obs_mean(h, ft).cpu().numpy()
+    assert m.size >= h.mean_total(cfg.obs_kind, cfg.n_bins)
+    n = h.mean_total(cfg.obs_kind, cfg.n_bins)
+    assert np.allclose(m[:n], mt[:n], rtol=1e-12, atol=1e-12 * np.abs(mt[:n]).max())
+    off = h.layout(2, cfg.obs_kind, cfg.n_bins).mean_offset
+    assert np.all(m[off:n] == 0.0)
+    with pytest.raises(ssa.SSAError, match="means already"):
+        ssa.obs_mean(h, f)
+    f0 = ssa.forward(h, cfg.replace(dobs_shared=False), th, x0, tie_capacity=0)
+    with pytest.raises(ssa.SSAError, match="shared d_obs"):
+        ssa.backward(h, cfg, th, x0, f0, torch.zeros(n, dtype=torch.float64, device="cuda"))
+    for bad, msg in ((cfg.replace(obs_kind=W.OBS_GRID), "bins only"),
+                     (cfg.replace(selection=W.SELECT_INVERSE_CDF), "per-trajectory"),
+                     (cfg.replace(n_bins=1025), "2048")):
+        with pytest.raises(ssa.SSAError, match=msg):
+            ssa.forward(h, bad, th, x0)
+    hl = ssa.Net(nets[:1], Bs[:1], t_obs=[5.0], exec_mode="lane")
+    with pytest.raises(ssa.SSAError, match="specialised"):
+        ssa.forward(hl, cfg, th[: nets[0].n_params], _x0(nets[:1], Bs[:1]))
