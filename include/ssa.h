@@ -106,13 +106,14 @@ enum { SSA_SELECT_GUMBEL_MAX = 0, SSA_SELECT_INVERSE_CDF = 1 };
 enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1, SSA_OBS_ENSEMBLE_MEAN = 2 };
 /* SSA_OBS_ENSEMBLE_MEAN: ssa_forward writes the ensemble means themselves
  * (the ssa_obs_mean layout, double [sum W_n]) and never stores the values of
- * single trajectories.  Each wave sums its trajectories' values in LDS in a
- * fixed lane order, each 64-trajectory tile leaves one row of sums, and the
- * rows of a network are reduced in a fixed order, so the result is the same
- * on every call.  Bin observations, topology-specialised lane mode,
- * n_bins * (n_obs + 1) <= 2048 (a wave holds its sums and the bin widths in
- * LDS); ssa_backward then needs dobs_shared.  Anything else returns
- * SSA_ENOTSUP. */
+ * single trajectories.  Each wave sums its trajectories' values in LDS with
+ * integer additions: runs of whole bins as counts in difference arrays (exact),
+ * the bins an interval or the tail only partly covers in fixed point with
+ * 2^-32 resolution (the means carry at most 2^-33 absolute error from it).
+ * Each 64-trajectory tile leaves one row of sums and the rows of a network are
+ * reduced in a fixed order, so the result is the same on every call.  Bin
+ * observations, topology-specialised lane mode, n_bins * n_obs <= 1000;
+ * ssa_backward then needs dobs_shared.  Anything else returns SSA_ENOTSUP. */
 
 /* How ssa_backward obtains the fired channel of each step.
  *   SSA_BWD_TAPE:      ssa_forward stores the fired channel index of every

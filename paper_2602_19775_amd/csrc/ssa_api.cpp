@@ -119,9 +119,9 @@ int resolve_bwd_mode(const ssa_config *cfg)
 }
 
 constexpr int kMaxRecomputeSegment = 64;
-// LDS doubles a wave of the ensemble-mean forward holds: n_bins * n_obs sums
-// and n_bins bin widths (4 waves x 16 KiB a block)
-constexpr int64_t kMeanMaxValues = 2048;
+// values a wave of the ensemble-mean forward sums in LDS (16 bytes each:
+// a fixed-point sum and two difference-array counts; 4 waves a block)
+constexpr int64_t kMeanMaxValues = 1000;
 
 bool bounded_steps(const ssa_config *cfg)
 {
@@ -243,8 +243,8 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
         if (cfg->obs_kind != SSA_OBS_BINS)
             return fail(SSA_ENOTSUP, "the ensemble-mean forward observes bins only");
         for (const NetDev &nd : net->nets_h)
-            if ((int64_t)(nd.n_obs + 1) * cfg->n_bins > kMeanMaxValues)
-                return fail(SSA_ENOTSUP, "the ensemble-mean forward needs n_bins * (n_obs + 1) <= 2048");
+            if ((int64_t)nd.n_obs * cfg->n_bins > kMeanMaxValues)
+                return fail(SSA_ENOTSUP, "the ensemble-mean forward needs n_bins * n_obs <= 1000");
     }
     if (cfg->obs_layout != SSA_OBS_POINT_MAJOR || cfg->dobs_shared)
         for (const auto &gr : net->groups)
@@ -316,9 +316,10 @@ ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hi
             e = launch_fill_u32(p.work_counter, 1, 0u, stream);
             if (e == hipSuccess) e = wave_launch(gr.wave_class, p, backward, gr.wave_blocks, stream);
         } else {
-            const size_t mean_lds = !backward && p.obs_ens ? sizeof(double) * spec_waves_per_block *
-                                                                 (size_t)p.n_bins * (gr.spec_nobs + 1)
-                                                           : 0;
+            const size_t mean_lds = !backward && p.obs_ens
+                                        ? spec_waves_per_block * (16 * (size_t)p.n_bins * gr.spec_nobs +
+                                                                  8 * (size_t)gr.spec_nobs)
+                                        : 0;
             e = gr.spec ? spec_launch(gr.kernels, p, backward, mean_lds, stream)
                         : lane_launch(gr.lane_class, p, backward, stream);
         }

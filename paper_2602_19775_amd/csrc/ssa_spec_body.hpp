@@ -99,45 +99,71 @@ __device__ __forceinline__ double readlane_f64(double v, int l)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// The ensemble-mean forward's counterpart of fill_runs: lane l's single bin
-// fb_l (values fv_l, the bin an interval completes or the one the path stops
-// in; -1 for none) and its run [lo_l, hi_l) are added to the wave's LDS sums
-// ens [bin][obs], one lane at a time in lane order, so every sum takes its
-// terms in the same order on every run.  wtab[b] holds bin b's width as the
-// per-bin accumulation computes it.  Every lane of the wave must be active.
+// Fixed-point scale of the single-bin values the ensemble-mean forward sums.
+constexpr double kFixScale = 4294967296.0;   // 2^32
+
+// The ensemble-mean forward's additions for one lane: the value of a single
+// bin fb (the bin an interval completes or the one the path stops in; -1 for
+// none) in fixed point with 2^-32 resolution, and the run [lo, hi) of whole
+// bins holding the count x as +x at lo and -x at hi in a difference array of
+// counts (dsc for bins an interval crosses, whose values are the count times
+// the bin width over the nominal width; dun for the held tail, whose values
+// are the count).  Integer additions commute, so the wave's sums do not depend
+// on the order in which its lanes reach them.
 template <class NET>
-__device__ __forceinline__ void add_runs(double *ens, const double *wtab, int fb,
-                                         const double (&fv)[obs_cap(NET::NOBS)], int lo, int hi,
-                                         const int (&X)[NET::N + 1], bool scaled, double inv_dt)
+__device__ __forceinline__ void ens_add(long long *sfp, int *dsc, int *dun, int fb,
+                                        const double (&fv)[obs_cap(NET::NOBS)], int lo, int hi,
+                                        const int (&X)[NET::N + 1], bool scaled)
 {
     constexpr int NOBS = NET::NOBS;
-    if constexpr (NOBS > 0) {
-        const int lane = threadIdx.x & 63;
-        uint64_t m = ballot(fb >= 0 || hi > lo);
-        while (m != 0ull) {
-            const int l = __builtin_ctzll(m);
-            m &= m - 1;
-            const int rfb = __builtin_amdgcn_readlane(fb, l);
-            if (rfb >= 0) {
-                double v = 0.0;
+    if (fb >= 0) {
 #pragma unroll
-                for (int u = 0; u < NOBS; ++u) {
-                    const double fu = readlane_f64(fv[u], l);
-                    v = lane == u ? fu : v;
-                }
-                if (lane < NOBS) ens[rfb * NOBS + lane] += v;
-            }
-            const int rlo = __builtin_amdgcn_readlane(lo, l), rhi = __builtin_amdgcn_readlane(hi, l);
-            int xv[NOBS];
+        for (int o = 0; o < NOBS; ++o)
+            atomicAdd((unsigned long long *)&sfp[fb * NOBS + o], (unsigned long long)(long long)rint(fv[o] * kFixScale));
+    }
+    if (hi > lo) {
+        int *d = scaled ? dsc : dun;
 #pragma unroll
-            for (int o = 0; o < NOBS; ++o) xv[o] = __builtin_amdgcn_readlane(X[NET::OBS[o]], l);
-            for (int q = rlo * NOBS + lane; q < rhi * NOBS; q += 64) {
-                const int b = q / NOBS, o = q - b * NOBS;
-                int x = xv[0];
+        for (int o = 0; o < NOBS; ++o) {
+            const int x = X[NET::OBS[o]];
+            atomicAdd(&d[lo * NOBS + o], x);
+            atomicAdd(&d[hi * NOBS + o], -x);
+        }
+    }
+}
+
+// The wave's row of sums [bin][obs]: each lane takes a contiguous chunk of
+// bins, the difference arrays are summed over the chunks before it (an
+// exclusive scan over the lanes), and each bin's sum is the fixed-point part
+// plus the crossed-bin counts times the bin width over the nominal width plus
+// the tail counts.  Every lane of the wave must be active.
+template <class NET>
+__device__ __forceinline__ void ens_row(double *row, const long long *sfp, const int *dsc, const int *dun,
+                                        int n_bins, double t_obs, double inv_dt)
+{
+    constexpr int NOBS = NET::NOBS;
+    const int lane = threadIdx.x & 63;
+    const int per = (n_bins + 63) / 64;
+    const int b0 = min(lane * per, n_bins), b1 = min(b0 + per, n_bins);
 #pragma unroll
-                for (int u = 1; u < NOBS; ++u) x = o == u ? xv[u] : x;
-                ens[q] += scaled ? ((double)x * wtab[b]) * inv_dt : (double)x;
-            }
+    for (int o = 0; o < NOBS; ++o) {
+        int ts = 0, tu = 0;
+        for (int b = b0; b < b1; ++b) {
+            ts += dsc[b * NOBS + o];
+            tu += dun[b * NOBS + o];
+        }
+        int cs = ts, cu = tu;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int as = __shfl_up(cs, off), au = __shfl_up(cu, off);
+            if (lane >= off) { cs += as; cu += au; }
+        }
+        int ps = cs - ts, pu = cu - tu;
+        for (int b = b0; b < b1; ++b) {
+            ps += dsc[b * NOBS + o];
+            pu += dun[b * NOBS + o];
+            const double w = fmax(bin_edge(t_obs, b + 1, n_bins) - bin_edge(t_obs, b, n_bins), 0.0);
+            row[b * NOBS + o] = (double)sfp[b * NOBS + o] * (1.0 / kFixScale) + ((double)ps * w) * inv_dt + (double)pu;
         }
     }
 }
@@ -227,7 +253,8 @@ __device__ __forceinline__ void rates(const RunParams &p, const NetDev &nd, floa
 // TMB: bin observations in the trajectory-major layout, whose whole bins are
 // filled by the wave (the other kernels take either layout through strides).
 // ENS (with TMB): only the ensemble means are kept; each wave sums its
-// trajectories' bins in LDS and stores one row of sums for its tile.
+// trajectories' bins in LDS (integer additions, so in any order) and stores
+// one row of sums for its tile.
 template <class NET, bool HAS_T_END, bool GRID, bool CDF = false, bool TMB = false, bool ENS = false>
 __device__ void forward_run(const RunParams &p)
 {
@@ -269,15 +296,16 @@ __device__ void forward_run(const RunParams &p)
     const int64_t orow = p.obs_tm ? (int64_t)NOBS : (int64_t)NOBS * B, ocol = p.obs_tm ? 1 : B;
     double *obs_base = p.obs + nd.obsb_off * npts;
     double *obs_lane = obs_base + (p.obs_tm ? i * npts * NOBS : i);
-    // ensemble-mean forward: the wave's sums [bin][obs] in LDS, cleared here,
-    // followed by its table of bin widths
-    extern __shared__ double s_ens[];
-    double *ens = ENS ? s_ens + (int64_t)wid * n_bins * (NOBS + 1) : nullptr;
-    double *wtab = ENS ? ens + n_bins * NOBS : nullptr;
+    // ensemble-mean forward: the wave's fixed-point single-bin sums and its
+    // two difference arrays of counts in LDS, cleared here
+    extern __shared__ long long s_ens[];
+    const int ens_w = n_bins * NOBS;
+    long long *sfp = ENS ? s_ens + (int64_t)wid * (2 * ens_w + NOBS) : nullptr;
+    int *dsc = ENS ? (int *)(sfp + ens_w) : nullptr;
+    int *dun = ENS ? dsc + ens_w + NOBS : nullptr;
     if (ENS) {
-        for (int q = lane; q < n_bins * NOBS; q += 64) ens[q] = 0.0;
-        for (int b = lane; b < n_bins; b += 64)
-            wtab[b] = fmax(bin_edge(t_obs, b + 1, n_bins) - bin_edge(t_obs, b, n_bins), 0.0);
+        for (int q = lane; q < ens_w; q += 64) sfp[q] = 0;
+        for (int q = lane; q < ens_w + NOBS; q += 64) { dsc[q] = 0; dun[q] = 0; }
     }
     // grid observation: next grid point gi, at time grid_t >= t
     int gi = 0;
@@ -424,7 +452,7 @@ __device__ void forward_run(const RunParams &p)
                 bin = b;
                 bin_hi = b < n_bins ? bin_edge(t_obs, b + 1, n_bins) : INFINITY;
             }
-            if (ENS) add_runs<NET>(ens, wtab, fb, fv, run_lo, run_hi, X, true, inv_dt);
+            if (ENS) ens_add<NET>(sfp, dsc, dun, fb, fv, run_lo, run_hi, X, true);
             else if (TMB) fill_runs<NET>(obs_base, it.first, npts, run_lo, run_hi, X, true, t_obs, n_bins, inv_dt);
             if (!TMB && crossing) {
                 double t0 = t;
@@ -488,10 +516,12 @@ __device__ void forward_run(const RunParams &p)
 #pragma unroll
         for (int o = 0; o < NO; ++o)
             fv[o] = (acc[o] + (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0)) * inv_dt;
-        add_runs<NET>(ens, wtab, tail ? bin : -1, fv, tail ? bin + 1 : 0, tail ? n_bins : 0, X, false, inv_dt);
-        // the tile's row of sums
-        double *row = p.tile_sums + nd.tobs_off * n_bins + (int64_t)(it.first >> 6) * n_bins * NOBS;
-        for (int q = lane; q < n_bins * NOBS; q += 64) row[q] = ens[q];
+        ens_add<NET>(sfp, dsc, dun, tail ? bin : -1, fv, tail ? bin + 1 : 0, tail ? n_bins : 0, X, false);
+        // every lane's additions land before the row is read back
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        ens_row<NET>(p.tile_sums + nd.tobs_off * n_bins + (int64_t)(it.first >> 6) * n_bins * NOBS, sfp, dsc, dun,
+                     n_bins, t_obs, inv_dt);
     } else if (TMB) {
         fill_runs<NET>(obs_base, it.first, npts, valid && bin < n_bins ? bin + 1 : 0,
                        valid && bin < n_bins ? n_bins : 0, X, false, t_obs, n_bins, inv_dt);
