@@ -111,8 +111,9 @@ enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1, SSA_OBS_ENSEMBLE_MEAN = 
  * the bins an interval or the tail only partly covers in fixed point with
  * 2^-32 resolution (the means carry at most 2^-33 absolute error from it).
  * Each 64-trajectory tile leaves one row of sums and the rows of a network are
- * reduced in a fixed order, so the result is the same on every call.  Bin
- * observations, topology-specialised lane mode, n_bins * n_obs <= 1000;
+ * reduced in a fixed order, so the result is the same on every call.  Bin and
+ * grid observations (grid values are summed in the same fixed point, the held
+ * tail as counts), topology-specialised lane mode, n_bins * n_obs <= 1000;
  * ssa_backward then needs dobs_shared.  Anything else returns SSA_ENOTSUP. */
 
 /* How ssa_backward obtains the fired channel of each step.

@@ -240,8 +240,8 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
         cfg->obs_layout != SSA_OBS_ENSEMBLE_MEAN)
         return fail(SSA_EINVAL, "obs_layout must be SSA_OBS_POINT_MAJOR, SSA_OBS_TRAJ_MAJOR or SSA_OBS_ENSEMBLE_MEAN");
     if (cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN) {
-        if (cfg->obs_kind != SSA_OBS_BINS)
-            return fail(SSA_ENOTSUP, "the ensemble-mean forward observes bins only");
+        if (cfg->obs_kind == SSA_OBS_FINAL)
+            return fail(SSA_ENOTSUP, "the ensemble-mean forward observes bins or grid points only");
         for (const NetDev &nd : net->nets_h)
             if ((int64_t)nd.n_obs * cfg->n_bins > kMeanMaxValues)
                 return fail(SSA_ENOTSUP, "the ensemble-mean forward needs n_bins * n_obs <= 1000");

@@ -80,9 +80,11 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
     // the backward of bin observations with a shared dL/dobs block
     s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_bwd_sh"
          "(ssa::RunParams p) { ssa::spec::backward<Net, false, true>(p); }\n";
-    // the forward of bin observations that keeps only the ensemble means
+    // the forwards of bin and grid observations that keep only the ensemble means
     s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_ens"
          "(ssa::RunParams p) { ssa::spec::forward<Net, false, false, true, true>(p); }\n";
+    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_grid_ens"
+         "(ssa::RunParams p) { ssa::spec::forward<Net, true, false, false, true>(p); }\n";
     // the forward of bin observations in the trajectory-major layout
     s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_tm"
          "(ssa::RunParams p) { ssa::spec::forward<Net, false, false, true>(p); }\n";
@@ -141,7 +143,8 @@ bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
         hipModuleGetFunction(&k.fwd_cdf, k.module, "ssa_spec_fwd_cdf") != hipSuccess ||
         hipModuleGetFunction(&k.fwd_tm, k.module, "ssa_spec_fwd_tm") != hipSuccess ||
         hipModuleGetFunction(&k.bwd_sh, k.module, "ssa_spec_bwd_sh") != hipSuccess ||
-        hipModuleGetFunction(&k.fwd_ens, k.module, "ssa_spec_fwd_ens") != hipSuccess) {
+        hipModuleGetFunction(&k.fwd_ens, k.module, "ssa_spec_fwd_ens") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_grid_ens, k.module, "ssa_spec_fwd_grid_ens") != hipSuccess) {
         *log = "loading the compiled module failed";
         return false;
     }
@@ -160,7 +163,7 @@ hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, 
     const bool grid = p.obs_kind == 2;
     hipFunction_t f = backward ? (grid ? k.bwd_grid : p.dobs_prefix ? k.bwd_sh : k.bwd)
                                : (p.selection == 1 ? k.fwd_cdf
-                                  : grid           ? k.fwd_grid
+                                  : grid           ? (p.obs_ens ? k.fwd_grid_ens : k.fwd_grid)
                                   : p.obs_ens      ? k.fwd_ens
                                   : p.obs_tm && p.obs_kind == 1 ? k.fwd_tm
                                                    : k.fwd);

@@ -21,6 +21,7 @@ struct SpecKernels {
     hipFunction_t fwd_tm = nullptr;     // bin observation, trajectory-major layout
     hipFunction_t bwd_sh = nullptr;     // bin observation, shared dL/dobs (prefix sums)
     hipFunction_t fwd_ens = nullptr;    // bin observation, ensemble means only (LDS tile sums)
+    hipFunction_t fwd_grid_ens = nullptr;   // grid observation, ensemble means only
 };
 
 // Source of the specialised kernel pair for one network (host tables).

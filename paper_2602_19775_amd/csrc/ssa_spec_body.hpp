@@ -252,9 +252,9 @@ __device__ __forceinline__ void rates(const RunParams &p, const NetDev &nd, floa
 // (Sec. 2) instead of the Gumbel-max race; such a run has no backward.
 // TMB: bin observations in the trajectory-major layout, whose whole bins are
 // filled by the wave (the other kernels take either layout through strides).
-// ENS (with TMB): only the ensemble means are kept; each wave sums its
-// trajectories' bins in LDS (integer additions, so in any order) and stores
-// one row of sums for its tile.
+// ENS (with TMB, or with GRID): only the ensemble means are kept; each wave
+// sums its trajectories' bins or grid points in LDS (integer additions, so in
+// any order) and stores one row of sums for its tile.
 template <class NET, bool HAS_T_END, bool GRID, bool CDF = false, bool TMB = false, bool ENS = false>
 __device__ void forward_run(const RunParams &p)
 {
@@ -480,9 +480,14 @@ __device__ void forward_run(const RunParams &p)
                 while (grid_t < tn) {
                     const double f = (grid_t - t) * inv_tau;
 #pragma unroll
-                    for (int o = 0; o < NOBS; ++o)
-                        obs_lane[gi * orow + o * ocol] =
-                            (double)X[NET::OBS[o]] + f * (double)delta_of<NET>(j1, NET::OBS[o]);
+                    for (int o = 0; o < NOBS; ++o) {
+                        const double v = (double)X[NET::OBS[o]] + f * (double)delta_of<NET>(j1, NET::OBS[o]);
+                        if (ENS)
+                            atomicAdd((unsigned long long *)&sfp[gi * NOBS + o],
+                                      (unsigned long long)(long long)rint(v * kFixScale));
+                        else
+                            obs_lane[gi * orow + o * ocol] = v;
+                    }
                     gi += 1;
                     grid_t = gi < n_bins ? grid_time(t_obs, gi, n_bins) : INFINITY;
                 }
@@ -510,13 +515,22 @@ __device__ void forward_run(const RunParams &p)
     }
     // hold the last state up to t_obs: the rest of the current bin, then every
     // later bin, whose average is the last state itself
-    if (ENS) {
+    if (ENS && grid) {
+        // grid points at or after the last event hold the last state
+        const bool tail = valid && gi < n_bins;
+        double fv[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) fv[o] = 0.0;
+        ens_add<NET>(sfp, dsc, dun, -1, fv, tail ? gi : 0, tail ? n_bins : 0, X, false);
+    } else if (ENS) {
         const bool tail = valid && bin < n_bins;
         double fv[NO];
 #pragma unroll
         for (int o = 0; o < NO; ++o)
             fv[o] = (acc[o] + (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0)) * inv_dt;
         ens_add<NET>(sfp, dsc, dun, tail ? bin : -1, fv, tail ? bin + 1 : 0, tail ? n_bins : 0, X, false);
+    }
+    if (ENS) {
         // every lane's additions land before the row is read back
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -546,7 +560,7 @@ __device__ void forward_run(const RunParams &p)
         for (int o = 0; o < NOBS; ++o) obs_lane[o * ocol] = (double)X[NET::OBS[o]];
     }
     // grid points after the last event hold the last state
-    if (grid)
+    if (grid && !ENS)
         for (int gg = n_bins - 1; gg >= gi; --gg)
 #pragma unroll
             for (int o = 0; o < NOBS; ++o) obs_lane[gg * orow + o * ocol] = (double)X[NET::OBS[o]];

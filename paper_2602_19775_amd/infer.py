@@ -14,12 +14,10 @@
   0.001 for the dimerisation, 0.05 to 0.0005 for the channel), the learning
   rate geometrically as well (the channel's in proportion to the
   temperature, Sec. 4.4).
-- **Layout.** Bin observations are summed over the ensemble inside the
-  forward, which stores only the means; grid observations are written
-  trajectory by trajectory (trajectory-major) and reduced to the means by the
-  library.  The backward reads the loss gradient as one block shared by all
-  trajectories (every trajectory's dL/dobs is the same for a loss of
-  ensemble means).
+- **Layout.** The observation is summed over the ensemble inside the
+  forward, which stores only the means.  The backward reads the loss
+  gradient as one block shared by all trajectories (every trajectory's
+  dL/dobs is the same for a loss of ensemble means).
 - **Graph.** One optimisation step is captured once into a HIP graph and
   replayed per epoch. The step is: forward, loss gradient, backward, RMSprop
   update, schedule update and epoch count. The epoch, the temperature and the
@@ -93,8 +91,7 @@ class Trainer:
         self.epochs = epochs
         self.n_pts = cfg.n_bins if cfg.obs_kind != W.OBS_FINAL else 1
         self.n_obs, self.B = len(true_net.obs_species), n_traj
-        layout = W.OBS_ENSEMBLE_MEAN if cfg.obs_kind == W.OBS_BINS else W.OBS_TRAJ_MAJOR
-        self.cfg = cfg.replace(temperature=t0, obs_layout=layout, dobs_shared=True)
+        self.cfg = cfg.replace(temperature=t0, obs_layout=W.OBS_ENSEMBLE_MEAN, dobs_shared=True)
         P_, O_ = self.n_pts, self.n_obs
         # target ensemble means
         ht = ssa.Net([true_net], [n_target], t_obs=[self.t_obs])

@@ -222,13 +222,13 @@ def test_shared_bins_backward_variants(ssa, bwd_mode, T):
     _parity(gpu, r, ids, cfg)
 
 
-@pytest.mark.parametrize("case", ["channel_bins", "abc_bins"])
+@pytest.mark.parametrize("case", ["channel_bins", "abc_bins", "abc_grid"])
 def test_ensemble_mean_forward(ssa, case):
-    """The forward that keeps only the ensemble means of the bins: against
-    the mean of the oracle's bin averages over every trajectory (the same
-    near-tie choices), against the trajectory-major forward of the same seeds
-    reduced by ssa_obs_mean, repeatable bit for bit, and followed by the same
-    backward as that forward."""
+    """The forward that keeps only the ensemble means of the bins or grid
+    points: against the mean of the oracle's values over every trajectory
+    (the same near-tie choices), against the trajectory-major forward of the
+    same seeds reduced by ssa_obs_mean, repeatable bit for bit, and followed
+    by the same backward as that forward."""
     mk, cfg, B = CASES[case]
     net = mk()
     nob = len(net.obs_species)
@@ -248,13 +248,16 @@ def test_ensemble_mean_forward(ssa, case):
     drift = float(np.max(np.abs(f1.t_final.cpu().numpy() - r.t_final)))
     ref = np.asarray(r.obs, np.float64).reshape(B, cfg.n_bins, nob).mean(axis=0)
     big = float(np.abs(r.obs).max())
-    atol = 4.0 * big * drift * cfg.n_bins / cfg.t_obs + 1e-12
+    # the per-trajectory bars of the parity tests (bins: a count jump times
+    # the clock drift over the bin width; grid: relative to the counts' scale)
+    atol = (4.0 * big * drift * cfg.n_bins / cfg.t_obs if cfg.obs_kind == W.OBS_BINS else 1e-5 * big) + 1e-12
     assert np.all(np.abs(m1 - ref) <= 1e-5 * np.abs(ref) + atol)
     # the trajectory-major forward of the same seeds, reduced by the library
     tm = cfg.replace(obs_layout=W.OBS_TRAJ_MAJOR, dobs_shared=True)
     f3 = ssa.forward(h, tm, th, x0, tie_capacity=1 << 16, bwd_mode="tape")
     m3 = ssa.obs_mean(h, f3).cpu().numpy().reshape(cfg.n_bins, nob)
-    # partly covered bins are summed in fixed point: at most 2^-33 absolute
+    # partly covered bins and grid values are summed in fixed point: at most
+    # 2^-33 absolute
     assert np.allclose(m1, m3, rtol=1e-12, atol=2.0 ** -32)
     # the backward reads checkpoints and tape only: the same after both forwards
     d = torch.tensor(np.random.default_rng(2).normal(size=cfg.n_bins * nob), device="cuda")
@@ -287,7 +290,7 @@ def test_ensemble_mean_forward_networks_and_limits(ssa):
     f0 = ssa.forward(h, cfg.replace(dobs_shared=False), th, x0, tie_capacity=0)
     with pytest.raises(ssa.SSAError, match="shared d_obs"):
         ssa.backward(h, cfg, th, x0, f0, torch.zeros(n, dtype=torch.float64, device="cuda"))
-    for bad, msg in ((cfg.replace(obs_kind=W.OBS_GRID), "bins only"),
+    for bad, msg in ((cfg.replace(obs_kind=W.OBS_FINAL), "bins or grid points only"),
                      (cfg.replace(selection=W.SELECT_INVERSE_CDF), "per-trajectory"),
                      (cfg.replace(n_bins=1001), "1000")):
         with pytest.raises(ssa.SSAError, match=msg):
