@@ -22,6 +22,7 @@ namespace wave {
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 constexpr int kMaxN = 64;
+constexpr int kOne = kMaxN;   // LDS state slot holding the constant 1 (a missing reactant)
 constexpr int kObsMax = 4;
 constexpr int kFold = 32;
 
@@ -107,7 +108,7 @@ struct LaneChannels {
             const int jj = w - 1;
             j[q] = jj;
             on[q] = jj >= 0 && jj < nd.M;
-            s1[q] = s2[q] = kNoSpecies;
+            s1[q] = s2[q] = kOne;
             homo[q] = 0;
             csr[q] = 0;
             c[q] = 0.f;
@@ -116,8 +117,8 @@ struct LaneChannels {
             for (int e = 0; e < kVecSlots / 2; ++e) ve[q][e] = 0u;
             if (on[q]) {
                 const ReactDesc r = rd[jj];
-                s1[q] = r.s1;
-                s2[q] = r.s2;
+                s1[q] = r.s1 == kNoSpecies ? kOne : r.s1;
+                s2[q] = r.s2 == kNoSpecies ? kOne : r.s2;
                 homo[q] = r.homodimer;
                 csr[q] = r.csr;
                 c[q] = expf(p.theta[nd.param_off + r.rate]) * r.mult;
@@ -166,9 +167,11 @@ struct GroupTab {
     }
 };
 
+// Count of species s; a channel's missing reactant reads slot kOne, which
+// holds 1 for the whole item.
 __device__ __forceinline__ int xval(const int *sx, int s)
 {
-    return s == kNoSpecies ? 1 : sx[s];
+    return sx[s];
 }
 
 template <int L, int BPL>
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
 {
     constexpr int G = 64 / L;                 // trajectories per wavefront
     constexpr int C = 4 * BPL;
-    __shared__ int s_x[kWaves][G][kMaxN];
+    __shared__ int s_x[kWaves][G][kMaxN + 1];   // + the constant-1 slot kOne
     extern __shared__ int32_t s_dyn[];
     const int wid = uniform_i((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -277,6 +280,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
         const int64_t g = nd.traj_off + i;
         const uint32_t tid = p.traj_ids ? p.traj_ids[g] : (uint32_t)g;
         for (int s = gl; s < N; s += L) sx[s] = have ? p.x0[nd.state_off + s * B + i] : 0;
+        if (gl == 0) sx[kOne] = 1;
         wave_sync();
         int osp[kObsMax];
 #pragma unroll
@@ -446,7 +450,7 @@ void bwd_kernel(RunParams p)
     constexpr int C = 4 * BPL;
     constexpr int MMAX = 4 * BPL * L;          // channel slots of a group
     constexpr int KREC = 64;
-    __shared__ int s_x[kWaves][G][kMaxN];
+    __shared__ int s_x[kWaves][G][kMaxN + 1];   // + the constant-1 slot kOne
     __shared__ float s_lam32[kWaves][G][kMaxN];      // FP32 view of lambda (base + increments)
     __shared__ float s_inc[kWaves][G][2 * MMAX + 1];  // per-channel contributions to dlambda[s1], dlambda[s2],
                                                       // in incidence-slot order, + a sink slot
@@ -492,6 +496,7 @@ void bwd_kernel(RunParams p)
         kmax = uniform_i(kmax);
 
         for (int s = gl; s < N; s += L) sx[s] = have ? p.x_final[nd.state_off + s * B + i] : 0;
+        if (gl == 0) sx[kOne] = 1;
         double t = have ? p.t_final[g] : 0.0;
         int osp[kObsMax];
 #pragma unroll
@@ -864,7 +869,7 @@ size_t wave_static_lds(int cls, bool backward)
     const int L = wave_class_lanes(cls);
     const int G = 64 / L;
     const int bpl = cls == kWave_L64x2 ? 2 : 1;
-    size_t b = sizeof(int) * wave::kWaves * G * wave::kMaxN;
+    size_t b = sizeof(int) * wave::kWaves * G * (wave::kMaxN + 1);
     if (backward)
         b += sizeof(float) * wave::kWaves * G * wave::kMaxN + sizeof(float) * wave::kWaves * G * (2 * 4 * bpl * L + 1) +
              wave::kWaves * G * 64;
