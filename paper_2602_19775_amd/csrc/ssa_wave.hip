@@ -718,16 +718,25 @@ void bwd_kernel(RunParams p)
                             }
                         }
                     } else {
-                        // padding entries are species 0 with delta 0
+                        // padding entries are species 0 with delta 0; the
+                        // entries stay packed across the step loop (to save
+                        // registers) and are decoded here, all of the
+                        // channel's reads of lambda issued before the first
+                        // is waited for, then summed in entry order
+                        uint32_t w[kVecSlots / 2];
+#pragma unroll
+                        for (int e2 = 0; e2 < kVecSlots / 2; ++e2) {
+                            w[e2] = ch.ve[q][e2];
+                            asm volatile("" : "+v"(w[e2]));
+                        }
+                        float lv[kVecSlots];
+#pragma unroll
+                        for (int e = 0; e < kVecSlots; ++e)
+                            lv[e] = slam[(int)((w[e >> 1] >> (16 * (e & 1))) & 0xFFu)];
 #pragma unroll
                         for (int e = 0; e < kVecSlots; ++e) {
-                            // decoded per step (kept packed across the loop to save registers)
-                            uint32_t w = ch.ve[q][e >> 1];
-                            asm volatile("" : "+v"(w));
-                            const uint32_t h = w >> (16 * (e & 1));
-                            const int sp = (int)(h & 0xFFu);
-                            const int dl = (int)(int8_t)(uint8_t)((h >> 8) & 0xFFu);
-                            s += (float)dl * slam[sp];
+                            const int dl = (int)(int8_t)(uint8_t)((w[e >> 1] >> (16 * (e & 1) + 8)) & 0xFFu);
+                            s += (float)dl * lv[e];
                         }
                     }
                     wv[q] = s;
