@@ -228,7 +228,19 @@ __device__ __forceinline__ float from_owner(const float (&v)[C], Owner o)
     return __shfl(mine, o.lane);
 }
 
-// X += sign * v_j through the sparse change vector (lane e applies entry e).
+// X += sign * v_j through the sparse change vector (lane e applies entry e);
+// csr is channel j's descriptor tab.desc[j].
+template <int L>
+__device__ __forceinline__ void group_apply_desc(const GroupTab &tab, int *sx, int csr, int sign, int gl, bool act)
+{
+    const int beg = csr & 0xFFFFFF, cnt = (int)((uint32_t)csr >> 24);
+    for (int e = gl; e < cnt; e += L) {
+        const int32_t ent = tab.ent[beg + e];
+        if (act) sx[csr_species(ent)] += sign * csr_delta(ent);
+    }
+    wave_sync();
+}
+
 template <int L>
 __device__ __forceinline__ void group_apply(const GroupTab &tab, int *sx, int j, int sign, int gl, bool act)
 {
@@ -649,12 +661,14 @@ void bwd_kernel(RunParams p)
                     }
                     j = (int)((tword >> (p.tape_bits * (k & (spw - 1)))) & tmask);
                 }
-                // observed counts of X_{k+1}, then X_{k+1} -> X_k
+                // observed counts of X_{k+1}, then X_{k+1} -> X_k (the fired
+                // channel's descriptor is read together with the counts)
+                const int jcsr = tab.desc[on_k ? j : 0];
                 int xn[kObsMax];
 #pragma unroll
                 for (int o = 0; o < kObsMax; ++o) xn[o] = o < nd.n_obs ? sx[osp[o]] : 0;
                 wave_sync();
-                group_apply<L>(tab, sx, on_k ? j : 0, -1, gl, on_k);
+                group_apply_desc<L>(tab, sx, jcsr, -1, gl, on_k);
 
                 float a[C], A1[C], A2[C];
                 float a0 = 0.f;
