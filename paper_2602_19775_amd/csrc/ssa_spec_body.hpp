@@ -91,14 +91,6 @@ __device__ __forceinline__ void fill_runs(double *blk, int64_t first, int64_t np
     }
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int l)
-{
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
 // Fixed-point scale of the single-bin values the ensemble-mean forward sums.
 constexpr double kFixScale = 4294967296.0;   // 2^32
 
