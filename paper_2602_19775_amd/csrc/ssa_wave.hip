@@ -785,10 +785,15 @@ void bwd_kernel(RunParams p)
                     for (int m = 0; m < SPL; ++m) {
                         const int s = gl + L * m;
                         if (s < N) {
-                            // the species' slots in order, four reads in flight
+                            // the species' slots in order, eight reads in flight
                             const int end = tab.inc_ptr[s + 1];
                             int e = tab.inc_ptr[s];
                             float d = 0.f;
+                            for (; e + 8 <= end; e += 8) {
+                                const float v0 = sinc[e], v1 = sinc[e + 1], v2 = sinc[e + 2], v3 = sinc[e + 3];
+                                const float v4 = sinc[e + 4], v5 = sinc[e + 5], v6 = sinc[e + 6], v7 = sinc[e + 7];
+                                d = (((((((d + v0) + v1) + v2) + v3) + v4) + v5) + v6) + v7;
+                            }
                             for (; e + 4 <= end; e += 4) {
                                 const float v0 = sinc[e], v1 = sinc[e + 1], v2 = sinc[e + 2], v3 = sinc[e + 3];
                                 d = (((d + v0) + v1) + v2) + v3;
