@@ -719,10 +719,10 @@ void bwd_kernel(RunParams p)
                 const float rys = fast_rcp(ys);
                 // w_q = v_q . lambda(k+1)
                 float wv[C];
+                if (p.wide_ve) {
 #pragma unroll
-                for (int q = 0; q < C; ++q) {
-                    float s = 0.f;
-                    if (p.wide_ve) {
+                    for (int q = 0; q < C; ++q) {
+                        float s = 0.f;
                         if (ch.on[q]) {
                             const int d = tab.desc[ch.j[q]];
                             const int beg = d & 0xFFFFFF, cnt = (int)((uint32_t)d >> 24);
@@ -731,29 +731,41 @@ void bwd_kernel(RunParams p)
                                 s += (float)csr_delta(ent) * slam[csr_species(ent)];
                             }
                         }
-                    } else {
-                        // padding entries are species 0 with delta 0; the
-                        // entries stay packed across the step loop (to save
-                        // registers) and are decoded here, all of the
-                        // channel's reads of lambda issued before the first
-                        // is waited for, then summed in entry order
-                        uint32_t w[kVecSlots / 2];
+                        wv[q] = s;
+                    }
+                } else {
+                    // padding entries are species 0 with delta 0; the entries
+                    // stay packed across the step loop (to save registers)
+                    // and are decoded here, two channels at a time with all
+                    // their reads of lambda issued before the first is waited
+                    // for, then each channel summed in entry order
 #pragma unroll
-                        for (int e2 = 0; e2 < kVecSlots / 2; ++e2) {
-                            w[e2] = ch.ve[q][e2];
-                            asm volatile("" : "+v"(w[e2]));
-                        }
-                        float lv[kVecSlots];
+                    for (int q0 = 0; q0 < C; q0 += 2) {
+                        uint32_t w[2][kVecSlots / 2];
 #pragma unroll
-                        for (int e = 0; e < kVecSlots; ++e)
-                            lv[e] = slam[(int)((w[e >> 1] >> (16 * (e & 1))) & 0xFFu)];
+                        for (int h = 0; h < 2; ++h)
 #pragma unroll
-                        for (int e = 0; e < kVecSlots; ++e) {
-                            const int dl = (int)(int8_t)(uint8_t)((w[e >> 1] >> (16 * (e & 1) + 8)) & 0xFFu);
-                            s += (float)dl * lv[e];
+                            for (int e2 = 0; e2 < kVecSlots / 2; ++e2) {
+                                w[h][e2] = ch.ve[q0 + h][e2];
+                                asm volatile("" : "+v"(w[h][e2]));
+                            }
+                        float lv[2][kVecSlots];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int e = 0; e < kVecSlots; ++e)
+                                lv[h][e] = slam[(int)((w[h][e >> 1] >> (16 * (e & 1))) & 0xFFu)];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            float s = 0.f;
+#pragma unroll
+                            for (int e = 0; e < kVecSlots; ++e) {
+                                const int dl = (int)(int8_t)(uint8_t)((w[h][e >> 1] >> (16 * (e & 1) + 8)) & 0xFFu);
+                                s += (float)dl * lv[h][e];
+                            }
+                            wv[q0 + h] = s;
                         }
                     }
-                    wv[q] = s;
                 }
                 // reference value w_j from the lane owning channel j
                 const float wref = from_owner<L, C>(wv, own);
