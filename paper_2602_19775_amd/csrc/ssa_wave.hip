@@ -328,13 +328,21 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
                 }
                 ck_left -= 1;
             }
-            // propensities of the lane's channels
+            // propensities of the lane's channels (every operand index is a
+            // valid slot, kOne for a missing reactant or an unused channel
+            // slot, so all the reads go out before the first is waited for)
             float a[C];
             float a0 = 0.f;
+            int xr1[C], xr2[C];
 #pragma unroll
             for (int q = 0; q < C; ++q) {
-                const float x1 = (float)xval(sx, ch.s1[q]);
-                const float x2 = (float)(xval(sx, ch.s2[q]) - ch.homo[q]);
+                xr1[q] = xval(sx, ch.s1[q]);
+                xr2[q] = xval(sx, ch.s2[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                const float x1 = (float)xr1[q];
+                const float x2 = (float)(xr2[q] - ch.homo[q]);
                 a[q] = ch.on[q] ? fabsf((ch.c[q] * x1) * x2) : 0.f;
                 a0 += a[q];
             }
