@@ -113,7 +113,8 @@ enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1, SSA_OBS_ENSEMBLE_MEAN = 
  * Each 64-trajectory tile leaves one row of sums and the rows of a network are
  * reduced in a fixed order, so the result is the same on every call.  Bin and
  * grid observations (grid values are summed in the same fixed point, the held
- * tail as counts), topology-specialised lane mode, n_bins * n_obs <= 1000;
+ * tail as counts), topology-specialised lane mode, n_bins * n_obs <= 1000 and
+ * 16 * n_bins * n_obs + 8 * n_obs <= 16384 (the LDS of one wave);
  * ssa_backward then needs dobs_shared.  Anything else returns SSA_ENOTSUP. */
 
 /* How ssa_backward obtains the fired channel of each step.

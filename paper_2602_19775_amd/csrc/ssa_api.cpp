@@ -120,8 +120,11 @@ int resolve_bwd_mode(const ssa_config *cfg)
 
 constexpr int kMaxRecomputeSegment = 64;
 // values a wave of the ensemble-mean forward sums in LDS (16 bytes each:
-// a fixed-point sum and two difference-array counts; 4 waves a block)
+// a fixed-point sum and two difference-array counts, plus 8 bytes an observed
+// species for the arrays' end slots), and the LDS of a wave (4 waves a block
+// within the 64 KiB a workgroup may hold)
 constexpr int64_t kMeanMaxValues = 1000;
+constexpr int64_t kMeanLdsPerWave = 16384;
 
 bool bounded_steps(const ssa_config *cfg)
 {
@@ -243,8 +246,10 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
         if (cfg->obs_kind == SSA_OBS_FINAL)
             return fail(SSA_ENOTSUP, "the ensemble-mean forward observes bins or grid points only");
         for (const NetDev &nd : net->nets_h)
-            if ((int64_t)nd.n_obs * cfg->n_bins > kMeanMaxValues)
-                return fail(SSA_ENOTSUP, "the ensemble-mean forward needs n_bins * n_obs <= 1000");
+            if ((int64_t)nd.n_obs * cfg->n_bins > kMeanMaxValues ||
+                16 * (int64_t)nd.n_obs * cfg->n_bins + 8 * (int64_t)nd.n_obs > kMeanLdsPerWave)
+                return fail(SSA_ENOTSUP, "the ensemble-mean forward needs n_bins * n_obs <= 1000 and its sums "
+                                         "within 16 KiB of LDS a wave");
     }
     if (cfg->obs_layout != SSA_OBS_POINT_MAJOR || cfg->dobs_shared)
         for (const auto &gr : net->groups)
