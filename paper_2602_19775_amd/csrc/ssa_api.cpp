@@ -122,7 +122,8 @@ constexpr int kMaxRecomputeSegment = 64;
 // values a wave of the ensemble-mean forward sums in LDS (16 bytes each:
 // a fixed-point sum and two difference-array counts, plus 8 bytes an observed
 // species for the arrays' end slots), and the LDS of a wave (4 waves a block
-// within the 64 KiB a workgroup may hold)
+// within the 64 KiB a workgroup may hold; with at most kObsMax observed
+// species the first bound implies the second)
 constexpr int64_t kMeanMaxValues = 1000;
 constexpr int64_t kMeanLdsPerWave = 16384;
 

@@ -298,10 +298,3 @@ def test_ensemble_mean_forward_networks_and_limits(ssa):
     hl = ssa.Net(nets[:1], Bs[:1], t_obs=[5.0], exec_mode="lane")
     with pytest.raises(ssa.SSAError, match="specialised"):
         ssa.forward(hl, cfg, th[: nets[0].n_params], _x0(nets[:1], Bs[:1]))
-    # 50 observed species x 20 bins: 1,000 values, but with the arrays' end
-    # slots more than a wave's 16 KiB of LDS
-    big = W.random_network(np.random.default_rng(3), n_range=(56, 56), m_range=(40, 40))
-    hb = ssa.Net([big], [64], t_obs=[5.0], obs_species=[list(range(50))], exec_mode="spec")
-    cb = cfg.replace(n_bins=20)
-    with pytest.raises(ssa.SSAError, match="16 KiB"):
-        ssa.forward(hb, cb, torch.tensor(big.theta0, device="cuda"), _x0([big], [64]))
