@@ -2,9 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
 benchmark's CPU-baseline leg may use this module; the product path never does.
-It imports nothing from the HIP package except the seeded input descriptions
-in ``paper_2602_19775_amd.workloads`` (which hold none of the method's
-arithmetic).
+It imports nothing from the HIP package: callers hand it the seeded input
+descriptions (networks, run settings) as plain objects and arrays.
 """
 from __future__ import annotations
 
@@ -53,7 +52,8 @@ class _Cfg(C.Structure):
                 ("n_steps", C.c_int64), ("t_end", C.c_double), ("obs_kind", C.c_int32),
                 ("n_bins", C.c_int32), ("t_obs", C.c_double), ("n_obs", C.c_int32),
                 ("obs_species", C.c_void_p), ("temperature", C.c_double),
-                ("tie_threshold", C.c_double), ("clock_tol", C.c_double), ("selection", C.c_int32)]
+                ("tie_threshold", C.c_double), ("clock_tol", C.c_double), ("selection", C.c_int32),
+                ("edge_window", C.c_double)]
 
 
 class _Grn(C.Structure):
@@ -87,6 +87,8 @@ def lib():
         L.orc_forward.restype = C.c_int
         L.orc_adjoint.argtypes = common + [C.c_void_p] * 6 + [C.POINTER(_Stats), C.c_int]
         L.orc_adjoint.restype = C.c_int
+        L.orc_adjoint_kappa.argtypes = common + [C.c_void_p] * 7 + [C.POINTER(_Stats), C.c_int]
+        L.orc_adjoint_kappa.restype = C.c_int
         L.orc_trace.argtypes = [C.POINTER(_Net), C.POINTER(_Cfg), C.c_void_p, C.c_uint32,
                                 C.c_void_p, C.c_int64] + [C.c_void_p] * 7
         L.orc_trace.restype = C.c_int64
@@ -144,6 +146,7 @@ class OracleResult:
     n_bad: np.ndarray
     bin_edge_dist: np.ndarray
     grad: Optional[np.ndarray] = None   # [n_traj, P]
+    kappa: Optional[np.ndarray] = None  # [n_traj, P] conditioning of each gradient component
 
 
 class _Keep:
@@ -157,7 +160,7 @@ class _Keep:
         return a
 
 
-def _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species=None):
+def _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species=None, edge_window=0.0):
     reactant = keep(np.ascontiguousarray(net.reactant, np.int32))
     rate_index = keep(np.ascontiguousarray(net.rate_index, np.int32))
     stoich = keep(np.ascontiguousarray(net.stoich, np.int32))
@@ -168,7 +171,7 @@ def _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species=None):
     c = _Cfg(cfg.seed, cfg.purpose, cfg.epoch, min(int(cfg.n_steps), 2 ** 62),
              float(cfg.t_end), cfg.obs_kind, cfg.n_bins, float(cfg.t_obs), len(obs_sp),
              _p(obs_sp).value, float(cfg.temperature), tie_threshold, clock_tol,
-             int(getattr(cfg, "selection", 0)))
+             int(getattr(cfg, "selection", 0)), float(edge_window))
     return n, c
 
 
@@ -188,11 +191,16 @@ def _overrides(n_traj, ties, keep):
 
 def run(net, cfg, theta, x0: np.ndarray, traj_ids=None, ties=None, d_obs=None,
         tie_threshold: float = 1e-6, clock_tol: float = 1e-5, n_threads: int = 0,
-        obs_species=None) -> OracleResult:
+        obs_species=None, kappa: bool = False, edge_window: float = 0.0) -> OracleResult:
     """Simulate (and, if d_obs is given, differentiate) a set of trajectories.
 
     x0: [n_traj, N] or [N] (broadcast).  traj_ids: global trajectory ids (the
-    Philox counter), default 0..n_traj-1.  theta: ln k as float32 values."""
+    Philox counter), default 0..n_traj-1.  theta: ln k as float32 values.
+    kappa: also return the conditioning of every gradient component (the sum
+    over steps of the magnitudes of its terms, see orc_adjoint_kappa).
+    edge_window: bins, with ties holding the GPU's kind-2 (bin-edge) records:
+    the relative window within which the adjoint takes the GPU's side of a bin
+    edge for an event time (0: the oracle's own clock decides)."""
     keep = _Keep()
     N = net.n_species
     x0 = np.asarray(x0, np.int32)
@@ -205,11 +213,12 @@ def run(net, cfg, theta, x0: np.ndarray, traj_ids=None, ties=None, d_obs=None,
         x0 = np.repeat(x0[None, :], n_traj, axis=0)
     x0 = keep(np.ascontiguousarray(x0, np.int32))
     assert x0.shape == (n_traj, N)
-    n, c = _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species)
+    n, c = _structs(net, cfg, keep, tie_threshold, clock_tol, obs_species, edge_window)
     th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
     ov = _overrides(n_traj, ties, keep)
     n_obs = c.n_obs
-    obs_shape = (n_traj, cfg.n_bins, n_obs) if cfg.obs_kind in (1, 2) else (n_traj, n_obs)
+    obs_shape = ((n_traj, cfg.n_bins, n_obs) if cfg.obs_kind in (1, 2)
+                 else (n_traj, n_obs + 1) if cfg.obs_kind == 3 else (n_traj, n_obs))
     res = OracleResult(np.zeros((n_traj, N), np.int32), np.zeros(n_traj), np.zeros(n_traj, np.int32),
                        np.zeros(obs_shape), np.zeros(n_traj), np.zeros(n_traj, np.int32),
                        np.zeros(n_traj, np.int32), np.zeros(n_traj, np.int32), np.zeros(n_traj))
@@ -224,9 +233,15 @@ def run(net, cfg, theta, x0: np.ndarray, traj_ids=None, ties=None, d_obs=None,
     else:
         d = keep(np.ascontiguousarray(np.broadcast_to(d_obs, obs_shape), np.float64))
         res.grad = np.zeros((n_traj, net.n_params))
-        rc = L.orc_adjoint(C.byref(n), C.byref(c), _p(th), n_traj, _p(traj_ids), _p(x0), ovp,
-                           _p(d), _p(res.x_final), _p(res.t_final), _p(res.steps_done),
-                           _p(res.obs), _p(res.grad), C.byref(st), n_threads)
+        if kappa:
+            res.kappa = np.zeros((n_traj, net.n_params))
+            rc = L.orc_adjoint_kappa(C.byref(n), C.byref(c), _p(th), n_traj, _p(traj_ids), _p(x0), ovp,
+                                     _p(d), _p(res.x_final), _p(res.t_final), _p(res.steps_done),
+                                     _p(res.obs), _p(res.grad), _p(res.kappa), C.byref(st), n_threads)
+        else:
+            rc = L.orc_adjoint(C.byref(n), C.byref(c), _p(th), n_traj, _p(traj_ids), _p(x0), ovp,
+                               _p(d), _p(res.x_final), _p(res.t_final), _p(res.steps_done),
+                               _p(res.obs), _p(res.grad), C.byref(st), n_threads)
     if rc != 0:
         raise RuntimeError("oracle rejected its arguments")
     return res

@@ -121,6 +121,33 @@ static void add_grad_log_h(const int32_t *rs, const int32_t *X, double c, double
     g[s2] += c / (double)X[s2];
 }
 
+/* |dh_j/dX| added into g with weight c >= 0 (magnitudes for the conditioning
+ * sums of the adjoint; X >= 0). */
+static void add_abs_grad_h(const int32_t *rs, const int32_t *X, double c, double *g)
+{
+    int s1 = rs[0], s2 = rs[1];
+    if (s1 < 0) return;
+    if (s2 < 0) { g[s1] += c; return; }
+    if (s1 == s2) { g[s1] += c * fabs((double)X[s1] - 0.5); return; }
+    g[s1] += c * (double)X[s2];
+    g[s2] += c * (double)X[s1];
+}
+
+/* |d ln h_j/dX| added into g with weight c >= 0 (only where h_j > 0). */
+static void add_abs_grad_log_h(const int32_t *rs, const int32_t *X, double c, double *g)
+{
+    int s1 = rs[0], s2 = rs[1];
+    if (s1 < 0) return;
+    if (s2 < 0) { g[s1] += c / (double)X[s1]; return; }
+    if (s1 == s2) {
+        double x = (double)X[s1];
+        g[s1] += c * fabs(2.0 * x - 1.0) / (x * (x - 1.0));
+        return;
+    }
+    g[s1] += c / (double)X[s1];
+    g[s2] += c / (double)X[s2];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Observation helpers: exact bin averages of a piecewise-constant path.     */
 /* ------------------------------------------------------------------------ */
@@ -281,7 +308,7 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
         while (p_ov < p_end && ov->step[p_ov] < k_step) ++p_ov;
         for (int64_t p = p_ov; p < p_end && ov->step[p] == k_step; ++p) {
             if (ov->kind[p] == 1) ov_clock = ov->val[p];
-            else ov_react = ov->val[p];
+            else if (ov->kind[p] == 0) ov_react = ov->val[p];
         }
 
         /* stop rule: fire only while t + tau <= t_end */
@@ -379,6 +406,11 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
         for (int s = 0; s < N; ++s) X[s] += v[s];
         t += tau;
 
+        /* state k_step + 1 of the run: one of the last n_bins states? */
+        if (cfg->obs_kind == ORC_OBS_TAIL && k_step >= cfg->n_steps - cfg->n_bins) {
+            for (int o = 0; o < cfg->n_obs; ++o) obs_acc[o] += (double)X[cfg->obs_species[o]];
+            obs_acc[cfg->n_obs] += t;
+        }
         if (cfg->obs_kind == ORC_OBS_BINS)
             for (int b = 1; b <= cfg->n_bins; ++b) {
                 double d = fabs(t - bin_edge(cfg, b));
@@ -399,6 +431,15 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
             tr->t[k_step + 1] = t;
         }
     }
+    /* tail means: the states the run did not reach hold the last one */
+    if (cfg->obs_kind == ORC_OBS_TAIL) {
+        const int64_t k0 = cfg->n_steps - cfg->n_bins;
+        const int64_t rem = cfg->n_steps - (k_step > k0 ? k_step : k0);
+        if (rem > 0) {
+            for (int o = 0; o < cfg->n_obs; ++o) obs_acc[o] += (double)rem * (double)X[cfg->obs_species[o]];
+            obs_acc[cfg->n_obs] += (double)rem * t;
+        }
+    }
     /* the path is held at its last state up to t_obs */
     if (cfg->obs_kind == ORC_OBS_BINS) {
         for (int o = 0; o < cfg->n_obs; ++o) xo[o] = (double)X[cfg->obs_species[o]];
@@ -414,12 +455,17 @@ static int64_t simulate_one(const orc_net *net, const orc_cfg *cfg, const double
 
 static int obs_width(const orc_cfg *cfg)
 {
+    if (cfg->obs_kind == ORC_OBS_TAIL) return cfg->n_obs + 1;
     return cfg->obs_kind == ORC_OBS_FINAL ? cfg->n_obs : cfg->n_bins * cfg->n_obs;
 }
 
 static void finish_obs(const orc_cfg *cfg, const int32_t *X, double *obs)
 {
     if (cfg->obs_kind == ORC_OBS_GRID) return;
+    if (cfg->obs_kind == ORC_OBS_TAIL) {
+        for (int i = 0; i <= cfg->n_obs; ++i) obs[i] /= (double)cfg->n_bins;
+        return;
+    }
     if (cfg->obs_kind == ORC_OBS_BINS) {
         double inv = (double)cfg->n_bins / cfg->t_obs;
         for (int i = 0; i < cfg->n_bins * cfg->n_obs; ++i) obs[i] *= inv;
@@ -436,7 +482,10 @@ static int check_args(const orc_net *net, const orc_cfg *cfg)
         return -1;
     if (cfg->obs_kind == ORC_OBS_GRID && (cfg->n_bins < 2 || !(cfg->t_obs > 0.0)))
         return -1;
-    if (cfg->obs_kind < ORC_OBS_FINAL || cfg->obs_kind > ORC_OBS_GRID) return -1;
+    if (cfg->obs_kind == ORC_OBS_TAIL &&
+        (cfg->n_bins < 1 || cfg->n_steps < cfg->n_bins || cfg->n_steps > ((int64_t)1 << 40)))
+        return -1;
+    if (cfg->obs_kind < ORC_OBS_FINAL || cfg->obs_kind > ORC_OBS_TAIL) return -1;
     if (cfg->selection != ORC_SELECT_GUMBEL_MAX && cfg->selection != ORC_SELECT_INVERSE_CDF) return -1;
     if (cfg->n_obs < 0 || (cfg->n_obs > 0 && !cfg->obs_species)) return -1;
     if (!(cfg->temperature > 0.0)) return -1;
@@ -498,15 +547,58 @@ int orc_forward(const orc_net *net, const orc_cfg *cfg, const double *theta,
     return err ? -1 : 0;
 }
 
-/* Reverse sweep of the straight-through surrogate for one stored path. */
+/* Bin of an event time t_{k+1} = t for the clock-derivative term, taking the
+ * GPU's side of a bin edge it lies close to (kind-2 overrides, see the header):
+ * edge i is at t_obs i / n_bins, i = 1 .. n_bins; the side decides between
+ * bin i - 1 and bin i (or nothing past t_obs). */
+static int edge_side_bin(const orc_cfg *cfg, double t, int b, const orc_overrides *ov, int64_t q,
+                         int64_t step, int32_t *n_bad)
+{
+    int ei = (int)floor(t * (double)cfg->n_bins / cfg->t_obs + 0.5);
+    if (ei < 1) ei = 1;
+    if (ei > cfg->n_bins) ei = cfg->n_bins;
+    const double e = bin_edge(cfg, ei);
+    const double d = fabs(t - e);
+    int side = -1;
+    if (ov)
+        for (int64_t i = ov->off[q]; i < ov->off[q + 1]; ++i)
+            if (ov->step[i] == step && ov->kind[i] == 2) side = ov->val[i];
+    if (side < 0) {
+        if (d <= 0.5 * cfg->edge_window * e && n_bad) ++*n_bad;
+        return b;
+    }
+    if (d > cfg->edge_window * e) {
+        if (n_bad) ++*n_bad;
+        return b;
+    }
+    if (side) return ei < cfg->n_bins ? ei : -1;
+    return ei - 1;
+}
+
+/* Reverse sweep of the straight-through surrogate for one stored path.
+ *
+ * kappa (optional, [P]) receives the conditioning of each gradient component:
+ * the sum over steps of the magnitudes of the terms that make up that step's
+ * contribution, before they cancel.  Alongside the adjoint it carries a
+ * magnitude adjoint Lam_X / Lam_t, the running sum of |every increment| of
+ * lambda_X / lambda_t, so a term built from v_j . lambda is bounded by
+ * sum_q |v_jq| Lam_q.  For parameter i, step k adds, over the channels j of i,
+ *   (y~_j / T) (W_j + W_ref + sum_l y~_l W_l) + Lam_t (tau / a0) a_j
+ * with W_j = sum_q |v_jq| Lam_q(k+1) and ref the fired channel.  A floating
+ * point evaluation with unit roundoff u of the same recursion carries an error
+ * of order u * kappa_i in component i, whatever cancellation leaves of it. */
 static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
-                        const path_t *p, const double *dobs, double *grad, double *work)
+                        const path_t *p, const double *dobs, double *grad, double *kappa, double *work,
+                        const orc_overrides *ov, int64_t q, int32_t *n_bad)
 {
     const int N = net->n_species, M = net->n_reactions, P = net->n_params;
     const int nobs = cfg->n_obs;
     const double T = cfg->temperature;
     const int bins = cfg->obs_kind == ORC_OBS_BINS;
     const int grid = cfg->obs_kind == ORC_OBS_GRID;
+    const int tail = cfg->obs_kind == ORC_OBS_TAIL;
+    /* tail observation: states tail_lo .. n_steps enter the means */
+    const int64_t tail_lo = tail ? cfg->n_steps - cfg->n_bins + 1 : 0;
     const double inv_dt = bins ? (double)cfg->n_bins / cfg->t_obs : 0.0;
     double *lamX = work;              /* [N] */
     double *dX = lamX + N;            /* [N] */
@@ -515,10 +607,15 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
     double *w = y + M;                /* [M] */
     double *g = w + M;                /* [M] */
     double *ones = g + M;             /* [n_obs] */
+    double *LamX = ones + nobs;       /* [N]  magnitude adjoint */
+    double *dXa = LamX + N;           /* [N] */
+    double *Wa = dXa + N;             /* [M] */
     for (int o = 0; o < nobs; ++o) ones[o] = 1.0;
     memset(grad, 0, sizeof(double) * P);
+    if (kappa) memset(kappa, 0, sizeof(double) * P);
     memset(lamX, 0, sizeof(double) * N);
-    double lamt = 0.0;
+    memset(LamX, 0, sizeof(double) * N);
+    double lamt = 0.0, Lamt = 0.0;
 
     const int64_t n = p->n;
     /* direct dependence of L on the final state */
@@ -527,15 +624,36 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
         double *tmp = calloc((size_t)cfg->n_bins * nobs, sizeof(double));
         add_interval(cfg, p->t[n], cfg->t_obs, ones, tmp);
         for (int b = 0; b < cfg->n_bins; ++b)
-            for (int o = 0; o < nobs; ++o)
-                lamX[cfg->obs_species[o]] += dobs[(size_t)b * nobs + o] * tmp[(size_t)b * nobs + o] * inv_dt;
+            for (int o = 0; o < nobs; ++o) {
+                const double d = dobs[(size_t)b * nobs + o] * tmp[(size_t)b * nobs + o] * inv_dt;
+                lamX[cfg->obs_species[o]] += d;
+                LamX[cfg->obs_species[o]] += fabs(d);
+            }
         free(tmp);
     } else if (grid) {
         /* grid times at or after the last event see the final state */
         for (int g = grid_first_at_or_after(cfg, p->t[n]); g < cfg->n_bins; ++g)
-            for (int o = 0; o < nobs; ++o) lamX[cfg->obs_species[o]] += dobs[(size_t)g * nobs + o];
+            for (int o = 0; o < nobs; ++o) {
+                lamX[cfg->obs_species[o]] += dobs[(size_t)g * nobs + o];
+                LamX[cfg->obs_species[o]] += fabs(dobs[(size_t)g * nobs + o]);
+            }
+    } else if (tail) {
+        /* the tail states at or after the last event are the final state and clock */
+        const int64_t first = n > tail_lo ? n : tail_lo;
+        const double wf = (double)(cfg->n_steps + 1 - first) / (double)cfg->n_bins;
+        if (wf > 0.0) {
+            for (int o = 0; o < nobs; ++o) {
+                lamX[cfg->obs_species[o]] += dobs[o] * wf;
+                LamX[cfg->obs_species[o]] += fabs(dobs[o] * wf);
+            }
+            lamt += dobs[nobs] * wf;
+            Lamt += fabs(dobs[nobs] * wf);
+        }
     } else {
-        for (int o = 0; o < nobs; ++o) lamX[cfg->obs_species[o]] += dobs[o];
+        for (int o = 0; o < nobs; ++o) {
+            lamX[cfg->obs_species[o]] += dobs[o];
+            LamX[cfg->obs_species[o]] += fabs(dobs[o]);
+        }
     }
 
     double *tmp = bins ? calloc((size_t)cfg->n_bins * nobs, sizeof(double)) : NULL;
@@ -548,10 +666,14 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
         /* direct dL/dt_{k+1}: t_{k+1} ends the interval at X_k and starts the one at X_{k+1} */
         if (bins) {
             int b = bin_of(cfg, tk1);
+            if (cfg->edge_window > 0.0)
+                b = edge_side_bin(cfg, tk1, b, ov, q, kk, n_bad);
             if (b >= 0)
                 for (int o = 0; o < nobs; ++o) {
                     int s = cfg->obs_species[o];
-                    lamt += dobs[(size_t)b * nobs + o] * (double)(Xk[s] - Xk1[s]) * inv_dt;
+                    const double d = dobs[(size_t)b * nobs + o] * (double)(Xk[s] - Xk1[s]) * inv_dt;
+                    lamt += d;
+                    Lamt += fabs(d);
                 }
         }
 
@@ -567,8 +689,11 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
                 for (int o = 0; o < nobs; ++o) {
                     const int s = cfg->obs_species[o];
                     const double d = dobs[(size_t)g * nobs + o];
+                    const double dt_ = d * (double)(Xk1[s] - Xk[s]) * (-f / (tk1 - tk));
                     lamX[s] += d * f;
-                    lamt += d * (double)(Xk1[s] - Xk[s]) * (-f / (tk1 - tk));
+                    lamt += dt_;
+                    LamX[s] += fabs(d * f);
+                    Lamt += fabs(dt_);
                 }
             }
         }
@@ -611,18 +736,42 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
 
         for (int j = 0; j < M; ++j) grad[net->rate_index[j]] += g[j] + c * a[j];
 
+        if (kappa) {
+            /* magnitudes of the step's terms (see the comment above) */
+            int jref = p->j[kk];
+            double wy = 0.0;
+            for (int j = 0; j < M; ++j) {
+                const int32_t *v = net->stoich + (size_t)j * N;
+                double s = 0.0;
+                for (int q = 0; q < N; ++q) s += fabs((double)v[q]) * LamX[q];
+                Wa[j] = s;
+                wy += y[j] * s;
+            }
+            for (int j = 0; j < M; ++j)
+                kappa[net->rate_index[j]] += (a[j] > 0.0 ? y[j] * (Wa[j] + Wa[jref] + wy) / T : 0.0) +
+                                             Lamt * (tau / a0) * a[j];
+        }
+
         memset(dX, 0, sizeof(double) * N);
+        memset(dXa, 0, sizeof(double) * N);
         for (int j = 0; j < M; ++j) {
             if (a[j] > 0.0) add_grad_log_h(net->reactant + 2 * j, Xk, g[j], dX);
             add_grad_h(net->reactant + 2 * j, Xk, c * k[j], dX);
+            if (kappa) {
+                if (a[j] > 0.0) add_abs_grad_log_h(net->reactant + 2 * j, Xk, fabs(g[j]), dXa);
+                add_abs_grad_h(net->reactant + 2 * j, Xk, fabs(c) * k[j], dXa);
+            }
         }
         /* direct dL/dX_k from the interval [t_k, t_{k+1}) */
         if (bins) {
             memset(tmp, 0, sizeof(double) * (size_t)cfg->n_bins * nobs);
             add_interval(cfg, tk, tk1, ones, tmp);
             for (int b = 0; b < cfg->n_bins; ++b)
-                for (int o = 0; o < nobs; ++o)
-                    dX[cfg->obs_species[o]] += dobs[(size_t)b * nobs + o] * tmp[(size_t)b * nobs + o] * inv_dt;
+                for (int o = 0; o < nobs; ++o) {
+                    const double d = dobs[(size_t)b * nobs + o] * tmp[(size_t)b * nobs + o] * inv_dt;
+                    dX[cfg->obs_species[o]] += d;
+                    dXa[cfg->obs_species[o]] += fabs(d);
+                }
         }
         /* the X_k and t_k parts of this interval's grid times */
         if (grid)
@@ -631,11 +780,27 @@ static void adjoint_one(const orc_net *net, const orc_cfg *cfg, const double *k,
                 for (int o = 0; o < nobs; ++o) {
                     const int s = cfg->obs_species[o];
                     const double d = dobs[(size_t)g * nobs + o];
+                    const double dt_ = d * (double)(Xk1[s] - Xk[s]) * ((f - 1.0) / (tk1 - tk));
                     dX[s] += d * (1.0 - f);
-                    lamt += d * (double)(Xk1[s] - Xk[s]) * ((f - 1.0) / (tk1 - tk));
+                    lamt += dt_;
+                    dXa[s] += fabs(d * (1.0 - f));
+                    Lamt += fabs(dt_);
                 }
             }
-        for (int q = 0; q < N; ++q) lamX[q] += dX[q];
+        /* X_k and t_k as tail states */
+        if (tail && kk >= tail_lo) {
+            const double inv_m = 1.0 / (double)cfg->n_bins;
+            for (int o = 0; o < nobs; ++o) {
+                dX[cfg->obs_species[o]] += dobs[o] * inv_m;
+                dXa[cfg->obs_species[o]] += fabs(dobs[o] * inv_m);
+            }
+            lamt += dobs[nobs] * inv_m;
+            Lamt += fabs(dobs[nobs] * inv_m);
+        }
+        for (int q = 0; q < N; ++q) {
+            lamX[q] += dX[q];
+            LamX[q] += dXa[q];
+        }
     }
     free(tmp);
 }
@@ -645,6 +810,16 @@ int orc_adjoint(const orc_net *net, const orc_cfg *cfg, const double *theta,
                 const orc_overrides *ov, const double *d_obs,
                 int32_t *x_final, double *t_final, int32_t *steps_done, double *obs,
                 double *grad, const orc_stats *stats, int n_threads)
+{
+    return orc_adjoint_kappa(net, cfg, theta, n_traj, traj_ids, x0, ov, d_obs, x_final, t_final,
+                             steps_done, obs, grad, NULL, stats, n_threads);
+}
+
+int orc_adjoint_kappa(const orc_net *net, const orc_cfg *cfg, const double *theta,
+                      int64_t n_traj, const uint32_t *traj_ids, const int32_t *x0,
+                      const orc_overrides *ov, const double *d_obs,
+                      int32_t *x_final, double *t_final, int32_t *steps_done, double *obs,
+                      double *grad, double *kappa, const orc_stats *stats, int n_threads)
 {
     if (check_args(net, cfg) || n_traj < 0) return -1;
     /* the straight-through backward needs the Gumbel noise of the race */
@@ -662,7 +837,7 @@ int orc_adjoint(const orc_net *net, const orc_cfg *cfg, const double *theta,
         path_t path;
         memset(&path, 0, sizeof(path));
         double *scratch = malloc(sizeof(double) * (2 * M + 1 + cfg->n_obs + 1));
-        double *work = malloc(sizeof(double) * (2 * N + 4 * M + cfg->n_obs + 1));
+        double *work = malloc(sizeof(double) * (4 * N + 5 * M + cfg->n_obs + 1));
         if (!scratch || !work) err |= 1;
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
@@ -681,8 +856,11 @@ int orc_adjoint(const orc_net *net, const orc_cfg *cfg, const double *theta,
             t_final[q] = t;
             steps_done[q] = (int32_t)n;
             finish_obs(cfg, X, o);
+            int32_t edge_bad = 0;
+            adjoint_one(net, cfg, k, &path, d_obs + (size_t)q * W, grad + (size_t)q * P,
+                        kappa ? kappa + (size_t)q * P : NULL, work, ov, q, &edge_bad);
+            st.n_bad += edge_bad;
             store_stats(stats, q, &st);
-            adjoint_one(net, cfg, k, &path, d_obs + (size_t)q * W, grad + (size_t)q * P, work);
         }
         path_free(&path);
         free(scratch);

@@ -34,8 +34,12 @@ typedef struct orc_net {
 /* FINAL: final counts.  BINS: exact time averages over n_bins uniform bins of
  * [0, t_obs].  GRID: the path linearly interpolated between its event points
  * (t_k, X_k) at n_bins uniform grid times t_obs g / (n_bins - 1), held at its
- * last state after the last event (Sec. 4.1). */
-enum { ORC_OBS_FINAL = 0, ORC_OBS_BINS = 1, ORC_OBS_GRID = 2 };
+ * last state after the last event (Sec. 4.1).  TAIL: the mean of each
+ * observed count over the last m = n_bins states X_{n-m+1} .. X_n of an
+ * n = n_steps step run, and as value n_obs the mean of their times t_k (the
+ * quantities the oscillator's rate-of-change loss compares, Sec. 4.2); a run
+ * that stops early holds its last state and clock over the remaining steps. */
+enum { ORC_OBS_FINAL = 0, ORC_OBS_BINS = 1, ORC_OBS_GRID = 2, ORC_OBS_TAIL = 3 };
 
 /* Channel selection of the forward: the Gumbel-max (exponential race) of
  * Sec. 3.2, or the standard direct method's inverse CDF (Sec. 2: the first j
@@ -58,12 +62,21 @@ typedef struct orc_cfg {
     double tie_threshold;   /* relative margin that counts as a near-tie (1e-6) */
     double clock_tol;       /* relative window |t + tau - t_end| <= clock_tol * t_end */
     int32_t selection;      /* ORC_SELECT_* */
+    double edge_window;     /* bins: relative window around a bin edge inside which the adjoint
+                               takes the GPU's side of the edge for an event time (0: off) */
 } orc_cfg;
 
 /* Per-trajectory overrides taken from the GPU's near-tie log.  For trajectory
  * q the entries ov_off[q] .. ov_off[q+1]-1 are sorted by step.
  * kind 0: reaction near-tie, val = reaction the GPU fired.
- * kind 1: clock near-tie at t_end, val = 1 if the GPU fired, 0 if it stopped. */
+ * kind 1: clock near-tie at t_end, val = 1 if the GPU fired, 0 if it stopped.
+ * kind 2: the event time of the step lies within the GPU's edge window of a bin
+ *         edge; val = 1 if the GPU's clock put it at or after the edge.  With
+ *         cfg->edge_window > 0 the adjoint assigns the event's clock-derivative
+ *         term to the bin on that side (the derivative of a bin average with
+ *         respect to an event time jumps at an edge).  An event of the oracle
+ *         within half the window of an edge without such an entry, or an entry
+ *         for an event farther than the window, counts in n_bad. */
 typedef struct orc_overrides {
     const int64_t *off;     /* [n_traj+1] */
     const int64_t *step;
@@ -93,7 +106,8 @@ void orc_step_uniforms(uint64_t seed, uint32_t purpose, uint32_t epoch, uint32_t
                        uint32_t step, int32_t n_words, double *u);
 
 /* Forward simulation of n_traj trajectories (x0 and x_final are [n_traj][N]).
- * obs: [n_traj][n_bins][n_obs] bin averages, or [n_traj][n_obs] final counts.
+ * obs: [n_traj][n_bins][n_obs] bin averages or grid values, [n_traj][n_obs]
+ * final counts, or [n_traj][n_obs + 1] tail means (counts, then the clock).
  * theta: [P] (FP32 values promoted).  ov and stats may be NULL.
  * Returns 0, or -1 on invalid arguments. */
 int orc_forward(const orc_net *net, const orc_cfg *cfg, const double *theta,
@@ -109,6 +123,17 @@ int orc_adjoint(const orc_net *net, const orc_cfg *cfg, const double *theta,
                 const orc_overrides *ov, const double *d_obs,
                 int32_t *x_final, double *t_final, int32_t *steps_done, double *obs,
                 double *grad, const orc_stats *stats, int n_threads);
+
+/* orc_adjoint plus kappa [n_traj][P] (may be NULL): per trajectory and
+ * parameter, the sum over steps of the magnitudes of the terms that make up
+ * each step's gradient contribution (propagated through a magnitude adjoint),
+ * the conditioning that bounds the rounding error of an evaluation of the
+ * same recursion at lower precision. */
+int orc_adjoint_kappa(const orc_net *net, const orc_cfg *cfg, const double *theta,
+                      int64_t n_traj, const uint32_t *traj_ids, const int32_t *x0,
+                      const orc_overrides *ov, const double *d_obs,
+                      int32_t *x_final, double *t_final, int32_t *steps_done, double *obs,
+                      double *grad, double *kappa, const orc_stats *stats, int n_threads);
 
 /* Step-by-step record of one trajectory (at most cap steps):
  * X [(cap+1)][N], t [cap+1], tau [cap], j [cap], a [cap][M], u [cap][M+1],

@@ -24,6 +24,9 @@ OBS_FINAL = 0   # final copy numbers of the observed species
 OBS_BINS = 1    # exact time average of the piecewise-constant path over uniform bins (Sec. 4.4)
 OBS_GRID = 2    # the path linearly interpolated between its event points at n_bins uniform
                 # times t_obs g / (n_bins - 1), held after the last event (Sec. 4.1)
+OBS_TAIL = 3    # the mean of each observed count over the last n_bins of the n_steps + 1
+                # states of a run, then the mean of their times (the rate-of-change loss
+                # of Sec. 4.2); a run that stops early holds its last state and clock
 
 # Channel selection of the forward: the Gumbel-max (exponential race) of
 # Sec. 3.2, or the standard direct method's inverse CDF (Sec. 2), which has
@@ -196,6 +199,31 @@ def oscillator(rate_seed: int = 0, log10_range=(-2.0, 3.0), rates=None) -> Netwo
     ]
     x0 = [1, 0, 1, 0, 0, 0, 0, 0, 0]
     return _net("oscillator", OSC_SPECIES, R, 15, np.log(rates), x0, ["R"], list(OSC_PARAMS))
+
+
+# The five protein rates of the oscillator that the start-point-map inference
+# of Sec. 4.2 recovers, at the values the paper gives for them.
+OSC_PROTEIN_PARAMS = ("beta_A", "beta_R", "delta_A", "delta_R", "gamma_C")
+OSC_PROTEIN_RATES = (50.0, 5.0, 1.0, 0.2, 2.0)
+
+
+def start_point_oscillator(rate_seed: int = 0, protein_rates=OSC_PROTEIN_RATES) -> Network:
+    """The oscillator of the start-point-map inference (Sec. 4.2), observing
+    the three proteins A, R and C.  The five protein rates (translation of A
+    and R, degradation of A and R, complex formation) take the paper's values;
+    the other ten distinct rates, which the paper holds at nominal values given
+    in a supplement that is not available, are the seeded ones of
+    oscillator(rate_seed)."""
+    base = oscillator(rate_seed)
+    rates = np.exp(base.theta0.astype(np.float64))
+    for name, k in zip(OSC_PROTEIN_PARAMS, protein_rates):
+        rates[OSC_PARAMS.index(name)] = k
+    net = oscillator(rate_seed, rates=rates)
+    idx = {s_: i for i, s_ in enumerate(net.species)}
+    net.obs_species = np.asarray([idx["A"], idx["R"], idx["C"]], np.int32)
+    net.name = "start_point_oscillator"
+    net.validate()
+    return net
 
 
 def random_network(g: np.random.Generator, name: str = "random",

@@ -71,8 +71,10 @@ def surrogate_F(net, cfg, theta, theta_ref, tr, d_obs):
     t = 0.0
     bins = cfg.obs_kind == W.OBS_BINS
     grid = cfg.obs_kind == W.OBS_GRID
+    tail = cfg.obs_kind == W.OBS_TAIL
     obs = np.zeros((cfg.n_bins, len(net.obs_species))) if (bins or grid) else None
     tg = _grid(cfg) if grid else None
+    states, times = [X], [t]
     for s in range(n):
         a = k * _h(net, X)
         tau = E[s, 0] / a.sum()
@@ -86,20 +88,36 @@ def surrogate_F(net, cfg, theta, theta_ref, tr, d_obs):
                 obs[g] = X[net.obs_species] + f * (Xn - X)[net.obs_species]
         X = Xn
         t += tau
+        states.append(X)
+        times.append(t)
     if bins:
         obs += np.outer(_overlaps(t, cfg.t_obs, cfg.t_obs, cfg.n_bins), X[net.obs_species])
         obs *= cfg.n_bins / cfg.t_obs
     elif grid:
         obs[tg >= t] = X[net.obs_species]
+    elif tail:
+        mx, mt = _tail_means(cfg, states, times, net.obs_species, lambda v: np.stack(v).mean(0), np.mean)
+        obs = np.concatenate([mx, [mt]])
     else:
         obs = X[net.obs_species]
     return float(np.sum(d_obs * obs))
 
 
-def literal_st_grad(net, cfg, theta0, tr, d_obs):
-    """torch float64 autograd through y_ST = stopgrad(y - y~) + y~ (Eq. 5)."""
+def _tail_means(cfg, states, times, osp, mean_x, mean_t):
+    """Tail observation: the mean of the observed counts over the last
+    n_bins of the n_steps + 1 states of the run (states the run did not
+    reach hold its last one), then the mean of their times."""
+    last = len(states) - 1
+    ks = [min(k, last) for k in range(cfg.n_steps - cfg.n_bins + 1, cfg.n_steps + 1)]
+    mx = mean_x([states[k][osp] for k in ks])
+    mt = mean_t([times[k] for k in ks])
+    return mx, mt
+
+
+def literal_st_grad(net, cfg, theta0, tr, d_obs, dt=torch.float64):
+    """torch autograd (float64 unless asked otherwise) through
+    y_ST = stopgrad(y - y~) + y~ (Eq. 5)."""
     T = cfg.temperature
-    dt = torch.float64
     theta = torch.tensor(theta0.astype(np.float64), dtype=dt, requires_grad=True)
     ri = torch.tensor(net.rate_index, dtype=torch.long)
     k = torch.exp(theta[ri])
@@ -109,7 +127,9 @@ def literal_st_grad(net, cfg, theta0, tr, d_obs):
     t = torch.zeros((), dtype=dt)
     bins = cfg.obs_kind == W.OBS_BINS
     grid = cfg.obs_kind == W.OBS_GRID
+    tail = cfg.obs_kind == W.OBS_TAIL
     osp = torch.tensor(net.obs_species, dtype=torch.long)
+    states, times = [X], [t]
     edges = torch.linspace(0.0, cfg.t_obs, cfg.n_bins + 1, dtype=dt) if bins else None
     obs = torch.zeros((cfg.n_bins, len(net.obs_species)), dtype=dt) if bins else None
     tg = _grid(cfg) if grid else None
@@ -154,16 +174,22 @@ def literal_st_grad(net, cfg, theta0, tr, d_obs):
                 gobs[g] = X[osp] + (float(tg[g]) - t) / (t1 - t) * (Xn - X)[osp]
         X = Xn
         t = t + tau
+        states.append(X)
+        times.append(t)
     if bins:
         obs = obs + torch.outer(ov(t, torch.tensor(cfg.t_obs, dtype=dt)), X[osp])
         obs = obs * (cfg.n_bins / cfg.t_obs)
     elif grid:
         obs = torch.stack([X[osp] if v is None else v for v in gobs])
+    elif tail:
+        mx, mt = _tail_means(cfg, states, times, osp, lambda v: torch.stack(v).mean(0),
+                             lambda v: torch.stack(v).mean())
+        obs = torch.cat([mx, mt.reshape(1)])
     else:
         obs = X[osp]
     L = torch.sum(torch.tensor(d_obs, dtype=dt) * obs)
     L.backward()
-    return theta.grad.numpy()
+    return theta.grad.numpy().astype(np.float64)
 
 
 def _case(name):
@@ -195,13 +221,26 @@ def _case(name):
     elif name == "channel_grid_absorbing":
         net = W.ion_channel_coi()
         cfg = W.RunConfig(n_steps=50, obs_kind=W.OBS_GRID, n_bins=10, t_obs=6.0, temperature=0.3)
+    elif name == "abc_tail":
+        net = W.dimerization_abc()
+        cfg = W.RunConfig(n_steps=60, obs_kind=W.OBS_TAIL, n_bins=40, temperature=0.5)
+    elif name == "oscillator_tail":
+        net = W.start_point_oscillator()
+        x0 = np.array([0, 1, 1, 0, 3, 7, 40, 120, 15], np.int32)
+        net = W.Network(net.name, net.species, net.reactant, net.rate_index, net.stoich, net.n_params,
+                        net.theta0, x0, net.obs_species, net.param_names)
+        cfg = W.RunConfig(n_steps=150, obs_kind=W.OBS_TAIL, n_bins=100, temperature=0.5)
+    elif name == "channel_tail_absorbing":
+        net = W.ion_channel_coi()
+        cfg = W.RunConfig(n_steps=30, obs_kind=W.OBS_TAIL, n_bins=12, temperature=0.3)
     else:
         raise KeyError(name)
     return net, cfg, g
 
 
 CASES = ["dimer_bins", "dimer_bins_coldT", "abc_final", "oscillator_bins", "random_bins",
-         "channel_absorbing", "abc_grid", "abc_grid_coldT", "channel_grid_absorbing"]
+         "channel_absorbing", "abc_grid", "abc_grid_coldT", "channel_grid_absorbing",
+         "abc_tail", "oscillator_tail", "channel_tail_absorbing"]
 
 
 def _prepare(orc, name, traj_id=1):
@@ -213,6 +252,7 @@ def _prepare(orc, name, traj_id=1):
         cfg = cfg.replace(t_obs=float(tr0.t[-1]) * 0.8)
     tr = orc.trace(net, cfg, theta0, net.x0, traj_id=traj_id, cap=cfg.n_steps)
     shape = ((cfg.n_bins, len(net.obs_species)) if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID)
+             else (len(net.obs_species) + 1,) if cfg.obs_kind == W.OBS_TAIL
              else (len(net.obs_species),))
     d_obs = g.normal(size=shape)
     r = orc.run(net, cfg, theta0, net.x0[None, :], traj_ids=[traj_id], d_obs=d_obs[None])
@@ -290,3 +330,97 @@ def test_grid_observation_is_linear_interpolation(orc, name):
         for o, sp in enumerate(net.obs_species):
             ref = np.interp(tg, tr.t, tr.X[:, sp].astype(np.float64))
             assert np.allclose(r.obs[0, :, o], ref, rtol=0, atol=1e-12), (q, o)
+
+
+# ---------------------------------------------------------------------------
+# The conditioning kappa of each gradient component (orc_adjoint_kappa): the
+# sum over steps of the magnitudes of the terms of that step's contribution,
+# propagated through a magnitude adjoint.  Two properties pin it: it bounds the
+# component itself (every term is bounded by its magnitude), and it bounds the
+# rounding error of the same recursion evaluated at lower precision.
+
+def _kappa(orc, name, traj_id=1):
+    net, cfg, theta0, tr, d_obs, grad = _prepare(orc, name, traj_id)
+    r = orc.run(net, cfg, theta0, net.x0[None, :], traj_ids=[traj_id], d_obs=d_obs[None], kappa=True)
+    assert np.array_equal(r.grad[0], grad)
+    return net, cfg, theta0, tr, d_obs, grad, r.kappa[0]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_kappa_bounds_the_gradient(orc, name):
+    for q in (1, 2, 5):
+        _, _, _, _, _, grad, kappa = _kappa(orc, name, q)
+        assert np.all(kappa >= 0) and np.all(np.isfinite(kappa))
+        assert np.all(np.abs(grad) <= kappa * (1 + 1e-12) + 1e-300), (grad, kappa)
+
+
+@pytest.mark.parametrize("q", [1, 2, 5])
+@pytest.mark.parametrize("name", CASES)
+def test_kappa_bounds_float32_rounding(orc, name, q):
+    """The literal stop-gradient graph evaluated by torch in float32 differs
+    from the FP64 gradient by at most c 2^-24 kappa per component.  c counts
+    the roundings of a term: 16 for the adjoint algebra, plus the soft
+    sample's relative error, which this graph builds from logits
+    z_j = ln a_j + G_j rounded to float32 and from exp((z_j - max z)/T): an
+    absolute error of about 2^-24 (|z_j| + |z_j - max z|), rounded twice in
+    the softmax and twice more in its backward, divided by T."""
+    net, cfg, theta0, tr, d_obs, grad, kappa = _kappa(orc, name, q)
+    g32 = literal_st_grad(net, cfg, theta0, tr, d_obs, dt=torch.float32)
+    act = tr.a > 0
+    z = np.where(act, np.log(np.where(act, tr.a, 1.0)) - np.log(-np.log(tr.u[:, 1:])), -np.inf)
+    zspan = np.abs(z) + (z.max(axis=1, keepdims=True) - z)
+    c = 16.0 + 8.0 * float(zspan[act].max()) / cfg.temperature
+    err = np.abs(g32 - grad)
+    assert np.all(err <= c * 2.0 ** -24 * kappa), (err, c * 2.0 ** -24 * kappa)
+
+
+@pytest.mark.parametrize("name", ["abc_tail", "oscillator_tail", "channel_tail_absorbing"])
+def test_tail_observation_is_the_mean_of_the_last_states(orc, name):
+    """The tail observation is the plain mean of the last n_bins of the
+    n_steps + 1 states of the traced path and of their times; a path that
+    stops early (absorbing state) holds its last state and clock."""
+    net, cfg, _ = _case(name)
+    for q in range(6):
+        tr = orc.trace(net, cfg, net.theta0, net.x0, traj_id=q, cap=cfg.n_steps)
+        r = orc.run(net, cfg, net.theta0, net.x0[None, :], traj_ids=[q])
+        n = len(tr.j)
+        idx = np.minimum(np.arange(cfg.n_steps - cfg.n_bins + 1, cfg.n_steps + 1), n)
+        ref = np.concatenate([tr.X[idx][:, net.obs_species].mean(0), [tr.t[idx].mean()]])
+        assert r.obs.shape == (1, len(net.obs_species) + 1)
+        assert np.allclose(r.obs[0], ref, rtol=1e-14, atol=0), (q, r.obs[0], ref)
+    if name == "channel_tail_absorbing":
+        assert n < cfg.n_steps      # the last path traced absorbed before the end
+
+
+def test_bin_edge_side_from_the_gpu_log(orc):
+    """Kind-2 overrides (an event time close to a bin edge): the adjoint takes
+    the given side of the edge for the clock-derivative term.  Taking the
+    side the oracle's own clock is on changes nothing; taking the other side
+    gives the one-sided derivative from there, which the oracle itself
+    returns when the edge moves to the other side of the event by 1e-10
+    relative; an event near an edge without a record, or a record far from
+    any edge, counts as a disagreement."""
+    net = W.dimerization_2a()
+    base = W.RunConfig(n_steps=60, obs_kind=W.OBS_FINAL, temperature=0.5)
+    tr = orc.trace(net, base, net.theta0, net.x0, traj_id=0, cap=60)
+    k = 25                                    # the event of step k - 1 happens at t_k
+    nb, i = 6, 2
+    t_obs = float(tr.t[k]) * nb / i           # edge i sits on that event
+    cfg = base.replace(obs_kind=W.OBS_BINS, n_bins=nb, t_obs=t_obs)
+    d = np.random.default_rng(4).normal(size=(1, nb, 1))
+    e = t_obs * i / nb
+    assert abs(e - tr.t[k]) <= 1e-12 * e
+    run = lambda c, ties, ew: orc.run(net, c, net.theta0, net.x0[None, :], traj_ids=[0], ties=ties, d_obs=d,
+                                      edge_window=ew)
+    plain = run(cfg, None, 0.0)
+    own = 1 if tr.t[k] >= e else 0
+    r = run(cfg, [(0, k - 1, 2, own)], 4e-7)
+    assert r.n_bad[0] == 0 and np.array_equal(r.grad, plain.grad)
+    assert run(cfg, None, 4e-7).n_bad[0] == 1
+    assert run(cfg, [(0, k - 1, 2, own), (0, k - 3, 2, 1)], 4e-7).n_bad[0] == 1
+    flipped = run(cfg, [(0, k - 1, 2, 1 - own)], 4e-7)
+    assert flipped.n_bad[0] == 0 and not np.allclose(flipped.grad, plain.grad)
+    # move the edge across the event instead
+    shifted = run(cfg.replace(t_obs=t_obs * (1.0 + (1e-10 if own else -1e-10))), None, 0.0)
+    assert (shifted.t_final == plain.t_final).all()
+    assert np.allclose(flipped.grad, shifted.grad, rtol=1e-6, atol=1e-8 * np.abs(shifted.grad).max())
