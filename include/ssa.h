@@ -39,8 +39,8 @@
  *   steps_done         int32  [sum B_n]
  *   obs / d_obs        double [sum W_n*B_n]        (block [W_n][B_n], or [B_n][W_n] with
  *                       SSA_OBS_TRAJ_MAJOR; W_n = n_bins*n_obs_n as [point][obs] for bins
- *                       and grids, n_obs_n for final counts; [sum W_n] with
- *                       SSA_OBS_ENSEMBLE_MEAN)
+ *                       and grids, n_obs_n for final counts, n_obs_n + 1 for tail means;
+ *                       [sum W_n] with SSA_OBS_ENSEMBLE_MEAN)
  *   ensemble means     double [sum W_n]            (ssa_obs_mean; a shared d_obs)
  *   d_params_per_traj  float  [sum P_n*B_n]        (block [P_n][B_n])
  * ssa_net_layout() returns every offset.
@@ -79,7 +79,18 @@ typedef enum ssa_status {
  *                  last event (the interpolated ensemble trajectories of
  *                  Sec. 4.1).  Runs in the topology-specialised lane mode
  *                  only: any other plan returns SSA_ENOTSUP. */
-enum { SSA_OBS_FINAL = 0, SSA_OBS_BINS = 1, SSA_OBS_GRID = 2 };
+enum { SSA_OBS_FINAL = 0, SSA_OBS_BINS = 1, SSA_OBS_GRID = 2, SSA_OBS_TAIL = 3 };
+/*   SSA_OBS_TAIL   obs[o][B] for o < n_obs: the mean of observed count o over
+ *                  the last m = n_bins of the n_steps + 1 states X_0 .. X_n of
+ *                  the run, and obs[n_obs][B]: the mean of their times t_k
+ *                  (the per-segment rate of change of the start-point map,
+ *                  Sec. 4.2, is (mean count - start count) / mean time).  A
+ *                  trajectory that stops early (absorbing state, t_end) holds
+ *                  its last state and clock over the remaining states.  Needs
+ *                  a bounded n_steps, 1 <= n_bins <= n_steps, the point-major
+ *                  layout with a per-trajectory d_obs, the Gumbel-max selection
+ *                  and the topology-specialised lane mode (else SSA_ENOTSUP);
+ *                  W_n = n_obs_n + 1, and ssa_net_layout returns its offsets. */
 
 /* Channel selection of the forward:
  *   SSA_SELECT_GUMBEL_MAX   argmax_j ln a_j + G_j (Sec. 3.2), run as the exponential
@@ -115,7 +126,10 @@ enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1, SSA_OBS_ENSEMBLE_MEAN = 
  * grid observations (grid values are summed in the same fixed point, the held
  * tail as counts), topology-specialised lane mode, n_bins * n_obs <= 1000 and
  * 16 * n_bins * n_obs + 8 * n_obs <= 16384 (the LDS of one wave);
- * ssa_backward then needs dobs_shared.  Anything else returns SSA_ENOTSUP. */
+ * ssa_backward then needs dobs_shared.  Anything else returns SSA_ENOTSUP.
+ * The sums are exact for observed counts below 2^25 (64 trajectories add into
+ * one slot); a larger count is left out and raises the overflow flag that
+ * ssa_device_status reports as SSA_EOVERFLOW. */
 
 /* How ssa_backward obtains the fired channel of each step.
  *   SSA_BWD_TAPE:      ssa_forward stores the fired channel index of every
@@ -193,8 +207,9 @@ typedef struct ssa_config {
     const uint32_t *traj_ids;      /* optional DEVICE [sum B_n] global trajectory ids; NULL: 0..B-1 */
     int32_t n_steps;               /* fire at most this many channels per trajectory */
     double t_end;                  /* fire only while t + tau <= t_end; +INFINITY: no limit */
-    int32_t obs_kind;              /* SSA_OBS_FINAL, SSA_OBS_BINS or SSA_OBS_GRID */
-    int32_t n_bins;                /* bins (>= 1) or grid points (>= 2) per observed species */
+    int32_t obs_kind;              /* SSA_OBS_FINAL, SSA_OBS_BINS, SSA_OBS_GRID or SSA_OBS_TAIL */
+    int32_t n_bins;                /* bins (>= 1) or grid points (>= 2) per observed species, or
+                                      the tail length m of SSA_OBS_TAIL */
     float temperature;             /* Gumbel-Softmax temperature T of Eq. (3), > 0 */
     int32_t ckpt_every;            /* K: steps between state checkpoints (>= 1) */
     int32_t bwd_mode;              /* SSA_BWD_* */
@@ -208,9 +223,15 @@ typedef struct ssa_config {
 } ssa_config;
 
 /* One logged step where the selection (kind 0) or the t_end stop decision
- * (kind 1) was within the library's FP32 error of the alternative:
+ * (kind 1) was within the library's FP32 error of the alternative, or (kind 2)
+ * where the event time fell close to a bin edge:
  * kind 0: relative gap of the two smallest E_j/a_j <= 2e-6;
- * kind 1: |t + tau - t_end| <= 1e-5 t_end, chosen = 1 if the step fired. */
+ * kind 1: |t + tau - t_end| <= 1e-5 t_end, chosen = 1 if the step fired;
+ * kind 2: bin observation, topology-specialised lane mode:
+ *         |t + tau - e| <= 4e-7 e for the edge e = t_obs i / n_bins, i >= 1;
+ *         chosen = 1 if t + tau >= e (the derivative of the bin averages with
+ *         respect to this event time is taken on that side of the edge),
+ *         second = i, margin = (t + tau - e) / e. */
 typedef struct ssa_tie {
     uint32_t traj;                 /* packed trajectory index (not the global id) */
     uint32_t step;

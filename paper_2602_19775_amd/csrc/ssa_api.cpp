@@ -89,7 +89,7 @@ struct ssa_net {
     std::vector<Group> groups;
     uint32_t *flags_d = nullptr;
     int64_t traj_total = 0, state_total = 0, param_total = 0, obsb_total = 0, part_total = 0,
-            ppt_total = 0, obsw_total = 0, tobs_total = 0;
+            ppt_total = 0, obsw_total = 0, tobs_total = 0, obst_total = 0, obstw_total = 0;
     int max_M = 0;
     int64_t max_B = 0;
     int device = 0;
@@ -171,7 +171,28 @@ size_t grad_work_bytes(const ssa_net *net)
 // values per trajectory of network nd for the observation of cfg
 int64_t obs_width(const NetDev &nd, const ssa_config *cfg)
 {
+    if (cfg->obs_kind == SSA_OBS_TAIL) return (int64_t)nd.n_obs + 1;
     return (int64_t)nd.n_obs * (cfg->obs_kind != SSA_OBS_FINAL ? cfg->n_bins : 1);
+}
+
+// first value of network nd in the observation buffer and in the buffer of
+// ensemble means, for the observation kind and point count of a query
+int64_t obs_block_offset(const NetDev &nd, int32_t obs_kind, int32_t n_bins)
+{
+    if (obs_kind == SSA_OBS_TAIL) return nd.obst_off;
+    return nd.obsb_off * (obs_kind != SSA_OBS_FINAL ? n_bins : 1);
+}
+
+int64_t mean_block_offset(const NetDev &nd, int32_t obs_kind, int32_t n_bins)
+{
+    if (obs_kind == SSA_OBS_TAIL) return nd.obstw_off;
+    return nd.obsw_off * (obs_kind != SSA_OBS_FINAL ? n_bins : 1);
+}
+
+// values of the whole observation buffer for cfg (0: nothing observed)
+int64_t obs_total(const ssa_net *net, const ssa_config *cfg)
+{
+    return cfg->obs_kind == SSA_OBS_TAIL ? net->obst_total : net->obsb_total;
 }
 
 // The ensemble-mean chunk sums follow the gradient region of the work buffer.
@@ -215,8 +236,20 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
     if (!cfg) return fail(SSA_EINVAL, "config is NULL");
     if (cfg->n_steps < 0) return fail(SSA_EINVAL, "n_steps must be >= 0");
     if (!(cfg->t_end > 0.0)) return fail(SSA_EINVAL, "t_end must be > 0 (use INFINITY for no limit)");
-    if (cfg->obs_kind != SSA_OBS_FINAL && cfg->obs_kind != SSA_OBS_BINS && cfg->obs_kind != SSA_OBS_GRID)
-        return fail(SSA_EINVAL, "obs_kind must be SSA_OBS_FINAL, SSA_OBS_BINS or SSA_OBS_GRID");
+    if (cfg->obs_kind != SSA_OBS_FINAL && cfg->obs_kind != SSA_OBS_BINS && cfg->obs_kind != SSA_OBS_GRID &&
+        cfg->obs_kind != SSA_OBS_TAIL)
+        return fail(SSA_EINVAL, "obs_kind must be SSA_OBS_FINAL, SSA_OBS_BINS, SSA_OBS_GRID or SSA_OBS_TAIL");
+    if (cfg->obs_kind == SSA_OBS_TAIL) {
+        if (!bounded_steps(cfg) || cfg->n_bins < 1 || cfg->n_bins > cfg->n_steps)
+            return fail(SSA_EINVAL, "tail observation needs a bounded n_steps and 1 <= n_bins <= n_steps");
+        if (cfg->obs_layout != SSA_OBS_POINT_MAJOR || cfg->dobs_shared)
+            return fail(SSA_ENOTSUP, "the tail observation runs in the point-major layout with a per-trajectory d_obs");
+        if (cfg->selection != SSA_SELECT_GUMBEL_MAX)
+            return fail(SSA_ENOTSUP, "the tail observation runs with the Gumbel-max selection");
+        for (const auto &gr : net->groups)
+            if (gr.n_items && !gr.spec)
+                return fail(SSA_ENOTSUP, "the tail observation runs in the topology-specialised lane mode only");
+    }
     if (cfg->obs_kind == SSA_OBS_BINS) {
         if (cfg->n_bins < 1) return fail(SSA_EINVAL, "bin observation needs n_bins >= 1");
         for (const NetDev &nd : net->nets_h)
@@ -506,6 +539,8 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         nd.obsb_off = net->obsb_total;
         nd.obsw_off = net->obsw_total;
         nd.tobs_off = net->tobs_total;
+        nd.obst_off = net->obst_total;
+        nd.obstw_off = net->obstw_total;
         nd.part_off = net->part_total;
         nd.ppt_off = net->ppt_total;
         nd.t_obs = d->t_obs ? d->t_obs[n] : 0.0;
@@ -577,6 +612,8 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         net->obsb_total += (int64_t)nob * B;
         net->obsw_total += nob;
         net->tobs_total += (int64_t)((B + 63) / 64) * nob;
+        net->obst_total += (int64_t)(nob + 1) * B;
+        net->obstw_total += nob + 1;
         net->part_total += (int64_t)M * B;
         net->ppt_total += (int64_t)P * B;
         net->max_M = std::max(net->max_M, M);
@@ -695,9 +732,9 @@ ssa_status ssa_net_layout(const ssa_net *net, int32_t obs_kind, int32_t n_bins, 
     out->traj_offset = nd.traj_off;
     out->state_offset = nd.state_off;
     out->param_offset = nd.param_off;
-    out->obs_offset = nd.obsb_off * (obs_kind != SSA_OBS_FINAL ? n_bins : 1);
+    out->obs_offset = obs_block_offset(nd, obs_kind, n_bins);
     out->ppt_offset = nd.ppt_off;
-    out->mean_offset = nd.obsw_off * (obs_kind != SSA_OBS_FINAL ? n_bins : 1);
+    out->mean_offset = mean_block_offset(nd, obs_kind, n_bins);
     return SSA_OK;
 }
 
@@ -721,7 +758,7 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
     if (s != SSA_OK) return s;
     if (!theta || !x0 || !x_final || !t_final || !steps_done)
         return fail(SSA_EINVAL, "theta, x0, x_final, t_final and steps_done are required");
-    if (net->obsb_total > 0 && !obs) return fail(SSA_EINVAL, "obs is NULL but species are observed");
+    if (obs_total(net, cfg) > 0 && !obs) return fail(SSA_EINVAL, "obs is NULL but species are observed");
     if (!work || work_bytes < work_bytes_for(net, cfg)) return fail(SSA_EWORKSPACE, "work buffer too small");
     if ((ties == nullptr) != (n_ties == nullptr)) return fail(SSA_EINVAL, "ties and n_ties go together");
     const CkptLayout L = ckpt_layout(net, cfg);
@@ -768,12 +805,11 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
     return SSA_OK;
 }
 
-ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *theta, const int32_t *x0,
+static ssa_status backward_impl(const ssa_net *net, const ssa_config *cfg, const float *theta, const int32_t *x0,
                         const int32_t *x_final, const double *t_final, const int32_t *steps_done,
                         const void *ckpt, size_t ckpt_bytes, const double *d_obs, float *d_params,
                         float *d_params_per_traj, void *work, size_t work_bytes, hipStream_t stream)
 {
-    g_last_error.clear();
     ssa_status s = check_config(net, cfg);
     if (s == SSA_OK && cfg->selection != SSA_SELECT_GUMBEL_MAX)
         return fail(SSA_ENOTSUP, "the straight-through backward needs the Gumbel-max selection");
@@ -782,7 +818,7 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
         return fail(SSA_ENOTSUP, "after an ensemble-mean forward the backward needs a shared d_obs");
     if (!theta || !x0 || !x_final || !t_final || !steps_done || !d_params)
         return fail(SSA_EINVAL, "theta, x0, x_final, t_final, steps_done and d_params are required");
-    if (net->obsb_total > 0 && !d_obs) return fail(SSA_EINVAL, "d_obs is NULL but species are observed");
+    if (obs_total(net, cfg) > 0 && !d_obs) return fail(SSA_EINVAL, "d_obs is NULL but species are observed");
     const CkptLayout L = ckpt_layout(net, cfg);
     if (L.bytes == 0) return fail(SSA_EINVAL, "the backward needs a bounded n_steps");
     if (!ckpt || ckpt_bytes < L.bytes) return fail(SSA_EWORKSPACE, "checkpoint buffer too small");
@@ -820,6 +856,16 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
     return SSA_OK;
 }
 
+ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *theta, const int32_t *x0,
+                        const int32_t *x_final, const double *t_final, const int32_t *steps_done,
+                        const void *ckpt, size_t ckpt_bytes, const double *d_obs, float *d_params,
+                        float *d_params_per_traj, void *work, size_t work_bytes, hipStream_t stream)
+{
+    g_last_error.clear();
+    return backward_impl(net, cfg, theta, x0, x_final, t_final, steps_done, ckpt, ckpt_bytes, d_obs, d_params,
+                         d_params_per_traj, work, work_bytes, stream);
+}
+
 ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double *obs, double *mean,
                         void *work, size_t work_bytes, hipStream_t stream)
 {
@@ -828,16 +874,15 @@ ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double 
     if (s != SSA_OK) return s;
     if (cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN)
         return fail(SSA_EINVAL, "ensemble-mean observations are means already");
-    if (net->obsw_total > 0 && (!obs || !mean)) return fail(SSA_EINVAL, "obs and mean are required");
+    if (obs_total(net, cfg) > 0 && (!obs || !mean)) return fail(SSA_EINVAL, "obs and mean are required");
     if (!work || work_bytes < work_bytes_for(net, cfg)) return fail(SSA_EWORKSPACE, "work buffer too small");
     double *sums = (double *)((char *)work + grad_work_bytes(net));
-    const int64_t npts = cfg->obs_kind != SSA_OBS_FINAL ? cfg->n_bins : 1;
     for (const NetDev &nd : net->nets_h) {
         const int64_t W = obs_width(nd, cfg);
         if (W == 0) continue;
-        hipError_t e = launch_obs_mean(obs + nd.obsb_off * npts, nd.B, W,
+        hipError_t e = launch_obs_mean(obs + obs_block_offset(nd, cfg->obs_kind, cfg->n_bins), nd.B, W,
                                        cfg->obs_layout == SSA_OBS_TRAJ_MAJOR, sums,
-                                       mean + nd.obsw_off * npts, nd.B, stream);
+                                       mean + mean_block_offset(nd, cfg->obs_kind, cfg->n_bins), nd.B, stream);
         if (e != hipSuccess) return hip_fail(e, "ensemble mean");
     }
     return SSA_OK;

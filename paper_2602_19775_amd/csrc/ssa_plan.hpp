@@ -56,6 +56,8 @@ struct NetDev {
                          // ensemble means and a shared dL/dobs
     int64_t tobs_off;    // sum of ceil(B / 64) * n_obs (times n_bins): per-tile sums of the
                          // ensemble-mean forward, [tile][n_bins][n_obs] per network
+    int64_t obst_off;    // sum of (n_obs + 1) * B: tail observations [n_obs + 1][B] per network
+    int64_t obstw_off;   // sum of (n_obs + 1): their ensemble means
     double t_obs;
 };
 
@@ -85,6 +87,13 @@ enum : uint32_t { kFlagOverflow = 1u, kFlagNonFinite = 2u };
 constexpr float kTieLog = 2e-6f;
 // Stop-decision window at t_end (relative to t_end).
 constexpr double kClockTieLog = 1e-5;
+// Bin-edge window of the bin observation (relative to the edge's time): an
+// event time this close to a bin edge is logged with the side of the edge the
+// FP32-accumulated clock put it on.  The derivative of a bin average with
+// respect to an event time jumps at an edge, so that side decides which bin's
+// dL/dobs enters the clock adjoint; a checker whose clock differs by less than
+// half this window can take the same side.
+constexpr double kEdgeLog = 4e-7;
 
 struct RunParams {
     const NetDev *nets;

@@ -93,6 +93,11 @@ __device__ __forceinline__ void fill_runs(double *blk, int64_t first, int64_t np
 
 // Fixed-point scale of the single-bin values the ensemble-mean forward sums.
 constexpr double kFixScale = 4294967296.0;   // 2^32
+// Largest observed count the ensemble-mean forward sums exactly: 64 lanes add
+// into one slot, so a count below 2^25 keeps the int32 difference arrays and
+// the int64 fixed-point sums (count * 2^32 each) within range.  A larger one
+// raises the overflow flag.
+constexpr double kEnsMaxCount = 33554432.0;  // 2^25
 
 // The ensemble-mean forward's additions for one lane: the value of a single
 // bin fb (the bin an interval completes or the one the path stops in; -1 for
@@ -101,27 +106,39 @@ constexpr double kFixScale = 4294967296.0;   // 2^32
 // counts (dsc for bins an interval crosses, whose values are the count times
 // the bin width over the nominal width; dun for the held tail, whose values
 // are the count).  Integer additions commute, so the wave's sums do not depend
-// on the order in which its lanes reach them.
+// on the order in which its lanes reach them.  Returns true when a value is
+// too large to be summed exactly (kEnsMaxCount); it is then left out.
 template <class NET>
-__device__ __forceinline__ void ens_add(long long *sfp, int *dsc, int *dun, int fb,
+__device__ __forceinline__ bool ens_add(long long *sfp, int *dsc, int *dun, int fb,
                                         const double (&fv)[obs_cap(NET::NOBS)], int lo, int hi,
                                         const int (&X)[NET::N + 1], bool scaled)
 {
     constexpr int NOBS = NET::NOBS;
+    bool big = false;
     if (fb >= 0) {
 #pragma unroll
-        for (int o = 0; o < NOBS; ++o)
-            atomicAdd((unsigned long long *)&sfp[fb * NOBS + o], (unsigned long long)(long long)rint(fv[o] * kFixScale));
+        for (int o = 0; o < NOBS; ++o) {
+            const bool ok = fabs(fv[o]) < kEnsMaxCount;
+            big = big || !ok;
+            if (ok)
+                atomicAdd((unsigned long long *)&sfp[fb * NOBS + o],
+                          (unsigned long long)(long long)rint(fv[o] * kFixScale));
+        }
     }
     if (hi > lo) {
         int *d = scaled ? dsc : dun;
 #pragma unroll
         for (int o = 0; o < NOBS; ++o) {
             const int x = X[NET::OBS[o]];
-            atomicAdd(&d[lo * NOBS + o], x);
-            atomicAdd(&d[hi * NOBS + o], -x);
+            const bool ok = x > -(int)kEnsMaxCount && x < (int)kEnsMaxCount;
+            big = big || !ok;
+            if (ok) {
+                atomicAdd(&d[lo * NOBS + o], x);
+                atomicAdd(&d[hi * NOBS + o], -x);
+            }
         }
     }
+    return big;
 }
 
 // The wave's row of sums [bin][obs]: each lane takes a contiguous chunk of
@@ -283,10 +300,18 @@ __device__ void forward_run(const RunParams &p)
     double acc[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) acc[o] = 0.0;
-    // observation block [point][obs][B], or [B][point][obs] trajectory-major
-    const int64_t npts = p.obs_kind != 0 ? n_bins : 1;
+    // tail observation: the states k + 1 >= n_steps - n_bins + 1 (the last
+    // n_bins of the run) are summed, counts and clock
+    const bool tail = !GRID && p.obs_kind == 3;
+    const int tail_k = tail ? p.n_steps - n_bins : 0x7FFFFFFF;
+    double tacc[NO], tacc_t = 0.0;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) tacc[o] = 0.0;
+    // observation block [point][obs][B], or [B][point][obs] trajectory-major;
+    // the tail observation is [obs + clock][B]
+    const int64_t npts = (p.obs_kind != 0 && !tail) ? n_bins : 1;
     const int64_t orow = p.obs_tm ? (int64_t)NOBS : (int64_t)NOBS * B, ocol = p.obs_tm ? 1 : B;
-    double *obs_base = p.obs + nd.obsb_off * npts;
+    double *obs_base = p.obs + (tail ? nd.obst_off : nd.obsb_off * npts);
     double *obs_lane = obs_base + (p.obs_tm ? i * npts * NOBS : i);
     // ensemble-mean forward: the wave's fixed-point single-bin sums and its
     // two difference arrays of counts in LDS, cleared here
@@ -303,6 +328,10 @@ __device__ void forward_run(const RunParams &p)
     int gi = 0;
     double grid_t = grid ? 0.0 : INFINITY;
     const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
+    // bin-edge log: an event time outside (e_lo, e_hi), the current bin
+    // narrowed by kEdgeLog at both edges, takes the rare path
+    const bool edge_log = bins && p.ties != nullptr;
+    double e_lo = -INFINITY, e_hi = edge_log ? bin_hi * (1.0 - kEdgeLog) : INFINITY;
 
     const int bits = p.tape_bits;
     const int spw = bits ? 32 / bits : 0;
@@ -395,7 +424,8 @@ __device__ void forward_run(const RunParams &p)
         const bool gcross = grid && fire && grid_t < tn;    // grid points in [t, t + tau)
         const bool odd = active && !(a0 >= 0.f);
         const bool stop = active && !fire;
-        if (ballot(clock_tie || near_tie || crossing || gcross || odd || stop) != 0ull) {
+        const bool edgy = fire && (tn >= e_hi || tn <= e_lo);   // implies crossing when edge_log
+        if (ballot(clock_tie || near_tie || crossing || gcross || odd || stop || edgy) != 0ull) {
             if (ballot(stop) != 0ull) any = ballot(fire) != 0ull;
             if (odd) flags |= kFlagNonFinite;
             if (clock_tie)
@@ -444,8 +474,11 @@ __device__ void forward_run(const RunParams &p)
                 bin = b;
                 bin_hi = b < n_bins ? bin_edge(t_obs, b + 1, n_bins) : INFINITY;
             }
-            if (ENS) ens_add<NET>(sfp, dsc, dun, fb, fv, run_lo, run_hi, X, true);
-            else if (TMB) fill_runs<NET>(obs_base, it.first, npts, run_lo, run_hi, X, true, t_obs, n_bins, inv_dt);
+            if (ENS) {
+                if (ens_add<NET>(sfp, dsc, dun, fb, fv, run_lo, run_hi, X, true)) flags |= kFlagOverflow;
+            } else if (TMB) {
+                fill_runs<NET>(obs_base, it.first, npts, run_lo, run_hi, X, true, t_obs, n_bins, inv_dt);
+            }
             if (!TMB && crossing) {
                 double t0 = t;
                 while (bin < n_bins) {
@@ -466,6 +499,19 @@ __device__ void forward_run(const RunParams &p)
                     bin_hi = bin < n_bins ? bin_edge(t_obs, bin + 1, n_bins) : INFINITY;
                 }
             }
+            if (edge_log && edgy) {
+                // the edges around the bin holding t + tau (edge i is at t_obs i / n_bins)
+                const int bl = bin < n_bins ? bin : n_bins;
+                const double lo = bl >= 1 ? bin_edge(t_obs, bl, n_bins) : -INFINITY;
+                const double hi = bl < n_bins ? bin_edge(t_obs, bl + 1, n_bins) : INFINITY;
+                int ei = -1;
+                double e = 0.0;
+                if (bl >= 1 && fabs(tn - lo) <= kEdgeLog * lo) { ei = bl; e = lo; }
+                else if (bl < n_bins && fabs(tn - hi) <= kEdgeLog * hi) { ei = bl + 1; e = hi; }
+                if (ei >= 1) log_tie(p, (uint32_t)g, k, tn >= e ? 1 : 0, ei, (float)((tn - e) / e), 2);
+                e_lo = bl >= 1 ? lo * (1.0 + kEdgeLog) : -INFINITY;
+                e_hi = bl < n_bins ? hi * (1.0 - kEdgeLog) : INFINITY;
+            }
             if (gcross) {
                 // interpolate between (t, X) and (t + tau, X + v_j)
                 const double inv_tau = 1.0 / (double)tau;
@@ -474,10 +520,13 @@ __device__ void forward_run(const RunParams &p)
 #pragma unroll
                     for (int o = 0; o < NOBS; ++o) {
                         const double v = (double)X[NET::OBS[o]] + f * (double)delta_of<NET>(j1, NET::OBS[o]);
-                        if (ENS)
-                            atomicAdd((unsigned long long *)&sfp[gi * NOBS + o],
-                                      (unsigned long long)(long long)rint(v * kFixScale));
-                        else
+                        if (ENS) {
+                            if (fabs(v) < kEnsMaxCount)
+                                atomicAdd((unsigned long long *)&sfp[gi * NOBS + o],
+                                          (unsigned long long)(long long)rint(v * kFixScale));
+                            else
+                                flags |= kFlagOverflow;
+                        } else
                             obs_lane[gi * orow + o * ocol] = v;
                     }
                     gi += 1;
@@ -491,6 +540,12 @@ __device__ void forward_run(const RunParams &p)
         t = fire ? tn : t;
         n_done += fire ? 1 : 0;
         active = fire;
+        if (k >= tail_k) {
+            // state k + 1 (held by a lane that stopped)
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) tacc[o] += (double)X[NET::OBS[o]];
+            tacc_t += t;
+        }
 #pragma unroll
         for (int q = 0; q < NW; ++q) wd[q] = wn[q];
         if (!any) {
@@ -513,14 +568,15 @@ __device__ void forward_run(const RunParams &p)
         double fv[NO];
 #pragma unroll
         for (int o = 0; o < NO; ++o) fv[o] = 0.0;
-        ens_add<NET>(sfp, dsc, dun, -1, fv, tail ? gi : 0, tail ? n_bins : 0, X, false);
+        if (ens_add<NET>(sfp, dsc, dun, -1, fv, tail ? gi : 0, tail ? n_bins : 0, X, false)) flags |= kFlagOverflow;
     } else if (ENS) {
         const bool tail = valid && bin < n_bins;
         double fv[NO];
 #pragma unroll
         for (int o = 0; o < NO; ++o)
             fv[o] = (acc[o] + (double)X[NET::OBS[o]] * fmax(fmin(bin_hi, t_obs) - t, 0.0)) * inv_dt;
-        ens_add<NET>(sfp, dsc, dun, tail ? bin : -1, fv, tail ? bin + 1 : 0, tail ? n_bins : 0, X, false);
+        if (ens_add<NET>(sfp, dsc, dun, tail ? bin : -1, fv, tail ? bin + 1 : 0, tail ? n_bins : 0, X, false))
+            flags |= kFlagOverflow;
     }
     if (ENS) {
         // every lane's additions land before the row is read back
@@ -534,6 +590,19 @@ __device__ void forward_run(const RunParams &p)
     }
     if (!valid) return;
     if (spw && (k & (spw - 1)) != 0) p.tape[(int64_t)(k >> tshift) * p.traj_total + g] = tword;
+    if (tail) {
+        // the tail states past the last step every lane of the wave stopped at hold the last one
+        const int rem = p.n_steps - max(k, tail_k);
+        if (rem > 0) {
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) tacc[o] += (double)rem * (double)X[NET::OBS[o]];
+            tacc_t += (double)rem * t;
+        }
+        const double inv_m = 1.0 / (double)n_bins;
+#pragma unroll
+        for (int o = 0; o < NOBS; ++o) obs_lane[o * B] = tacc[o] * inv_m;
+        obs_lane[NOBS * B] = tacc_t * inv_m;
+    }
     if (!ENS && bin < n_bins) {
 #pragma unroll
         for (int o = 0; o < NO; ++o) {
@@ -628,13 +697,22 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     const int n_bins = p.n_bins;
     const double t_obs = nd.t_obs;
     const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
+    // tail observation: the states X_k, k >= tail_lo, enter the means
+    const bool tail = !GRID && p.obs_kind == 3;
+    const int tail_lo = tail ? p.n_steps - n_bins + 1 : 0x7FFFFFFF;
     // dL/dobs in the observation layout, or one block per network shared by
     // its trajectories
-    const int64_t npts = p.obs_kind != 0 ? n_bins : 1;
+    const int64_t npts = (p.obs_kind != 0 && !tail) ? n_bins : 1;
     const bool dtm = p.obs_tm || p.dobs_shared;
     const int64_t drow = dtm ? (int64_t)NOBS : (int64_t)NOBS * B, dcol = dtm ? 1 : B;
-    const double *dobs_lane = p.d_obs + (p.dobs_shared ? nd.obsw_off * npts
-                                                      : nd.obsb_off * npts + (p.obs_tm ? i * npts * NOBS : i));
+    const double *dobs_lane = p.d_obs + (tail ? nd.obst_off + i
+                                         : p.dobs_shared ? nd.obsw_off * npts
+                                         : nd.obsb_off * npts + (p.obs_tm ? i * npts * NOBS : i));
+    // tail: dL/dobs over the tail length, per observed count and for the clock
+    float tdo[NO];
+    double tdt = 0.0;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) tdo[o] = 0.f;
     // prefix sums [obs][n_bins + 1] of the shared block (SH)
     const double *pre = SH ? p.dobs_prefix + nd.obsw_off * (int64_t)(n_bins + 1) : nullptr;
 
@@ -688,6 +766,20 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
         } else if (p.obs_kind == 0) {
 #pragma unroll
             for (int o = 0; o < NOBS; ++o) lam[NET::OBS[o]] += dobs_lane[o * dcol];
+        } else if (tail) {
+            // X_n, t_n and the held copies of them among the tail states
+            const double inv_m = 1.0 / (double)n_bins;
+            const int first = max(n, tail_lo);
+            const double wf = (double)(p.n_steps + 1 - first) * inv_m;
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                const double d = dobs_lane[o * B];
+                tdo[o] = (float)(d * inv_m);
+                if (wf > 0.0) lam[NET::OBS[o]] += d * wf;
+            }
+            const double dt_ = dobs_lane[NOBS * B];
+            tdt = dt_ * inv_m;
+            if (wf > 0.0) lam_t += dt_ * wf;
         }
     }
     // grid observation: the points at or after the last event see the final
@@ -926,6 +1018,12 @@ __device__ void backward_run(const RunParams &p, uint8_t (*s_tape)[kRecSteps][64
     #pragma unroll
                     for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += gx[o];
                     lam_t += glt;
+                }
+                // X_k and t_k as tail states
+                if (k >= tail_lo) {
+    #pragma unroll
+                    for (int o = 0; o < NOBS; ++o) dlam[NET::OBS[o]] += tdo[o];
+                    lam_t += tdt;
                 }
             t = t_k;
         };

@@ -168,11 +168,15 @@ class Net:
         return L
 
     def obs_total(self, obs_kind: int, n_bins: int) -> int:
+        if obs_kind == W.OBS_TAIL:
+            return sum((len(o) + 1) * b for o, b in zip(self.obs_species, self.n_traj))
         per = sum(len(o) * b for o, b in zip(self.obs_species, self.n_traj))
         return per * (n_bins if obs_kind in (W.OBS_BINS, W.OBS_GRID) else 1)
 
     def mean_total(self, obs_kind: int, n_bins: int) -> int:
         """Length of the ensemble-mean buffer (and of a shared d_obs)."""
+        if obs_kind == W.OBS_TAIL:
+            return sum(len(o) + 1 for o in self.obs_species)
         per = sum(len(o) for o in self.obs_species)
         return per * (n_bins if obs_kind in (W.OBS_BINS, W.OBS_GRID) else 1)
 
@@ -189,7 +193,8 @@ def make_cfg(cfg: W.RunConfig, tie_capacity: int = 0, bwd_mode: str = "auto",
     n_steps = int(min(cfg.n_steps, 2 ** 31 - 1))
     return _Cfg(int(cfg.seed) & (2 ** 64 - 1), int(cfg.purpose), int(cfg.epoch), _ptr(d_epoch),
                 _ptr(traj_ids), n_steps, float(cfg.t_end), int(cfg.obs_kind),
-                int(cfg.n_bins if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID) else 0), float(cfg.temperature),
+                int(cfg.n_bins if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID, W.OBS_TAIL) else 0),
+                float(cfg.temperature),
                 int(cfg.ckpt_every), _BWD[bwd_mode], int(tie_capacity), _ptr(d_temperature),
                 int(cfg.selection), int(cfg.obs_layout), int(bool(cfg.dobs_shared)))
 
@@ -339,14 +344,19 @@ def selftest_neglog(first: int, count: int) -> torch.Tensor:
 
 # ---------------------------------------------------------------------------
 class SimulateST(torch.autograd.Function):
-    """obs = simulate(theta) with the straight-through backward of libssa."""
+    """obs = simulate(theta) with the straight-through backward of libssa:
+    forward = ssa_forward (hard choices, checkpoints and choice tape kept),
+    backward = ssa_backward on the incoming dL/dobs (float64), returning
+    dL/dtheta (float32).  x0 is not differentiable."""
 
     @staticmethod
-    def forward(ctx, theta, net, cfg, x0, bwd_mode, tie_capacity):
+    def forward(ctx, theta, net, cfg, x0, bwd_mode, tie_capacity, record):
         fwd = forward(net, cfg, theta.detach().contiguous(), x0, keep_ckpt=True,
                       tie_capacity=tie_capacity, bwd_mode=bwd_mode)
         ctx.net, ctx.cfg, ctx.fwd = net, cfg, fwd
         ctx.save_for_backward(theta, x0)
+        if record is not None:
+            record["forward"] = fwd
         return fwd.obs
 
     @staticmethod
@@ -354,12 +364,15 @@ class SimulateST(torch.autograd.Function):
         theta, x0 = ctx.saved_tensors
         d = backward(ctx.net, ctx.cfg, theta.detach().contiguous(), x0, ctx.fwd,
                      d_obs.to(torch.float64).contiguous())
-        return d, None, None, None, None, None
+        return d, None, None, None, None, None, None
 
 
 def simulate(theta: torch.Tensor, net: Net, cfg: W.RunConfig, x0: torch.Tensor,
-             bwd_mode: str = "auto", tie_capacity: int = 0) -> torch.Tensor:
-    return SimulateST.apply(theta, net, cfg, x0, bwd_mode, tie_capacity)
+             bwd_mode: str = "auto", tie_capacity: int = 0, record: Optional[dict] = None) -> torch.Tensor:
+    """Differentiable simulation: the observation (float64, the layout of
+    ssa_forward's obs) as a function of theta.  record, if given, receives the
+    forward's buffers under "forward" (final state, clock, near-tie log)."""
+    return SimulateST.apply(theta, net, cfg, x0, bwd_mode, tie_capacity, record)
 
 
 # ---------------------------------------------------------------------------

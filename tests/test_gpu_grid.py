@@ -42,9 +42,10 @@ def _check(ssa, net, cfg, B, n_sample, bwd_mode="tape", seed=0):
     keep = edge_safe(gpu, r, ids)
     assert keep.mean() > 0.5
     rtol = grad_rtol(cfg.temperature)
-    for k in np.flatnonzero(keep):
-        assert_grad_parity(gpu["ppt"][ids[k]], r.grad[k], rtol=rtol)
-    assert_grad_parity(gpu["ppt"][ids][keep].sum(0), r.grad[keep].sum(0), rtol=rtol)
+    T = cfg.temperature
+    assert_grad_parity(gpu["ppt"][ids], r.grad, keep, rtol=rtol, kappa=r.kappa, T=T)
+    assert_grad_parity(gpu["ppt"][ids][keep].sum(0), r.grad[keep].sum(0), rtol=rtol,
+                       kappa=r.kappa[keep].sum(0), T=T)
     # the reduction is the FP64 sum of the per-trajectory gradients
     tot = gpu["ppt"].astype(np.float64).sum(0)
     mag = np.abs(gpu["ppt"].astype(np.float64)).sum(0)

@@ -69,8 +69,9 @@ def _parity(gpu, r, ids, cfg):
     assert_forward_parity(gpu, r, ids, cfg)
     keep = edge_safe(gpu, r, ids)
     assert keep.mean() > 0.5
-    for k in np.flatnonzero(keep):
-        assert_grad_parity(gpu["ppt"][ids[k]], r.grad[k], rtol=1e-5)
+    assert_grad_parity(gpu["ppt"][ids], r.grad, keep, kappa=r.kappa, T=cfg.temperature)
+    assert_grad_parity(gpu["ppt"][ids][keep].sum(0), r.grad[keep].sum(0), kappa=r.kappa[keep].sum(0),
+                       T=cfg.temperature)
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -92,8 +93,9 @@ def test_traj_major_parity(ssa, case, shared):
     if shared and cfg.obs_kind == W.OBS_BINS:
         # whole bins enter through prefix sums of the shared block: the same
         # terms in another order and in FP64
-        for q in range(B):
-            assert_grad_parity(gpu["ppt"][q], ref["ppt"][q], rtol=1e-5)
+        # (two GPU layouts, not oracle parity: within 1e-5 of each row's scale)
+        gd = np.abs(gpu["ppt"].astype(np.float64) - ref["ppt"])
+        assert np.all(gd <= 1e-5 * np.abs(ref["ppt"]).max(axis=1, keepdims=True))
         tot = ref["ppt"].astype(np.float64).sum(0)
         assert np.allclose(gpu["d_params"], ref["d_params"], rtol=1e-5,
                            atol=1e-6 * np.abs(ref["ppt"].astype(np.float64)).sum(0).max())
@@ -131,14 +133,13 @@ def test_shared_dobs_two_networks(ssa):
                               index)
         dn = np.broadcast_to(blocks[k][None], (len(ids),) + blocks[k].shape).copy()
         r = oracle.run(net, cfg.replace(obs_layout=0, dobs_shared=False), net.theta0, net.x0,
-                       traj_ids=L.traj_offset + ids, ties=ov, d_obs=dn)
+                       traj_ids=L.traj_offset + ids, ties=ov, d_obs=dn, kappa=True)
         assert r.n_bad.sum() == 0
         drift = float(np.max(np.abs(tf[L.traj_offset + ids] - r.t_final)))
         keep = r.bin_edge_dist > 50 * max(drift, 1e-12)
         assert keep.mean() > 0.5
         gk = ppt[L.ppt_offset: L.ppt_offset + net.n_params * B].reshape(net.n_params, B).T[ids]
-        for j in np.flatnonzero(keep):
-            assert_grad_parity(gk[j], r.grad[j], rtol=1e-5)
+        assert_grad_parity(gk, r.grad, keep, kappa=r.kappa, T=cfg.temperature)
 
 
 def test_layout_needs_the_specialised_mode(ssa):

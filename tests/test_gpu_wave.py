@@ -59,7 +59,8 @@ def check_batch(h, fwd, nets, B, cfg, d_obs=None, ppt=None):
         if d_obs is not None:
             blk = d_obs[L.obs_offset: L.obs_offset + (cfg.n_bins if bins else 1) * nob * b]
             dob = (blk.reshape(cfg.n_bins, nob, b).transpose(2, 0, 1) if bins else blk.reshape(nob, b).T)
-        r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=L.traj_offset + np.arange(b), ties=ov, d_obs=dob)
+        r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=L.traj_offset + np.arange(b), ties=ov, d_obs=dob,
+                       kappa=dob is not None)
         ob = obs[L.obs_offset: L.obs_offset + (cfg.n_bins if bins else 1) * nob * b]
         gpu = {"x_final": xf[L.state_offset: L.state_offset + net.n_species * b].reshape(net.n_species, b).T,
                "t_final": tf[L.traj_offset: L.traj_offset + b],
@@ -71,7 +72,7 @@ def check_batch(h, fwd, nets, B, cfg, d_obs=None, ppt=None):
             g = ppt[L.ppt_offset: L.ppt_offset + net.n_params * b].reshape(net.n_params, b).T
             keep = edge_safe(gpu, r, ids) if bins else np.ones(b, bool)
             assert keep.mean() > 0.7
-            assert_grad_parity(g, r.grad, keep, rtol=1e-5)
+            assert_grad_parity(g, r.grad, keep, kappa=r.kappa, T=cfg.temperature)
 
 
 def test_wave_small_batch_forward(ssa, wave_mode):
@@ -124,7 +125,8 @@ def check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt):
         ov = _ties_for_oracle([t for t in ties if L.traj_offset <= t["traj"] < L.traj_offset + b], L.traj_offset)
         blk = d_obs[L.obs_offset: L.obs_offset + c.n_bins * nob * b]
         dob = blk.reshape(c.n_bins, nob, b).transpose(2, 0, 1)
-        r = oracle.run(net, c, net.theta0, net.x0, traj_ids=L.traj_offset + np.arange(b), ties=ov, d_obs=dob)
+        r = oracle.run(net, c, net.theta0, net.x0, traj_ids=L.traj_offset + np.arange(b), ties=ov, d_obs=dob,
+                       kappa=True)
         ob = obs[L.obs_offset: L.obs_offset + c.n_bins * nob * b]
         gpu = {"x_final": xf[L.state_offset: L.state_offset + net.n_species * b].reshape(net.n_species, b).T,
                "t_final": tf[L.traj_offset: L.traj_offset + b],
@@ -135,7 +137,7 @@ def check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt):
         gg = ppt[L.ppt_offset: L.ppt_offset + net.n_params * b].reshape(net.n_params, b).T
         keep = edge_safe(gpu, r, ids)
         assert keep.mean() > 0.7
-        assert_grad_parity(gg, r.grad, keep, rtol=1e-5)
+        assert_grad_parity(gg, r.grad, keep, kappa=r.kappa, T=c.temperature)
 
 
 def test_wave_dimer_gradients(ssa, wave_mode):
@@ -148,7 +150,7 @@ def test_wave_dimer_gradients(ssa, wave_mode):
     gpu, r, ids, _ = run_pair(ssa, net, cfg, B, d_obs=d_obs, exec_mode="wave")
     assert_forward_parity(gpu, r, ids, cfg)
     keep = edge_safe(gpu, r, ids)
-    assert_grad_parity(gpu["ppt"], r.grad, keep)
+    assert_grad_parity(gpu["ppt"], r.grad, keep, kappa=r.kappa, T=cfg.temperature)
 
 
 def test_wave_backward_deterministic(ssa, wave_mode):
