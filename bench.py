@@ -1,16 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the batched exact SSA step, forward and forward+backward, on one MI355X.
 
-Default workload: reversible dimerisation 2A <-> A2 (kf = 1e-3, kb = 0.1, A(0) = 100),
-65,536 trajectories x 10,000 steps each, observation = exact bin averages of A
-over 20 bins on [0, 2500], loss = MSE of per-bin ensemble mean and variance
-against targets from a seeded run at kf = 2e-3, kb = 0.05, Gumbel-Softmax
-temperature 0.5, checkpoints every 256 steps, gradients with respect to ln k.
+Default workload: the activator-repressor oscillator (9 species, 16 mass-action
+channels, 15 seeded rates), 65,536 trajectories x 200,000 steps each (1.31e10
+fired reactions a pass), observation = exact bin averages of R over 256 bins,
+loss = MSE of the ensemble-mean normalised autocorrelation of R at lags 1-64
+against a run with a second seeded rate vector, Gumbel-Softmax temperature
+0.5, checkpoints every 1,024 steps, gradients with respect to ln k.  The
+reversible dimerisation 2A <-> A2 (65,536 x 10,000 steps, 20 bins, moment MSE)
+is reported beside it under other_workloads.
 
-Other workloads (--workload): the oscillator (9 species, 16 channels, 65,536
-trajectories x 200,000 steps), an uneven batch of 4,096 random networks in one
-launch, and the 784 -> 256 -> 10 gene-network classifier (512 images x 32
-trajectories x 2,000 steps, cross-entropy on the final output counts).
+Other workloads (--workload): the dimer alone, an uneven batch of 4,096 random
+networks in one launch, the 784 -> 256 -> 10 gene-network classifier (512
+images x 32 trajectories x 2,000 steps, cross-entropy on the final output
+counts), the two rate-inference trainers and the selection-variant study.
 
 One timed step = ssa_forward + loss (PyTorch FP64) + ssa_backward (+ the FP64
 gradient reduction).  `value` counts fired reactions per second of that step;
@@ -99,6 +102,96 @@ def measure_issue_costs():
     f32 = t[3]                      # fma
     return {"int": i32, "fp32": f32, "mad": t[0] - i32, "log": t[1] - f32, "rcp": t[2] - f32,
             "cvt": t[6] - i32, "f64": t[5]}
+
+
+def gpu_rounding_constant(T: float) -> float:
+    """Rounding constant of the GPU's gradient against the oracle's
+    conditioning kappa (the same as the parity tests use)."""
+    return 32.0 + 32.0 / T
+
+
+def grad_error_detail(g_gpu, r, t_gpu, cfg) -> dict:
+    """Per-trajectory gradient error of a sample against the oracle: the
+    distribution of ||g - g*|| / ||g*|| over the trajectories (with bins and
+    no edge log, those whose event times stay clear of every bin edge by 50
+    times the clock drift), and
+    the worst component against the parity bar
+    min(1e-5 ||g*||_inf, max(1e-5 |g*_i|, c(T) 2^-24 kappa_i))."""
+    drift = float(np.max(np.abs(t_gpu - r.t_final))) if len(t_gpu) else 0.0
+    keep = np.ones(len(t_gpu), bool)
+    if cfg.obs_kind != 0 and not getattr(r, "edge_window", 0.0) > 0.0:
+        keep = r.bin_edge_dist > 50.0 * max(drift, 1e-12)
+    g, ref, kap = g_gpu[keep], r.grad[keep], r.kappa[keep]
+    out = {"sampled": int(len(t_gpu)), "compared": int(keep.sum()), "clock_drift": drift}
+    if not keep.any():
+        return out
+    nrm = np.linalg.norm(ref, axis=1)
+    ok = nrm > 0
+    rel = np.linalg.norm(g - ref, axis=1)[ok] / nrm[ok]
+    err = np.abs(g - ref)
+    scale = np.abs(ref).max(axis=1, keepdims=True)
+    bar = np.minimum(1e-5 * scale, np.maximum(1e-5 * np.abs(ref),
+                                              gpu_rounding_constant(cfg.temperature) * 2.0 ** -24 * kap))
+    out.update({"rel_err_median": float(np.median(rel)) if rel.size else 0.0,
+                "rel_err_p90": float(np.percentile(rel, 90)) if rel.size else 0.0,
+                "rel_err_max": float(rel.max()) if rel.size else 0.0,
+                "worst_component_over_bar": float((err / np.where(bar > 0, bar, np.inf)).max()),
+                "worst_err_over_u_kappa": float((err / np.where(kap > 0, 2.0 ** -24 * kap, np.inf)).max())})
+    return out
+
+
+def host_info() -> dict:
+    """The host's CPUs: its count, this process's affinity, the thread share
+    (OMP_NUM_THREADS) and the lscpu model name."""
+    import subprocess
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    model = ""
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"os_cpu_count": os.cpu_count(), "affinity_cpus": aff,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "model": model}
+
+
+def cpu_threads() -> int:
+    """Threads the oracle leg may use: every CPU this process may run on,
+    within the host's thread share (OMP_NUM_THREADS) when one is set."""
+    info = host_info()
+    n = info["affinity_cpus"]
+    if info["omp_num_threads"]:
+        try:
+            n = min(n, int(info["omp_num_threads"]))
+        except ValueError:
+            pass
+    return max(1, n)
+
+
+def cpu_baseline(run, n_total: int, n_try: int, seconds: float, what: str) -> dict:
+    """The oracle timed on the host: run(ids, threads) simulates the
+    trajectories `ids` and returns their fired steps.  A short calibration
+    sizes a sample of about `seconds` of work on all threads; a sample of n_try
+    trajectories is also timed on one thread."""
+    threads = cpu_threads()
+    n_cal = min(n_total, max(n_try, 2 * threads))
+    c0 = time.perf_counter()
+    run(np.arange(n_cal), threads)
+    dt = time.perf_counter() - c0
+    n_cpu = int(min(n_total, max(n_cal, n_cal * seconds / max(dt, 1e-3))))
+    c0 = time.perf_counter()
+    steps = float(run(np.arange(n_cpu), threads))
+    dt = time.perf_counter() - c0
+    c1 = time.perf_counter()
+    steps1 = float(run(np.arange(n_try), 1))
+    dt1 = time.perf_counter() - c1
+    return {"value": steps / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_cpu} {what}", "seconds": dt,
+            "value_1core": steps1 / dt1, "sample_1core": f"{n_try} {what}",
+            "host": host_info()}
 
 
 # Library sources each workload's kernels are built from.
@@ -329,22 +422,13 @@ def bench_grn(args, torch, dev):
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        n_try = 32
-        c0 = time.perf_counter()
-        ids = np.arange(n_try)
-        oracle.grn_run(net, cfg, wl.theta, u_gpu, ids // wl.n_rep, traj_ids=ids,
-                       d_obs=np.zeros((n_try, net.n_out)), n_threads=threads)
-        dt = time.perf_counter() - c0
-        n_cpu = int(min(wl.n_traj, max(n_try, n_try * args.cpu_seconds / max(dt, 1e-3))))
-        ids = np.arange(n_cpu)
-        c0 = time.perf_counter()
-        rc = oracle.grn_run(net, cfg, wl.theta, u_gpu, ids // wl.n_rep, traj_ids=ids,
-                            d_obs=np.zeros((n_cpu, net.n_out)), n_threads=threads)
-        dt = time.perf_counter() - c0
-        cpu = {"value": float(rc.steps_done.sum() / dt), "unit": "steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"{n_cpu} of the {wl.n_traj} trajectories, full {cfg.n_steps} steps, "
-                         "forward+adjoint in FP64 on the GPU's hidden pre-activations"}
+        cpu = cpu_baseline(
+            lambda ids, threads: oracle.grn_run(net, cfg, wl.theta, u_gpu, ids // wl.n_rep, traj_ids=ids,
+                                                d_obs=np.zeros((len(ids), net.n_out)),
+                                                n_threads=threads).steps_done.sum(),
+            wl.n_traj, 32, args.cpu_seconds,
+            f"of the {wl.n_traj} trajectories, full {cfg.n_steps} steps, "
+            "forward+adjoint in FP64 on the GPU's hidden pre-activations")
 
     out = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
@@ -469,14 +553,10 @@ def bench_infer(args, torch, dev):
                      "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS})
     cpu = None
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        n_cpu = 2048
-        c0 = time.perf_counter()
-        rc = oracle.run(tr.net, cfg, th, tr.net.x0, traj_ids=np.arange(n_cpu),
-                        d_obs=np.zeros((n_cpu, G, O)), n_threads=threads)
-        dt = time.perf_counter() - c0
-        cpu = {"value": float(rc.steps_done.sum()) / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"{n_cpu} of the {B} trajectories, {n_steps} steps, forward+adjoint in FP64"}
+        cpu = cpu_baseline(
+            lambda ids, threads: oracle.run(tr.net, cfg, th, tr.net.x0, traj_ids=ids,
+                                            d_obs=np.zeros((len(ids), G, O)), n_threads=threads).steps_done.sum(),
+            B, 2048, args.cpu_seconds, f"of the {B} trajectories, {n_steps} steps, forward+adjoint in FP64")
     sweep = None
     if args.sweep and not coi:
         sweep = []
@@ -564,15 +644,246 @@ def bench_selection(args, torch, dev):
     print(json.dumps(out))
 
 
+def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> dict:
+    """One timed step = ssa_forward + loss (PyTorch FP64) + ssa_backward for the
+    dimer, oscillator or uneven-batch workload; returns the JSON record.
+    light: no autotuning, graph replay or CPU baseline (a secondary line)."""
+    from paper_2602_19775_amd import losses, ssa
+    from paper_2602_19775_amd import workloads as W
+
+    if workload in ("dimer", "oscillator"):
+        if workload == "dimer":
+            wl = W.dimer_fwdbwd_64k(args.n_traj, args.n_steps or 10000)
+        else:
+            wl = W.oscillator_fwdbwd_64k(args.n_traj, args.n_steps or 200000)
+        cfg = wl.cfg.replace(ckpt_every=args.ckpt_every or wl.cfg.ckpt_every)
+        nets, Bs, name = [wl.net], [wl.n_traj], wl.name
+        h = ssa.Net(nets, Bs, t_obs=[cfg.t_obs])
+        theta = torch.tensor(wl.net.theta0, device=dev)
+        x0 = torch.tensor(wl.x0_soa().reshape(-1), device=dev)
+        if workload == "dimer":
+            theta_t = torch.tensor(np.log(np.array(W.DIMER_TARGET_RATES)).astype(np.float32), device=dev)
+        else:
+            theta_t = torch.tensor(wl.extra["target_net"].theta0, device=dev)
+    else:
+        bw = W.uneven_batch(n_steps=args.n_steps or 5000)
+        cfg = bw.cfg.replace(ckpt_every=args.ckpt_every or bw.cfg.ckpt_every)
+        nets, Bs, name = bw.nets, bw.n_traj, bw.name
+        h = ssa.Net(nets, Bs)
+        theta = torch.tensor(bw.theta(), device=dev)
+        x0 = torch.tensor(bw.x0_packed(), device=dev)
+        theta_t = torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device=dev)
+    plan = None
+    bwd_mode = args.bwd_mode
+    if args.autotune and not light:
+        from paper_2602_19775_amd import autotune
+        t_obs_l = [cfg.t_obs] * len(nets) if cfg.obs_kind == W.OBS_BINS else None
+        plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l)
+        h = plan.net(nets, Bs, t_obs_l)
+        cfg = plan.config(cfg)
+        bwd_mode = plan.bwd_mode
+    net, B = nets[0], Bs[0]
+    nb, nob = cfg.n_bins, len(net.obs_species)
+
+    # targets: a seeded run at the target rates (separate stream purpose), untimed
+    tcfg = cfg.replace(purpose=W.PURPOSE_TARGET)
+    tf = ssa.forward(h, tcfg, theta_t, x0, keep_ckpt=False, tie_capacity=0)
+    if workload == "dimer":
+        tm, tv = losses.bin_moments(tf.obs, nb, nob, B)
+        tm, tv = tm.clone(), tv.clone()
+
+        def loss_fn(obs):
+            return losses.moment_mse(obs, tm, tv, nb, nob, B)
+    elif workload == "oscillator":
+        tac = losses.mean_autocorrelation(tf.obs, nb, B, 64).clone()
+
+        def loss_fn(obs):
+            return losses.autocorrelation_mse(obs, tac, nb, B, 64)
+    else:
+        # final counts, [sum n_obs][256]: ensemble mean of every observed species
+        rows = sum(len(n.obs_species) for n in nets)
+        tmean = tf.obs[: rows * B].view(rows, B).mean(dim=1).clone()
+
+        def loss_fn(obs):
+            return ((obs[: rows * B].view(rows, B).mean(dim=1) - tmean) ** 2).mean()
+    del tf
+
+    tie_cap = {"dimer": 1 << 16, "oscillator": 1 << 22, "uneven": 1 << 23}[workload]
+    bufs = ssa.forward(h, cfg, theta, x0, tie_capacity=tie_cap, bwd_mode=bwd_mode)
+    d_params = torch.empty(h.param_total, dtype=torch.float32, device=dev)
+
+    def step(record=None):
+        if record is not None:
+            record[0].record()
+        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=tie_cap, bwd_mode=bwd_mode)
+        if record is not None:
+            record[1].record()
+        obs = bufs.obs.detach().requires_grad_(True)
+        loss = loss_fn(obs)
+        (d_obs,) = torch.autograd.grad(loss, obs)
+        if record is not None:
+            record[2].record()
+        ssa.backward(h, cfg, theta, x0, bufs, d_obs, d_params=d_params)
+        if record is not None:
+            record[3].record()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        loss = step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fired = int(bufs.steps_done.sum().item())
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    loss_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    step_stats = spread([e[0].elapsed_time(e[3]) for e in evs])
+    value = fired / (ms_step * 1e-3)
+
+    # forward-only rate of the plain forward (no checkpoints, no choice tape)
+    pbufs = ssa.forward(h, cfg, theta, x0, keep_ckpt=False, tie_capacity=tie_cap, bwd_mode=bwd_mode)
+    for _ in range(args.warmup):
+        ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=bwd_mode)
+    torch.cuda.synchronize()
+    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    f0 = time.perf_counter()
+    for k in range(args.steps):
+        fevs[k][0].record()
+        ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=bwd_mode)
+        fevs[k][1].record()
+    torch.cuda.synchronize()
+    f1 = time.perf_counter()
+    fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
+    fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
+    del pbufs
+    n_ties = int(bufs.n_ties.item())
+    assert ssa.device_status(h) == 0
+    kinds = bufs.tie_records()["kind"]
+    n_edge = int((kinds == 2).sum())
+
+    # the same step captured into one HIP graph (the epoch advances on the
+    # device, so every replay draws a fresh stream), replayed
+    graph = None
+    if not args.no_graph and not light:
+        from paper_2602_19775_amd.graph import CapturedStep
+        ep = torch.zeros(1, dtype=torch.int32, device=dev)
+        gbufs = ssa.forward(h, cfg, theta, x0, tie_capacity=0, bwd_mode=bwd_mode, d_epoch=ep)
+        gdp = torch.empty_like(d_params)
+
+        def gstep():
+            ssa.forward(h, cfg, theta, x0, buffers=gbufs, tie_capacity=0, bwd_mode=bwd_mode, d_epoch=ep)
+            gobs = gbufs.obs.detach().requires_grad_(True)
+            (gd,) = torch.autograd.grad(loss_fn(gobs), gobs)
+            ssa.backward(h, cfg, theta, x0, gbufs, gd, d_params=gdp)
+            ep.add_(1)
+        cap = CapturedStep(gstep, warmup=args.warmup)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for _ in range(args.steps):
+            cap.replay()
+        torch.cuda.synchronize()
+        g1 = time.perf_counter()
+        gfired = int(gbufs.steps_done.sum().item())
+        graph = {"steps_per_s": gfired * args.steps / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / args.steps}
+        del cap, gbufs
+
+    # gradient error against the oracle on a sample of trajectories (of the
+    # first network of the batch): per-trajectory and summed, with the
+    # oracle's conditioning of every component
+    import oracle
+    obs = bufs.obs.detach().requires_grad_(True)
+    loss = loss_fn(obs)
+    (d_obs,) = torch.autograd.grad(loss, obs)
+    _, ppt = ssa.backward(h, cfg, theta, x0, bufs, d_obs, per_traj=True)
+    n_sample = {"dimer": 64, "oscillator": 64, "uneven": 64}[workload]
+    sample = np.arange(0, B, max(1, B // n_sample))[:n_sample]
+    bins = cfg.obs_kind == W.OBS_BINS
+    dnp = d_obs.cpu().numpy()
+    dob = (dnp[: nb * nob * B].reshape(nb, nob, B).transpose(2, 0, 1)[sample] if bins
+           else dnp[: nob * B].reshape(nob, B).T[sample])
+    ties = bufs.tie_records()
+    idx = {int(q): k for k, q in enumerate(sample)}
+    ov = [(idx[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
+          for t in ties if int(t["traj"]) in idx]
+    # bins in the specialised mode: the forward logs the side of every bin edge an
+    # event time falls close to, and the oracle takes it (EDGE_WINDOW of the tests)
+    ew = 4e-7 if (bins and workload in ("dimer", "oscillator")) else 0.0
+    r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=sample, ties=ov, d_obs=dob, kappa=True, edge_window=ew)
+    r.edge_window = ew
+    g_gpu = ppt.cpu().numpy()[: net.n_params * B].reshape(net.n_params, B).T[sample].astype(np.float64)
+    xf = bufs.x_final.cpu().numpy()[: net.n_species * B].reshape(net.n_species, B).T[sample]
+    counts_exact = bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
+    grad_rel_err = float(np.linalg.norm(g_gpu.sum(0) - r.grad.sum(0)) / np.linalg.norm(r.grad.sum(0)))
+    grad_detail = grad_error_detail(g_gpu, r, bufs.t_final.cpu().numpy()[sample], cfg)
+
+    # roofline of the dominant kernel (ALU-bound): algorithmic operations of a
+    # launch weighted by their measured issue cost, over the kernel's time,
+    # against the full-rate issue limit of the vector ALUs
+    inv2 = abs(1.0 / cfg.temperature - 2.0) < 1e-12
+    cost = measure_issue_costs()
+    wsum = float(sum(Bs))
+
+    def avg_ops(backward):
+        tot = {}
+        for n_, b_ in zip(nets, Bs):
+            o = alu_ops_per_step(n_, backward, inv2)
+            for k_, v_ in o.items():
+                tot[k_] = tot.get(k_, 0.0) + v_ * b_ / wsum
+        return tot
+    ops_b, ops_f = avg_ops(True), avg_ops(False)
+    if bwd_ms >= fwd_ms:
+        dom, dom_ms, ops = "backward", bwd_ms, ops_b
+    else:
+        dom, dom_ms, ops = "forward", fwd_ms, ops_f
+    per_step = slots(ops, cost)
+    achieved = fired * per_step / (dom_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
+                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": profiled_traffic(workload, dom),
+                "slots_per_step": per_step, "ops_per_step": ops, "issue_cost_slots": cost,
+                "kernel_ms": dom_ms,
+                "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
+
+    cpu = None
+    if not args.no_cpu_baseline and not light:
+        zero = (lambda n: np.zeros((n, nb, nob))) if bins else (lambda n: np.zeros((n, nob)))
+        cpu = cpu_baseline(
+            lambda ids, threads: oracle.run(net, cfg, net.theta0, net.x0, traj_ids=ids, d_obs=zero(len(ids)),
+                                            n_threads=threads).steps_done.sum(),
+            B, {"dimer": 32, "oscillator": 4, "uneven": 16}[workload], args.cpu_seconds,
+            f"of the {B} trajectories, full {cfg.n_steps} steps, forward+adjoint in FP64")
+
+    return {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "n_traj": int(sum(Bs)), "n_networks": len(nets), "steps_per_traj": cfg.n_steps, "n_bins": nb,
+                   "t_obs": cfg.t_obs, "temperature": cfg.temperature, "ckpt_every": cfg.ckpt_every,
+                   "bwd_mode": bwd_mode,
+                   "plan": None if plan is None else {"exec_mode": plan.exec_mode, "wave_split": plan.wave_split}},
+        "forward_steps_per_s": fwd_rate, "graph_replay": graph, "fwdbwd_over_forward": value / fwd_rate,
+        "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
+        "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
+        "grad_rel_err": grad_rel_err, "grad_error": grad_detail, "counts_bit_exact_sample": counts_exact,
+        "near_ties": n_ties - n_edge, "bin_edge_events": n_edge, "loss": float(loss.item()),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dimer",
+    ap.add_argument("--workload", default="oscillator",
                     choices=["dimer", "oscillator", "uneven", "grn", "abc_infer", "coi_infer", "selection"],
-                    help="dimer: 2A<->A2, 65,536 x 10,000 steps (default); "
-                         "oscillator: 9 species / 16 channels, 65,536 x 200,000 steps; "
+                    help="oscillator: 9 species / 16 channels, 65,536 x 200,000 steps (default); "
+                         "dimer: 2A<->A2, 65,536 x 10,000 steps; "
                          "uneven: 4,096 random networks x 256 trajectories x 5,000 steps; "
                          "grn: 784->256->10 gene-network classifier, 512 images x 32 trajectories x 2,000 steps; "
                          "abc_infer: rate inference for A+B<->C, 100,000 x 250 steps, 250 captured epochs; "
@@ -589,7 +900,9 @@ def main():
                     help="pick the execution plan with the autotuner (untimed; cached under ~/.cache)")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="oscillator: skip the secondary dimer line (other_workloads)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -624,225 +937,11 @@ def main():
         print(json.dumps({"copy_bytes": n * 4, "launches": 3}))
         return
 
-    if args.workload in ("dimer", "oscillator"):
-        if args.workload == "dimer":
-            wl = W.dimer_fwdbwd_64k(args.n_traj, args.n_steps or 10000)
-        else:
-            wl = W.oscillator_fwdbwd_64k(args.n_traj, args.n_steps or 200000)
-        cfg = wl.cfg.replace(ckpt_every=args.ckpt_every or wl.cfg.ckpt_every)
-        nets, Bs, name = [wl.net], [wl.n_traj], wl.name
-        h = ssa.Net(nets, Bs, t_obs=[cfg.t_obs])
-        theta = torch.tensor(wl.net.theta0, device=dev)
-        x0 = torch.tensor(wl.x0_soa().reshape(-1), device=dev)
-        if args.workload == "dimer":
-            theta_t = torch.tensor(np.log(np.array(W.DIMER_TARGET_RATES)).astype(np.float32), device=dev)
-        else:
-            theta_t = torch.tensor(wl.extra["target_net"].theta0, device=dev)
-    else:
-        bw = W.uneven_batch(n_steps=args.n_steps or 5000)
-        cfg = bw.cfg.replace(ckpt_every=args.ckpt_every or bw.cfg.ckpt_every)
-        nets, Bs, name = bw.nets, bw.n_traj, bw.name
-        h = ssa.Net(nets, Bs)
-        theta = torch.tensor(bw.theta(), device=dev)
-        x0 = torch.tensor(bw.x0_packed(), device=dev)
-        theta_t = torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device=dev)
-    plan = None
-    if args.autotune:
-        from paper_2602_19775_amd import autotune
-        t_obs_l = [cfg.t_obs] * len(nets) if cfg.obs_kind == W.OBS_BINS else None
-        plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l)
-        h = plan.net(nets, Bs, t_obs_l)
-        cfg = plan.config(cfg)
-        args.bwd_mode = plan.bwd_mode
-    net, B = nets[0], Bs[0]
-    nb, nob = cfg.n_bins, len(net.obs_species)
 
-    # targets: a seeded run at the target rates (separate stream purpose), untimed
-    tcfg = cfg.replace(purpose=W.PURPOSE_TARGET)
-    tf = ssa.forward(h, tcfg, theta_t, x0, keep_ckpt=False, tie_capacity=0)
-    if args.workload == "dimer":
-        tm, tv = losses.bin_moments(tf.obs, nb, nob, B)
-        tm, tv = tm.clone(), tv.clone()
-
-        def loss_fn(obs):
-            return losses.moment_mse(obs, tm, tv, nb, nob, B)
-    elif args.workload == "oscillator":
-        tac = losses.mean_autocorrelation(tf.obs, nb, B, 64).clone()
-
-        def loss_fn(obs):
-            return losses.autocorrelation_mse(obs, tac, nb, B, 64)
-    else:
-        # final counts, [sum n_obs][256]: ensemble mean of every observed species
-        rows = sum(len(n.obs_species) for n in nets)
-        tmean = tf.obs[: rows * B].view(rows, B).mean(dim=1).clone()
-
-        def loss_fn(obs):
-            return ((obs[: rows * B].view(rows, B).mean(dim=1) - tmean) ** 2).mean()
-    del tf
-
-    tie_cap = {"dimer": 1 << 16, "oscillator": 1 << 22, "uneven": 1 << 23}[args.workload]
-    bufs = ssa.forward(h, cfg, theta, x0, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
-    d_params = torch.empty(h.param_total, dtype=torch.float32, device=dev)
-
-    def step(record=None):
-        if record is not None:
-            record[0].record()
-        ssa.forward(h, cfg, theta, x0, buffers=bufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
-        if record is not None:
-            record[1].record()
-        obs = bufs.obs.detach().requires_grad_(True)
-        loss = loss_fn(obs)
-        (d_obs,) = torch.autograd.grad(loss, obs)
-        if record is not None:
-            record[2].record()
-        ssa.backward(h, cfg, theta, x0, bufs, d_obs, d_params=d_params)
-        if record is not None:
-            record[3].record()
-        return loss
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        loss = step(evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fired = int(bufs.steps_done.sum().item())
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    loss_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
-    step_stats = spread([e[0].elapsed_time(e[3]) for e in evs])
-    value = fired / (ms_step * 1e-3)
-
-    # forward-only rate of the plain forward (no checkpoints, no choice tape)
-    pbufs = ssa.forward(h, cfg, theta, x0, keep_ckpt=False, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
-    for _ in range(args.warmup):
-        ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
-    torch.cuda.synchronize()
-    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
-    f0 = time.perf_counter()
-    for k in range(args.steps):
-        fevs[k][0].record()
-        ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=args.bwd_mode)
-        fevs[k][1].record()
-    torch.cuda.synchronize()
-    f1 = time.perf_counter()
-    fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
-    fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
-    del pbufs
-    n_ties = int(bufs.n_ties.item())
-    assert ssa.device_status(h) == 0
-
-    # the same step captured into one HIP graph (the epoch advances on the
-    # device, so every replay draws a fresh stream), replayed
-    graph = None
-    if not args.no_graph:
-        from paper_2602_19775_amd.graph import CapturedStep
-        ep = torch.zeros(1, dtype=torch.int32, device=dev)
-        gbufs = ssa.forward(h, cfg, theta, x0, tie_capacity=0, bwd_mode=args.bwd_mode, d_epoch=ep)
-        gdp = torch.empty_like(d_params)
-
-        def gstep():
-            ssa.forward(h, cfg, theta, x0, buffers=gbufs, tie_capacity=0, bwd_mode=args.bwd_mode, d_epoch=ep)
-            gobs = gbufs.obs.detach().requires_grad_(True)
-            (gd,) = torch.autograd.grad(loss_fn(gobs), gobs)
-            ssa.backward(h, cfg, theta, x0, gbufs, gd, d_params=gdp)
-            ep.add_(1)
-        cap = CapturedStep(gstep, warmup=args.warmup)
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        for _ in range(args.steps):
-            cap.replay()
-        torch.cuda.synchronize()
-        g1 = time.perf_counter()
-        gfired = int(gbufs.steps_done.sum().item())
-        graph = {"steps_per_s": gfired * args.steps / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / args.steps}
-        del cap, gbufs
-
-    # gradient relative error against the oracle on a sample of trajectories
-    # (of the first network of the batch)
-    import oracle
-    obs = bufs.obs.detach().requires_grad_(True)
-    loss = loss_fn(obs)
-    (d_obs,) = torch.autograd.grad(loss, obs)
-    _, ppt = ssa.backward(h, cfg, theta, x0, bufs, d_obs, per_traj=True)
-    n_sample = {"dimer": 64, "oscillator": 16, "uneven": 64}[args.workload]
-    sample = np.arange(0, B, max(1, B // n_sample))[:n_sample]
-    bins = cfg.obs_kind == W.OBS_BINS
-    dnp = d_obs.cpu().numpy()
-    dob = (dnp[: nb * nob * B].reshape(nb, nob, B).transpose(2, 0, 1)[sample] if bins
-           else dnp[: nob * B].reshape(nob, B).T[sample])
-    ties = bufs.tie_records()
-    idx = {int(q): k for k, q in enumerate(sample)}
-    ov = [(idx[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
-          for t in ties if int(t["traj"]) in idx]
-    r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=sample, ties=ov, d_obs=dob)
-    g_gpu = ppt.cpu().numpy()[: net.n_params * B].reshape(net.n_params, B).T[sample].astype(np.float64)
-    xf = bufs.x_final.cpu().numpy()[: net.n_species * B].reshape(net.n_species, B).T[sample]
-    counts_exact = bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
-    grad_rel_err = float(np.linalg.norm(g_gpu.sum(0) - r.grad.sum(0)) / np.linalg.norm(r.grad.sum(0)))
-
-    # roofline of the dominant kernel (ALU-bound): algorithmic operations of a
-    # launch weighted by their measured issue cost, over the kernel's time,
-    # against the full-rate issue limit of the vector ALUs
-    inv2 = abs(1.0 / cfg.temperature - 2.0) < 1e-12
-    cost = measure_issue_costs()
-    wsum = float(sum(Bs))
-
-    def avg_ops(backward):
-        tot = {}
-        for n_, b_ in zip(nets, Bs):
-            o = alu_ops_per_step(n_, backward, inv2)
-            for k_, v_ in o.items():
-                tot[k_] = tot.get(k_, 0.0) + v_ * b_ / wsum
-        return tot
-    ops_b, ops_f = avg_ops(True), avg_ops(False)
-    if bwd_ms >= fwd_ms:
-        dom, dom_ms, ops = "backward", bwd_ms, ops_b
-    else:
-        dom, dom_ms, ops = "forward", fwd_ms, ops_f
-    per_step = slots(ops, cost)
-    achieved = fired * per_step / (dom_ms * 1e-3)
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": profiled_traffic(args.workload, dom),
-                "slots_per_step": per_step, "ops_per_step": ops, "issue_cost_slots": cost,
-                "kernel_ms": dom_ms,
-                "fwd_frac": fired * slots(ops_f, cost) / (fwd_ms * 1e-3) / PEAK_LANE_SLOTS}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        n_try = {"dimer": 32, "oscillator": 4, "uneven": 16}[args.workload]
-        c0 = time.perf_counter()
-        oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n_try), d_obs=np.zeros((n_try, nb, nob) if bins else (n_try, nob)),
-                   n_threads=threads)
-        dt = time.perf_counter() - c0
-        n_cpu = int(min(B, max(n_try, n_try * args.cpu_seconds / max(dt, 1e-3))))
-        c0 = time.perf_counter()
-        rc = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(n_cpu),
-                        d_obs=np.zeros((n_cpu, nb, nob) if bins else (n_cpu, nob)), n_threads=threads)
-        dt = time.perf_counter() - c0
-        cpu = {"value": float(rc.steps_done.sum() / dt), "unit": "steps/s", "cores": threads, "kind": "oracle",
-               "sample": f"{n_cpu} of the {B} trajectories, full {cfg.n_steps} steps, forward+adjoint in FP64"}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": name, "n_traj": int(sum(Bs)), "n_networks": len(nets), "steps_per_traj": cfg.n_steps, "n_bins": nb,
-                   "t_obs": cfg.t_obs, "temperature": cfg.temperature, "ckpt_every": cfg.ckpt_every,
-                   "bwd_mode": args.bwd_mode,
-                   "plan": None if plan is None else {"exec_mode": plan.exec_mode, "wave_split": plan.wave_split}},
-        "forward_steps_per_s": fwd_rate, "graph_replay": graph, "fwdbwd_over_forward": value / fwd_rate,
-        "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
-        "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
-        "grad_rel_err": grad_rel_err, "counts_bit_exact_sample": counts_exact, "near_ties": n_ties,
-        "loss": float(loss.item()), "roofline": roofline, "cpu_baseline": cpu,
-    }
+    out = bench_mass_action(args, torch, dev, args.workload)
+    if args.workload == "oscillator" and not args.no_extra:
+        # the dimer workload as a secondary line: same contract, no CPU leg
+        out["other_workloads"] = {"dimer": bench_mass_action(args, torch, dev, "dimer", light=True)}
     print(json.dumps(out))
 
 
