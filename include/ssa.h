@@ -290,6 +290,24 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
                         const double *d_obs, float *d_params, float *d_params_per_traj,
                         void *work, size_t work_bytes, hipStream_t stream);
 
+/* ssa_backward without a work buffer, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and kernels as ssa_backward,
+ * minus work / work_bytes: the scratch lives in a file-scope device array of
+ * the library, 32 MiB, one copy per GPU (resolved by ssa_net_create on the
+ * handle's device and held until the process ends).  A configuration whose
+ * work_bytes (ssa_buffer_sizes) exceed 32 MiB returns SSA_EWORKSPACE before
+ * anything is enqueued.  Nothing is allocated or freed.  All calls on one GPU
+ * share the array, and each call overwrites it: calls that overlap on one GPU
+ * (concurrent streams, or host threads without ordering) race and must be
+ * serialised by the caller.  The backward writes every value it reads back
+ * from the scratch, so no clearing between calls is needed. */
+ssa_status ssa_backward_static(const ssa_net *net, const ssa_config *cfg, const float *theta,
+                               const int32_t *x0, const int32_t *x_final, const double *t_final,
+                               const int32_t *steps_done, const void *ckpt, size_t ckpt_bytes,
+                               const double *d_obs, float *d_params, float *d_params_per_traj,
+                               hipStream_t stream);
+
 /* One direct-method step (step index `step`) for every trajectory, for
  * step-wise inspection.  x (state layout) and t [sum B_n] are updated in
  * place for trajectories that fire.  chosen [sum B_n]: fired channel, -1 if

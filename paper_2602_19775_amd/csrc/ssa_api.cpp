@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -93,7 +94,40 @@ struct ssa_net {
     int max_M = 0;
     int64_t max_B = 0;
     int device = 0;
+    void *scratch = nullptr;     // this device's copy of the static scratch array
 };
+
+// Scratch of ssa_backward_static: a file-scope device array, one copy per
+// GPU, in place of the caller's work buffer.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address): ssa_net_create resolves the address of the current device's copy
+// once per device and every handle keeps it.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_of_device;
+
+// Device address of `scratch` on `device`, which must be the current device.
+hipError_t static_scratch(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_of_device.find(device);
+    if (it != g_scratch_of_device.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_of_device[device] = ptr;
+    *out = ptr;
+    return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -632,6 +666,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     for (auto &kv : wave_items) std::stable_sort(kv.second.begin(), kv.second.end(), by_cost);
 
     hipError_t e = hipGetDevice(&net->device);
+    if (e == hipSuccess) e = static_scratch(net->device, &net->scratch);
     if (e == hipSuccess) e = upload(&net->nets_d, net->nets_h);
     if (e == hipSuccess) e = upload(&net->rd_d, rd);
     if (e == hipSuccess) e = upload(&net->rows_d, rows);
@@ -864,6 +899,24 @@ ssa_status ssa_backward(const ssa_net *net, const ssa_config *cfg, const float *
     g_last_error.clear();
     return backward_impl(net, cfg, theta, x0, x_final, t_final, steps_done, ckpt, ckpt_bytes, d_obs, d_params,
                          d_params_per_traj, work, work_bytes, stream);
+}
+
+ssa_status ssa_backward_static(const ssa_net *net, const ssa_config *cfg, const float *theta, const int32_t *x0,
+                               const int32_t *x_final, const double *t_final, const int32_t *steps_done,
+                               const void *ckpt, size_t ckpt_bytes, const double *d_obs, float *d_params,
+                               float *d_params_per_traj, hipStream_t stream)
+{
+    g_last_error.clear();
+    ssa_status s = check_config(net, cfg);
+    if (s != SSA_OK) return s;
+    if (!net->scratch) return fail(SSA_EHIP, "the static scratch of this device was not resolved");
+    const size_t need = work_bytes_for(net, cfg);
+    if (need > kStaticScratchBytes)
+        return fail(SSA_EWORKSPACE, "this backward needs " + std::to_string(need) +
+                                        " bytes of scratch; the static array holds " +
+                                        std::to_string(kStaticScratchBytes));
+    return backward_impl(net, cfg, theta, x0, x_final, t_final, steps_done, ckpt, ckpt_bytes, d_obs, d_params,
+                         d_params_per_traj, net->scratch, kStaticScratchBytes, stream);
 }
 
 ssa_status ssa_obs_mean(const ssa_net *net, const ssa_config *cfg, const double *obs, double *mean,

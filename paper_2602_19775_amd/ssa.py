@@ -65,7 +65,7 @@ EXPORTS = ["ssa_config_default", "ssa_net_create", "ssa_net_destroy", "ssa_net_s
            "ssa_buffer_sizes", "ssa_forward", "ssa_backward", "ssa_step_batch", "ssa_device_status",
            "ssa_status_string", "ssa_last_error", "ssa_selftest_philox", "ssa_selftest_neglog",
            "ssa_grn_create", "ssa_grn_destroy", "ssa_grn_buffer_sizes", "ssa_grn_forward",
-           "ssa_grn_backward", "ssa_grn_device_status", "ssa_obs_mean"]
+           "ssa_grn_backward", "ssa_grn_device_status", "ssa_obs_mean", "ssa_backward_static"]
 
 
 def lib():
@@ -86,6 +86,7 @@ def lib():
                                   C.c_size_t, V]
         L.ssa_backward.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, C.c_size_t, V, V, V, V,
                                    C.c_size_t, V]
+        L.ssa_backward_static.argtypes = [V, C.POINTER(_Cfg), V, V, V, V, V, V, C.c_size_t, V, V, V, V]
         L.ssa_step_batch.argtypes = [V, C.POINTER(_Cfg), V, V, V, C.c_uint32, V, V, V, V]
         L.ssa_obs_mean.argtypes = [V, C.POINTER(_Cfg), V, V, V, C.c_size_t, V]
         L.ssa_device_status.argtypes = [V, V, C.POINTER(C.c_uint32)]
@@ -287,6 +288,21 @@ def backward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, 
                             fwd.work.numel(), _stream(stream))
     _check(rc, "ssa_backward")
     return (d_params, ppt) if per_traj else d_params
+
+
+def backward_static(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, fwd: Forward,
+                    d_obs: torch.Tensor, d_params: torch.Tensor, ppt: Optional[torch.Tensor] = None, stream=None):
+    """Runs ssa_backward_static: ssa_backward with the library's static device
+    scratch instead of a work buffer (the caller provides the outputs
+    d_params float32 [param_total] and, optionally, ppt [sum P_n*B_n])."""
+    assert fwd.ckpt is not None, "the forward kept no checkpoints"
+    assert d_obs.dtype == torch.float64 and d_obs.is_cuda and d_obs.is_contiguous()
+    assert d_params.dtype == torch.float32 and d_params.numel() >= net.param_total
+    rc = lib().ssa_backward_static(net.handle, C.byref(fwd.ccfg), _ptr(theta), _ptr(x0), _ptr(fwd.x_final),
+                                   _ptr(fwd.t_final), _ptr(fwd.steps_done), _ptr(fwd.ckpt), fwd.ckpt.numel(),
+                                   _ptr(d_obs), _ptr(d_params), _ptr(ppt), _stream(stream))
+    _check(rc, "ssa_backward_static")
+    return d_params
 
 
 def obs_mean(net: Net, fwd: Forward, out: Optional[torch.Tensor] = None, obs: Optional[torch.Tensor] = None,
