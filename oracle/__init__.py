@@ -107,6 +107,13 @@ def lib():
         L.orc_grn_trace.argtypes = [C.POINTER(_Grn), C.POINTER(_Cfg), C.c_void_p, C.c_void_p,
                                     C.c_uint32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.orc_grn_trace.restype = C.c_int64
+        L.orc_grn_soft_run.argtypes = [C.POINTER(_Grn), C.POINTER(_Cfg), C.c_void_p, C.c_void_p, C.c_int64,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.orc_grn_soft_run.restype = C.c_int
+        L.orc_grn_soft_trace.argtypes = [C.POINTER(_Grn), C.POINTER(_Cfg), C.c_void_p, C.c_void_p, C.c_uint32,
+                                         C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.orc_grn_soft_trace.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -387,3 +394,69 @@ def grn_trace(net, cfg, theta, u_row, traj_id: int = 0, x0=None, cap: int = 1000
     if n < 0:
         raise RuntimeError("oracle rejected its arguments")
     return j[:n], t[:n + 1]
+
+
+@dataclass
+class GrnSoftResult:
+    x_final: np.ndarray        # [n_traj, n_hid + n_out] real
+    t_final: np.ndarray
+    obs: np.ndarray            # [n_traj, n_out]
+    grad_c: Optional[np.ndarray] = None   # [n_traj, n_compact]
+
+
+def _soft_cfg(cfg):
+    if np.isfinite(cfg.t_end):
+        raise ValueError("the relaxed forward runs a fixed number of steps (t_end must be infinite)")
+    return _Cfg(cfg.seed, cfg.purpose, cfg.epoch, min(int(cfg.n_steps), 2 ** 62), float(cfg.t_end),
+                0, 0, 0.0, 0, None, float(cfg.temperature), 1e-6, 1e-5)
+
+
+def grn_soft_run(net, cfg, theta, u_hid, image_of, x0=None, traj_ids=None, d_obs=None,
+                 n_threads: int = 0, theta64: bool = False) -> GrnSoftResult:
+    """Relaxed forward (Eq. 4) of GRN trajectories and, with d_obs
+    [n_traj, n_out], the gradient of sum d_obs * O_final through the whole
+    relaxed map.  u_hid: [n_images, n_hid] hidden pre-activations.  theta is
+    rounded to FP32 first (the values the library holds) unless theta64."""
+    keep = _Keep()
+    g = _grn(net)
+    image_of = keep(np.ascontiguousarray(image_of, np.int32))
+    n_traj = len(image_of)
+    N = net.n_hid + net.n_out
+    if traj_ids is None:
+        traj_ids = np.arange(n_traj, dtype=np.uint32)
+    traj_ids = keep(np.ascontiguousarray(traj_ids, np.uint32))
+    x0 = np.zeros((n_traj, N)) if x0 is None else np.asarray(x0, np.float64)
+    x0 = keep(np.ascontiguousarray(np.broadcast_to(x0, (n_traj, N)), np.float64))
+    u = keep(np.ascontiguousarray(u_hid, np.float64))
+    th = np.asarray(theta, np.float64) if theta64 else np.asarray(theta, np.float32).astype(np.float64)
+    th = keep(np.ascontiguousarray(th))
+    c = _soft_cfg(cfg)
+    res = GrnSoftResult(np.zeros((n_traj, N)), np.zeros(n_traj), np.zeros((n_traj, net.n_out)))
+    dp = None
+    if d_obs is not None:
+        d = keep(np.ascontiguousarray(np.broadcast_to(d_obs, (n_traj, net.n_out)), np.float64))
+        res.grad_c = np.zeros((n_traj, net.n_compact))
+        dp = _p(d)
+    rc = lib().orc_grn_soft_run(C.byref(g), C.byref(c), _p(th), _p(u), n_traj, _p(traj_ids), _p(image_of),
+                                _p(x0), dp, _p(res.x_final), _p(res.t_final), _p(res.obs),
+                                _p(res.grad_c) if res.grad_c is not None else None, n_threads)
+    if rc != 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return res
+
+
+def grn_soft_trace(net, cfg, theta, u_row, traj_id: int = 0, x0=None, cap: int = 1000):
+    """The relaxed path of one trajectory: states [n+1, N] and clock [n+1]."""
+    keep = _Keep()
+    g = _grn(net)
+    N = net.n_hid + net.n_out
+    x = keep(np.ascontiguousarray(np.zeros(N) if x0 is None else x0, np.float64))
+    u = keep(np.ascontiguousarray(u_row, np.float64))
+    th = keep(np.ascontiguousarray(np.asarray(theta, np.float32).astype(np.float64)))
+    c = _soft_cfg(cfg)
+    X = np.zeros((cap + 1, N))
+    t = np.zeros(cap + 1)
+    n = lib().orc_grn_soft_trace(C.byref(g), C.byref(c), _p(th), _p(u), traj_id, _p(x), cap, _p(X), _p(t))
+    if n < 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return X[:n + 1], t[:n + 1]

@@ -567,7 +567,10 @@ static int edge_side_bin(const orc_cfg *cfg, double t, int b, const orc_override
         if (d <= 0.5 * cfg->edge_window * e && n_bad) ++*n_bad;
         return b;
     }
-    if (d > cfg->edge_window * e) {
+    /* the GPU logged it within the window of its own clock: the two clocks
+     * differ by less than half the window, so a record is consistent up to
+     * twice the window from the oracle's event */
+    if (d > 2.0 * cfg->edge_window * e) {
         if (n_bad) ++*n_bad;
         return b;
     }

@@ -76,7 +76,7 @@ typedef struct orc_cfg {
  *         term to the bin on that side (the derivative of a bin average with
  *         respect to an event time jumps at an edge).  An event of the oracle
  *         within half the window of an edge without such an entry, or an entry
- *         for an event farther than the window, counts in n_bad. */
+ *         for an event farther than twice the window, counts in n_bad. */
 typedef struct orc_overrides {
     const int64_t *off;     /* [n_traj+1] */
     const int64_t *step;
@@ -203,6 +203,26 @@ int orc_grn_run(const orc_grn *net, const orc_cfg *cfg, const double *theta,
 int64_t orc_grn_trace(const orc_grn *net, const orc_cfg *cfg, const double *theta,
                       const double *u_row, uint32_t traj_id, const int32_t *x0, int64_t cap,
                       int32_t *j, double *t);
+
+/* Relaxed (soft) forward of Eq. 4 and its exact adjoint.  The state is real:
+ * every step takes the soft sample y_j = softmax_j((ln a_j + G_j)/T) of Eq. 3
+ * over the channels with a_j > 0 (same noise words as the hard forward,
+ * G_j = -ln(-ln u_{1+j})) and moves X by sum_j y_j v_j; propensities are
+ * evaluated at the real state, a decay channel of a gene at or below zero
+ * having a_j = 0.  The clock advances by -ln(u_0)/a0.  Runs exactly n_steps
+ * steps (production never stops); cfg->t_end must be infinite.
+ * With d_obs, grad_c [n_traj][orc_grn_n_compact] receives the gradient of
+ * sum_o d_obs[o] O_o(final) through the whole relaxed map (no stop-gradient).
+ * x0, x_final [n_traj][N] real; obs [n_traj][n_out] the final output levels. */
+int orc_grn_soft_run(const orc_grn *net, const orc_cfg *cfg, const double *theta, const double *u_hid,
+                     int64_t n_traj, const uint32_t *traj_ids, const int32_t *image_of, const double *x0,
+                     const double *d_obs, double *x_final, double *t_final, double *obs, double *grad_c,
+                     int n_threads);
+
+/* The relaxed path of one trajectory: X [(cap+1)][N] states, t [cap+1].
+ * Returns the number of steps taken. */
+int64_t orc_grn_soft_trace(const orc_grn *net, const orc_cfg *cfg, const double *theta, const double *u_row,
+                           uint32_t traj_id, const double *x0, int64_t cap, double *X, double *t);
 
 #ifdef __cplusplus
 }

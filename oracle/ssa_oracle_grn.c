@@ -24,6 +24,9 @@
  *     Fig. 1), with d ln a_j / d(parameters, state) of the regulated kinetics.
  *     The observation (final output counts) does not depend on event times,
  *     so the waiting-time path carries no gradient here.
+ *   - The relaxed forward of Eq. 4 (the first phase of the two-phase training
+ *     of Sec. 3.5): the state is real and every step moves it by the soft
+ *     sample's expected change; its adjoint differentiates that whole map.
  */
 #include "ssa_oracle.h"
 
@@ -382,6 +385,204 @@ int64_t orc_grn_trace(const orc_grn *net, const orc_cfg *cfg, const double *thet
     }
     free(buf);
     free(X);
+    par_free(&p);
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relaxed (soft) forward of the gene network (Sec. 3.3, Eq. 4)              */
+/* ------------------------------------------------------------------------ */
+
+/* Propensities at a real-valued state: a relaxed count at or below zero gives
+ * its decay channel a zero propensity (the channel is out of the soft sample,
+ * as an exhausted reactant puts a channel out of the hard process). */
+static double soft_propensities(const grn_par_t *p, const double *sh, const double *X, double *v, double *a)
+{
+    const int H = p->H, O = p->O;
+    double a0 = 0.0;
+    for (int h = 0; h < H; ++h) {
+        a[h] = p->beta * sh[h];
+        a[H + h] = X[h] > 0.0 ? p->delta[h] * X[h] : 0.0;
+    }
+    for (int o = 0; o < O; ++o) {
+        double s = p->c[o];
+        for (int h = 0; h < H; ++h) s += p->U[(size_t)o * H + h] * X[h];
+        v[o] = s;
+        a[2 * H + o] = p->beta * sigmoid(s);
+        a[2 * H + O + o] = X[H + o] > 0.0 ? p->delta[H + o] * X[H + o] : 0.0;
+    }
+    for (int j = 0; j < p->M; ++j) a0 += a[j];
+    return a0;
+}
+
+/* Soft sample of Eq. (3): y_j = softmax_j((ln a_j + G_j) / T) over the
+ * channels with a_j > 0, G_j = -ln(-ln u_{1+j}). */
+static void soft_sample(int M, const double *a, const double *u, double T, double *y)
+{
+    double zmax = -INFINITY;
+    for (int j = 0; j < M; ++j)
+        if (a[j] > 0.0) {
+            y[j] = (log(a[j]) - log(-log(u[1 + j]))) / T;
+            if (y[j] > zmax) zmax = y[j];
+        }
+    double zs = 0.0;
+    for (int j = 0; j < M; ++j) {
+        y[j] = a[j] > 0.0 ? exp(y[j] - zmax) : 0.0;
+        zs += y[j];
+    }
+    for (int j = 0; j < M; ++j) y[j] /= zs;
+}
+
+/* Relaxed path of one trajectory: X_{k+1} = X_k + sum_j y_j v_j (Eq. 4),
+ * t_{k+1} = t_k - ln(u_0) / a0(X_k).  X [(n_steps + 1)][N] receives the
+ * states (X[0] = x0), t [n_steps + 1] the clock.  Returns the steps taken. */
+static int64_t simulate_grn_soft(const grn_par_t *p, const orc_cfg *cfg, const double *sh,
+                                 uint32_t traj_id, double *X, double *t, double *u, double *a,
+                                 double *v, double *y)
+{
+    const int M = p->M, N = p->N;
+    t[0] = 0.0;
+    int64_t k = 0;
+    for (; k < cfg->n_steps; ++k) {
+        const double *Xk = X + (size_t)k * N;
+        double *Xn = X + (size_t)(k + 1) * N;
+        const double a0 = soft_propensities(p, sh, Xk, v, a);
+        if (!(a0 > 0.0)) break;
+        orc_step_uniforms(cfg->seed, cfg->purpose, cfg->epoch, traj_id, (uint32_t)k, M + 1, u);
+        soft_sample(M, a, u, cfg->temperature, y);
+        memcpy(Xn, Xk, sizeof(double) * N);
+        for (int j = 0; j < M; ++j) {
+            int s, d;
+            channel_effect(p, j, &s, &d);
+            Xn[s] += (double)d * y[j];
+        }
+        t[k + 1] = t[k] - log(u[0]) / a0;
+    }
+    return k;
+}
+
+/* Reverse sweep of the relaxed map (every step differentiated, no stop
+ * gradient): lambda_k = lambda_{k+1} + sum_j g_j grad_X ln a_j(X_k) with
+ * g_j = y_j (w_j - sum_l y_l w_l) / T and w_j = v_j . lambda_{k+1}, the
+ * Jacobian of Eq. 4's update transposed.  The parameters get
+ * sum_k sum_j g_j d ln a_j / d(parameter).  X: the stored path. */
+static void adjoint_grn_soft(const grn_par_t *p, const orc_cfg *cfg, const double *sh, uint32_t traj_id,
+                             const double *X, int64_t n, const double *dobs, double *g_c, double *u,
+                             double *a, double *v, double *y, double *w, double *lam)
+{
+    const int H = p->H, O = p->O, M = p->M, N = p->N;
+    const double T = cfg->temperature;
+    double *du = g_c, *dU = du + H, *dc = dU + (size_t)O * H, *dpsi = dc + O;
+    memset(g_c, 0, sizeof(double) * (size_t)(H + O * H + O + H + O));
+    for (int s = 0; s < H; ++s) lam[s] = 0.0;
+    for (int o = 0; o < O; ++o) lam[H + o] = dobs[o];
+    double *dlam = lam + N;
+    for (int64_t k = n - 1; k >= 0; --k) {
+        const double *Xk = X + (size_t)k * N;
+        soft_propensities(p, sh, Xk, v, a);
+        orc_step_uniforms(cfg->seed, cfg->purpose, cfg->epoch, traj_id, (uint32_t)k, M + 1, u);
+        soft_sample(M, a, u, T, y);
+        double wbar = 0.0;
+        for (int j = 0; j < M; ++j) {
+            int sp, dd;
+            channel_effect(p, j, &sp, &dd);
+            w[j] = (double)dd * lam[sp];
+            wbar += y[j] * w[j];
+        }
+        memset(dlam, 0, sizeof(double) * N);
+        for (int j = 0; j < M; ++j) {
+            if (!(a[j] > 0.0)) continue;
+            const double g = y[j] * (w[j] - wbar) / T;
+            if (j < H) {
+                du[j] += g * (1.0 - sh[j]);
+            } else if (j < 2 * H) {
+                const int h = j - H;
+                dpsi[h] += g * p->dfac[h];
+                dlam[h] += g / Xk[h];
+            } else if (j < 2 * H + O) {
+                const int o = j - 2 * H;
+                const double e = g * (1.0 - sigmoid(v[o]));
+                dc[o] += e;
+                for (int h = 0; h < H; ++h) {
+                    dU[(size_t)o * H + h] += e * Xk[h];
+                    dlam[h] += e * p->U[(size_t)o * H + h];
+                }
+            } else {
+                const int o = j - 2 * H - O;
+                dpsi[H + o] += g * p->dfac[H + o];
+                dlam[H + o] += g / Xk[H + o];
+            }
+        }
+        for (int q = 0; q < N; ++q) lam[q] += dlam[q];
+    }
+}
+
+int orc_grn_soft_run(const orc_grn *net, const orc_cfg *cfg, const double *theta, const double *u_hid,
+                     int64_t n_traj, const uint32_t *traj_ids, const int32_t *image_of, const double *x0,
+                     const double *d_obs, double *x_final, double *t_final, double *obs, double *grad_c,
+                     int n_threads)
+{
+    if (!grn_args_ok(net, cfg) || n_traj < 0 || !u_hid || !image_of || !x0 || cfg->n_steps < 0 ||
+        cfg->n_steps > ((int64_t)1 << 28) || isfinite(cfg->t_end))
+        return -1;
+    grn_par_t p;
+    if (par_init(net, theta, &p)) { par_free(&p); return -1; }
+    const int H = p.H, O = p.O, M = p.M, N = p.N;
+    const int64_t C = orc_grn_n_compact(net), n_steps = cfg->n_steps;
+    int err = 0;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel num_threads(n_threads) reduction(|:err)
+#endif
+    {
+        double *buf = malloc(sizeof(double) * (size_t)(H + (M + 1) + M + O + M + M + 2 * N));
+        double *X = malloc(sizeof(double) * (size_t)(n_steps + 1) * N);
+        double *t = malloc(sizeof(double) * (size_t)(n_steps + 1));
+        if (!buf || !X || !t) err |= 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t q = 0; q < n_traj; ++q) {
+            if (!buf || !X || !t) continue;
+            double *sh = buf, *u = sh + H, *a = u + (M + 1), *v = a + M, *y = v + O, *w = y + M, *lam = w + M;
+            const double *urow = u_hid + (size_t)image_of[q] * H;
+            for (int h = 0; h < H; ++h) sh[h] = sigmoid(urow[h]);
+            memcpy(X, x0 + (size_t)q * N, sizeof(double) * N);
+            const uint32_t id = traj_ids ? traj_ids[q] : (uint32_t)q;
+            const int64_t n = simulate_grn_soft(&p, cfg, sh, id, X, t, u, a, v, y);
+            memcpy(x_final + (size_t)q * N, X + (size_t)n * N, sizeof(double) * N);
+            t_final[q] = t[n];
+            for (int o = 0; o < O; ++o) obs[(size_t)q * O + o] = X[(size_t)n * N + H + o];
+            if (d_obs)
+                adjoint_grn_soft(&p, cfg, sh, id, X, n, d_obs + (size_t)q * O, grad_c + (size_t)q * C,
+                                 u, a, v, y, w, lam);
+        }
+        free(buf);
+        free(X);
+        free(t);
+    }
+    par_free(&p);
+    return err ? -1 : 0;
+}
+
+int64_t orc_grn_soft_trace(const orc_grn *net, const orc_cfg *cfg, const double *theta, const double *u_row,
+                           uint32_t traj_id, const double *x0, int64_t cap, double *X, double *t)
+{
+    if (!grn_args_ok(net, cfg) || cap < 0 || !u_row || isfinite(cfg->t_end)) return -1;
+    grn_par_t p;
+    if (par_init(net, theta, &p)) { par_free(&p); return -1; }
+    const int H = p.H, O = p.O, M = p.M, N = p.N;
+    orc_cfg c = *cfg;
+    if (c.n_steps > cap) c.n_steps = cap;
+    double *buf = malloc(sizeof(double) * (size_t)(H + (M + 1) + M + O + M));
+    int64_t n = -1;
+    if (buf) {
+        double *sh = buf, *u = sh + H, *a = u + (M + 1), *v = a + M, *y = v + O;
+        for (int h = 0; h < H; ++h) sh[h] = sigmoid(u_row[h]);
+        memcpy(X, x0, sizeof(double) * N);
+        n = simulate_grn_soft(&p, &c, sh, traj_id, X, t, u, a, v, y);
+    }
+    free(buf);
     par_free(&p);
     return n;
 }
