@@ -220,6 +220,10 @@ typedef struct ssa_config {
     int32_t selection;             /* SSA_SELECT_*: how the forward picks the channel */
     int32_t obs_layout;            /* SSA_OBS_POINT_MAJOR, SSA_OBS_TRAJ_MAJOR or SSA_OBS_ENSEMBLE_MEAN */
     int32_t dobs_shared;           /* nonzero: d_obs holds one dL/dobs block [W_n] per network */
+    int32_t relaxed;               /* 1: the relaxed forward of Eq. 4 (Sec. 3.3) and the exact
+                                      backward of that map, the first phase of the two-phase
+                                      training (Sec. 3.5); gene-network runs only (SSA_ENOTSUP
+                                      elsewhere).  0: the exact forward (default) */
 } ssa_config;
 
 /* One logged step where the selection (kind 0) or the t_end stop decision
@@ -368,9 +372,19 @@ const char *ssa_last_error(void);
  *   d_compact        double [B][C], C = n_hid + n_out*n_hid + n_out + n_hid + n_out:
  *                    per trajectory [dL/du (n_hid) | dL/dU | dL/dc | dL/dpsi]
  *                    (dL/db = dL/du; dL/dW = sum_q dL/du_q bf16(x_{image q})^T)
- * Runs use cfg->seed, purpose, epoch, d_epoch, traj_ids, n_steps, temperature
- * and tie_capacity; the observation is always the final output counts, and
- * cfg->t_end must be +INFINITY (SSA_ENOTSUP otherwise).
+ * Runs use cfg->seed, purpose, epoch, d_epoch, traj_ids, n_steps, temperature,
+ * d_temperature, tie_capacity and relaxed; the observation is always the final
+ * output counts, and cfg->t_end must be +INFINITY (SSA_ENOTSUP otherwise).
+ *
+ * Relaxed runs (cfg->relaxed = 1; Eq. 4, Sec. 3.3): the state is real and
+ * every step moves it by sum_j y~_j v_j, the soft sample of Eq. 3 at the
+ * forward's noise (temperature cfg->temperature, or *d_temperature), with a
+ * decay channel of a gene at or below zero out of the sample.  obs receives
+ * the final output levels (real), x_final their roundings to the nearest
+ * integer; no near-ties are logged.  The tape buffer then holds the starting
+ * point of every step, (n_steps + 1) rows of n_hid + 32 floats per trajectory
+ * (ssa_grn_buffer_sizes reports it), and ssa_grn_backward returns the
+ * gradient of the relaxed map itself (no stop-gradient).
  * ------------------------------------------------------------------------ */
 typedef struct ssa_grn_desc {
     int32_t n_in;                  /* input factors per image (>= 1) */

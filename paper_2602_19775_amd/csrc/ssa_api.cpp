@@ -326,6 +326,8 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
                                          "run in the topology-specialised lane mode only");
     if (cfg->selection != SSA_SELECT_GUMBEL_MAX && cfg->selection != SSA_SELECT_INVERSE_CDF)
         return fail(SSA_EINVAL, "unknown selection");
+    if (cfg->relaxed)
+        return fail(SSA_ENOTSUP, "the relaxed forward runs on the gene-network classifier only");
     if (cfg->selection == SSA_SELECT_INVERSE_CDF) {
         if (cfg->obs_layout == SSA_OBS_ENSEMBLE_MEAN)
             return fail(SSA_ENOTSUP, "the inverse-CDF selection writes per-trajectory observations");

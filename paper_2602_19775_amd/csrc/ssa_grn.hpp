@@ -31,6 +31,10 @@ struct GrnParams {
     uint32_t *tape;             // [B][tape_words]: the fired channel of step k is the 16-bit
                                 // half (k & 1) of word 64 * (k >> 7) + ((k >> 1) & 63)
     int32_t tape_words;
+    int32_t relaxed;            // nonzero: the relaxed forward of Eq. 4 and its exact backward
+    float *soft;                // relaxed runs: [B][n_steps + 1][kHid + 2 kMaxOut] starting
+                                // point of every step (hidden levels, output levels, output
+                                // pre-activations), in place of the tape
     TieRec *ties;
     uint32_t *n_ties;
     uint32_t tie_cap;

@@ -43,6 +43,9 @@ ssa_status check_cfg(const ssa_grn *g, const ssa_config *cfg)
     if (!(cfg->temperature > 0.f) || !std::isfinite(cfg->temperature))
         return fail(SSA_EINVAL, "temperature must be finite and > 0");
     if (cfg->tie_capacity < 0) return fail(SSA_EINVAL, "tie_capacity must be >= 0");
+    if (cfg->relaxed != 0 && cfg->relaxed != 1) return fail(SSA_EINVAL, "relaxed must be 0 or 1");
+    if (cfg->relaxed && cfg->selection != SSA_SELECT_GUMBEL_MAX)
+        return fail(SSA_ENOTSUP, "the relaxed forward takes the Gumbel-Softmax sample (selection must be Gumbel-max)");
     return SSA_OK;
 }
 
@@ -51,8 +54,14 @@ size_t tape_words(const ssa_config *cfg)
     return (size_t)64 * (size_t)((cfg->n_steps + 127) / 128);
 }
 
+// Relaxed runs store the starting point of every step instead of the fired
+// channels: (n_steps + 1) rows of kHid + 2 kMaxOut floats per trajectory.
+constexpr size_t kSoftRowFloats = grn::kHid + 2 * grn::kMaxOut;
+
 size_t tape_bytes_for(const ssa_grn *g, const ssa_config *cfg)
 {
+    if (cfg->relaxed)
+        return align_up(sizeof(float) * kSoftRowFloats * ((size_t)cfg->n_steps + 1) * (size_t)g->B);
     return align_up(sizeof(uint32_t) * tape_words(cfg) * (size_t)g->B);
 }
 
@@ -83,6 +92,7 @@ grn::GrnParams base_params(const ssa_grn *g, const ssa_config *cfg, const float 
     p.off_psi = p.off_c + O;
     p.x_img = x_img;
     p.tape_words = (int32_t)tape_words(cfg);
+    p.relaxed = cfg->relaxed;
     p.flags = g->flags_d;
     p.seed_lo = (uint32_t)cfg->seed;
     p.seed_hi = (uint32_t)(cfg->seed >> 32);
@@ -167,8 +177,9 @@ ssa_status ssa_grn_forward(const ssa_grn *g, const ssa_config *cfg, const float 
     p.t_final = t_final;
     p.steps_done = steps_done;
     p.obs = obs;
-    p.tape = (uint32_t *)tape;
-    p.ties = reinterpret_cast<TieRec *>(ties);
+    p.tape = cfg->relaxed ? nullptr : (uint32_t *)tape;
+    p.soft = cfg->relaxed ? (float *)tape : nullptr;
+    p.ties = cfg->relaxed ? nullptr : reinterpret_cast<TieRec *>(ties);
     p.n_ties = n_ties;
     p.tie_cap = (uint32_t)cfg->tie_capacity;
     hipError_t e = hipSuccess;
@@ -201,7 +212,8 @@ ssa_status ssa_grn_backward(const ssa_grn *g, const ssa_config *cfg, const float
     p.x0 = x0;
     p.x_final = const_cast<int32_t *>(x_final);
     p.steps_done = const_cast<int32_t *>(steps_done);
-    p.tape = (uint32_t *)const_cast<void *>(tape);
+    p.tape = cfg->relaxed ? nullptr : (uint32_t *)const_cast<void *>(tape);
+    p.soft = cfg->relaxed ? (float *)const_cast<void *>(tape) : nullptr;
     p.d_obs = d_obs;
     char *w = (char *)work;
     p.part = d_compact ? d_compact : (double *)w;

@@ -50,7 +50,7 @@ class _Cfg(C.Structure):
                 ("t_end", C.c_double), ("obs_kind", C.c_int32), ("n_bins", C.c_int32),
                 ("temperature", C.c_float), ("ckpt_every", C.c_int32), ("bwd_mode", C.c_int32),
                 ("tie_capacity", C.c_int32), ("d_temperature", C.c_void_p), ("selection", C.c_int32),
-                ("obs_layout", C.c_int32), ("dobs_shared", C.c_int32)]
+                ("obs_layout", C.c_int32), ("dobs_shared", C.c_int32), ("relaxed", C.c_int32)]
 
 
 TIE_DTYPE = np.dtype([("traj", np.uint32), ("step", np.uint32), ("chosen", np.int32),
@@ -197,7 +197,7 @@ def make_cfg(cfg: W.RunConfig, tie_capacity: int = 0, bwd_mode: str = "auto",
                 int(cfg.n_bins if cfg.obs_kind in (W.OBS_BINS, W.OBS_GRID, W.OBS_TAIL) else 0),
                 float(cfg.temperature),
                 int(cfg.ckpt_every), _BWD[bwd_mode], int(tie_capacity), _ptr(d_temperature),
-                int(cfg.selection), int(cfg.obs_layout), int(bool(cfg.dobs_shared)))
+                int(cfg.selection), int(cfg.obs_layout), int(bool(cfg.dobs_shared)), int(bool(cfg.relaxed)))
 
 
 @dataclass
