@@ -167,17 +167,35 @@ OSC_PARAMS = ["gamma_A", "theta_A", "gamma_R", "theta_R", "alpha_A", "alpha'_A",
               "delta_A", "delta_R", "gamma_C"]
 
 
-def oscillator(rate_seed: int = 0, log10_range=(-2.0, 3.0), rates=None) -> Network:
+# Nominal rates of the activator-repressor oscillator as published with the
+# model (Vilar, Kueh, Barkai and Leibler, PNAS 2002, the paper's ref. 30), per
+# hour and per molecule: promoter binding and release, transcription from the
+# free and bound promoters, translation, mRNA and protein decay, complex
+# formation.  The paper's five protein rates (Sec. 4.2) are these values.
+OSC_NOMINAL_RATES = {
+    "gamma_A": 1.0, "theta_A": 50.0, "gamma_R": 1.0, "theta_R": 100.0,
+    "alpha_A": 50.0, "alpha'_A": 500.0, "alpha_R": 0.01, "alpha'_R": 50.0,
+    "beta_A": 50.0, "beta_R": 5.0, "delta_MA": 10.0, "delta_MR": 0.5,
+    "delta_A": 1.0, "delta_R": 0.2, "gamma_C": 2.0,
+}
+
+
+def oscillator(rates=None, rate_seed: Optional[int] = None, log10_range=(-2.0, 3.0)) -> Network:
     """Activator-repressor oscillator of Sec. 4.2: 9 species, 16 mass-action channels
     (promoter binding/unbinding, transcription from both promoter states,
     translation, mRNA and protein degradation, A+R->C, C->R).  The complex C
     releases R at the activator's degradation rate, so 16 channels use 15 rates.
-    The paper's nominal rates are in a supplement that is not available, so the
-    rates are drawn log-uniformly (seeded) unless given."""
+    Rates: the given vector (OSC_PARAMS order), else log-uniform seeded ones if
+    rate_seed is given, else the nominal ones (OSC_NOMINAL_RATES).  Starts with
+    one free copy of each promoter and nothing else."""
     if rates is None:
-        g = np.random.default_rng(np.random.SeedSequence([rate_seed, 3]))
-        rates = 10.0 ** g.uniform(log10_range[0], log10_range[1], size=15)
+        if rate_seed is None:
+            rates = [OSC_NOMINAL_RATES[p] for p in OSC_PARAMS]
+        else:
+            g = np.random.default_rng(np.random.SeedSequence([rate_seed, 3]))
+            rates = 10.0 ** g.uniform(log10_range[0], log10_range[1], size=15)
     rates = np.asarray(rates, np.float64)
+    assert rates.shape == (15,)
     P = {n: i for i, n in enumerate(OSC_PARAMS)}
     R = [
         (("D_A", "A"), P["gamma_A"], {"D_A": -1, "A": -1, "D_A'": +1}),
@@ -202,23 +220,19 @@ def oscillator(rate_seed: int = 0, log10_range=(-2.0, 3.0), rates=None) -> Netwo
 
 
 # The five protein rates of the oscillator that the start-point-map inference
-# of Sec. 4.2 recovers, at the values the paper gives for them.
+# of Sec. 4.2 recovers (their values there are the nominal ones).
 OSC_PROTEIN_PARAMS = ("beta_A", "beta_R", "delta_A", "delta_R", "gamma_C")
-OSC_PROTEIN_RATES = (50.0, 5.0, 1.0, 0.2, 2.0)
+OSC_PROTEIN_RATES = tuple(OSC_NOMINAL_RATES[p] for p in OSC_PROTEIN_PARAMS)
 
 
-def start_point_oscillator(rate_seed: int = 0, protein_rates=OSC_PROTEIN_RATES) -> Network:
+def start_point_oscillator(protein_rates=OSC_PROTEIN_RATES) -> Network:
     """The oscillator of the start-point-map inference (Sec. 4.2), observing
-    the three proteins A, R and C.  The five protein rates (translation of A
-    and R, degradation of A and R, complex formation) take the paper's values;
-    the other ten distinct rates, which the paper holds at nominal values given
-    in a supplement that is not available, are the seeded ones of
-    oscillator(rate_seed)."""
-    base = oscillator(rate_seed)
-    rates = np.exp(base.theta0.astype(np.float64))
+    the three proteins A, R and C, with the given protein rates (beta_A,
+    beta_R, delta_A, delta_R, gamma_C) and the other rates nominal."""
+    rates = np.array([OSC_NOMINAL_RATES[p] for p in OSC_PARAMS])
     for name, k in zip(OSC_PROTEIN_PARAMS, protein_rates):
         rates[OSC_PARAMS.index(name)] = k
-    net = oscillator(rate_seed, rates=rates)
+    net = oscillator(rates)
     idx = {s_: i for i, s_ in enumerate(net.species)}
     net.obs_species = np.asarray([idx["A"], idx["R"], idx["C"]], np.int32)
     net.name = "start_point_oscillator"
@@ -289,6 +303,7 @@ class RunConfig:
     selection: int = 0                # SELECT_GUMBEL_MAX or SELECT_INVERSE_CDF (forward only)
     obs_layout: int = 0               # OBS_POINT_MAJOR, OBS_TRAJ_MAJOR or OBS_ENSEMBLE_MEAN
     dobs_shared: bool = False         # d_obs is one block per network (a loss of ensemble means)
+    relaxed: bool = False             # gene network: the relaxed forward of Eq. 4 and its backward
 
     def replace(self, **kw) -> "RunConfig":
         d = dict(self.__dict__)
@@ -336,14 +351,16 @@ def dimer_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 10000) -> Workload:
 
 # Observation window of the oscillator workload: 0.9 x the 1st percentile of the
 # clock after 200,000 steps in a 64-trajectory pilot run of the FP64 oracle
-# (pilot stream, initial rates); tests/golden/oscillator_pilot.py recomputes it.
+# (pilot stream, seeded rates of rate_seed 0); tests/golden/oscillator_pilot.py
+# recomputes it.
 OSC_T_OBS = 124299.29021959605
 
 
 def oscillator_fwdbwd_64k(n_traj: int = 65536, n_steps: int = 200000, t_obs: float = OSC_T_OBS) -> Workload:
-    """Activator-repressor oscillator with seeded rates: 65,536 trajectories x
-    200,000 steps, 256 exact bin averages of R on [0, t_obs], temperature 0.5,
-    checkpoints every 1,024 steps.  Targets come from a second seeded rate vector."""
+    """Activator-repressor oscillator with 15 log-uniform seeded rates in
+    [1e-2, 1e3] (rate_seed 0): 65,536 trajectories x 200,000 steps, 256 exact
+    bin averages of R on [0, t_obs], temperature 0.5, checkpoints every 1,024
+    steps.  Targets come from a second seeded rate vector (rate_seed 1)."""
     net = oscillator(rate_seed=0)
     cfg = RunConfig(seed=0, n_steps=n_steps, obs_kind=OBS_BINS, n_bins=256, t_obs=t_obs,
                     temperature=0.5, ckpt_every=1024)

@@ -1,6 +1,7 @@
 """Observation window of the oscillator workload, from a pilot run of the FP64
 oracle: t_obs = 0.9 x the 1st percentile of the clock after 200,000 steps over
-64 trajectories of the pilot stream (purpose 2) at the initial rates.  Prints
+64 trajectories of the pilot stream (purpose 2) at the seeded rates of
+rate_seed 0.  Prints
 the value stored as OSC_T_OBS in paper_2602_19775_amd/workloads.py."""
 import os
 import sys

@@ -72,7 +72,7 @@ def test_simulate_st_oscillator(ssa):
     """The oscillator: the ensemble mean of the final R count against a target,
     plus a per-trajectory nonlinear term so that dL/dobs differs between
     trajectories."""
-    net = W.oscillator(0)
+    net = W.oscillator()
     B = 512
     cfg = W.RunConfig(seed=22, n_steps=10000, obs_kind=W.OBS_FINAL, temperature=0.5, ckpt_every=1024)
 

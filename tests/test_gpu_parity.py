@@ -242,7 +242,7 @@ def test_dimer_forward_t_end_1024(ssa):
 
 
 def test_step_batch_matches_oracle_trace(ssa):
-    net = W.oscillator(0)
+    net = W.oscillator()
     B, steps = 100, 40
     cfg = W.RunConfig(seed=3, n_steps=steps)
     h = ssa.Net([net], [B])
@@ -313,7 +313,7 @@ def test_dimer_gradients_small(ssa, mode, exec_mode):
 
 
 def test_oscillator_gradients_small(ssa):
-    net = W.oscillator(0)
+    net = W.oscillator()
     B = 128
     cfg = W.RunConfig(seed=4, n_steps=3000, obs_kind=W.OBS_FINAL, temperature=0.5, ckpt_every=256)
     pilot = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=np.arange(16))

@@ -32,7 +32,7 @@ def test_inverse_cdf_dimer_to_t_end(ssa):
 
 
 def test_inverse_cdf_oscillator_bins(ssa):
-    net = W.oscillator(0)
+    net = W.oscillator()
     cfg = W.RunConfig(seed=5, n_steps=20000, obs_kind=W.OBS_BINS, n_bins=16, t_obs=0.0,
                       selection=W.SELECT_INVERSE_CDF)
     import oracle

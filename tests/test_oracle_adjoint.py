@@ -204,7 +204,11 @@ def _case(name):
         net = W.dimerization_abc()
         cfg = W.RunConfig(n_steps=80, obs_kind=W.OBS_FINAL, temperature=0.7)
     elif name == "oscillator_bins":
-        net = W.oscillator(0)
+        net = W.oscillator()
+        # a state inside the cycle (the initial state has no protein for a while)
+        x0 = np.array([1, 0, 0, 1, 2, 5, 30, 60, 200], np.int32)
+        net = W.Network(net.name, net.species, net.reactant, net.rate_index, net.stoich, net.n_params,
+                        net.theta0, x0, net.obs_species, net.param_names)
         cfg = W.RunConfig(n_steps=150, obs_kind=W.OBS_BINS, n_bins=7, t_obs=0.0, temperature=0.5)
     elif name == "random_bins":
         net = W.random_network_batch(3, seed=11, n_range=(4, 8), m_range=(8, 16))[2]

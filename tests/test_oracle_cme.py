@@ -188,7 +188,7 @@ def test_gumbel_max_selects_categorically(orc):
 def test_exponential_race_equals_gumbel_max(orc):
     """The oracle's argmin E_j/a_j picks exactly argmax_j [ln a_j + G_j] with
     G_j = -ln(-ln u_j) (Sec. 3.2), and its margin is the gap of the two best."""
-    net = W.oscillator(0)
+    net = W.oscillator()
     cfg = W.RunConfig(n_steps=3000)
     tr = orc.trace(net, cfg, net.theta0, net.x0, traj_id=5, cap=3000)
     assert len(tr.j) == 3000
@@ -209,7 +209,7 @@ def test_invariants_along_paths(orc):
     net = W.dimerization_2a()
     tr = orc.trace(net, W.RunConfig(n_steps=5000), net.theta0, net.x0, traj_id=3, cap=5000)
     assert np.all(tr.X[:, 0] + 2 * tr.X[:, 1] == 100) and np.all(tr.X >= 0)
-    osc = W.oscillator(0)
+    osc = W.oscillator()
     tr = orc.trace(osc, W.RunConfig(n_steps=20000), osc.theta0, osc.x0, traj_id=9, cap=20000)
     assert np.all(tr.X >= 0)
     assert np.all(tr.X[:, 0] + tr.X[:, 1] == 1) and np.all(tr.X[:, 2] + tr.X[:, 3] == 1)
@@ -252,7 +252,7 @@ def test_inverse_cdf_selects_categorically(orc):
 def test_inverse_cdf_reads_the_cumulative_sum(orc):
     """Along an oscillator path the chosen channel is the cumulative sum's
     crossing of u_1 a0, and the margin is the nearest interior boundary."""
-    net = W.oscillator(0)
+    net = W.oscillator()
     cfg = W.RunConfig(n_steps=2000, selection=W.SELECT_INVERSE_CDF)
     tr = orc.trace(net, cfg, net.theta0, net.x0, traj_id=9, cap=2000)
     c = np.cumsum(tr.a, axis=1)

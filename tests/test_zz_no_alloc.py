@@ -50,7 +50,7 @@ def test_static_backward_equals_allocating_backward(ssa):
 
 
 def test_static_backward_oscillator_then_smaller(ssa):
-    net = W.oscillator(0)
+    net = W.oscillator()
     cfg = W.RunConfig(seed=5, n_steps=3000, obs_kind=W.OBS_FINAL, temperature=0.5, ckpt_every=256)
     _pair(ssa, net, cfg, 4096, 3)
     _pair(ssa, net, cfg.replace(seed=6, n_steps=1000), 257, 4)
