@@ -84,3 +84,23 @@ def test_autocorrelation_fft_matches_lag_sums():
     (g1,) = torch.autograd.grad((r1 * w).sum(), obs)
     (g2,) = torch.autograd.grad((r2 * w).sum(), obs)
     assert torch.allclose(g1, g2, rtol=0, atol=1e-13)
+
+
+def test_start_point_rate_loss_gradient_written_out():
+    """The start-point map's loss gradient with respect to the tail
+    observations, written out, equals torch autograd of the same loss."""
+    import torch
+    from paper_2602_19775_amd.startpoint import rate_loss
+    g = torch.Generator().manual_seed(3)
+    S, R = 7, 5
+    obs = torch.rand(4 * S * R, generator=g, dtype=torch.float64) * 50 + 1.0
+    obs.view(4, S, R)[3] = torch.rand(S, R, generator=g, dtype=torch.float64) * 0.3 + 0.05
+    xs = torch.rand(S, 3, generator=g, dtype=torch.float64) * 40
+    tr = torch.randn(S, 3, generator=g, dtype=torch.float64) * 10
+    d = torch.zeros_like(obs)
+    loss = rate_loss(obs, xs, tr, S, R, d)
+    o = obs.clone().requires_grad_(True)
+    ref = rate_loss(o, xs, tr, S, R)
+    ref.sum().backward()
+    assert torch.allclose(loss, ref.detach(), rtol=1e-14, atol=0)
+    assert torch.allclose(d, o.grad, rtol=1e-12, atol=1e-15)
