@@ -36,7 +36,7 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes per clock x clock
 HBM_PEAK = 8.0e12                        # MI355X HBM3E, bytes/s
 
 
-def alu_ops_per_step(net, backward: bool, inv_t_is_2=True) -> dict:
+def alu_ops_per_step(net, backward: bool, inv_t_is_2=True, tangent: bool = False) -> dict:
     """Algorithmic vector-ALU operations of one step of one trajectory of a
     mass-action network, by kind: mad = 32x32->64-bit product, int = 32-bit
     integer add/logic/shift, fp32 = FP32 add/mul/FMA/compare/select, cvt =
@@ -67,6 +67,19 @@ def alu_ops_per_step(net, backward: bool, inv_t_is_2=True) -> dict:
         ops["int"] += nnz                            # state update (select of the fired change vector)
         ops["fp32"] += M + 3 * M                     # r_j, race compare/min/select
         ops["f64"] += 1 + n_obs                      # clock, bin integral
+        if tangent:
+            # forward-mode tangents for every channel rate q: the soft sample
+            # (rho, its power, the sum), then per q the propensity tangents
+            # (one product per reactant factor and the diagonal), d a0, dz,
+            # the weighted mean, dy, d tau; the state, clock and bin tangents
+            ops["rcp"] += M + 1
+            ops["fp32"] += M + (M if inv_t_is_2 else 3 * M) + M
+            if not inv_t_is_2:
+                ops["log"] += M
+            ops["fp32"] += M * (factors + M + M + 2 * M + 2 * M + 2 * M + 2)
+            ops["fp32"] += nnz * M
+            ops["cvt"] += 2 * N * M + 2 * n_obs * M
+            ops["f64"] += N * M + M + 2 * n_obs * M
         return ops
     ops["cvt"] += 1 + 2 * n_obs                      # clock, time-path and bin terms
     ops["int"] += nnz                                # reversed state update
@@ -675,6 +688,8 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
         theta_t = torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device=dev)
     plan = None
     bwd_mode = args.bwd_mode
+    if bwd_mode == "auto":
+        bwd_mode = "tangent" if workload == "dimer" else "tape"
     if args.autotune and not light:
         from paper_2602_19775_amd import autotune
         t_obs_l = [cfg.t_obs] * len(nets) if cfg.obs_kind == W.OBS_BINS else None
@@ -829,10 +844,12 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
     cost = measure_issue_costs()
     wsum = float(sum(Bs))
 
+    tangent = bwd_mode == "tangent"
+
     def avg_ops(backward):
         tot = {}
         for n_, b_ in zip(nets, Bs):
-            o = alu_ops_per_step(n_, backward, inv2)
+            o = alu_ops_per_step(n_, backward, inv2, tangent=tangent and not backward)
             for k_, v_ in o.items():
                 tot[k_] = tot.get(k_, 0.0) + v_ * b_ / wsum
         return tot
@@ -892,7 +909,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="abc_infer: also run the k2 sweep (8 targets)")
     ap.add_argument("--epochs", type=int, default=0,
                     help="abc_infer / coi_infer: replayed epochs (0: the protocol's; fewer for profiling)")
-    ap.add_argument("--bwd-mode", default="tape", choices=["tape", "recompute"])
+    ap.add_argument("--bwd-mode", default="auto", choices=["auto", "tape", "recompute", "tangent"],
+                    help="auto: forward-mode tangents for the dimer (few channels), the tape otherwise")
     ap.add_argument("--n-traj", type=int, default=65536)
     ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")
     ap.add_argument("--ckpt-every", type=int, default=0, help="checkpoint interval (0: the workload's)")

@@ -140,8 +140,22 @@ enum { SSA_OBS_POINT_MAJOR = 0, SSA_OBS_TRAJ_MAJOR = 1, SSA_OBS_ENSEMBLE_MEAN = 
  *   SSA_BWD_RECOMPUTE: nothing per step is stored; the backward re-runs each
  *                      segment forward from its checkpoint to recover the
  *                      choices, then sweeps it in reverse.
- *   SSA_BWD_AUTO:      the library picks. */
-enum { SSA_BWD_AUTO = 0, SSA_BWD_TAPE = 1, SSA_BWD_RECOMPUTE = 2 };
+ *   SSA_BWD_TANGENT:   forward-mode accumulation of the same straight-through
+ *                      derivative (Eqs. 3-7): ssa_forward carries dX/d ln k_q
+ *                      and dt/d ln k_q for every channel q along the path and
+ *                      writes d obs / d ln k_q into the "checkpoint" buffer
+ *                      ([point][obs][channel][B] per network, FP64, at
+ *                      n_obs * M * B values per point and network; no
+ *                      checkpoints or tape); ssa_backward contracts them with
+ *                      d_obs, with no reverse sweep.  For batches in the
+ *                      topology-specialised lane mode whose networks have at
+ *                      most 4 channels and N * M <= 32, the final or bin
+ *                      observation in the point-major layout with a
+ *                      per-trajectory d_obs, step-limited runs (t_end =
+ *                      INFINITY) and the Gumbel-max selection; otherwise
+ *                      SSA_ENOTSUP.  The temperature is read by the forward.
+ *   SSA_BWD_AUTO:      the library picks (tape). */
+enum { SSA_BWD_AUTO = 0, SSA_BWD_TAPE = 1, SSA_BWD_RECOMPUTE = 2, SSA_BWD_TANGENT = 3 };
 
 /* Host description of one or more networks (all pointers are HOST memory and
  * are copied by ssa_net_create).  Channel tables are packed network after

@@ -38,7 +38,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssa_mi355x", "a
 class Plan:
     exec_mode: str = "auto"       # "spec" | "lane" | "wave" | "auto"
     wave_split: int = -1          # wave mode: 1 one launch per width, 0 one launch
-    bwd_mode: str = "tape"        # "tape" | "recompute"
+    bwd_mode: str = "tape"        # "tape" | "recompute" | "tangent"
     ckpt_every: int = 256
 
     def net(self, nets, n_traj, t_obs=None) -> ssa.Net:
@@ -57,6 +57,8 @@ def candidate_plans(n_steps: int) -> List[Plan]:
             for k in ks:
                 out.append(Plan(mode, split, "tape", k))
             out.append(Plan(mode, split, "recompute", 64))
+    # forward-mode tangents (networks with few channels, specialised mode)
+    out.append(Plan("spec", -1, "tangent", ks[-1]))
     return out
 
 

@@ -90,8 +90,9 @@ struct ssa_net {
     std::vector<Group> groups;
     uint32_t *flags_d = nullptr;
     int64_t traj_total = 0, state_total = 0, param_total = 0, obsb_total = 0, part_total = 0,
-            ppt_total = 0, obsw_total = 0, tobs_total = 0, obst_total = 0, obstw_total = 0;
+            ppt_total = 0, obsw_total = 0, tobs_total = 0, obst_total = 0, obstw_total = 0, tanw_total = 0;
     int max_M = 0;
+    bool tangent_fit = false;   // every network runs in the specialised mode within the tangent limits
     int64_t max_B = 0;
     int device = 0;
     void *scratch = nullptr;     // this device's copy of the static scratch array
@@ -170,6 +171,13 @@ CkptLayout ckpt_layout(const ssa_net *net, const ssa_config *cfg)
 {
     CkptLayout L;
     if (!bounded_steps(cfg) || cfg->ckpt_every < 1) return L;
+    if (cfg->bwd_mode == SSA_BWD_TANGENT) {
+        // no checkpoints or tape: the tangents d obs / d ln k_q
+        const int64_t npts = cfg->obs_kind == SSA_OBS_BINS ? cfg->n_bins : 1;
+        L.bytes = align_up(sizeof(double) * (size_t)(net->tanw_total * npts), 256);
+        if (L.bytes == 0) L.bytes = 256;
+        return L;
+    }
     L.n_ckpt = (cfg->n_steps + cfg->ckpt_every - 1) / cfg->ckpt_every;
     if (resolve_bwd_mode(cfg) == SSA_BWD_TAPE) {
         L.tape_bits = bits_for(net->max_M);
@@ -303,7 +311,21 @@ ssa_status check_config(const ssa_net *net, const ssa_config *cfg)
         return fail(SSA_EINVAL, "temperature must be finite and > 0");
     if (cfg->ckpt_every < 1) return fail(SSA_EINVAL, "ckpt_every must be >= 1");
     const int mode = resolve_bwd_mode(cfg);
-    if (mode != SSA_BWD_TAPE && mode != SSA_BWD_RECOMPUTE) return fail(SSA_EINVAL, "unknown bwd_mode");
+    if (mode != SSA_BWD_TAPE && mode != SSA_BWD_RECOMPUTE && mode != SSA_BWD_TANGENT)
+        return fail(SSA_EINVAL, "unknown bwd_mode");
+    if (mode == SSA_BWD_TANGENT) {
+        if (!net->tangent_fit)
+            return fail(SSA_ENOTSUP, "forward-mode tangents need the topology-specialised lane mode and networks of "
+                                     "at most 4 channels and 32 species x channels");
+        if (cfg->obs_kind != SSA_OBS_FINAL && cfg->obs_kind != SSA_OBS_BINS)
+            return fail(SSA_ENOTSUP, "forward-mode tangents run with the final or bin observation");
+        if (cfg->obs_layout != SSA_OBS_POINT_MAJOR || cfg->dobs_shared)
+            return fail(SSA_ENOTSUP, "forward-mode tangents use the point-major layout with a per-trajectory d_obs");
+        if (cfg->t_end != INFINITY) return fail(SSA_ENOTSUP, "forward-mode tangents run step-limited paths (no t_end)");
+        if (cfg->selection != SSA_SELECT_GUMBEL_MAX)
+            return fail(SSA_ENOTSUP, "forward-mode tangents need the Gumbel-max selection");
+        if (!bounded_steps(cfg)) return fail(SSA_EINVAL, "forward-mode tangents need a bounded n_steps");
+    }
     if (mode == SSA_BWD_RECOMPUTE && cfg->ckpt_every > kMaxRecomputeSegment)
         return fail(SSA_EINVAL, "recompute mode needs ckpt_every <= 64");
     if (cfg->tie_capacity < 0) return fail(SSA_EINVAL, "tie_capacity must be >= 0");
@@ -534,6 +556,9 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         else if (all_lane_fit) mode = kLane;
         else return bail(SSA_ESHAPE, "no execution mode fits this batch (at most 64 species and 511 channels)");
     }
+    net->tangent_fit = mode == kSpec && max_M <= kTanMaxChannels;
+    for (int n = 0; n < nn && net->tangent_fit; ++n)
+        if ((int64_t)d->n_species[n] * d->n_reactions[n] > kTanMaxStateTangents) net->tangent_fit = false;
     if (mode == kSpec) {
         for (auto &kv : spec_kernels) {
             std::string log;
@@ -577,6 +602,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         nd.tobs_off = net->tobs_total;
         nd.obst_off = net->obst_total;
         nd.obstw_off = net->obstw_total;
+        nd.tanw_off = net->tanw_total;
         nd.part_off = net->part_total;
         nd.ppt_off = net->ppt_total;
         nd.t_obs = d->t_obs ? d->t_obs[n] : 0.0;
@@ -650,6 +676,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
         net->tobs_total += (int64_t)((B + 63) / 64) * nob;
         net->obst_total += (int64_t)(nob + 1) * B;
         net->obstw_total += nob + 1;
+        net->tanw_total += (int64_t)nob * M * B;
         net->part_total += (int64_t)M * B;
         net->ppt_total += (int64_t)P * B;
         net->max_M = std::max(net->max_M, M);
@@ -809,7 +836,9 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
     p.t_final = t_final;
     p.steps_done = steps_done;
     p.obs = obs;
-    if (ckpt) {
+    if (ckpt && cfg->bwd_mode == SSA_BWD_TANGENT) {
+        p.tangent = (double *)ckpt;
+    } else if (ckpt) {
         char *base = (char *)ckpt;
         p.ck_t = (double *)(base + L.off_t);
         p.ck_x = (int32_t *)(base + L.off_x);
@@ -868,6 +897,20 @@ static ssa_status backward_impl(const ssa_net *net, const ssa_config *cfg, const
     p.t_final = const_cast<double *>(t_final);
     p.steps_done = const_cast<int32_t *>(steps_done);
     p.d_obs = d_obs;
+    p.partials = (double *)((char *)work + kWorkHeader);
+    p.work_counter = (uint32_t *)((char *)work + 64);
+    double *chunk_sums = (double *)((char *)work + kWorkHeader + partials_bytes(net));
+    if (cfg->bwd_mode == SSA_BWD_TANGENT) {
+        // the forward's tangents contracted with dL/dobs: no reverse sweep
+        const int npts = cfg->obs_kind == SSA_OBS_BINS ? cfg->n_bins : 1;
+        hipError_t e = launch_tangent_contract(net->nets_d, net->n_networks, net->traj_total, npts, d_obs,
+                                               (const double *)ckpt, p.partials, stream);
+        if (e == hipSuccess)
+            e = launch_reduce_params(net->nets_d, net->pmap_off_d, net->pmap_ch_d, net->param_net_d, net->param_total,
+                                     net->max_B, p.partials, chunk_sums, d_params, d_params_per_traj, stream);
+        if (e != hipSuccess) return hip_fail(e, "tangent contraction");
+        return SSA_OK;
+    }
     const char *base = (const char *)ckpt;
     p.ck_t = (double *)(base + L.off_t);
     p.ck_x = (int32_t *)(base + L.off_x);
@@ -875,8 +918,6 @@ static ssa_status backward_impl(const ssa_net *net, const ssa_config *cfg, const
     p.n_ckpt = L.n_ckpt;
     p.tape_bits = L.tape_words ? L.tape_bits : 0;
     p.tape_words = L.tape_words;
-    p.partials = (double *)((char *)work + kWorkHeader);
-    p.work_counter = (uint32_t *)((char *)work + 64);
     if (prefix_work_bytes(net, cfg) > 0) {
         double *pre = (double *)((char *)work + grad_work_bytes(net) + mean_work_bytes(net, cfg));
         hipError_t e = launch_dobs_prefix(net->nets_d, net->n_networks, cfg->n_bins, d_obs, pre, stream);
@@ -885,7 +926,6 @@ static ssa_status backward_impl(const ssa_net *net, const ssa_config *cfg, const
     }
     s = launch_all_classes(net, p, true, stream);
     if (s != SSA_OK) return s;
-    double *chunk_sums = (double *)((char *)work + kWorkHeader + partials_bytes(net));
     hipError_t e = launch_reduce_params(net->nets_d, net->pmap_off_d, net->pmap_ch_d, net->param_net_d,
                                         net->param_total, net->max_B, p.partials, chunk_sums, d_params,
                                         d_params_per_traj, stream);

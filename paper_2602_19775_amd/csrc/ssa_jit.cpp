@@ -90,6 +90,10 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
          "(ssa::RunParams p) { ssa::spec::forward<Net, false, false, true>(p); }\n";
     s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_cdf"
          "(ssa::RunParams p) { ssa::spec::forward<Net, false, true>(p); }\n";
+    // the forward with forward-mode tangents (an empty kernel for a network
+    // with more channels than the tangents carry)
+    s << "extern \"C\" __global__ void __launch_bounds__(ssa::spec::kBlock) ssa_spec_fwd_tan"
+         "(ssa::RunParams p) { ssa::spec::forward_tangent<Net>(p); }\n";
     return s.str();
 }
 
@@ -144,7 +148,8 @@ bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
         hipModuleGetFunction(&k.fwd_tm, k.module, "ssa_spec_fwd_tm") != hipSuccess ||
         hipModuleGetFunction(&k.bwd_sh, k.module, "ssa_spec_bwd_sh") != hipSuccess ||
         hipModuleGetFunction(&k.fwd_ens, k.module, "ssa_spec_fwd_ens") != hipSuccess ||
-        hipModuleGetFunction(&k.fwd_grid_ens, k.module, "ssa_spec_fwd_grid_ens") != hipSuccess) {
+        hipModuleGetFunction(&k.fwd_grid_ens, k.module, "ssa_spec_fwd_grid_ens") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_tan, k.module, "ssa_spec_fwd_tan") != hipSuccess) {
         *log = "loading the compiled module failed";
         return false;
     }
@@ -162,7 +167,8 @@ hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, 
     void *args[] = {&copy};
     const bool grid = p.obs_kind == 2;
     hipFunction_t f = backward ? (grid ? k.bwd_grid : p.dobs_prefix ? k.bwd_sh : k.bwd)
-                               : (p.selection == 1 ? k.fwd_cdf
+                               : (p.tangent ? k.fwd_tan
+                                  : p.selection == 1 ? k.fwd_cdf
                                   : grid           ? (p.obs_ens ? k.fwd_grid_ens : k.fwd_grid)
                                   : p.obs_ens      ? k.fwd_ens
                                   : p.obs_tm && p.obs_kind == 1 ? k.fwd_tm

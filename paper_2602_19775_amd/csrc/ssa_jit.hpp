@@ -22,6 +22,7 @@ struct SpecKernels {
     hipFunction_t bwd_sh = nullptr;     // bin observation, shared dL/dobs (prefix sums)
     hipFunction_t fwd_ens = nullptr;    // bin observation, ensemble means only (LDS tile sums)
     hipFunction_t fwd_grid_ens = nullptr;   // grid observation, ensemble means only
+    hipFunction_t fwd_tan = nullptr;    // final and bin observations with forward-mode tangents
 };
 
 // Source of the specialised kernel pair for one network (host tables).

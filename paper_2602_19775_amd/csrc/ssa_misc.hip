@@ -338,6 +338,47 @@ hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_ma
     return hipGetLastError();
 }
 
+// Per-channel gradient partials of forward-mode tangents: for global
+// trajectory g of network n (found by bisection over traj_off),
+//   partials[part_off + q B + i] = sum over points pt and observed species o of
+//     d_obs[(obsb_off npts) + (pt n_obs + o) B + i] * tangent[(tanw_off npts) + ((pt n_obs + o) M + q) B + i]
+// in FP64, in (pt, o) order.
+__global__ __launch_bounds__(256) void tangent_contract_kernel(const NetDev *nets, int n_networks, int64_t traj_total,
+                                                               int npts, const double *d_obs, const double *tangent,
+                                                               double *partials)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= traj_total) return;
+    int lo = 0, hi = n_networks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (nets[mid].traj_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const NetDev nd = nets[lo];
+    const int64_t B = nd.B, i = g - nd.traj_off;
+    const double *dob = d_obs + nd.obsb_off * npts + i;
+    const double *tan = tangent + nd.tanw_off * npts + i;
+    for (int q = 0; q < nd.M; ++q) {
+        double acc = 0.0;
+        for (int pt = 0; pt < npts; ++pt)
+            for (int o = 0; o < nd.n_obs; ++o) {
+                const int64_t r = (int64_t)pt * nd.n_obs + o;
+                acc += dob[r * B] * tan[(r * nd.M + q) * B];
+            }
+        partials[nd.part_off + (int64_t)q * B + i] = acc;
+    }
+}
+
+hipError_t launch_tangent_contract(const NetDev *nets, int n_networks, int64_t traj_total, int npts,
+                                   const double *d_obs, const double *tangent, double *partials, hipStream_t stream)
+{
+    if (traj_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tangent_contract_kernel, dim3((unsigned)((traj_total + 255) / 256)), dim3(256), 0, stream, nets,
+                       n_networks, traj_total, npts, d_obs, tangent, partials);
+    return hipGetLastError();
+}
+
 hipError_t launch_dobs_prefix(const NetDev *nets, int n_networks, int n_bins, const double *d_obs, double *pre,
                               hipStream_t stream)
 {

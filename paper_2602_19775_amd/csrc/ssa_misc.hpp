@@ -28,6 +28,11 @@ hipError_t launch_obs_mean(const double *obs, int64_t B, int64_t W, bool traj_ma
 // (networks at obsw_off * n_bins in d_obs, at obsw_off * (n_bins + 1) in pre).
 hipError_t launch_dobs_prefix(const NetDev *nets, int n_networks, int n_bins, const double *d_obs, double *pre,
                               hipStream_t stream);
+// Per-channel FP64 gradient partials [M][B] per network from forward-mode
+// tangents ([point][obs][channel][B] at tanw_off * npts) and a per-trajectory
+// dL/dobs (point-major).
+hipError_t launch_tangent_contract(const NetDev *nets, int n_networks, int64_t traj_total, int npts,
+                                   const double *d_obs, const double *tangent, double *partials, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
 hipError_t launch_selftest_philox(const uint32_t *ck, uint32_t *out, int64_t n, hipStream_t stream);
 hipError_t launch_selftest_neglog(uint32_t first, int64_t count, float *out, hipStream_t stream);

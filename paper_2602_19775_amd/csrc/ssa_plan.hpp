@@ -58,6 +58,8 @@ struct NetDev {
                          // ensemble-mean forward, [tile][n_bins][n_obs] per network
     int64_t obst_off;    // sum of (n_obs + 1) * B: tail observations [n_obs + 1][B] per network
     int64_t obstw_off;   // sum of (n_obs + 1): their ensemble means
+    int64_t tanw_off;    // sum of n_obs * M * B: forward-mode tangents d obs / d ln k_q per
+                         // observation point, [point][obs][channel][B] per network
     double t_obs;
 };
 
@@ -94,6 +96,11 @@ constexpr double kClockTieLog = 1e-5;
 // dL/dobs enters the clock adjoint; a checker whose clock differs by less than
 // half this window can take the same side.
 constexpr double kEdgeLog = 4e-7;
+
+// Forward-mode tangents (SSA_BWD_TANGENT) carry dX/d ln k_q for every channel
+// rate q: networks with at most this many channels and species x channels.
+constexpr int kTanMaxChannels = 4;
+constexpr int kTanMaxStateTangents = 32;
 
 struct RunParams {
     const NetDev *nets;
@@ -147,6 +154,7 @@ struct RunParams {
     const double *dobs_prefix;   // bins, shared d_obs: [obs][n_bins + 1] prefix sums per network
     double *tile_sums;           // ensemble-mean forward: per-tile sums (NetDev::tobs_off)
     int32_t obs_ens;             // the forward writes ensemble means (tile sums) only
+    double *tangent;             // forward-mode tangents (SSA_BWD_TANGENT): forward out, backward in
 
     // wave mode: species -> range of incidence slots, and per channel the
     // slots of its (role 1, role 2) contributions: pos1 | pos2 << 16 with

@@ -643,6 +643,306 @@ __device__ void forward(const RunParams &p)
 }
 
 // --------------------------------------------------------------------------
+// Forward-mode tangents (SSA_BWD_TANGENT).  For a network with few channels
+// the forward carries, for every channel rate q, the tangents dX/d ln k_q and
+// dt/d ln k_q of the straight-through surrogate along the path it fires, and
+// writes d obs / d ln k_q; the gradient of any loss is then the contraction of
+// those with dL/dobs, and no reverse sweep, checkpoint or tape is needed.  The
+// surrogate is the one the backward differentiates (Eq. 5):
+//   X_{k+1} = X_k + sum_j v_j (y_j + y~_j - stopgrad(y~_j)),
+//   t_{k+1} = t_k + E_0 / a0(X_k),
+// so per step d y~_j = y~_j (dz_j - sum_i y~_i dz_i) with
+// dz_j = d ln a_j / T, d tau = -(tau / a0) d a0, and the bin averages move
+// with the state tangents inside each interval and with the clock tangents
+// at its ends.  Forward and reverse accumulation of one function's
+// derivative agree; the rounding differs.  Final and bin observations
+// (point-major), step-limited runs.
+template <class NET>
+constexpr bool tangent_fits()
+{
+    return NET::M <= kTanMaxChannels && NET::N * NET::M <= kTanMaxStateTangents;
+}
+
+template <class NET>
+__device__ void forward_tangent(const RunParams &p)
+{
+    if constexpr (tangent_fits<NET>()) {
+    constexpr int N = NET::N, M = NET::M, NOBS = NET::NOBS, NO = obs_cap(NET::NOBS);
+    const int wid = uniform_i((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int item_idx = blockIdx.x * kWaves + wid;
+    if (item_idx >= p.n_items) return;
+    const LaneItem it = p.items[item_idx];
+    const NetDev nd = p.nets[it.net];
+
+    float c[M];
+    rates<NET>(p, nd, c);
+
+    const bool valid = lane < it.count;
+    const int64_t B = nd.B;
+    const int64_t i = it.first + (valid ? lane : 0);
+    const int64_t g = nd.traj_off + i;
+    const uint32_t tid = p.traj_ids ? p.traj_ids[g] : (uint32_t)g;
+    const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
+    const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
+    const float T = run_temperature(p);
+    const float invT = 1.0f / T;
+
+    int X[N + 1];
+#pragma unroll
+    for (int s = 0; s < N; ++s) X[s] = p.x0[nd.state_off + s * B + i];
+    X[N] = 1;
+    // tangents: the initial state does not depend on the rates
+    double dX[N][M], dt[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        dt[q] = 0.0;
+#pragma unroll
+        for (int s = 0; s < N; ++s) dX[s][q] = 0.0;
+    }
+
+    const bool bins = p.obs_kind == 1 && NOBS > 0;
+    const int n_bins = p.n_bins;
+    const double t_obs = nd.t_obs;
+    int bin = bins ? 0 : n_bins;
+    double bin_hi = bins ? bin_edge(t_obs, 1, n_bins) : INFINITY;
+    double acc[NO], dacc[NO][M];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        acc[o] = 0.0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) dacc[o][q] = 0.0;
+    }
+    const int64_t npts = p.obs_kind != 0 ? n_bins : 1;
+    double *obs_lane = p.obs + nd.obsb_off * npts + i;
+    double *tan_lane = p.tangent + nd.tanw_off * npts + i;
+    const int64_t orow = (int64_t)NOBS * B;
+    const int64_t trow = (int64_t)NOBS * M * B;     // [point][obs][channel][B]
+    const double inv_dt = bins ? (double)n_bins / t_obs : 0.0;
+    const bool edge_log = bins && p.ties != nullptr;
+    double e_lo = -INFINITY, e_hi = edge_log ? bin_hi * (1.0 - kEdgeLog) : INFINITY;
+
+    double t = 0.0;
+    bool active = valid;
+    int n_done = 0;
+    uint32_t flags = 0u;
+
+    constexpr int NW = Blocks<NET>::W;
+    uint32_t wd[NW];
+    words<NET, NW>(0u, tid, pe, p.seed_lo, p.seed_hi, wd);
+    bool any = ballot(active) != 0ull;
+    int k = 0;
+    for (; any && k < p.n_steps; ++k) {
+        float a[M], A1[M], A2[M];
+        const float a0 = propensities<NET, true>(c, X, a, A1, A2);
+        const float tau = neglog_u(wd[0]) * fast_rcp(a0);
+        const double tn = t + (double)tau;
+        float r[M];
+        float r1 = INFINITY, r2 = INFINITY;
+        int j1 = 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            r[j] = neglog_u(wd[1 + j]) * fast_rcp(a[j]);
+            const bool lt = r[j] < r1;
+            r2 = lt ? r1 : fminf(r2, r[j]);
+            j1 = lt ? j : j1;
+            r1 = fminf(r1, r[j]);
+        }
+        uint32_t wn[NW];
+        words<NET, NW>((uint32_t)(k + 1), tid, pe, p.seed_lo, p.seed_hi, wn);
+
+        const bool fire = active && a0 > 0.f;
+        const bool in_bin = fire && tn <= bin_hi;
+        const bool near_tie = fire && r2 <= r1 * (1.f + kTieLog);
+        const bool crossing = fire && !in_bin && bin < n_bins;
+        const bool odd = active && !(a0 >= 0.f);
+        const bool stop = active && !fire;
+        const bool edgy = fire && (tn >= e_hi || tn <= e_lo);
+
+        // tangents of this step: d a_j / d ln k_q at X_k, the soft sample and
+        // its derivative, d tau
+        float dXf[N + 1][M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+#pragma unroll
+            for (int s = 0; s < N; ++s) dXf[s][q] = (float)dX[s][q];
+            dXf[N][q] = 0.f;
+        }
+        float y[M], ysum = 0.f;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const float rho = r[j] == r1 ? 1.0f : r1 * fast_rcp(r[j]);      // a_j = 0: r = inf, rho = 0
+            float w = rho;
+            if (T == 0.5f) w = rho * rho;
+            else if (T != 1.0f) w = rho > 0.f ? exp2f(log2f(rho) * invT) : 0.f;
+            y[j] = w;
+            ysum += w;
+        }
+        const float rys = fast_rcp(ysum);
+        const float rcp_a0 = fast_rcp(a0);
+        float dtau[M], dy[M][M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            // dy_j = y~_j sum_i y~_i (dz_j - dz_i), with the differences taken
+            // against the fired channel first: the fired channel's y~ is close
+            // to 1 at low T, and dz_j - sum_i y~_i dz_i would cancel
+            float da0 = 0.f;
+            float dz[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const float da = (j == q ? a[j] : 0.f) + A2[j] * dXf[NET::S1[j]][q] + A1[j] * dXf[NET::S2[j]][q];
+                da0 += da;
+                dz[j] = a[j] > 0.f ? da * fast_rcp(a[j]) * invT : 0.f;
+            }
+            float dzref = dz[0];
+#pragma unroll
+            for (int j = 1; j < M; ++j) dzref = j == j1 ? dz[j] : dzref;
+            float zbar = 0.f;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                dz[j] -= dzref;
+                zbar += y[j] * rys * dz[j];
+            }
+            dtau[q] = -tau * rcp_a0 * da0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) dy[j][q] = y[j] * rys * (dz[j] - zbar);
+        }
+
+        if (ballot(near_tie || crossing || odd || stop || edgy) != 0ull) {
+            if (ballot(stop) != 0ull) any = ballot(fire) != 0ull;
+            if (odd) flags |= kFlagNonFinite;
+            if (near_tie) {
+                int j2 = -1;
+                float best = INFINITY;
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j != j1 && r[j] < best) { best = r[j]; j2 = j; }
+                log_tie(p, (uint32_t)g, k, j1, j2, (r2 - r1) / r1, 0);
+            }
+            if (crossing) {
+                // the bins the interval completes: their averages and tangents
+                double t0 = t;
+                bool first = true;
+                while (bin < n_bins) {
+                    const double hi = bin_hi;
+                    if (tn <= hi) {
+#pragma unroll
+                        for (int o = 0; o < NO; ++o) {
+                            const double xo = (double)X[NET::OBS[o]];
+                            acc[o] += xo * (tn - t0);
+#pragma unroll
+                            for (int q = 0; q < M; ++q)
+                                dacc[o][q] += (double)dXf[NET::OBS[o]][q] * (tn - t0) +
+                                              xo * (first ? (double)dtau[q] : dt[q] + (double)dtau[q]);
+                        }
+                        break;
+                    }
+                    const double seg = fmax(hi - t0, 0.0);
+#pragma unroll
+                    for (int o = 0; o < NO; ++o) {
+                        const double xo = (double)X[NET::OBS[o]];
+                        acc[o] += xo * seg;
+                        if (o < NOBS) obs_lane[bin * orow + o * B] = acc[o] * inv_dt;
+                        acc[o] = 0.0;
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            dacc[o][q] += (double)dXf[NET::OBS[o]][q] * seg - (first && seg > 0.0 ? xo * dt[q] : 0.0);
+                            if (o < NOBS) tan_lane[bin * trow + (o * M + q) * B] = dacc[o][q] * inv_dt;
+                            dacc[o][q] = 0.0;
+                        }
+                    }
+                    first = false;
+                    t0 = fmax(t0, hi);
+                    bin += 1;
+                    bin_hi = bin < n_bins ? bin_edge(t_obs, bin + 1, n_bins) : INFINITY;
+                }
+            }
+            if (edge_log && edgy) {
+                const int bl = bin < n_bins ? bin : n_bins;
+                const double lo = bl >= 1 ? bin_edge(t_obs, bl, n_bins) : -INFINITY;
+                const double hi = bl < n_bins ? bin_edge(t_obs, bl + 1, n_bins) : INFINITY;
+                int ei = -1;
+                double e = 0.0;
+                if (bl >= 1 && fabs(tn - lo) <= kEdgeLog * lo) { ei = bl; e = lo; }
+                else if (bl < n_bins && fabs(tn - hi) <= kEdgeLog * hi) { ei = bl + 1; e = hi; }
+                if (ei >= 1) log_tie(p, (uint32_t)g, k, tn >= e ? 1 : 0, ei, (float)((tn - e) / e), 2);
+                e_lo = bl >= 1 ? lo * (1.0 + kEdgeLog) : -INFINITY;
+                e_hi = bl < n_bins ? hi * (1.0 - kEdgeLog) : INFINITY;
+            }
+        }
+        if (in_bin) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                const double xo = (double)X[NET::OBS[o]];
+                acc[o] += xo * (double)tau;
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+                    dacc[o][q] += (double)(dXf[NET::OBS[o]][q] * tau) + xo * (double)dtau[q];
+            }
+        }
+        if (fire) {
+#pragma unroll
+            for (int s = 0; s < N; ++s)
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    float dv = 0.f;
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        if (NET::V[j][s] != 0) dv += (float)NET::V[j][s] * dy[j][q];
+                    dX[s][q] += (double)dv;
+                }
+#pragma unroll
+            for (int q = 0; q < M; ++q) dt[q] += (double)dtau[q];
+        }
+        apply<NET>(X, fire ? j1 : -1, +1);
+        t = fire ? tn : t;
+        n_done += fire ? 1 : 0;
+        active = fire;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) wd[q] = wn[q];
+    }
+    if (!valid) return;
+    if (bin < n_bins) {
+        // hold the last state up to t_obs: the rest of the current bin, then
+        // every later bin, whose average is the last state itself
+        const double seg = fmax(fmin(bin_hi, t_obs) - t, 0.0);
+#pragma unroll
+        for (int o = 0; o < NOBS; ++o) {
+            const double xo = (double)X[NET::OBS[o]];
+            obs_lane[bin * orow + o * B] = (acc[o] + xo * seg) * inv_dt;
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+                tan_lane[bin * trow + (o * M + q) * B] =
+                    (dacc[o][q] + dX[NET::OBS[o]][q] * seg - (seg > 0.0 ? xo * dt[q] : 0.0)) * inv_dt;
+        }
+        for (int bb = n_bins - 1; bb > bin; --bb)
+#pragma unroll
+            for (int o = 0; o < NOBS; ++o) {
+                obs_lane[bb * orow + o * B] = (double)X[NET::OBS[o]];
+#pragma unroll
+                for (int q = 0; q < M; ++q) tan_lane[bb * trow + (o * M + q) * B] = dX[NET::OBS[o]][q];
+            }
+    }
+    if (p.obs_kind == 0) {
+#pragma unroll
+        for (int o = 0; o < NOBS; ++o) {
+            obs_lane[o * B] = (double)X[NET::OBS[o]];
+#pragma unroll
+            for (int q = 0; q < M; ++q) tan_lane[(o * M + q) * B] = dX[NET::OBS[o]][q];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        p.x_final[nd.state_off + s * B + i] = X[s];
+        if (X[s] < 0) flags |= kFlagOverflow;
+    }
+    p.t_final[g] = t;
+    p.steps_done[g] = n_done;
+    if (flags) atomicOr(p.flags, flags);
+    }
+}
+
+// --------------------------------------------------------------------------
 // TMODE: 2 -> T = 1/2 (y~ ~ rho^2), 1 -> T = 1 (y~ ~ rho), 0 -> y~ ~ rho^(1/T).
 // RECOMPUTE: the choices of a segment come from re-running it into LDS
 // instead of the tape.

@@ -21,8 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libssa.so")
 
 SSA_OK = 0
-BWD_AUTO, BWD_TAPE, BWD_RECOMPUTE = 0, 1, 2
-_BWD = {"auto": BWD_AUTO, "tape": BWD_TAPE, "recompute": BWD_RECOMPUTE}
+BWD_AUTO, BWD_TAPE, BWD_RECOMPUTE, BWD_TANGENT = 0, 1, 2, 3
+_BWD = {"auto": BWD_AUTO, "tape": BWD_TAPE, "recompute": BWD_RECOMPUTE, "tangent": BWD_TANGENT}
 
 _lib = None
 
