@@ -630,8 +630,9 @@ def bench_selection(args, torch, dev):
         n_rep = args.steps if name == "dimer" else max(1, args.steps // 5)
         for label, sel in (("inverse_cdf", W.SELECT_INVERSE_CDF), ("gumbel_max", W.SELECT_GUMBEL_MAX)):
             c = cfg.replace(selection=sel)
-            b = ssa.forward(h, c, th, x0, keep_ckpt=False, tie_capacity=1 << 20)
-            dt = timed(lambda: ssa.forward(h, c, th, x0, keep_ckpt=False, tie_capacity=1 << 20, buffers=b), n_rep)
+            # the oscillator's 256 bins log about 1.2e6 bin-edge events besides its near-ties
+            b = ssa.forward(h, c, th, x0, keep_ckpt=False, tie_capacity=1 << 22)
+            dt = timed(lambda: ssa.forward(h, c, th, x0, keep_ckpt=False, tie_capacity=1 << 22, buffers=b), n_rep)
             fired = int(b.steps_done.sum().item())
             row[label + "_forward_steps_per_s"] = fired / dt
             if sel == W.SELECT_INVERSE_CDF:
@@ -680,9 +681,12 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
             theta_t = torch.tensor(wl.extra["target_net"].theta0, device=dev)
     else:
         bw = W.uneven_batch(n_steps=args.n_steps or 5000)
-        cfg = bw.cfg.replace(ckpt_every=args.ckpt_every or bw.cfg.ckpt_every)
+        # cfg.t_obs is the first network's window (the oracle's sample is drawn
+        # from it); every network observes its own window
+        cfg = bw.cfg.replace(ckpt_every=args.ckpt_every or bw.cfg.ckpt_every,
+                             t_obs=bw.t_obs[0] if bw.t_obs else 0.0)
         nets, Bs, name = bw.nets, bw.n_traj, bw.name
-        h = ssa.Net(nets, Bs)
+        h = ssa.Net(nets, Bs, t_obs=bw.t_obs)
         theta = torch.tensor(bw.theta(), device=dev)
         x0 = torch.tensor(bw.x0_packed(), device=dev)
         theta_t = torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device=dev)
@@ -692,7 +696,8 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
         bwd_mode = "tangent" if workload == "dimer" else "tape"
     if args.autotune and not light:
         from paper_2602_19775_amd import autotune
-        t_obs_l = [cfg.t_obs] * len(nets) if cfg.obs_kind == W.OBS_BINS else None
+        t_obs_l = (bw.t_obs if workload == "uneven" else [cfg.t_obs] * len(nets)) \
+            if cfg.obs_kind == W.OBS_BINS else None
         plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l)
         h = plan.net(nets, Bs, t_obs_l)
         cfg = plan.config(cfg)
@@ -715,8 +720,9 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
         def loss_fn(obs):
             return losses.autocorrelation_mse(obs, tac, nb, B, 64)
     else:
-        # final counts, [sum n_obs][256]: ensemble mean of every observed species
-        rows = sum(len(n.obs_species) for n in nets)
+        # per network [n_bins][n_obs][256] (or [n_obs][256] for final counts):
+        # the ensemble mean of every observed species in every bin
+        rows = sum(len(n.obs_species) for n in nets) * (nb if cfg.obs_kind == W.OBS_BINS else 1)
         tmean = tf.obs[: rows * B].view(rows, B).mean(dim=1).clone()
 
         def loss_fn(obs):

@@ -15,6 +15,7 @@ Rate constants are parameterised as theta = ln k (Sec. 4.1).
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+import os
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -376,6 +377,7 @@ class BatchWorkload:
     n_traj: List[int]
     cfg: RunConfig
     target_nets: List[Network] = None
+    t_obs: List[float] = None         # per-network observation windows (bins)
 
     def theta(self) -> np.ndarray:
         return np.concatenate([n.theta0 for n in self.nets]).astype(np.float32)
@@ -385,13 +387,30 @@ class BatchWorkload:
                                for n, b in zip(self.nets, self.n_traj)]).astype(np.int32)
 
 
+# Observation windows of the uneven batch (seed 0, in network order), written by
+# tests/golden/uneven_pilot.py from an FP64 oracle pilot run.
+UNEVEN_T_OBS_FILE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                                 "uneven_t_obs.txt")
+
+
+def uneven_t_obs(n_networks: int) -> List[float]:
+    with open(UNEVEN_T_OBS_FILE) as f:
+        vals = [float(line) for line in f if line.strip() and not line.startswith("#")]
+    if n_networks > len(vals):
+        raise ValueError(f"the pilot file holds {len(vals)} networks")
+    return vals[:n_networks]
+
+
 def uneven_batch(n_networks: int = 4096, traj_per_network: int = 256, n_steps: int = 5000,
-                 seed: int = 0) -> BatchWorkload:
+                 seed: int = 0, obs_kind: int = OBS_BINS, n_bins: int = 4) -> BatchWorkload:
     """4,096 random mass-action networks (4-64 species, 8-256 channels, orders
     0-2, change vectors in {-2..2}, log-uniform rates in [1e-3, 1e2], Poisson(50)
-    initial counts), 256 trajectories each, 5,000 steps, final counts of up to 4
-    species observed, temperature 0.5, checkpoints every 256 steps.  Targets use
-    the same networks with every rate scaled by a seeded factor in [0.5, 2]."""
+    initial counts), 256 trajectories each, 5,000 steps, temperature 0.5,
+    checkpoints every 256 steps.  Observation: exact averages of up to 4
+    observed species over 4 bins of each network's own window t_obs (0.9 x the
+    smallest clock after 5,000 steps in an oracle pilot, seed 0), or their
+    final counts.  Targets use the same networks with every rate scaled by a
+    seeded factor in [0.5, 2]."""
     nets = random_network_batch(n_networks, seed=seed)
     g = np.random.default_rng(np.random.SeedSequence([seed, 4]))
     targets = []
@@ -400,9 +419,18 @@ def uneven_batch(n_networks: int = 4096, traj_per_network: int = 256, n_steps: i
                     (n.theta0 + np.log(g.uniform(0.5, 2.0, size=n.n_params))).astype(np.float32),
                     n.x0, n.obs_species, n.param_names)
         targets.append(t)
-    cfg = RunConfig(seed=seed, n_steps=n_steps, obs_kind=OBS_FINAL, temperature=0.5, ckpt_every=256)
-    return BatchWorkload(f"uneven_{n_networks}nets_{traj_per_network}traj_{n_steps}steps", nets,
-                         [traj_per_network] * n_networks, cfg, targets)
+    t_obs = None
+    if obs_kind == OBS_BINS:
+        if seed != 0:
+            raise ValueError("the pilot windows cover the seed-0 batch")
+        t_obs = uneven_t_obs(n_networks)
+        cfg = RunConfig(seed=seed, n_steps=n_steps, obs_kind=OBS_BINS, n_bins=n_bins, temperature=0.5,
+                        ckpt_every=256)
+    else:
+        cfg = RunConfig(seed=seed, n_steps=n_steps, obs_kind=OBS_FINAL, temperature=0.5, ckpt_every=256)
+    kind = f"{n_bins}bins" if obs_kind == OBS_BINS else "final"
+    return BatchWorkload(f"uneven_{n_networks}nets_{traj_per_network}traj_{n_steps}steps_{kind}", nets,
+                         [traj_per_network] * n_networks, cfg, targets, t_obs)
 
 
 # --------------------------------------------------------------------------

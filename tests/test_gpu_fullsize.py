@@ -142,12 +142,18 @@ def test_oscillator_65536x200000_final_counts(ssa):
 
 
 def test_uneven_batch_4096x256x5000(ssa):
+    """The uneven batch as benchmarked: 4 bins over each network's own window,
+    the loss of ensemble means per network, species and bin.  Wave mode keeps
+    no bin-edge log, so a sampled trajectory's gradient is compared when its
+    event times stay clear of the edges (edge_safe); at least 3 of its 4 in
+    every sampled network."""
     bw = W.uneven_batch()
     nets, Bs, cfg = bw.nets, bw.n_traj, bw.cfg
-    h = ssa.Net(nets, Bs)
+    nb = cfg.n_bins
+    h = ssa.Net(nets, Bs, t_obs=bw.t_obs)
     th = torch.tensor(bw.theta(), device="cuda")
     x0 = torch.tensor(bw.x0_packed(), device="cuda")
-    rows = sum(len(n.obs_species) for n in nets)
+    rows = sum(len(n.obs_species) for n in nets) * nb
     Bn = Bs[0]
     tf = ssa.forward(h, cfg.replace(purpose=W.PURPOSE_TARGET),
                      torch.tensor(np.concatenate([n.theta0 for n in bw.target_nets]), device="cuda"), x0,
@@ -168,21 +174,25 @@ def test_uneven_batch_4096x256x5000(ssa):
     picks = np.unique(np.concatenate([[0, len(nets) - 1], g.choice(len(nets), 14, replace=False)]))
     for n in picks:
         net = nets[n]
-        L = h.layout(int(n), cfg.obs_kind, cfg.n_bins)
+        ncfg = cfg.replace(t_obs=bw.t_obs[n])
+        L = h.layout(int(n), cfg.obs_kind, nb)
         nob, N, P = len(net.obs_species), net.n_species, net.n_params
         ids = np.array([0, 1, 129, Bn - 1])
         index = {int(L.traj_offset + q): k for k, q in enumerate(ids)}
         ov = [(index[int(t["traj"])], int(t["step"]), int(t["kind"]), int(t["chosen"]))
               for t in ties if int(t["traj"]) in index]
-        dn = dob[L.obs_offset: L.obs_offset + nob * Bn].reshape(nob, Bn).T[ids]
-        r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=L.traj_offset + ids, ties=ov, d_obs=dn, kappa=True)
+        blk = lambda a: a[L.obs_offset: L.obs_offset + nb * nob * Bn].reshape(nb, nob, Bn).transpose(2, 0, 1)
+        r = oracle.run(net, ncfg, net.theta0, net.x0, traj_ids=L.traj_offset + ids, ties=ov, d_obs=blk(dob)[ids],
+                       kappa=True)
         gpu = {"x_final": xf[L.state_offset: L.state_offset + N * Bn].reshape(N, Bn).T,
                "t_final": tfin[L.traj_offset: L.traj_offset + Bn],
                "steps_done": sd[L.traj_offset: L.traj_offset + Bn],
-               "obs": ob[L.obs_offset: L.obs_offset + nob * Bn].reshape(nob, Bn).T}
-        assert_forward_parity(gpu, r, ids, cfg)
+               "obs": blk(ob)}
+        assert_forward_parity(gpu, r, ids, ncfg)
+        keep = edge_safe(gpu, r, ids)
+        assert keep.sum() >= 3, (n, keep)
         gq = pp[L.ppt_offset: L.ppt_offset + P * Bn].reshape(P, Bn).T
-        assert_grad_parity(gq[ids], r.grad, kappa=r.kappa, T=cfg.temperature)
+        assert_grad_parity(gq[ids], r.grad, keep, kappa=r.kappa, T=cfg.temperature)
         tot = gq.astype(np.float64).sum(0)
         mag = np.abs(gq.astype(np.float64)).sum(0)
         dpn = dp.cpu().numpy()[L.param_offset: L.param_offset + P]

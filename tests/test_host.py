@@ -104,3 +104,13 @@ def test_start_point_rate_loss_gradient_written_out():
     ref.sum().backward()
     assert torch.allclose(loss, ref.detach(), rtol=1e-14, atol=0)
     assert torch.allclose(d, o.grad, rtol=1e-12, atol=1e-15)
+
+
+def test_uneven_windows_file():
+    """The uneven batch's per-network observation windows (written by the oracle
+    pilot script): one positive finite value per network, in network order."""
+    from paper_2602_19775_amd import workloads as W
+    t = np.asarray(W.uneven_t_obs(4096))
+    assert t.shape == (4096,) and np.all(np.isfinite(t)) and np.all(t > 0)
+    b = W.uneven_batch(16)
+    assert b.cfg.obs_kind == W.OBS_BINS and b.cfg.n_bins == 4 and b.t_obs == list(t[:16])
