@@ -20,6 +20,7 @@ gradient reduction).  `value` counts fired reactions per second of that step;
 the inputs are resident in HBM before timing starts.  Prints one JSON line.
 """
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -694,11 +695,14 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
     bwd_mode = args.bwd_mode
     if bwd_mode == "auto":
         bwd_mode = "tangent" if workload == "dimer" else "tape"
-    if args.autotune and not light:
+    autotune_on = args.autotune if args.autotune is not None else workload == "uneven"
+    if autotune_on and not light:
         from paper_2602_19775_amd import autotune
         t_obs_l = (bw.t_obs if workload == "uneven" else [cfg.t_obs] * len(nets)) \
             if cfg.obs_kind == W.OBS_BINS else None
-        plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l)
+        tune_log = []
+        plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l, log=tune_log.append)
+        print("\n".join(["autotune:"] + (tune_log or ["cached plan " + plan.name])), file=sys.stderr, flush=True)
         h = plan.net(nets, Bs, t_obs_l)
         cfg = plan.config(cfg)
         bwd_mode = plan.bwd_mode
@@ -888,7 +892,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
         "config": {"workload": name, "n_traj": int(sum(Bs)), "n_networks": len(nets), "steps_per_traj": cfg.n_steps, "n_bins": nb,
                    "t_obs": cfg.t_obs, "temperature": cfg.temperature, "ckpt_every": cfg.ckpt_every,
                    "bwd_mode": bwd_mode,
-                   "plan": None if plan is None else {"exec_mode": plan.exec_mode, "wave_split": plan.wave_split}},
+                   "plan": None if plan is None else dataclasses.asdict(plan)},
         "forward_steps_per_s": fwd_rate, "graph_replay": graph, "fwdbwd_over_forward": value / fwd_rate,
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
         "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
@@ -920,8 +924,9 @@ def main():
     ap.add_argument("--n-traj", type=int, default=65536)
     ap.add_argument("--n-steps", type=int, default=0, help="steps per trajectory (0: the workload's)")
     ap.add_argument("--ckpt-every", type=int, default=0, help="checkpoint interval (0: the workload's)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick the execution plan with the autotuner (untimed; cached under ~/.cache)")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=None,
+                    help="pick the execution plan with the autotuner (untimed; cached under ~/.cache); "
+                         "default: on for the uneven batch, off otherwise")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",

@@ -184,6 +184,15 @@ typedef struct ssa_network_desc {
     int32_t exec_mode;             /* SSA_EXEC_*: how trajectories map onto lanes */
     int32_t wave_split;            /* wave mode: -1 library's choice, 0 one persistent launch
                                       for the whole batch, 1 one launch per lane-group width */
+    int32_t wave_lanes;            /* wave mode: width cap, 8, 16, 32 or 64 lanes per trajectory
+                                      (0: 64, the library's choice).  A network goes to the
+                                      narrowest group of at most wave_lanes lanes in which each
+                                      lane draws one Philox block (four channel words); one that
+                                      needs more blocks runs on wave_lanes lanes drawing two
+                                      blocks each; one that needs more than 2 wave_lanes blocks
+                                      keeps the library's width.  Other values: SSA_EINVAL.  The
+                                      fired channels do not depend on the width; clocks and
+                                      gradients differ by the rounding order of group sums. */
 } ssa_network_desc;
 
 /* Execution modes.
@@ -194,8 +203,9 @@ typedef struct ssa_network_desc {
  *   SSA_EXEC_LANE: one trajectory per lane, generic kernels reading the tables
  *                  (up to 16 species and 32 channels).
  *   SSA_EXEC_WAVE: one trajectory per group of 8-64 lanes sharing its channels
- *                  (up to 64 species and 511 channels); persistent launches
- *                  pulling trajectories from a work counter in cost order.
+ *                  (up to 64 species and 511 channels; the group width is
+ *                  set by wave_lanes); persistent launches pulling
+ *                  trajectories from a work counter in cost order.
  *   SSA_EXEC_AUTO: the library picks (SPEC, else LANE for small batches, else WAVE). */
 enum { SSA_EXEC_AUTO = 0, SSA_EXEC_SPEC = 1, SSA_EXEC_LANE = 2, SSA_EXEC_WAVE = 3 };
 
@@ -280,7 +290,10 @@ ssa_status ssa_net_layout(const ssa_net *net, int32_t obs_kind, int32_t n_bins, 
 ssa_status ssa_buffer_sizes(const ssa_net *net, const ssa_config *cfg, size_t *ckpt_bytes,
                             size_t *work_bytes);
 
-/* Forward simulation of every trajectory.
+/* Forward simulation of every trajectory: the direct method of Sec. 2 with the
+ * channel chosen by Gumbel-max (Sec. 3.2) or by the inverse CDF
+ * (cfg->selection), the hard update of Eq. 6, and the path observed as
+ * Sec. 4.1-4.4 describe.
  *   theta [sum P_n] (ln k, float), x0 (int32 state layout);
  *   out: x_final, t_final, steps_done, obs (may be NULL if n_obs = 0);
  *   ckpt: may be NULL (then no backward is possible);
@@ -295,7 +308,9 @@ ssa_status ssa_forward(const ssa_net *net, const ssa_config *cfg, const float *t
                        ssa_tie *ties, uint32_t *n_ties, void *work, size_t work_bytes,
                        hipStream_t stream);
 
-/* Straight-through backward.  Inputs are the forward's inputs and outputs
+/* Straight-through backward (Sec. 3.1, Sec. 3.3-3.4, Eqs. 3-7, Fig. 1): the
+ * hard path of the forward with the gradient of the Gumbel-Softmax sample of
+ * Eq. 3 at temperature cfg->temperature.  Inputs are the forward's inputs and outputs
  * (same cfg, theta, x0) and d_obs = dL/dobs (double, obs layout; with
  * cfg->dobs_shared, one block of W_n values per network at its mean_offset,
  * used for every trajectory of the network).
@@ -326,8 +341,9 @@ ssa_status ssa_backward_static(const ssa_net *net, const ssa_config *cfg, const 
                                const double *d_obs, float *d_params, float *d_params_per_traj,
                                hipStream_t stream);
 
-/* One direct-method step (step index `step`) for every trajectory, for
- * step-wise inspection.  x (state layout) and t [sum B_n] are updated in
+/* One direct-method step (Sec. 2; the selection of Sec. 3.2 and the update of
+ * Eq. 6, as in ssa_forward) with step index `step` for every trajectory, for step-wise
+ * inspection.  x (state layout) and t [sum B_n] are updated in
  * place for trajectories that fire.  chosen [sum B_n]: fired channel, -1 if
  * a0 = 0, -2 if the step would pass t_end.  tau [sum B_n] float.
  * a: optional [sum M_n*B_n] propensities (block [M_n][B_n]). */

@@ -4,7 +4,9 @@ A plan is what `ssa.Net` and the run settings leave open:
 
 - the execution mode: one trajectory per lane with topology-specialised
   kernels, one per lane with generic kernels, or one per group of lanes;
-- for the lane-group mode, one persistent launch or one launch per width;
+- for the lane-group mode, one persistent launch or one launch per width, and
+  the widest group (lanes per trajectory; a network too large for one Philox
+  block per lane of a narrower group draws two per lane);
 - how the backward recovers the fired channels (choice tape or recompute);
 - the checkpoint interval K.
 
@@ -40,9 +42,16 @@ class Plan:
     wave_split: int = -1          # wave mode: 1 one launch per width, 0 one launch
     bwd_mode: str = "tape"        # "tape" | "recompute" | "tangent"
     ckpt_every: int = 256
+    wave_lanes: int = 0           # wave mode: widest lane group (0: 64)
+
+    @property
+    def name(self) -> str:
+        w = f"/w{self.wave_lanes}" if self.wave_lanes else ""
+        return f"{self.exec_mode}/split{self.wave_split}{w}/{self.bwd_mode}/K{self.ckpt_every}"
 
     def net(self, nets, n_traj, t_obs=None) -> ssa.Net:
-        return ssa.Net(nets, n_traj, t_obs=t_obs, exec_mode=self.exec_mode, wave_split=self.wave_split)
+        return ssa.Net(nets, n_traj, t_obs=t_obs, exec_mode=self.exec_mode, wave_split=self.wave_split,
+                       wave_lanes=self.wave_lanes)
 
     def config(self, cfg: W.RunConfig) -> W.RunConfig:
         return cfg.replace(ckpt_every=self.ckpt_every)
@@ -57,6 +66,12 @@ def candidate_plans(n_steps: int) -> List[Plan]:
             for k in ks:
                 out.append(Plan(mode, split, "tape", k))
             out.append(Plan(mode, split, "recompute", 64))
+    # narrower lane groups: more trajectories per wavefront, two Philox blocks
+    # per lane for the networks that need them
+    kw = 256 if 256 in ks else ks[-1]
+    for lanes in (32, 16):
+        for split in (1, 0):
+            out.append(Plan("wave", split, "tape", kw, lanes))
     # forward-mode tangents (networks with few channels, specialised mode)
     out.append(Plan("spec", -1, "tangent", ks[-1]))
     return out
@@ -138,7 +153,7 @@ def tune(nets: Sequence[W.Network], n_traj: Sequence[int], cfg: W.RunConfig, the
     timings = {}
     best, best_ms = None, math.inf
     for plan in (plans if plans is not None else candidate_plans(int(min(cfg.n_steps, 2 ** 31 - 1)))):
-        name = f"{plan.exec_mode}/split{plan.wave_split}/{plan.bwd_mode}/K{plan.ckpt_every}"
+        name = plan.name
         try:
             ms = _time_plan(plan, nets, n_traj, probe, theta, x0, t_obs, d_obs_fn, repeats)
         except ssa.SSAError as e:                # the library cannot run this plan for the batch

@@ -140,12 +140,15 @@ struct CkptLayout {
     size_t off_t = 0, off_x = 0, off_tape = 0, bytes = 0;
 };
 
+// Tape bits per step: enough for channel indices 0..M-1 (the wave mode runs
+// networks of up to 511 channels).
 int bits_for(int M)
 {
     if (M <= 2) return 1;
     if (M <= 4) return 2;
     if (M <= 16) return 4;
-    return 8;
+    if (M <= 256) return 8;
+    return 16;
 }
 
 int resolve_bwd_mode(const ssa_config *cfg)
@@ -543,7 +546,10 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
             ooff += nob;
         }
     }
-    const bool wave_fit = max_N <= kWaveMaxSpecies && wave_class_for(max_M) >= 0;
+    const int wave_lanes = d->wave_lanes == 0 ? 64 : d->wave_lanes;
+    if (wave_lanes != 8 && wave_lanes != 16 && wave_lanes != 32 && wave_lanes != 64)
+        return bail(SSA_EINVAL, "wave_lanes must be 0, 8, 16, 32 or 64");
+    const bool wave_fit = max_N <= kWaveMaxSpecies && wave_class_for(max_M, wave_lanes) >= 0;
     if (d->exec_mode < SSA_EXEC_AUTO || d->exec_mode > SSA_EXEC_WAVE) return bail(SSA_EINVAL, "unknown exec_mode");
     int mode = d->exec_mode;
     if (mode == kSpec && !all_spec_fit) return bail(SSA_ESHAPE, "specialised lane mode does not fit this batch");
@@ -565,7 +571,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
             if (!spec_compile(kv.first, &kv.second, &log)) return bail(SSA_EHIP, log);
         }
     }
-    const int wave_cls = mode == kWave ? wave_class_for(max_M) : -1;
+    const int wave_cls = mode == kWave ? wave_class_for(max_M, wave_lanes) : -1;
     // wave mode: one persistent launch for the whole batch, or one per
     // lane-group width with each network in the narrowest group that fits it
     // (the library's choice: one launch per width, which keeps lanes busy)
@@ -654,7 +660,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
             param_net.push_back(n);
         }
         if (mode == kWave) {
-            const int wc = wave_split ? wave_class_for(M) : wave_cls;
+            const int wc = wave_split ? wave_class_for(M, wave_lanes) : wave_cls;
             for (int i = 0; i < B; ++i) {
                 LaneItem it;
                 it.net = n; it.first = i; it.count = 1; it.pad = M;

@@ -48,6 +48,19 @@ struct Philox {
     }
 };
 
+// Index of workgroup b of n such that workgroups on one XCD get consecutive
+// indices.  The dispatcher deals workgroups to the 8 XCDs in turn, so b,
+// b + 8, b + 16, ... share an XCD and its L2; they map to one run of
+// consecutive indices (the first n mod 8 XCDs take one more than the
+// others).  A bijection of [0, n): neighbouring trajectories of a
+// trajectory-minor array then share cache lines within one L2.
+__device__ __forceinline__ int64_t xcd_local_index(int64_t b, int64_t n)
+{
+    constexpr int64_t kXcd = 8;
+    const int64_t base = n / kXcd, rem = n % kXcd, x = b % kXcd;
+    return x * base + (x < rem ? x : rem) + b / kXcd;
+}
+
 // Lattice uniform u = (2*(x>>9)+1) * 2^-24, exact in FP32 and strictly inside (0,1).
 __device__ __forceinline__ float lattice_u(uint32_t x)
 {

@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(RunParams p)
 // --------------------------------------------------------------------------
 // waves per SIMD the backward's registers are held to
 template <int L, int BPL>
-constexpr int bwd_waves() { return BPL == 1 && L == 64 ? 3 : 2; }
+constexpr int bwd_waves() { return BPL == 1 && L == 64 ? 3 : BPL == 2 && L < 64 ? 1 : 2; }
 
 // TMODE: 0 for 1/T = 2, 1 for 1/T = 1, 2 for any other temperature
 template <int L, int BPL, int TMODE>
@@ -474,7 +474,7 @@ void bwd_kernel(RunParams p)
     __shared__ float s_lam32[kWaves][G][kMaxN];      // FP32 view of lambda (base + increments)
     __shared__ float s_inc[kWaves][G][2 * MMAX + 1];  // per-channel contributions to dlambda[s1], dlambda[s2],
                                                       // in incidence-slot order, + a sink slot
-    __shared__ uint8_t s_tape[kWaves][G][KREC];
+    __shared__ uint16_t s_tape[kWaves][G][KREC];       // channel indices reach 510
     extern __shared__ int32_t s_dyn[];
     const int wid = uniform_i((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -482,7 +482,7 @@ void bwd_kernel(RunParams p)
     int *sx = s_x[wid][grp];
     float *slam = s_lam32[wid][grp];
     float *sinc = s_inc[wid][grp];
-    uint8_t *stape = s_tape[wid][grp];
+    uint16_t *stape = s_tape[wid][grp];
     GroupTab tab(s_dyn + (wid * G + grp) * p.tab_words, p);
     const uint32_t epoch = p.d_epoch ? *p.d_epoch : p.epoch;
     const uint32_t pe = (p.purpose << 24) | (epoch & 0xFFFFFFu);
@@ -618,7 +618,7 @@ void bwd_kernel(RunParams p)
                         r1 = fminf(r1, rq);
                     }
                     grace<L>(r1, j1, r2);
-                    if (on_k && gl == 0) stape[k - k_lo] = (uint8_t)j1;
+                    if (on_k && gl == 0) stape[k - k_lo] = (uint16_t)j1;
                     group_apply<L>(tab, sx, on_k ? j1 : 0, +1, gl, on_k);
                 }
                 // back to the state at the segment's end
@@ -873,9 +873,23 @@ void bwd_kernel(RunParams p)
 
 }  // namespace wave
 
-int wave_class_for(int max_M)
+int wave_class_for(int max_M, int max_lanes)
 {
     const int nb = (max_M + 1 + 3) / 4;
+    // one block per lane within the cap
+    if (nb <= 8 && max_lanes >= 8) return kWave_L8;
+    if (nb <= 16 && max_lanes >= 16) return kWave_L16;
+    if (nb <= 32 && max_lanes >= 32) return kWave_L32;
+    // two blocks per lane at the cap
+    if (nb <= 2 * max_lanes) {
+        switch (max_lanes) {
+        case 8: return kWave_L8x2;
+        case 16: return kWave_L16x2;
+        case 32: return kWave_L32x2;
+        default: break;
+        }
+    }
+    // too large for the cap: the library's own width
     if (nb <= 8) return kWave_L8;
     if (nb <= 16) return kWave_L16;
     if (nb <= 32) return kWave_L32;
@@ -887,11 +901,16 @@ int wave_class_for(int max_M)
 int wave_class_lanes(int cls)
 {
     switch (cls) {
-    case kWave_L8: return 8;
-    case kWave_L16: return 16;
-    case kWave_L32: return 32;
+    case kWave_L8: case kWave_L8x2: return 8;
+    case kWave_L16: case kWave_L16x2: return 16;
+    case kWave_L32: case kWave_L32x2: return 32;
     default: return 64;
     }
+}
+
+int wave_class_bpl(int cls)
+{
+    return cls == kWave_L64x2 || cls == kWave_L8x2 || cls == kWave_L16x2 || cls == kWave_L32x2 ? 2 : 1;
 }
 
 template <int L, int BPL>
@@ -916,11 +935,11 @@ size_t wave_static_lds(int cls, bool backward)
 {
     const int L = wave_class_lanes(cls);
     const int G = 64 / L;
-    const int bpl = cls == kWave_L64x2 ? 2 : 1;
+    const int bpl = wave_class_bpl(cls);
     size_t b = sizeof(int) * wave::kWaves * G * (wave::kMaxN + 1);
     if (backward)
         b += sizeof(float) * wave::kWaves * G * wave::kMaxN + sizeof(float) * wave::kWaves * G * (2 * 4 * bpl * L + 1) +
-             wave::kWaves * G * 64;
+             sizeof(uint16_t) * wave::kWaves * G * 64;
     return b;
 }
 
@@ -932,6 +951,9 @@ hipError_t wave_launch(int cls, const RunParams &p, bool backward, int n_blocks,
     case kWave_L32: return launch_wave<32, 1>(p, backward, n_blocks, stream);
     case kWave_L64: return launch_wave<64, 1>(p, backward, n_blocks, stream);
     case kWave_L64x2: return launch_wave<64, 2>(p, backward, n_blocks, stream);
+    case kWave_L8x2: return launch_wave<8, 2>(p, backward, n_blocks, stream);
+    case kWave_L16x2: return launch_wave<16, 2>(p, backward, n_blocks, stream);
+    case kWave_L32x2: return launch_wave<32, 2>(p, backward, n_blocks, stream);
     default: return hipErrorInvalidValue;
     }
 }

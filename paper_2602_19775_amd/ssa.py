@@ -36,7 +36,7 @@ class _Desc(C.Structure):
                 ("n_params", C.c_void_p), ("n_traj", C.c_void_p), ("n_obs", C.c_void_p),
                 ("reactant", C.c_void_p), ("rate_index", C.c_void_p), ("stoich", C.c_void_p),
                 ("obs_species", C.c_void_p), ("t_obs", C.c_void_p), ("exec_mode", C.c_int32),
-                ("wave_split", C.c_int32)]
+                ("wave_split", C.c_int32), ("wave_lanes", C.c_int32)]
 
 
 class _Layout(C.Structure):
@@ -133,7 +133,7 @@ class Net:
 
     def __init__(self, networks: Sequence[W.Network], n_traj: Sequence[int],
                  t_obs: Optional[Sequence[float]] = None, obs_species: Optional[Sequence] = None,
-                 exec_mode: str = "auto", wave_split: int = -1):
+                 exec_mode: str = "auto", wave_split: int = -1, wave_lanes: int = 0):
         self.networks = list(networks)
         self.n_traj = [int(b) for b in n_traj]
         nn = len(self.networks)
@@ -153,8 +153,9 @@ class Net:
             np.ascontiguousarray(t_obs if t_obs is not None else np.zeros(nn), np.float64),
         ]
         k = self._keep
-        d = _Desc(nn, *[a.ctypes.data_as(C.c_void_p).value for a in k], self.EXEC[exec_mode], int(wave_split))
-        self.exec_mode, self.wave_split = exec_mode, wave_split
+        d = _Desc(nn, *[a.ctypes.data_as(C.c_void_p).value for a in k], self.EXEC[exec_mode], int(wave_split),
+                  int(wave_lanes))
+        self.exec_mode, self.wave_split, self.wave_lanes = exec_mode, wave_split, wave_lanes
         h = C.c_void_p()
         _check(lib().ssa_net_create(C.byref(d), C.byref(h)), "ssa_net_create")
         self.handle = h

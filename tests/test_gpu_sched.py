@@ -36,7 +36,7 @@ def test_autotune_chooses_and_caches(ssa, tmp_path):
     timed = {k: v for k, v in entry["timings_ms"].items() if v is not None}
     assert len(timed) >= 6                      # spec, lane and wave plans all run the dimer
     assert min(timed.values()) == pytest.approx(
-        timed[f"{plan.exec_mode}/split{plan.wave_split}/{plan.bwd_mode}/K{plan.ckpt_every}"])
+        timed[plan.name])
     # a second call is a cache hit: nothing is timed
     def boom(*a, **k):
         raise AssertionError("timed a cached batch")
@@ -106,6 +106,35 @@ def _check_graph_against_eager(ssa, h, cfg, theta0, x0, loss_fn, lr, n_replays=4
         torch.cuda.synchronize()
     assert int(epoch.item()) == n_replays
     assert ssa.device_status(h) == 0
+
+
+def test_autotune_uneven_batch(ssa, tmp_path):
+    """The tuner on a reduced uneven batch (the first 48 networks of the
+    4,096-network generator, 64 trajectories each, their own 4-bin windows):
+    only wave plans run it (more than 16 topologies, channels beyond the
+    generic lane tables), every width and launch split among them, and the
+    chosen plan fires the channels of the library's default plan."""
+    from paper_2602_19775_amd import autotune as A
+    bw = W.uneven_batch(n_networks=48, traj_per_network=64, n_steps=400)
+    nets, Bs = bw.nets, bw.n_traj
+    cfg = bw.cfg.replace(t_obs=bw.t_obs[0])
+    theta = torch.tensor(bw.theta(), device="cuda")
+    x0 = torch.tensor(bw.x0_packed(), device="cuda")
+    cache = A.Cache(str(tmp_path / "tune.json"))
+    lines = []
+    plan = A.tune(nets, Bs, cfg, theta, x0, bw.t_obs, probe_steps=128, repeats=1, cache=cache, log=lines.append)
+    timed = {k: v for k, v in A.Cache(cache.path).data[A.signature(nets, Bs, cfg)]["timings_ms"].items()
+             if v is not None}
+    assert plan.exec_mode == "wave" and plan.name in timed
+    assert all(k.startswith("wave/") for k in timed), timed
+    assert {"wave/split1/tape/K256", "wave/split0/tape/K256", "wave/split1/w32/tape/K256",
+            "wave/split0/w16/tape/K256"} <= set(timed), lines
+    h = plan.net(nets, Bs, bw.t_obs)
+    f = ssa.forward(h, plan.config(cfg), theta, x0, bwd_mode=plan.bwd_mode)
+    f0 = ssa.forward(ssa.Net(nets, Bs, t_obs=bw.t_obs), cfg, theta, x0)
+    torch.cuda.synchronize()
+    assert torch.equal(f.steps_done, f0.steps_done)
+    assert torch.equal(f.x_final, f0.x_final)
 
 
 def test_graph_replay_dimer_specialised(ssa):

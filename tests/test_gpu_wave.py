@@ -168,3 +168,64 @@ def test_wave_backward_deterministic(ssa, wave_mode):
         outs.append((f.x_final.clone(), dp.clone(), ppt.clone()))
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("lanes,m_range", [(8, (20, 60)), (16, (40, 120)), (32, (90, 250)), (64, (300, 500))],
+                         ids=["w8", "w16", "w32", "w64"])
+def test_wave_narrow_groups_gradients(ssa, wave_mode, lanes, m_range):
+    """Groups capped at `lanes` lanes: networks that need more Philox blocks
+    than lanes draw two per lane (8 channel slots), several trajectories per
+    wavefront.  The fired channels are those of the default width; clocks and
+    gradients agree with the oracle at the usual bars."""
+    nets = W.random_network_batch(4, seed=31 + lanes, n_range=(4, 40), m_range=m_range)
+    B = [24, 9, 33, 16]
+    pilot = [oracle.run(n, W.RunConfig(seed=1, n_steps=200, purpose=2), n.theta0, n.x0,
+                        traj_ids=np.arange(8)) for n in nets]
+    t_obs = [float(np.min(r.t_final)) * 0.8 for r in pilot]
+    cfg = W.RunConfig(seed=6, n_steps=200, obs_kind=W.OBS_BINS, n_bins=4, t_obs=1.0, temperature=0.5,
+                      ckpt_every=64)
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    x0 = _x0(nets, B)
+    h = ssa.Net(nets, B, t_obs=t_obs, exec_mode="wave", wave_split=wave_mode, wave_lanes=lanes)
+    d_obs = np.random.default_rng(3).normal(size=h.obs_total(cfg.obs_kind, cfg.n_bins))
+    fwd = ssa.forward(h, cfg, th, x0, tie_capacity=1 << 16)
+    dp, ppt = ssa.backward(h, cfg, th, x0, fwd, torch.tensor(d_obs, device="cuda"), per_traj=True)
+    torch.cuda.synchronize()
+    assert ssa.device_status(h) == 0
+    check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt.cpu().numpy())
+    h0 = ssa.Net(nets, B, t_obs=t_obs, exec_mode="wave", wave_split=wave_mode)
+    f0 = ssa.forward(h0, cfg, th, x0, tie_capacity=1 << 16)
+    torch.cuda.synchronize()
+    assert torch.equal(fwd.steps_done, f0.steps_done)
+    assert torch.equal(fwd.x_final, f0.x_final)
+    assert torch.allclose(fwd.t_final, f0.t_final, rtol=1e-6, atol=0)
+
+
+def test_wave_lanes_values(ssa):
+    nets = W.random_network_batch(2, seed=3, n_range=(4, 8), m_range=(100, 110))
+    with pytest.raises(ssa.SSAError):
+        ssa.Net(nets, [8, 8], exec_mode="wave", wave_lanes=12)
+    ssa.Net(nets, [8, 8], exec_mode="wave", wave_lanes=8)         # 26+ blocks > 2 x 8: the library's width
+    ssa.Net(nets, [8, 8], exec_mode="wave", wave_lanes=16)        # two blocks on each of 16 lanes
+
+
+def test_wave_over_256_channels_recompute(ssa, wave_mode):
+    """Channel indices past 255 in the backward's recovered choices (the
+    recompute path keeps a segment's channels in LDS; the tape path is run
+    by the width test above)."""
+    nets = W.random_network_batch(3, seed=77, n_range=(10, 40), m_range=(260, 500))
+    assert all(n.n_reactions > 256 for n in nets)
+    B = [20, 13, 31]
+    pilot = [oracle.run(n, W.RunConfig(seed=1, n_steps=150, purpose=2), n.theta0, n.x0,
+                        traj_ids=np.arange(8)) for n in nets]
+    t_obs = [float(np.min(r.t_final)) * 0.8 for r in pilot]
+    cfg = W.RunConfig(seed=2, n_steps=150, obs_kind=W.OBS_BINS, n_bins=3, t_obs=1.0, temperature=0.5,
+                      ckpt_every=64)
+    g = np.random.default_rng(5)
+
+    def d_obs_fn(h):
+        return g.normal(size=h.obs_total(cfg.obs_kind, cfg.n_bins))
+
+    h, fwd, d_obs, ppt = run_batch(ssa, nets, B, cfg, d_obs_fn, bwd_mode="recompute", t_obs=t_obs,
+                                   wave_split=wave_mode)
+    check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt)

@@ -20,6 +20,9 @@ def test_candidate_plans():
     assert {p.exec_mode for p in plans} == {"spec", "lane", "wave"}
     assert all(p.ckpt_every <= 64 for p in plans if p.bwd_mode == "recompute")
     assert {p.wave_split for p in plans if p.exec_mode == "wave"} == {0, 1}
+    assert {p.wave_lanes for p in plans if p.exec_mode == "wave"} == {0, 16, 32}
+    assert all(p.wave_lanes == 0 for p in plans if p.exec_mode != "wave")
+    assert len({p.name for p in plans}) == len(plans)
     short = A.candidate_plans(100)
     assert max(p.ckpt_every for p in short) == 64
 
@@ -44,6 +47,14 @@ def test_cache_round_trip(tmp_path):
     c.put("k", p, {"wave/split1/recompute/K64": 1.5, "spec/split-1/tape/K256": None})
     assert A.Cache(path).get("k") == p
     assert json.load(open(path))["k"]["timings_ms"]["spec/split-1/tape/K256"] is None
+    q = A.Plan("wave", 0, "tape", 256, 16)
+    c.put("k2", q, {q.name: 2.0})
+    assert A.Cache(path).get("k2") == q and q.name == "wave/split0/w16/tape/K256"
+    # an entry written before the plan had a width reads as the library's width
+    data = json.load(open(path))
+    del data["k2"]["plan"]["wave_lanes"]
+    json.dump(data, open(path, "w"))
+    assert A.Cache(path).get("k2") == A.Plan("wave", 0, "tape", 256)
     with open(path, "w") as f:
         f.write("{not json")
     assert A.Cache(path).get("k") is None
