@@ -110,9 +110,10 @@ def test_wave_gradients_random_batch(ssa, wave_mode, mode):
     check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt)
 
 
-def check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt):
+def check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt, layouts=None):
     """check_batch with a per-network observation window (the oracle runs
-    network by network, each with its own window)."""
+    network by network, each with its own window).  `layouts` gives each
+    checked network's offsets when they are not networks 0, 1, ... of h."""
     ties = fwd.tie_records()
     xf = fwd.x_final.cpu().numpy()
     sd = fwd.steps_done.cpu().numpy()
@@ -120,7 +121,7 @@ def check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt):
     obs = fwd.obs.cpu().numpy()
     for n, (net, b) in enumerate(zip(nets, B)):
         c = cfg.replace(t_obs=t_obs[n])
-        L = h.layout(n, c.obs_kind, c.n_bins)
+        L = layouts[n] if layouts is not None else h.layout(n, c.obs_kind, c.n_bins)
         nob = len(net.obs_species)
         ov = _ties_for_oracle([t for t in ties if L.traj_offset <= t["traj"] < L.traj_offset + b], L.traj_offset)
         blk = d_obs[L.obs_offset: L.obs_offset + c.n_bins * nob * b]
@@ -229,3 +230,31 @@ def test_wave_over_256_channels_recompute(ssa, wave_mode):
     h, fwd, d_obs, ppt = run_batch(ssa, nets, B, cfg, d_obs_fn, bwd_mode="recompute", t_obs=t_obs,
                                    wave_split=wave_mode)
     check_batch_windows(h, fwd, nets, B, cfg, t_obs, d_obs, ppt)
+
+
+def test_wave_empty_network_in_batch(ssa, wave_mode):
+    """A network with no trajectories between two others: the persistent
+    queue skips it, the others match the oracle, and its parameters get a zero
+    gradient."""
+    nets = W.random_network_batch(3, seed=41, n_range=(4, 20), m_range=(20, 90))
+    B = [16, 0, 9]
+    pilot = [oracle.run(n, W.RunConfig(seed=1, n_steps=200, purpose=2), n.theta0, n.x0,
+                        traj_ids=np.arange(8)) for n in nets]
+    t_obs = [float(np.min(r.t_final)) * 0.8 for r in pilot]
+    cfg = W.RunConfig(seed=8, n_steps=200, obs_kind=W.OBS_BINS, n_bins=4, t_obs=1.0, temperature=0.5,
+                      ckpt_every=64)
+    g = np.random.default_rng(9)
+
+    def d_obs_fn(h):
+        return g.normal(size=h.obs_total(cfg.obs_kind, cfg.n_bins))
+
+    h, fwd, d_obs, ppt = run_batch(ssa, nets, B, cfg, d_obs_fn, bwd_mode="tape", t_obs=t_obs,
+                                   wave_split=wave_mode)
+    keep = [n for n, b in enumerate(B) if b > 0]
+    # the oracle checks network by network; the empty one has nothing to compare
+    check_batch_windows(h, fwd, [nets[n] for n in keep], [B[n] for n in keep], cfg, [t_obs[n] for n in keep],
+                        d_obs, ppt, layouts=[h.layout(n, cfg.obs_kind, cfg.n_bins) for n in keep])
+    th = torch.tensor(np.concatenate([n.theta0 for n in nets]), device="cuda")
+    dp, _ = ssa.backward(h, cfg, th, _x0(nets, B), fwd, torch.tensor(d_obs, device="cuda"), per_traj=True)
+    off = sum(n.n_params for n in nets[:1])
+    assert np.all(dp.cpu().numpy()[off:off + nets[1].n_params] == 0.0)
