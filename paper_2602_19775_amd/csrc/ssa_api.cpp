@@ -181,11 +181,11 @@ CkptLayout ckpt_layout(const ssa_net *net, const ssa_config *cfg)
         if (L.bytes == 0) L.bytes = 256;
         return L;
     }
-    L.n_ckpt = (cfg->n_steps + cfg->ckpt_every - 1) / cfg->ckpt_every;
+    L.n_ckpt = (int32_t)(((int64_t)cfg->n_steps + cfg->ckpt_every - 1) / cfg->ckpt_every);
     if (resolve_bwd_mode(cfg) == SSA_BWD_TAPE) {
         L.tape_bits = bits_for(net->max_M);
         const int spw = 32 / L.tape_bits;
-        L.tape_words = (cfg->n_steps + spw - 1) / spw + 1;
+        L.tape_words = (int32_t)(((int64_t)cfg->n_steps + spw - 1) / spw + 1);
     }
     size_t off = 0;
     L.off_t = off;

@@ -51,7 +51,7 @@ ssa_status check_cfg(const ssa_grn *g, const ssa_config *cfg)
 
 size_t tape_words(const ssa_config *cfg)
 {
-    return (size_t)64 * (size_t)((cfg->n_steps + 127) / 128);
+    return (size_t)64 * (size_t)(((int64_t)cfg->n_steps + 127) / 128);
 }
 
 // Relaxed runs store the starting point of every step instead of the fired
