@@ -117,6 +117,22 @@ def _check(rc: int, what: str):
         raise SSAError(f"{what}: {L.ssa_status_string(rc).decode()} ({L.ssa_last_error().decode()})")
 
 
+def _need(ok: bool, what: str):
+    """Argument check of the binding (kept under python -O: the kernels read
+    every buffer at the size the handle and the run settings imply)."""
+    if not ok:
+        raise ValueError(what)
+
+
+def _dev_tensor(t: torch.Tensor, dtype, n: int, name: str, exact: bool = True):
+    _need(isinstance(t, torch.Tensor) and t.is_cuda, f"{name} must be a device tensor")
+    _need(t.dtype == dtype, f"{name} must be {dtype}, not {t.dtype}")
+    _need(t.is_contiguous(), f"{name} must be contiguous")
+    _need(t.numel() == n if exact else t.numel() >= n,
+          f"{name} has {t.numel()} elements, {'' if exact else 'at least '}{n} expected")
+
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -137,7 +153,7 @@ class Net:
         self.networks = list(networks)
         self.n_traj = [int(b) for b in n_traj]
         nn = len(self.networks)
-        assert len(self.n_traj) == nn
+        _need(len(self.n_traj) == nn, "one trajectory count per network")
         obs = [np.asarray(n.obs_species if obs_species is None else obs_species[i], np.int32)
                for i, n in enumerate(self.networks)]
         self._keep = [
@@ -239,10 +255,14 @@ def forward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, *
     d_epoch (int32 [1]) and d_temperature (float32 [1]), if given, are read on the
     device by this forward and by the backward that uses its buffers."""
     if d_temperature is not None:
-        assert d_temperature.dtype == torch.float32 and d_temperature.is_cuda
+        _dev_tensor(d_temperature, torch.float32, 1, "d_temperature")
+    if d_epoch is not None:
+        _dev_tensor(d_epoch, torch.int32, 1, "d_epoch")
+    if traj_ids is not None:
+        _dev_tensor(traj_ids, torch.int32, net.traj_total, "traj_ids")
     dev = theta.device
-    assert theta.dtype == torch.float32 and theta.is_cuda and theta.numel() == net.param_total
-    assert x0.dtype == torch.int32 and x0.is_cuda and x0.numel() == net.state_total
+    _dev_tensor(theta, torch.float32, net.param_total, "theta")
+    _dev_tensor(x0, torch.int32, net.state_total, "x0")
     ccfg = make_cfg(cfg, tie_capacity, bwd_mode, traj_ids, d_epoch, d_temperature)
     ck_bytes, wk_bytes = buffer_sizes(net, ccfg)
     if buffers is None:
@@ -260,6 +280,13 @@ def forward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, *
             torch.empty(wk_bytes, dtype=torch.uint8, device=dev),
             ccfg)
     else:
+        obs_n = max(net.mean_total(cfg.obs_kind, cfg.n_bins) if cfg.obs_layout == W.OBS_ENSEMBLE_MEAN
+                    else net.obs_total(cfg.obs_kind, cfg.n_bins), 1)
+        _need(buffers.x_final.numel() >= net.state_total and buffers.t_final.numel() >= net.traj_total
+              and buffers.steps_done.numel() >= net.traj_total and buffers.obs.numel() >= obs_n
+              and buffers.work.numel() >= wk_bytes
+              and (buffers.ckpt is None or not keep_ckpt or buffers.ckpt.numel() >= ck_bytes),
+              "the buffers of another handle or run settings were passed")
         buffers.ccfg = ccfg
     b = buffers
     rc = lib().ssa_forward(net.handle, C.byref(ccfg), _ptr(theta), _ptr(x0), _ptr(b.x_final),
@@ -270,13 +297,27 @@ def forward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, *
     return b
 
 
+def _dobs_size(net: Net, c: "_Cfg") -> int:
+    """Values of dL/dobs the backward reads for the forward's settings: one
+    block of the ensemble-mean layout per network when it is shared (the only
+    d_obs an ensemble-mean forward accepts), else the observation's."""
+    if c.dobs_shared or c.obs_layout == W.OBS_ENSEMBLE_MEAN:
+        return net.mean_total(c.obs_kind, c.n_bins)
+    return net.obs_total(c.obs_kind, c.n_bins)
+
+
 def backward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, fwd: Forward,
              d_obs: torch.Tensor, per_traj: bool = False, d_params: Optional[torch.Tensor] = None,
              stream=None):
     """Runs ssa_backward; returns d_params (float32 [param_total]) and, if asked,
     per-trajectory gradients (float32 [sum P_n*B_n])."""
-    assert fwd.ckpt is not None, "the forward kept no checkpoints"
-    assert d_obs.dtype == torch.float64 and d_obs.is_cuda
+    _need(fwd.ckpt is not None, "the forward kept no checkpoints")
+    _dev_tensor(theta, torch.float32, net.param_total, "theta")
+    _dev_tensor(x0, torch.int32, net.state_total, "x0")
+    d_obs = d_obs.contiguous()
+    _dev_tensor(d_obs, torch.float64, _dobs_size(net, fwd.ccfg), "d_obs", exact=False)
+    if d_params is not None:
+        _dev_tensor(d_params, torch.float32, net.param_total, "d_params", exact=False)
     if d_params is None:
         d_params = torch.empty(net.param_total, dtype=torch.float32, device=theta.device)
     ppt = None
@@ -285,7 +326,7 @@ def backward(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.Tensor, 
         ppt = torch.empty(n, dtype=torch.float32, device=theta.device)
     rc = lib().ssa_backward(net.handle, C.byref(fwd.ccfg), _ptr(theta), _ptr(x0), _ptr(fwd.x_final),
                             _ptr(fwd.t_final), _ptr(fwd.steps_done), _ptr(fwd.ckpt), fwd.ckpt.numel(),
-                            _ptr(d_obs.contiguous()), _ptr(d_params), _ptr(ppt), _ptr(fwd.work),
+                            _ptr(d_obs), _ptr(d_params), _ptr(ppt), _ptr(fwd.work),
                             fwd.work.numel(), _stream(stream))
     _check(rc, "ssa_backward")
     return (d_params, ppt) if per_traj else d_params
@@ -296,9 +337,14 @@ def backward_static(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x0: torch.T
     """Runs ssa_backward_static: ssa_backward with the library's static device
     scratch instead of a work buffer (the caller provides the outputs
     d_params float32 [param_total] and, optionally, ppt [sum P_n*B_n])."""
-    assert fwd.ckpt is not None, "the forward kept no checkpoints"
-    assert d_obs.dtype == torch.float64 and d_obs.is_cuda and d_obs.is_contiguous()
-    assert d_params.dtype == torch.float32 and d_params.numel() >= net.param_total
+    _need(fwd.ckpt is not None, "the forward kept no checkpoints")
+    _dev_tensor(theta, torch.float32, net.param_total, "theta")
+    _dev_tensor(x0, torch.int32, net.state_total, "x0")
+    _dev_tensor(d_obs, torch.float64, _dobs_size(net, fwd.ccfg), "d_obs", exact=False)
+    _dev_tensor(d_params, torch.float32, net.param_total, "d_params", exact=False)
+    if ppt is not None:
+        _dev_tensor(ppt, torch.float32, sum(nw.n_params * b for nw, b in zip(net.networks, net.n_traj)), "ppt",
+                    exact=False)
     rc = lib().ssa_backward_static(net.handle, C.byref(fwd.ccfg), _ptr(theta), _ptr(x0), _ptr(fwd.x_final),
                                    _ptr(fwd.t_final), _ptr(fwd.steps_done), _ptr(fwd.ckpt), fwd.ckpt.numel(),
                                    _ptr(d_obs), _ptr(d_params), _ptr(ppt), _stream(stream))
@@ -313,11 +359,12 @@ def obs_mean(net: Net, fwd: Forward, out: Optional[torch.Tensor] = None, obs: Op
     float64 [mean_total].  Uses the forward's work buffer."""
     c = fwd.ccfg
     obs = fwd.obs if obs is None else obs
-    assert obs.dtype == torch.float64 and obs.is_cuda and obs.is_contiguous()
+    _dev_tensor(obs, torch.float64, net.mean_total(c.obs_kind, c.n_bins) if c.obs_layout == W.OBS_ENSEMBLE_MEAN
+                else net.obs_total(c.obs_kind, c.n_bins), "obs", exact=False)
     n = max(net.mean_total(c.obs_kind, c.n_bins), 1)
     if out is None:
         out = torch.empty(n, dtype=torch.float64, device=obs.device)
-    assert out.dtype == torch.float64 and out.numel() >= n and out.is_contiguous()
+    _dev_tensor(out, torch.float64, n, "out", exact=False)
     rc = lib().ssa_obs_mean(net.handle, C.byref(c), _ptr(obs), _ptr(out), _ptr(fwd.work), fwd.work.numel(),
                             _stream(stream))
     _check(rc, "ssa_obs_mean")
@@ -329,6 +376,9 @@ def step_batch(net: Net, cfg: W.RunConfig, theta: torch.Tensor, x: torch.Tensor,
     """One direct-method step in place; returns (chosen, tau, a)."""
     ccfg = make_cfg(cfg)
     dev = theta.device
+    _dev_tensor(theta, torch.float32, net.param_total, "theta")
+    _dev_tensor(x, torch.int32, net.state_total, "x")
+    _dev_tensor(t, torch.float64, net.traj_total, "t")
     chosen = torch.empty(net.traj_total, dtype=torch.int32, device=dev)
     tau = torch.empty(net.traj_total, dtype=torch.float32, device=dev)
     n_a = sum(nw.n_reactions * b for nw, b in zip(net.networks, net.n_traj))
@@ -446,11 +496,18 @@ def grn_forward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tens
     d_epoch / d_temperature: optional device scalars read by this forward and its backward."""
     dev = theta.device
     n = g.net
-    assert theta.dtype == torch.float32 and theta.is_cuda and theta.numel() == n.n_params
-    assert x_img.dtype == torch.float32 and x_img.is_cuda and x_img.shape == (g.n_images, n.n_in)
+    _dev_tensor(theta, torch.float32, n.n_params, "theta")
+    x_img = x_img.contiguous()
+    _need(tuple(x_img.shape) == (g.n_images, n.n_in), f"x_img must be [{g.n_images}, {n.n_in}]")
+    _dev_tensor(x_img, torch.float32, g.n_images * n.n_in, "x_img")
     if x0 is None:
         x0 = torch.zeros((n.n_species, g.B), dtype=torch.int32, device=dev)
-    assert x0.dtype == torch.int32 and x0.is_cuda and x0.numel() == n.n_species * g.B
+    x0 = x0.contiguous()       # kept with the buffers: the backward reads it too
+    _dev_tensor(x0, torch.int32, n.n_species * g.B, "x0")
+    for name, t in (("traj_ids", traj_ids), ("d_epoch", d_epoch), ("d_temperature", d_temperature)):
+        if t is not None:
+            _dev_tensor(t, torch.float32 if name == "d_temperature" else torch.int32,
+                        g.B if name == "traj_ids" else 1, name)
     ccfg = make_cfg(cfg, tie_capacity, "auto", traj_ids, d_epoch, d_temperature)
     tb, _ = grn_buffer_sizes(g, ccfg)
     if buffers is None:
@@ -470,8 +527,8 @@ def grn_forward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Tens
         buffers.ccfg = ccfg
         buffers.x0 = x0
     b = buffers
-    rc = lib().ssa_grn_forward(g.handle, C.byref(ccfg), _ptr(theta), _ptr(x_img.contiguous()),
-                               _ptr(x0.contiguous()), _ptr(b.u_hid), _ptr(b.x_final), _ptr(b.t_final),
+    rc = lib().ssa_grn_forward(g.handle, C.byref(ccfg), _ptr(theta), _ptr(x_img),
+                               _ptr(x0), _ptr(b.u_hid), _ptr(b.x_final), _ptr(b.t_final),
                                _ptr(b.steps_done), _ptr(b.obs), _ptr(b.tape),
                                b.tape.numel() if b.tape is not None else 0, _ptr(b.ties), _ptr(b.n_ties),
                                _stream(stream))
@@ -484,8 +541,12 @@ def grn_backward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Ten
                  work: Optional[torch.Tensor] = None, stream=None):
     """Runs ssa_grn_backward; returns d_params float32 [P] and, if asked, the
     compact per-trajectory gradients float64 [B, C]."""
-    assert fwd.tape is not None, "the forward kept no tape"
-    assert d_obs.dtype == torch.float64 and d_obs.is_cuda and d_obs.numel() == g.net.n_out * g.B
+    _need(fwd.tape is not None, "the forward kept no tape")
+    _dev_tensor(theta, torch.float32, g.net.n_params, "theta")
+    x_img = x_img.contiguous()
+    _dev_tensor(x_img, torch.float32, g.n_images * g.net.n_in, "x_img")
+    d_obs = d_obs.contiguous()
+    _dev_tensor(d_obs, torch.float64, g.net.n_out * g.B, "d_obs")
     dev = theta.device
     _, wb = grn_buffer_sizes(g, fwd.ccfg)
     if work is None:
@@ -493,9 +554,12 @@ def grn_backward(g: Grn, cfg: W.RunConfig, theta: torch.Tensor, x_img: torch.Ten
     if d_params is None:
         d_params = torch.empty(g.net.n_params, dtype=torch.float32, device=dev)
     comp = torch.empty((g.B, g.net.n_compact), dtype=torch.float64, device=dev) if per_traj else None
-    rc = lib().ssa_grn_backward(g.handle, C.byref(fwd.ccfg), _ptr(theta), _ptr(x_img.contiguous()),
-                                _ptr(fwd.x0.contiguous()), _ptr(fwd.u_hid), _ptr(fwd.x_final), _ptr(fwd.steps_done), _ptr(fwd.tape),
-                                fwd.tape.numel(), _ptr(d_obs.contiguous()), _ptr(d_params), _ptr(comp),
+    if d_params is not None:
+        _dev_tensor(d_params, torch.float32, g.net.n_params, "d_params", exact=False)
+    _dev_tensor(work, torch.uint8, wb, "work", exact=False)
+    rc = lib().ssa_grn_backward(g.handle, C.byref(fwd.ccfg), _ptr(theta), _ptr(x_img),
+                                _ptr(fwd.x0), _ptr(fwd.u_hid), _ptr(fwd.x_final), _ptr(fwd.steps_done), _ptr(fwd.tape),
+                                fwd.tape.numel(), _ptr(d_obs), _ptr(d_params), _ptr(comp),
                                 _ptr(work), work.numel(), _stream(stream))
     _check(rc, "ssa_grn_backward")
     return (d_params, comp) if per_traj else d_params
