@@ -906,7 +906,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="oscillator",
                     choices=["dimer", "oscillator", "uneven", "grn", "abc_infer", "coi_infer", "selection"],
                     help="oscillator: 9 species / 16 channels, 65,536 x 200,000 steps (default); "
