@@ -255,6 +255,12 @@ def profiled_traffic(workload: str, kernel: str):
     return None
 
 
+def progress(what: str):
+    """A line on stderr as each phase of a benchmark ends (the JSON line is the
+    only stdout)."""
+    print(f"[bench] {what}", file=sys.stderr, flush=True)
+
+
 def spread(ms) -> dict:
     """Median, minimum and maximum of per-step times (ms)."""
     a = np.asarray(ms, dtype=np.float64)
@@ -368,6 +374,34 @@ def bench_grn(args, torch, dev):
     fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
     fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
     del pbufs
+
+    # the uneven batch as one persistent launch for every network (each then
+    # runs on the lane-group class of the largest), beside the tuned plan
+    one_launch = None
+    if workload == "uneven" and not light and args.one_launch_steps > 0 and getattr(h, "wave_split", -1) != 0:
+        h1 = ssa.Net(nets, Bs, t_obs=bw.t_obs, exec_mode="wave", wave_split=0)
+        b1 = ssa.forward(h1, cfg, theta, x0, tie_capacity=0, bwd_mode=bwd_mode)
+        dp1 = torch.empty_like(d_params)
+
+        def step1():
+            ssa.forward(h1, cfg, theta, x0, buffers=b1, tie_capacity=0, bwd_mode=bwd_mode)
+            o1 = b1.obs.detach().requires_grad_(True)
+            (g1,) = torch.autograd.grad(loss_fn(o1), o1)
+            ssa.backward(h1, cfg, theta, x0, b1, g1, d_params=dp1)
+        step1()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(args.one_launch_steps):
+            step1()
+        torch.cuda.synchronize()
+        ms1 = (time.perf_counter() - s0) * 1e3 / args.one_launch_steps
+        ref = d_params.double()
+        one_launch = {"steps_per_s": int(b1.steps_done.sum().item()) / (ms1 * 1e-3), "ms_per_step": ms1,
+                      "steps": args.one_launch_steps,
+                      "counts_equal_tuned_plan": bool(torch.equal(b1.x_final, bufs.x_final)),
+                      "grad_max_diff_over_max": float((dp1.double() - ref).abs().max() / ref.abs().max())}
+        assert ssa.device_status(h1) == 0
+        del b1, h1, dp1
     n_ties = int(bufs.n_ties.item())
     assert ssa.grn_device_status(g) == 0
 
@@ -701,8 +735,13 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
         t_obs_l = (bw.t_obs if workload == "uneven" else [cfg.t_obs] * len(nets)) \
             if cfg.obs_kind == W.OBS_BINS else None
         tune_log = []
-        plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l, log=tune_log.append)
-        print("\n".join(["autotune:"] + (tune_log or ["cached plan " + plan.name])), file=sys.stderr, flush=True)
+
+        def tune_line(line):
+            tune_log.append(line)
+            progress("autotune " + line)
+        plan = autotune.tune(nets, Bs, cfg, theta, x0, t_obs_l, log=tune_line)
+        if not tune_log:
+            progress("autotune: cached plan " + plan.name)
         h = plan.net(nets, Bs, t_obs_l)
         cfg = plan.config(cfg)
         bwd_mode = plan.bwd_mode
@@ -756,6 +795,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    progress(f"{workload}: {args.warmup} warm-up steps done")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -765,6 +805,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
     t1 = time.perf_counter()
     fired = int(bufs.steps_done.sum().item())
     ms_step = (t1 - t0) * 1e3 / args.steps
+    progress(f"{workload}: {args.steps} timed steps, {ms_step:.1f} ms each")
     fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     loss_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     bwd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
@@ -787,6 +828,36 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
     fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
     fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
     del pbufs
+    progress(f"{workload}: forward-only steps done")
+
+    # the uneven batch as one persistent launch for every network (each then
+    # runs on the lane-group class of the largest), beside the tuned plan
+    one_launch = None
+    if workload == "uneven" and not light and args.one_launch_steps > 0 and getattr(h, "wave_split", -1) != 0:
+        h1 = ssa.Net(nets, Bs, t_obs=bw.t_obs, exec_mode="wave", wave_split=0)
+        b1 = ssa.forward(h1, cfg, theta, x0, tie_capacity=0, bwd_mode=bwd_mode)
+        dp1 = torch.empty_like(d_params)
+
+        def step1():
+            ssa.forward(h1, cfg, theta, x0, buffers=b1, tie_capacity=0, bwd_mode=bwd_mode)
+            o1 = b1.obs.detach().requires_grad_(True)
+            (g1,) = torch.autograd.grad(loss_fn(o1), o1)
+            ssa.backward(h1, cfg, theta, x0, b1, g1, d_params=dp1)
+        step1()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(args.one_launch_steps):
+            step1()
+        torch.cuda.synchronize()
+        ms1 = (time.perf_counter() - s0) * 1e3 / args.one_launch_steps
+        ref = d_params.double()
+        one_launch = {"steps_per_s": int(b1.steps_done.sum().item()) / (ms1 * 1e-3), "ms_per_step": ms1,
+                      "steps": args.one_launch_steps,
+                      "counts_equal_tuned_plan": bool(torch.equal(b1.x_final, bufs.x_final)),
+                      "grad_max_diff_over_max": float((dp1.double() - ref).abs().max() / ref.abs().max())}
+        assert ssa.device_status(h1) == 0
+        del b1, h1, dp1
+        progress(f"{workload}: one-launch steps done, {ms1:.1f} ms each")
     n_ties = int(bufs.n_ties.item())
     assert ssa.device_status(h) == 0
     kinds = bufs.tie_records()["kind"]
@@ -817,6 +888,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
         gfired = int(gbufs.steps_done.sum().item())
         graph = {"steps_per_s": gfired * args.steps / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / args.steps}
         del cap, gbufs
+        progress(f"{workload}: graph replays done")
 
     # gradient error against the oracle on a sample of trajectories (of the
     # first network of the batch): per-trajectory and summed, with the
@@ -846,6 +918,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
     counts_exact = bool(np.array_equal(xf, r.x_final)) and int(r.n_bad.sum()) == 0
     grad_rel_err = float(np.linalg.norm(g_gpu.sum(0) - r.grad.sum(0)) / np.linalg.norm(r.grad.sum(0)))
     grad_detail = grad_error_detail(g_gpu, r, bufs.t_final.cpu().numpy()[sample], cfg)
+    progress(f"{workload}: oracle sample compared")
 
     # roofline of the dominant kernel (ALU-bound): algorithmic operations of a
     # launch weighted by their measured issue cost, over the kernel's time,
@@ -894,6 +967,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
                    "bwd_mode": bwd_mode,
                    "plan": None if plan is None else dataclasses.asdict(plan)},
         "forward_steps_per_s": fwd_rate, "graph_replay": graph, "fwdbwd_over_forward": value / fwd_rate,
+        **({"one_persistent_launch": one_launch} if one_launch is not None else {}),
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
         "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
         "grad_rel_err": grad_rel_err, "grad_error": grad_detail, "counts_bit_exact_sample": counts_exact,
@@ -928,6 +1002,8 @@ def main():
                     help="pick the execution plan with the autotuner (untimed; cached under ~/.cache); "
                          "default: on for the uneven batch, off otherwise")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    ap.add_argument("--one-launch-steps", type=int, default=2,
+                    help="uneven: also time this many steps with every network in one persistent launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="oscillator: skip the secondary dimer line (other_workloads)")
