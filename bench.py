@@ -910,7 +910,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
           for t in ties if int(t["traj"]) in idx]
     # bins in the specialised mode: the forward logs the side of every bin edge an
     # event time falls close to, and the oracle takes it (EDGE_WINDOW of the tests)
-    ew = 4e-7 if (bins and workload in ("dimer", "oscillator")) else 0.0
+    ew = 4e-7 if bins else 0.0
     r = oracle.run(net, cfg, net.theta0, net.x0, traj_ids=sample, ties=ov, d_obs=dob, kappa=True, edge_window=ew)
     r.edge_window = ew
     g_gpu = ppt.cpu().numpy()[: net.n_params * B].reshape(net.n_params, B).T[sample].astype(np.float64)
