@@ -287,6 +287,10 @@ __global__ __launch_bounds__(kBlock) void fwd_lane_kernel(RunParams p)
     const double t_obs = nd.t_obs;
     Bins bs{0, bins ? bin_edge(t_obs, 1, n_bins) : INFINITY};
     if (!bins) bs.bin = n_bins;
+    // bin-edge log: an event time outside (e_lo, e_hi), the current bin
+    // narrowed by kEdgeLog at both edges, is compared with the edges
+    const bool edge_log = bins && p.ties != nullptr;
+    double e_lo = -INFINITY, e_hi = edge_log ? bs.hi * (1.0 - kEdgeLog) : INFINITY;
     double acc[kObsMax] = {0.0, 0.0, 0.0, 0.0};
     double *obs_lane = p.obs + nd.obsb_off * (p.obs_kind == 1 ? n_bins : 1) + i;
 
@@ -344,6 +348,19 @@ __global__ __launch_bounds__(kBlock) void fwd_lane_kernel(RunParams p)
             double xo[kObsMax];
             observe<NMAX>(X, w.osp, xo);
             bins_add<NMAX>(t, tn, xo, w.nob, bs, acc, obs_lane, B, n_bins, t_obs, false);
+        }
+        if (edge_log && (tn >= e_hi || tn <= e_lo)) {
+            // the edges around the bin holding t + tau (edge b is at t_obs b / n_bins)
+            const int bl = bs.bin < n_bins ? bs.bin : n_bins;
+            const double lo = bl >= 1 ? bin_edge(t_obs, bl, n_bins) : -INFINITY;
+            const double hi = bl < n_bins ? bin_edge(t_obs, bl + 1, n_bins) : INFINITY;
+            int ei = -1;
+            double e = 0.0;
+            if (bl >= 1 && fabs(tn - lo) <= kEdgeLog * lo) { ei = bl; e = lo; }
+            else if (bl < n_bins && fabs(tn - hi) <= kEdgeLog * hi) { ei = bl + 1; e = hi; }
+            if (ei >= 1) log_tie(p, (uint32_t)g, k, tn >= e ? 1 : 0, ei, (float)((tn - e) / e), 2);
+            e_lo = bl >= 1 ? lo * (1.0 + kEdgeLog) : -INFINITY;
+            e_hi = bl < n_bins ? hi * (1.0 - kEdgeLog) : INFINITY;
         }
         if (spw) {
             const int pos = k & (spw - 1);

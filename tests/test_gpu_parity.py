@@ -111,7 +111,7 @@ def run_pair(ssa, net, cfg, B, theta=None, d_obs=None, bwd_mode="auto", sample=N
     oracle_dobs = None
     if d_obs is not None:
         oracle_dobs = (np.transpose(d_obs, (2, 0, 1))[ids] if bins else np.asarray(d_obs).T[ids])
-    ew = EDGE_WINDOW if (exec_mode in ("auto", "spec", "wave") and cfg.obs_kind == W.OBS_BINS) else 0.0
+    ew = EDGE_WINDOW if cfg.obs_kind == W.OBS_BINS else 0.0      # every mode logs the side of close edges
     r = oracle.run(net, cfg, theta, net.x0, traj_ids=ids, ties=ov, d_obs=oracle_dobs,
                    kappa=oracle_dobs is not None, edge_window=ew)
     r.edge_window = ew
