@@ -14,8 +14,12 @@
   `n_tail` states (100) and the mean time of those states.
 - **Rate of change.** Per start point and protein: (mean over the replicates
   of the tail mean count - the start count) / (mean over the replicates of the
-  tail mean time).  Targets come from segments at the true rates (their own
-  stream), computed once for every start point.
+  tail mean time).  Targets come from segments at the true rates run every
+  epoch on the same counters as the model's segments (common random numbers:
+  at the true rates the two agree exactly, so the loss has no sampling floor);
+  `crn=False` instead computes them once for every start point on a stream of
+  their own.  By default the elapsed time is a normaliser of the rate, not
+  differentiated (`time_grad`).
 - **Loss.** Mean squared difference of the model's and the target's rates over
   a batch of start points and the three proteins.
 - **Optimiser.** RMSprop (decay 0.9, eps 1e-7) on theta = ln k of the five
@@ -119,10 +123,10 @@ class StartPointTrainer:
                  n_paths: int = 32, stride: int = 9, burn: int = 300_000, n_seg: int = 150, n_tail: int = 100,
                  n_rep: int = 25, batch: int = 8192, epochs: int = 3000, temperature: float = 3e-6,
                  lr0: float = 0.1, lr1: float = 0.01, rho: float = 0.9, eps: float = 1e-7, seed: int = 0,
-                 time_grad: bool = True):
+                 time_grad: bool = False, crn: bool = True):
         dev = torch.device("cuda")
         assert n_start % batch == 0
-        self.true_net, self.epochs, self.time_grad = true_net, epochs, time_grad
+        self.true_net, self.epochs, self.time_grad, self.crn = true_net, epochs, time_grad, crn
         N, nob = true_net.n_species, len(true_net.obs_species)
         assert nob == 3
         self.S, self.R, self.B = batch, n_rep, batch * n_rep
@@ -140,15 +144,18 @@ class StartPointTrainer:
         self.cfg = W.RunConfig(seed=seed, n_steps=n_seg, obs_kind=W.OBS_TAIL, n_bins=n_tail,
                                temperature=temperature, ckpt_every=n_seg)
         self.h = ssa.Net([true_net], [self.B])
-        # target rates of change, every start point, at the true rates
-        self.tr_all = torch.empty((self.n_batches, batch, nob), dtype=torch.float64, device=dev)
-        th_true = torch.tensor(true_net.theta0, device=dev)
-        tf = None
-        for b in range(self.n_batches):
-            tf = ssa.forward(self.h, self.cfg.replace(purpose=W.PURPOSE_TARGET, epoch=b), th_true, self.x0_all[b],
-                             keep_ckpt=False, tie_capacity=0, buffers=tf)
-            self.tr_all[b].copy_(self._rates(tf.obs, self.xs_all[b]).T)
-        del tf
+        # target rates of change at the true rates: once for every start point
+        # on a stream of their own, or (crn) every epoch on the model's stream
+        self.th_true = torch.tensor(true_net.theta0, device=dev)
+        self.tr_all = None
+        if not crn:
+            self.tr_all = torch.empty((self.n_batches, batch, nob), dtype=torch.float64, device=dev)
+            tf = None
+            for b in range(self.n_batches):
+                tf = ssa.forward(self.h, self.cfg.replace(purpose=W.PURPOSE_TARGET, epoch=b), self.th_true,
+                                 self.x0_all[b], keep_ckpt=False, tie_capacity=0, buffers=tf)
+                self.tr_all[b].copy_(self._rates(tf.obs, self.xs_all[b]).T)
+            del tf
         # model state, schedules and buffers (device scalars for the graph)
         theta = true_net.theta0.astype(np.float64).copy()
         theta[PROTEIN] = np.log(self.k_start)
@@ -165,11 +172,13 @@ class StartPointTrainer:
         self.epoch = torch.zeros(1, dtype=torch.int32, device=dev)
         self.x0 = self.x0_all[0].clone()
         self.xs = self.xs_all[0].clone()
-        self.tr = self.tr_all[0].clone()
+        self.tr = torch.zeros((batch, nob), dtype=torch.float64, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
         self.d_obs = torch.zeros((nob + 1) * self.B, dtype=torch.float64, device=dev)
         self.d_params = torch.zeros(self.h.param_total, dtype=torch.float32, device=dev)
         self.bufs = ssa.forward(self.h, self.cfg, self.theta, self.x0, tie_capacity=0, d_epoch=self.epoch)
+        self.tbufs = (ssa.forward(self.h, self.cfg, self.th_true, self.x0, keep_ckpt=False, tie_capacity=0,
+                                  d_epoch=self.epoch) if crn else None)
         self.graph: Optional[CapturedStep] = None
 
     def _rates(self, obs: torch.Tensor, xs: torch.Tensor) -> torch.Tensor:
@@ -183,7 +192,13 @@ class StartPointTrainer:
         b = torch.remainder(self.epoch, self.n_batches).long()
         self.x0.copy_(self.x0_all.index_select(0, b).view(-1))
         self.xs.copy_(self.xs_all.index_select(0, b).view(self.S, 3))
-        self.tr.copy_(self.tr_all.index_select(0, b).view(self.S, 3))
+        if self.crn:
+            # the true rates on the same counters as the model's segments
+            ssa.forward(self.h, self.cfg, self.th_true, self.x0, buffers=self.tbufs, keep_ckpt=False,
+                        tie_capacity=0, d_epoch=self.epoch)
+            self.tr.copy_(self._rates(self.tbufs.obs, self.xs).T)
+        else:
+            self.tr.copy_(self.tr_all.index_select(0, b).view(self.S, 3))
         ssa.forward(self.h, self.cfg, self.theta, self.x0, buffers=self.bufs, tie_capacity=0, d_epoch=self.epoch)
         self.loss.copy_(rate_loss(self.bufs.obs, self.xs, self.tr, self.S, self.R, self.d_obs, self.time_grad))
         ssa.backward(self.h, self.cfg, self.theta, self.x0, self.bufs, self.d_obs, d_params=self.d_params)

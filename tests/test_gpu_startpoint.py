@@ -6,10 +6,11 @@
   with the oracle tests/test_gpu_tail.py covers; its written-out loss
   gradient is checked on the CPU (tests/test_host.py).
 - A captured epoch replays exactly what the eager epoch computes.
-- The whole protocol at the paper's size moves the five protein rates toward
-  their true values.  It does not reach the paper's 1.2 % error: at
-  T = 3e-6 the selection part of the gradient comes from rare near-tie steps,
-  while the elapsed-time part is smooth.
+- With the targets on the model's counters (common random numbers), the loss
+  and its gradient are exactly 0 at the true rates.
+- The whole protocol at the paper's size, from rates off by factors of 2,
+  recovers the five protein rates to within a few per cent (the paper reports
+  1.2 %).
 """
 import numpy as np
 import pytest
@@ -71,18 +72,33 @@ def test_captured_epoch_equals_eager_epoch(sp):
         assert torch.equal(a, b)
 
 
-def test_protocol_moves_the_protein_rates_toward_the_truth(sp):
+def test_common_random_numbers_target_is_exact_at_the_truth(sp):
+    """Targets on the model's counters: at the true rates the model's segments
+    are the targets' segments, so the loss and its gradient are exactly 0."""
+    net = W.start_point_oscillator()
+    tr = sp.StartPointTrainer(net, np.asarray(W.OSC_PROTEIN_RATES), n_start=4096, n_paths=64, stride=9,
+                              burn=2000, batch=1024, n_rep=5, epochs=2)
+    for _ in range(2):
+        tr.step()
+        torch.cuda.synchronize()
+        assert float(tr.loss.item()) == 0.0
+        assert torch.count_nonzero(tr.d_params).item() == 0
+    assert np.allclose(tr.theta.cpu().numpy(), net.theta0)
+
+
+def test_protocol_recovers_the_protein_rates(sp):
     """The protocol at the paper's size (262,144 start points, 8,192 a batch,
     25 replicates of 150 steps, T = 3e-6, 3,000 epochs of RMSprop from 0.1
-    down to 1e-3) from rates off by factors of 2: the loss falls more than
-    tenfold and the error of the rates (median of the last quarter) falls
-    below half of the starting one."""
+    down to 1e-3) from rates off by factors of 2, targets on common random
+    numbers and the elapsed time as the rates' normaliser: the loss falls more
+    than a thousandfold and the five rates (median of the last quarter) come
+    within 5 % of the truth on average."""
     tr = sp.oscillator_start_points(epochs=3000, temperature=3e-6, lr0=0.1, lr1=1e-3)
     r = tr.run()
     ape0 = 100.0 * np.abs(r.k_start - r.k_true) / r.k_true
     n = r.epochs // 10
     print(f"\nstart-point map: loss {r.losses[:n].mean():.4g} -> {r.losses[-n:].mean():.4g}, "
-          f"MAPE {ape0.mean():.1f} % -> {r.ape.mean():.1f} %, rates {np.round(r.k_learned, 3).tolist()}, "
+          f"MAPE {ape0.mean():.1f} % -> {r.ape.mean():.2f} %, rates {np.round(r.k_learned, 3).tolist()}, "
           f"{r.epochs} epochs in {r.train_s:.1f} s")
-    assert r.losses[-n:].mean() < 0.1 * r.losses[:n].mean()
-    assert r.ape.mean() < 0.5 * ape0.mean()
+    assert r.losses[-n:].mean() < 1e-3 * r.losses[:n].mean()
+    assert r.ape.mean() < 5.0
