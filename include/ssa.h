@@ -206,7 +206,10 @@ typedef struct ssa_network_desc {
  *                  (up to 64 species and 511 channels; the group width is
  *                  set by wave_lanes); persistent launches pulling
  *                  trajectories from a work counter in cost order.
- *   SSA_EXEC_AUTO: the library picks (SPEC, else LANE for small batches, else WAVE). */
+ *   SSA_EXEC_AUTO: the library picks: SPEC when every network has at most 32
+ *                  channels (larger ones compile for minutes and spill in
+ *                  the specialised backward), else LANE for small batches,
+ *                  else WAVE. */
 enum { SSA_EXEC_AUTO = 0, SSA_EXEC_SPEC = 1, SSA_EXEC_LANE = 2, SSA_EXEC_WAVE = 3 };
 
 typedef struct ssa_net ssa_net;    /* opaque handle: device-resident tables */

@@ -436,6 +436,12 @@ ssa_status launch_all_classes(const ssa_net *net, RunParams p, bool backward, hi
 constexpr int kSpecMaxSpecies = 64;
 constexpr int kSpecMaxChannels = 64;
 constexpr int kSpecMaxTopologies = 16;
+// The library's own choice takes the specialised kernels for networks of at
+// most this many channels: past it their unrolled backward spills (kilobytes
+// of scratch a lane from about 48 channels) and compiling one topology grows
+// from tens of seconds to minutes.  SSA_EXEC_SPEC still accepts up to
+// kSpecMaxChannels.
+constexpr int kSpecAutoMaxChannels = 32;
 
 
 
@@ -556,7 +562,7 @@ ssa_status ssa_net_create(const ssa_network_desc *d, ssa_net **out)
     if (mode == kLane && !all_lane_fit) return bail(SSA_ESHAPE, "generic lane mode does not fit this batch");
     if (mode == kWave && !wave_fit) return bail(SSA_ESHAPE, "wave mode does not fit this batch");
     if (mode == 0) {
-        if (all_spec_fit) mode = kSpec;
+        if (all_spec_fit && max_M <= kSpecAutoMaxChannels) mode = kSpec;
         else if (all_lane_fit && nn <= 64) mode = kLane;
         else if (wave_fit) mode = kWave;
         else if (all_lane_fit) mode = kLane;
