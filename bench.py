@@ -375,33 +375,6 @@ def bench_grn(args, torch, dev):
     fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
     del pbufs
 
-    # the uneven batch as one persistent launch for every network (each then
-    # runs on the lane-group class of the largest), beside the tuned plan
-    one_launch = None
-    if workload == "uneven" and not light and args.one_launch_steps > 0 and getattr(h, "wave_split", -1) != 0:
-        h1 = ssa.Net(nets, Bs, t_obs=bw.t_obs, exec_mode="wave", wave_split=0)
-        b1 = ssa.forward(h1, cfg, theta, x0, tie_capacity=0, bwd_mode=bwd_mode)
-        dp1 = torch.empty_like(d_params)
-
-        def step1():
-            ssa.forward(h1, cfg, theta, x0, buffers=b1, tie_capacity=0, bwd_mode=bwd_mode)
-            o1 = b1.obs.detach().requires_grad_(True)
-            (g1,) = torch.autograd.grad(loss_fn(o1), o1)
-            ssa.backward(h1, cfg, theta, x0, b1, g1, d_params=dp1)
-        step1()
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        for _ in range(args.one_launch_steps):
-            step1()
-        torch.cuda.synchronize()
-        ms1 = (time.perf_counter() - s0) * 1e3 / args.one_launch_steps
-        ref = d_params.double()
-        one_launch = {"steps_per_s": int(b1.steps_done.sum().item()) / (ms1 * 1e-3), "ms_per_step": ms1,
-                      "steps": args.one_launch_steps,
-                      "counts_equal_tuned_plan": bool(torch.equal(b1.x_final, bufs.x_final)),
-                      "grad_max_diff_over_max": float((dp1.double() - ref).abs().max() / ref.abs().max())}
-        assert ssa.device_status(h1) == 0
-        del b1, h1, dp1
     n_ties = int(bufs.n_ties.item())
     assert ssa.grn_device_status(g) == 0
 
