@@ -39,8 +39,9 @@ HBM_PEAK = 8.0e12                        # MI355X HBM3E, bytes/s
 
 def alu_ops_per_step(net, backward: bool, inv_t_is_2=True, tangent: bool = False) -> dict:
     """Algorithmic vector-ALU operations of one step of one trajectory of a
-    mass-action network, by kind: mad = 32x32->64-bit product, int = 32-bit
-    integer add/logic/shift, fp32 = FP32 add/mul/FMA/compare/select, cvt =
+    mass-action network, by kind: mad = 32x32->64-bit product, bit3 = the
+    three-input bit operation (a ^ b ^ c), int = 32-bit integer
+    add/logic/shift, fp32 = FP32 add/mul/FMA/compare/select, cvt =
     int<->float conversion, log / rcp = transcendentals, f64 = FP64 add or FMA.
     Propensity work follows each channel's order: a zero-order channel's
     propensity is its rate, a first-order one costs one product and has a
@@ -57,7 +58,8 @@ def alu_ops_per_step(net, backward: bool, inv_t_is_2=True, tangent: bool = False
     nb = (M + 1 + 3) // 4
     w = M + 1                                        # Philox words used
     ops = {"mad": 20 * nb,                           # Philox4x32-10: two products a round
-           "int": 40 * nb + 2 * w,                   # four xors a round; word -> odd 24-bit integer
+           "bit3": 20 * nb,                          # and two three-input xors (one instruction each)
+           "int": 2 * w,                             # word -> odd 24-bit integer
            "cvt": w + factors, "fp32": 2 * w,        # lattice u = int * 2^-24, E = log2(u) * -ln 2
            "log": w, "rcp": 0, "f64": 0}
     ops["int"] += homo                               # X - 1 of homodimers
@@ -107,7 +109,7 @@ def measure_issue_costs():
     blocks, iters = 2048, 4096
     lanes = blocks * 256
     t = {}
-    for kind in range(7):
+    for kind in range(8):
         ms = L.ubench_run(kind, iters, blocks)
         if ms <= 0:
             raise RuntimeError("instruction probe failed")
@@ -115,7 +117,7 @@ def measure_issue_costs():
     i32 = t[4] / 2                  # xor + add
     f32 = t[3]                      # fma
     return {"int": i32, "fp32": f32, "mad": t[0] - i32, "log": t[1] - f32, "rcp": t[2] - f32,
-            "cvt": t[6] - i32, "f64": t[5]}
+            "cvt": t[6] - i32, "f64": t[5], "bit3": t[7] - i32}
 
 
 def gpu_rounding_constant(T: float) -> float:
@@ -279,7 +281,7 @@ def alu_ops_per_step_grn(n_hid: int, n_out: int, backward: bool, hidden_frac: fl
     M = 2 * (n_hid + n_out)
     nb = (M + 1 + 3) // 4
     w = M + 1
-    ops = {"mad": 20 * nb, "int": 40 * nb + 2 * w, "cvt": w, "fp32": 2 * w, "log": w, "rcp": 0, "f64": 0}
+    ops = {"mad": 20 * nb, "bit3": 20 * nb, "int": 2 * w, "cvt": w, "fp32": 2 * w, "log": w, "rcp": 0, "f64": 0}
     ops["cvt"] += n_hid + n_out                      # decay propensities delta * count
     ops["fp32"] += n_hid + n_out + M                 # their products, a0 sum
     # a hidden event: v_o += U_oh in FP64 and beta sigmoid(v_o) (FP64 range

@@ -36,9 +36,11 @@ struct Philox {
         for (int r = 0; r < 10; ++r) {
             const uint64_t pa = (uint64_t)kMulA * c0;
             const uint64_t pb = (uint64_t)kMulB * c2;
-            const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+            // hi ^ c ^ k as one three-input bit operation (truth table 0x96:
+            // the parity of the three inputs); the compiler issues two xors
+            const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0, 0x96);
             const uint32_t n1 = (uint32_t)pb;
-            const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+            const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1, 0x96);
             const uint32_t n3 = (uint32_t)pa;
             c0 = n0; c1 = n1; c2 = n2; c3 = n3;
             k0 += kWeylA;

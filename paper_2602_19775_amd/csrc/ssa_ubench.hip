@@ -42,6 +42,8 @@ __global__ __launch_bounds__(256) void probe(int iters, uint32_t seed, uint32_t 
                 d[c] = __builtin_fma(d[c], 0.999, 0.25);
             } else if (KIND == 6) {   // int -> float conversion
                 f[c] = (float)(__float_as_uint(f[c]) >> 9);
+            } else if (KIND == 7) {   // three-input bit operation (Philox's hi ^ c ^ k)
+                u[c] = __builtin_amdgcn_bitop3_b32(u[c], mul, 0x3C6EF372u, 0x96) + 0x3C6EF372u;
             }
         }
     }
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(256) void probe(int iters, uint32_t seed, uint32_t 
 // ops per lane executed by probe kind `kind` with `iters` iterations
 extern "C" double ubench_ops_per_lane(int kind, int iters)
 {
-    // kinds 0, 1, 2, 4 and 6 issue two instructions per chain step
+    // kinds 0, 1, 2, 4, 6 and 7 issue two instructions per chain step
     const double per = (kind == 3 || kind == 5) ? 1.0 : 2.0;
     return per * kChains * (double)iters;
 }
@@ -77,7 +79,8 @@ extern "C" float ubench_run(int kind, int iters, int blocks)
         case 3: hipLaunchKernelGGL(probe<3>, dim3(blocks), dim3(256), 0, 0, iters, 7u, sink); break;
         case 4: hipLaunchKernelGGL(probe<4>, dim3(blocks), dim3(256), 0, 0, iters, 7u, sink); break;
         case 5: hipLaunchKernelGGL(probe<5>, dim3(blocks), dim3(256), 0, 0, iters, 7u, sink); break;
-        default: hipLaunchKernelGGL(probe<6>, dim3(blocks), dim3(256), 0, 0, iters, 7u, sink); break;
+        case 6: hipLaunchKernelGGL(probe<6>, dim3(blocks), dim3(256), 0, 0, iters, 7u, sink); break;
+        default: hipLaunchKernelGGL(probe<7>, dim3(blocks), dim3(256), 0, 0, iters, 7u, sink); break;
         }
     };
     launch();   // warm-up
