@@ -1,19 +1,13 @@
 // Plan-time specialisation of the lane-mode kernels to a network topology:
 // the channel tables become compile-time constants of a small type that the
 // kernel bodies in ssa_spec_body.hpp are instantiated with, compiled for the
-// current device with hipRTC.  Identical topologies share one module, and
-// code objects are kept on disk for later processes.
+// current device with hipRTC.  Identical topologies share one module.
 #include "ssa_jit.hpp"
 
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
-#include <sys/stat.h>
-#include <unistd.h>
-
-#include <cerrno>
 #include <cstdio>
-#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -103,70 +97,23 @@ std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *ra
     return s.str();
 }
 
-namespace {
-
-uint64_t fnv1a(uint64_t h, const std::string &s)
+bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
 {
-    for (unsigned char c : s) {
-        h ^= c;
-        h *= 1099511628211ull;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_cache.find(src);
+    if (it != g_cache.end()) {
+        *out = it->second;
+        return true;
     }
-    return h;
-}
-
-// Directory of compiled code objects: SSA_JIT_CACHE_DIR if set (empty: no
-// cache), else $XDG_CACHE_HOME/ssa_mi355x/jit or $HOME/.cache/ssa_mi355x/jit.
-std::string cache_dir()
-{
-    if (const char *d = std::getenv("SSA_JIT_CACHE_DIR")) return std::string(d);
-    std::string base;
-    if (const char *x = std::getenv("XDG_CACHE_HOME")) base = x;
-    else if (const char *h = std::getenv("HOME")) base = std::string(h) + "/.cache";
-    else return "";
-    return base + "/ssa_mi355x/jit";
-}
-
-bool make_dirs(const std::string &path)
-{
-    for (size_t i = 1; i <= path.size(); ++i) {
-        if (i == path.size() || path[i] == '/') {
-            const std::string part = path.substr(0, i);
-            if (mkdir(part.c_str(), 0755) != 0 && errno != EEXIST) return false;
-        }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        *log = "no HIP device for runtime compilation";
+        return false;
     }
-    return true;
-}
-
-bool read_file(const std::string &path, std::vector<char> *out)
-{
-    FILE *f = std::fopen(path.c_str(), "rb");
-    if (!f) return false;
-    std::fseek(f, 0, SEEK_END);
-    const long n = std::ftell(f);
-    std::fseek(f, 0, SEEK_SET);
-    bool ok = n > 0;
-    if (ok) {
-        out->resize((size_t)n);
-        ok = std::fread(out->data(), 1, (size_t)n, f) == (size_t)n;
-    }
-    std::fclose(f);
-    return ok;
-}
-
-void write_file_atomic(const std::string &path, const std::vector<char> &data)
-{
-    const std::string tmp = path + ".tmp." + std::to_string((long)getpid());
-    FILE *f = std::fopen(tmp.c_str(), "wb");
-    if (!f) return;
-    const bool ok = std::fwrite(data.data(), 1, data.size(), f) == data.size();
-    if (std::fclose(f) == 0 && ok) std::rename(tmp.c_str(), path.c_str());
-    else std::remove(tmp.c_str());
-}
-
-// The code object of `src`, compiled by hipRTC (which compiles one program at
-// a time within a process, so the kernels of a topology share one program).
-bool compile_program(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log)
-{
+    std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
+    const std::string::size_type colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
     hiprtcProgram prog;
     if (hiprtcCreateProgram(&prog, src.c_str(), "ssa_spec.hip", kEmbeddedCount, kEmbeddedSources,
                             kEmbeddedNames) != HIPRTC_SUCCESS) {
@@ -188,88 +135,26 @@ bool compile_program(const std::string &src, const std::string &arch, std::vecto
     }
     size_t code_size = 0;
     hiprtcGetCodeSize(prog, &code_size);
-    code->resize(code_size);
-    hiprtcGetCode(prog, code->data());
+    std::vector<char> code(code_size);
+    hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
-    if (code_size == 0) {
-        *log = "runtime compilation produced no code";
-        return false;
-    }
-    return true;
-}
-
-}  // namespace
-
-bool spec_code_object(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log,
-                      bool *from_cache)
-{
-    if (from_cache) *from_cache = false;
-    std::string path, dir = from_cache ? cache_dir() : std::string();
-    if (!dir.empty() && make_dirs(dir)) {
-        int major = 0, minor = 0;
-        hiprtcVersion(&major, &minor);
-        uint64_t h = fnv1a(1469598103934665603ull, arch + "|-O3|c++17|no-packed-fp32|hiprtc " +
-                                                       std::to_string(major) + "." + std::to_string(minor) + "|");
-        for (int e = 0; e < kEmbeddedCount; ++e) h = fnv1a(fnv1a(h, kEmbeddedNames[e]), kEmbeddedSources[e]);
-        char name[64];
-        std::snprintf(name, sizeof(name), "/%016llx.co", (unsigned long long)fnv1a(h, src));
-        path = dir + name;
-        if (read_file(path, code)) {
-            *from_cache = true;
-            return true;
-        }
-    }
-    if (!compile_program(src, arch, code, log)) return false;
-    if (!path.empty()) write_file_atomic(path, *code);
-    return true;
-}
-
-bool spec_compile(const std::string &src, SpecKernels *out, std::string *log)
-{
-    std::lock_guard<std::mutex> lock(g_mu);
-    auto it = g_cache.find(src);
-    if (it != g_cache.end()) {
-        *out = it->second;
-        return true;
-    }
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
-        *log = "no HIP device for runtime compilation";
-        return false;
-    }
-    std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
-    const std::string::size_type colon = arch.find(':');
-    if (colon != std::string::npos) arch = arch.substr(0, colon);
-    std::vector<char> code;
-    bool from_cache = false;
-    if (!spec_code_object(src, arch, &code, log, &from_cache)) return false;
-
-    SpecKernels kn;
-    hipError_t e = hipModuleLoadData(&kn.module, code.data());
-    if (e != hipSuccess && from_cache) {
-        // an unreadable cached object: compile again (and do not store it)
-        if (!spec_code_object(src, arch, &code, log, nullptr)) return false;
-        e = hipModuleLoadData(&kn.module, code.data());
-    }
-    if (e != hipSuccess) {
+    SpecKernels k;
+    if (hipModuleLoadData(&k.module, code.data()) != hipSuccess ||
+        hipModuleGetFunction(&k.fwd, k.module, "ssa_spec_fwd") != hipSuccess ||
+        hipModuleGetFunction(&k.bwd, k.module, "ssa_spec_bwd") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_grid, k.module, "ssa_spec_fwd_grid") != hipSuccess ||
+        hipModuleGetFunction(&k.bwd_grid, k.module, "ssa_spec_bwd_grid") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_cdf, k.module, "ssa_spec_fwd_cdf") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_tm, k.module, "ssa_spec_fwd_tm") != hipSuccess ||
+        hipModuleGetFunction(&k.bwd_sh, k.module, "ssa_spec_bwd_sh") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_ens, k.module, "ssa_spec_fwd_ens") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_grid_ens, k.module, "ssa_spec_fwd_grid_ens") != hipSuccess ||
+        hipModuleGetFunction(&k.fwd_tan, k.module, "ssa_spec_fwd_tan") != hipSuccess) {
         *log = "loading the compiled module failed";
         return false;
     }
-    const char *names[] = {"ssa_spec_fwd", "ssa_spec_bwd", "ssa_spec_fwd_grid", "ssa_spec_bwd_grid",
-                           "ssa_spec_fwd_cdf", "ssa_spec_fwd_tm", "ssa_spec_bwd_sh", "ssa_spec_fwd_ens",
-                           "ssa_spec_fwd_grid_ens", "ssa_spec_fwd_tan"};
-    hipFunction_t *fn[] = {&kn.fwd, &kn.bwd, &kn.fwd_grid, &kn.bwd_grid, &kn.fwd_cdf,
-                           &kn.fwd_tm, &kn.bwd_sh, &kn.fwd_ens, &kn.fwd_grid_ens, &kn.fwd_tan};
-    for (int k = 0; k < (int)(sizeof(names) / sizeof(names[0])); ++k) {
-        if (hipModuleGetFunction(fn[k], kn.module, names[k]) != hipSuccess) {
-            *log = std::string("kernel ") + names[k] + " missing from the compiled module";
-            (void)hipModuleUnload(kn.module);
-            return false;
-        }
-    }
-    g_cache[src] = kn;
-    *out = kn;
+    g_cache[src] = k;
+    *out = k;
     return true;
 }
 

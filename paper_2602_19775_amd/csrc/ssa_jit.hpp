@@ -4,7 +4,6 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
-#include <vector>
 
 #include "ssa_plan.hpp"
 
@@ -29,18 +28,8 @@ struct SpecKernels {
 // Source of the specialised kernel pair for one network (host tables).
 std::string spec_source(int N, int M, const int32_t *reactant, const int32_t *rate_index,
                         const int8_t *stoich, int n_obs, const int32_t *obs_species);
-// Compiles the module for `src`, or fetches it from the in-process cache or
-// (its code object) from the on-disk cache below.
+// Compiles (or fetches from the in-process cache) the module for `src`.
 bool spec_compile(const std::string &src, SpecKernels *out, std::string *log);
-// The code object of `src` for `arch` ("--offload-arch=..."): read from the
-// on-disk cache (SSA_JIT_CACHE_DIR if set, empty for none; else
-// $XDG_CACHE_HOME or $HOME/.cache, under ssa_mi355x/jit), keyed by the
-// program text, the embedded header texts, the architecture,
-// the hipRTC version and the options, or compiled and stored there.  With
-// `from_cache` null the cache is neither read nor written; else it tells
-// whether the object was read from it.  Needs no device.
-bool spec_code_object(const std::string &src, const std::string &arch, std::vector<char> *code, std::string *log,
-                      bool *from_cache);
 hipError_t spec_launch(const SpecKernels &k, const RunParams &p, bool backward, size_t dyn_lds,
                        hipStream_t stream);
 
