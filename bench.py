@@ -263,6 +263,15 @@ def progress(what: str):
     print(f"[bench] {what}", file=sys.stderr, flush=True)
 
 
+def forward_reps(steps: int, fwd_s: float) -> int:
+    """Repetitions of the forward-only timing: the step count, raised so that
+    the timed forwards last at least half a second (a short forward timed
+    over a few launches is at the mercy of one late launch), at most 200."""
+    if fwd_s <= 0.0:
+        return steps
+    return int(min(max(steps, int(np.ceil(0.5 / fwd_s))), max(steps, 200)))
+
+
 def spread(ms) -> dict:
     """Median, minimum and maximum of per-step times (ms)."""
     a = np.asarray(ms, dtype=np.float64)
@@ -365,15 +374,19 @@ def bench_grn(args, torch, dev):
     for _ in range(args.warmup):
         ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=pbufs)
     torch.cuda.synchronize()
-    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    p0 = time.perf_counter()
+    ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=pbufs)
+    torch.cuda.synchronize()
+    n_fo = forward_reps(args.steps, time.perf_counter() - p0)
+    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n_fo)]
     f0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(n_fo):
         fevs[k][0].record()
         ssa.grn_forward(g, cfg, theta, x_img, tie_capacity=tie_cap, buffers=pbufs)
         fevs[k][1].record()
     torch.cuda.synchronize()
     f1 = time.perf_counter()
-    fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
+    fwd_rate = int(pbufs.steps_done.sum().item()) * n_fo / (f1 - f0)
     fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
     del pbufs
 
@@ -461,7 +474,7 @@ def bench_grn(args, torch, dev):
                    "steps_per_traj": cfg.n_steps, "n_params": net.n_params, "temperature": cfg.temperature},
         "forward_steps_per_s": fwd_rate, "fwdbwd_over_forward": value / fwd_rate, "graph_replay": graph,
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
-        "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
+        "step_ms": step_stats, "forward_only_ms": fwd_only_stats, "forward_only_reps": n_fo,
         "grad_rel_err": grad_rel_err, "counts_bit_exact_sample": counts_exact, "near_ties": n_ties,
         "loss": float(loss.item()), "roofline": roofline, "cpu_baseline": cpu,
     }
@@ -792,15 +805,19 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
     for _ in range(args.warmup):
         ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=bwd_mode)
     torch.cuda.synchronize()
-    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    p0 = time.perf_counter()
+    ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=bwd_mode)
+    torch.cuda.synchronize()
+    n_fo = forward_reps(args.steps, time.perf_counter() - p0)
+    fevs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n_fo)]
     f0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(n_fo):
         fevs[k][0].record()
         ssa.forward(h, cfg, theta, x0, buffers=pbufs, tie_capacity=tie_cap, bwd_mode=bwd_mode)
         fevs[k][1].record()
     torch.cuda.synchronize()
     f1 = time.perf_counter()
-    fwd_rate = int(pbufs.steps_done.sum().item()) * args.steps / (f1 - f0)
+    fwd_rate = int(pbufs.steps_done.sum().item()) * n_fo / (f1 - f0)
     fwd_only_stats = spread([e[0].elapsed_time(e[1]) for e in fevs])
     del pbufs
     progress(f"{workload}: forward-only steps done")
@@ -944,7 +961,7 @@ def bench_mass_action(args, torch, dev, workload: str, light: bool = False) -> d
         "forward_steps_per_s": fwd_rate, "graph_replay": graph, "fwdbwd_over_forward": value / fwd_rate,
         **({"one_persistent_launch": one_launch} if one_launch is not None else {}),
         "fwd_ms": fwd_ms, "loss_ms": loss_ms, "bwd_ms": bwd_ms,
-        "step_ms": step_stats, "forward_only_ms": fwd_only_stats,
+        "step_ms": step_stats, "forward_only_ms": fwd_only_stats, "forward_only_reps": n_fo,
         "grad_rel_err": grad_rel_err, "grad_error": grad_detail, "counts_bit_exact_sample": counts_exact,
         "near_ties": n_ties - n_edge, "bin_edge_events": n_edge, "loss": float(loss.item()),
         "roofline": roofline, "cpu_baseline": cpu,
